@@ -1,0 +1,927 @@
+/*
+ * Plain FP64 CPU oracle for restarted Halpern PDHG (LP, Algorithm 1) and
+ * restarted accelerated PDHG (QP, Algorithm 2) of "MPAX: Mathematical
+ * Programming in JAX" (arXiv 2412.09734).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke test and the
+ * benchmark's CPU-baseline leg, never by the GPU library.
+ *
+ * Every loop below follows one equation of the paper or one written reading of
+ * a point the paper leaves open (the readings are listed in the design notes
+ * with the same names used here: scaling, step size, primal weight, restart
+ * rule, KKT composition, check cadence, rAPDHG schedule, frozen schedule).
+ * Sums accumulate in long double; nothing is blocked or fused.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef long double ld;
+
+struct orc_ctx {
+    orc_problem p;       /* original data (caller-owned pointers) */
+    orc_options o;
+    int32_t m, n;
+    /* scaled constraint matrix: same layout as the input */
+    double *val;         /* CSR values (nnz) or dense (m*n) */
+    int dense;
+    /* scaled quadratic term */
+    double *qval;        /* CSR values */
+    double *qf;          /* n x r */
+    double *qd;          /* n */
+    double *dr, *dc;     /* D_r [m], D_c [n] */
+    double *c, *lc, *uc, *lv, *uv;   /* scaled data */
+    double eta, omega0, norm_a, norm_q;
+    int32_t power_iters;
+};
+
+/* ------------------------------------------------------------------------ */
+/* small helpers                                                            */
+
+static double clampd(double v, double lo, double hi) { return fmin(fmax(v, lo), hi); }
+
+static ld sumsq(const double *v, int32_t len) {
+    ld s = 0.0L;
+    for (int32_t i = 0; i < len; ++i) s += (ld)v[i] * (ld)v[i];
+    return s;
+}
+
+static ld dot(const double *a, const double *b, int32_t len) {
+    ld s = 0.0L;
+    for (int32_t i = 0; i < len; ++i) s += (ld)a[i] * (ld)b[i];
+    return s;
+}
+
+static double *dalloc(size_t len) {
+    double *p = (double *)calloc(len ? len : 1, sizeof(double));
+    if (!p) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    return p;
+}
+
+static ld *lalloc(size_t len) {
+    ld *p = (ld *)calloc(len ? len : 1, sizeof(ld));
+    if (!p) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    return p;
+}
+
+void orc_default_options(orc_options *o) {
+    o->eps = 1e-4;                 /* eps_abs = eps_rel = 1e-4, Appendix A */
+    o->iteration_limit = INT64_MAX;
+    o->check_every = 64;
+    o->ruiz_iters = 10;
+    o->pock_chambolle = 1;
+    o->gamma = 1.0;                /* Algorithm 1 uses 2 xhat - x */
+    o->step_safety = 0.998;
+    o->restart_sufficient = 0.2;
+    o->restart_necessary = 0.8;
+    o->restart_artificial = 0.36;
+    o->power_tol = 1e-7;
+    o->power_max_iters = 2000;
+    o->verbose = 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* products with the scaled matrices                                         */
+
+/* out = A~ v  (m-vector) */
+static void a_mul(const orc_ctx *s, const double *v, double *out) {
+    const int32_t m = s->m, n = s->n;
+    for (int32_t i = 0; i < m; ++i) {
+        ld acc = 0.0L;
+        if (s->dense) {
+            const double *row = s->val + (size_t)i * n;
+            for (int32_t j = 0; j < n; ++j) acc += (ld)row[j] * (ld)v[j];
+        } else {
+            for (int32_t e = s->p.rowptr[i]; e < s->p.rowptr[i + 1]; ++e)
+                acc += (ld)s->val[e] * (ld)v[s->p.colidx[e]];
+        }
+        out[i] = (double)acc;
+    }
+}
+
+/* out = A~' w  (n-vector): entries of each column summed in row order */
+static void at_mul(const orc_ctx *s, const double *w, double *out) {
+    const int32_t m = s->m, n = s->n;
+    ld *acc = lalloc(n);
+    for (int32_t i = 0; i < m; ++i) {
+        if (s->dense) {
+            const double *row = s->val + (size_t)i * n;
+            for (int32_t j = 0; j < n; ++j) acc[j] += (ld)row[j] * (ld)w[i];
+        } else {
+            for (int32_t e = s->p.rowptr[i]; e < s->p.rowptr[i + 1]; ++e)
+                acc[s->p.colidx[e]] += (ld)s->val[e] * (ld)w[i];
+        }
+    }
+    for (int32_t j = 0; j < n; ++j) out[j] = (double)acc[j];
+    free(acc);
+}
+
+/* out = Q~ v (zero when there is no quadratic term) */
+static void q_mul(const orc_ctx *s, const double *v, double *out) {
+    const int32_t n = s->n;
+    if (s->p.q_kind == 1) {
+        for (int32_t k = 0; k < n; ++k) {
+            ld acc = 0.0L;
+            for (int32_t e = s->p.q_rowptr[k]; e < s->p.q_rowptr[k + 1]; ++e)
+                acc += (ld)s->qval[e] * (ld)v[s->p.q_colidx[e]];
+            out[k] = (double)acc;
+        }
+    } else if (s->p.q_kind == 2) {
+        const int32_t r = s->p.q_rank;
+        ld *t = lalloc(r);
+        for (int32_t j = 0; j < n; ++j)
+            for (int32_t q = 0; q < r; ++q) t[q] += (ld)s->qf[(size_t)j * r + q] * (ld)v[j];
+        double *td = dalloc(r);
+        for (int32_t q = 0; q < r; ++q) td[q] = (double)t[q];
+        for (int32_t j = 0; j < n; ++j) {
+            ld acc = 0.0L;
+            for (int32_t q = 0; q < r; ++q) acc += (ld)s->qf[(size_t)j * r + q] * (ld)td[q];
+            acc += (ld)s->qd[j] * (ld)v[j];
+            out[j] = (double)acc;
+        }
+        free(t);
+        free(td);
+    } else {
+        for (int32_t k = 0; k < n; ++k) out[k] = 0.0;
+    }
+}
+
+/* out = Q v with the ORIGINAL quadratic term (for the KKT error) */
+static void q_mul_orig(const orc_problem *p, const double *v, double *out) {
+    const int32_t n = p->n;
+    if (p->q_kind == 1) {
+        for (int32_t k = 0; k < n; ++k) {
+            ld acc = 0.0L;
+            for (int32_t e = p->q_rowptr[k]; e < p->q_rowptr[k + 1]; ++e)
+                acc += (ld)p->q_val[e] * (ld)v[p->q_colidx[e]];
+            out[k] = (double)acc;
+        }
+    } else if (p->q_kind == 2) {
+        const int32_t r = p->q_rank;
+        ld *t = lalloc(r);
+        for (int32_t j = 0; j < n; ++j)
+            for (int32_t q = 0; q < r; ++q) t[q] += (ld)p->q_factor[(size_t)j * r + q] * (ld)v[j];
+        for (int32_t j = 0; j < n; ++j) {
+            ld acc = 0.0L;
+            for (int32_t q = 0; q < r; ++q) acc += (ld)p->q_factor[(size_t)j * r + q] * t[q];
+            acc += (ld)p->q_diag[j] * (ld)v[j];
+            out[j] = (double)acc;
+        }
+        free(t);
+    } else {
+        for (int32_t k = 0; k < n; ++k) out[k] = 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* validation                                                               */
+
+static int validate(const orc_problem *p) {
+    if (p->m < 0 || p->n < 1) return 0;
+    if (!p->c || !p->lv || !p->uv) return 0;
+    if (p->m > 0 && (!p->lc || !p->uc)) return 0;
+    if (!p->dense) {
+        if (!p->rowptr || p->rowptr[0] != 0) return 0;
+        for (int32_t i = 0; i < p->m; ++i) {
+            if (p->rowptr[i + 1] < p->rowptr[i]) return 0;
+            for (int32_t e = p->rowptr[i]; e < p->rowptr[i + 1]; ++e) {
+                int32_t j = p->colidx[e];
+                if (j < 0 || j >= p->n) return 0;
+                if (e > p->rowptr[i] && j <= p->colidx[e - 1]) return 0;
+                if (!isfinite(p->val[e])) return 0;
+            }
+        }
+    } else {
+        for (size_t e = 0; e < (size_t)p->m * p->n; ++e)
+            if (!isfinite(p->dense[e])) return 0;
+    }
+    for (int32_t j = 0; j < p->n; ++j) {
+        if (!isfinite(p->c[j])) return 0;
+        if (isnan(p->lv[j]) || isnan(p->uv[j]) || p->lv[j] > p->uv[j]) return 0;
+        if (p->lv[j] == INFINITY || p->uv[j] == -INFINITY) return 0;
+    }
+    for (int32_t i = 0; i < p->m; ++i) {
+        if (isnan(p->lc[i]) || isnan(p->uc[i]) || p->lc[i] > p->uc[i]) return 0;
+        if (p->lc[i] == INFINITY || p->uc[i] == -INFINITY) return 0;
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* preconditioning (Section 3: Ruiz, then Pock-Chambolle)                   */
+
+/* Apply row factors r and column factors s to the scaled copy:
+ * A~_ij <- A~_ij / (r_i s_j), D_r <- D_r / r, D_c <- D_c / s. */
+static void apply_factors(orc_ctx *s, const double *r, const double *cs) {
+    const int32_t m = s->m, n = s->n;
+    for (int32_t i = 0; i < m; ++i) {
+        if (s->dense) {
+            double *row = s->val + (size_t)i * n;
+            for (int32_t j = 0; j < n; ++j) row[j] = row[j] / (r[i] * cs[j]);
+        } else {
+            for (int32_t e = s->p.rowptr[i]; e < s->p.rowptr[i + 1]; ++e)
+                s->val[e] = s->val[e] / (r[i] * cs[s->p.colidx[e]]);
+        }
+        s->dr[i] = s->dr[i] / r[i];
+    }
+    for (int32_t j = 0; j < n; ++j) s->dc[j] = s->dc[j] / cs[j];
+}
+
+/* Ruiz equilibration: each pass divides row i by sqrt(max_j |A~_ij|) and
+ * column j by sqrt(max_i |A~_ij|) (both taken before the pass; a zero norm
+ * gives factor 1). Pock-Chambolle with alpha = 1: same with 1-norms. */
+static void scale(orc_ctx *s) {
+    const int32_t m = s->m, n = s->n;
+    double *r = dalloc(m), *cs = dalloc(n);
+    for (int32_t pass = 0; pass < s->o.ruiz_iters + (s->o.pock_chambolle ? 1 : 0); ++pass) {
+        const int pc = pass >= s->o.ruiz_iters;
+        ld *rn = lalloc(m), *cn = lalloc(n);
+        for (int32_t i = 0; i < m; ++i) {
+            if (s->dense) {
+                const double *row = s->val + (size_t)i * n;
+                for (int32_t j = 0; j < n; ++j) {
+                    ld a = fabsl((ld)row[j]);
+                    if (pc) { rn[i] += a; cn[j] += a; }
+                    else { if (a > rn[i]) rn[i] = a; if (a > cn[j]) cn[j] = a; }
+                }
+            } else {
+                for (int32_t e = s->p.rowptr[i]; e < s->p.rowptr[i + 1]; ++e) {
+                    int32_t j = s->p.colidx[e];
+                    ld a = fabsl((ld)s->val[e]);
+                    if (pc) { rn[i] += a; cn[j] += a; }
+                    else { if (a > rn[i]) rn[i] = a; if (a > cn[j]) cn[j] = a; }
+                }
+            }
+        }
+        for (int32_t i = 0; i < m; ++i) {
+            double v = (double)rn[i];
+            r[i] = v > 0.0 ? sqrt(v) : 1.0;
+        }
+        for (int32_t j = 0; j < n; ++j) {
+            double v = (double)cn[j];
+            cs[j] = v > 0.0 ? sqrt(v) : 1.0;
+        }
+        apply_factors(s, r, cs);
+        free(rn);
+        free(cn);
+    }
+    free(r);
+    free(cs);
+}
+
+/* ------------------------------------------------------------------------ */
+/* power iteration for ||A~||_2 and ||Q~||_2                                 */
+
+static double power_norm_a(const orc_ctx *s, int32_t *iters) {
+    const int32_t m = s->m, n = s->n;
+    double *v = dalloc(n), *w = dalloc(m), *u = dalloc(n);
+    for (int32_t j = 0; j < n; ++j) v[j] = 1.0 / sqrt((double)n);
+    double lam = 0.0, lam_prev = 0.0;
+    int32_t it = 0;
+    for (it = 1; it <= s->o.power_max_iters; ++it) {
+        a_mul(s, v, w);
+        lam = (double)sumsq(w, m);            /* Rayleigh quotient of A~'A~ */
+        at_mul(s, w, u);
+        double nu = sqrtl(sumsq(u, n));
+        if (!(nu > 0.0)) { lam = 0.0; break; }
+        for (int32_t j = 0; j < n; ++j) v[j] = u[j] / nu;
+        if (it > 1 && fabs(lam - lam_prev) <= s->o.power_tol * lam) break;
+        lam_prev = lam;
+    }
+    if (it > s->o.power_max_iters) it = s->o.power_max_iters;
+    if (iters) *iters = it;
+    free(v); free(w); free(u);
+    return sqrt(lam);
+}
+
+static double power_norm_q(const orc_ctx *s) {
+    const int32_t n = s->n;
+    if (s->p.q_kind == 0) return 0.0;
+    double *v = dalloc(n), *w = dalloc(n);
+    for (int32_t j = 0; j < n; ++j) v[j] = 1.0 / sqrt((double)n);
+    double lam = 0.0, lam_prev = 0.0;
+    for (int32_t it = 1; it <= s->o.power_max_iters; ++it) {
+        q_mul(s, v, w);
+        lam = (double)dot(v, w, n);
+        double nw = sqrtl(sumsq(w, n));
+        if (!(nw > 0.0)) { lam = 0.0; break; }
+        for (int32_t j = 0; j < n; ++j) v[j] = w[j] / nw;
+        if (it > 1 && fabs(lam - lam_prev) <= s->o.power_tol * fabs(lam)) break;
+        lam_prev = lam;
+    }
+    free(v); free(w);
+    return lam;
+}
+
+/* ------------------------------------------------------------------------ */
+/* setup                                                                     */
+
+orc_ctx *orc_create(const orc_problem *p, const orc_options *o) {
+    if (!validate(p)) return NULL;
+    orc_ctx *s = (orc_ctx *)calloc(1, sizeof(orc_ctx));
+    s->p = *p;
+    s->o = *o;
+    s->m = p->m;
+    s->n = p->n;
+    const int32_t m = p->m, n = p->n;
+    s->dense = p->dense != NULL;
+    size_t nv = s->dense ? (size_t)m * n : (size_t)p->rowptr[m];
+    s->val = dalloc(nv);
+    memcpy(s->val, s->dense ? p->dense : p->val, nv * sizeof(double));
+    s->dr = dalloc(m);
+    s->dc = dalloc(n);
+    for (int32_t i = 0; i < m; ++i) s->dr[i] = 1.0;
+    for (int32_t j = 0; j < n; ++j) s->dc[j] = 1.0;
+    scale(s);
+    /* transformed data: c~ = D_c c, l~_c = D_r l_c, l~_v = l_v / D_c */
+    s->c = dalloc(n); s->lv = dalloc(n); s->uv = dalloc(n);
+    s->lc = dalloc(m); s->uc = dalloc(m);
+    for (int32_t j = 0; j < n; ++j) {
+        s->c[j] = s->dc[j] * p->c[j];
+        s->lv[j] = p->lv[j] / s->dc[j];
+        s->uv[j] = p->uv[j] / s->dc[j];
+    }
+    for (int32_t i = 0; i < m; ++i) {
+        s->lc[i] = s->dr[i] * p->lc[i];
+        s->uc[i] = s->dr[i] * p->uc[i];
+    }
+    /* Q~ = D_c Q D_c */
+    if (p->q_kind == 1) {
+        size_t qn = (size_t)p->q_rowptr[n];
+        s->qval = dalloc(qn);
+        for (int32_t k = 0; k < n; ++k)
+            for (int32_t e = p->q_rowptr[k]; e < p->q_rowptr[k + 1]; ++e)
+                s->qval[e] = (s->dc[k] * p->q_val[e]) * s->dc[p->q_colidx[e]];
+    } else if (p->q_kind == 2) {
+        const int32_t r = p->q_rank;
+        s->qf = dalloc((size_t)n * r);
+        s->qd = dalloc(n);
+        for (int32_t j = 0; j < n; ++j) {
+            for (int32_t q = 0; q < r; ++q)
+                s->qf[(size_t)j * r + q] = s->dc[j] * p->q_factor[(size_t)j * r + q];
+            s->qd[j] = (s->dc[j] * s->dc[j]) * p->q_diag[j];
+        }
+    }
+    /* step size: eta = safety / ||A~||_2 (1 when A~ = 0) */
+    s->norm_a = power_norm_a(s, &s->power_iters);
+    s->eta = s->norm_a > 0.0 ? s->o.step_safety / s->norm_a : 1.0;
+    s->norm_q = power_norm_q(s);
+    /* initial primal weight: ||c~|| / ||b~||, b~_i = largest finite |bound| */
+    double *bt = dalloc(m);
+    for (int32_t i = 0; i < m; ++i) {
+        double b = 0.0;
+        if (isfinite(s->lc[i])) b = fmax(b, fabs(s->lc[i]));
+        if (isfinite(s->uc[i])) b = fmax(b, fabs(s->uc[i]));
+        bt[i] = b;
+    }
+    double cn = (double)sqrtl(sumsq(s->c, n)), bn = (double)sqrtl(sumsq(bt, m));
+    s->omega0 = (cn > 1e-10 && bn > 1e-10) ? cn / bn : 1.0;
+    free(bt);
+    return s;
+}
+
+void orc_destroy(orc_ctx *s) {
+    if (!s) return;
+    free(s->val); free(s->qval); free(s->qf); free(s->qd);
+    free(s->dr); free(s->dc); free(s->c); free(s->lc); free(s->uc);
+    free(s->lv); free(s->uv);
+    free(s);
+}
+
+void orc_scaling(const orc_ctx *s, double *dr, double *dc, double *eta, double *omega,
+                 double *norm_a, double *norm_q, int32_t *power_iters) {
+    if (dr) memcpy(dr, s->dr, sizeof(double) * s->m);
+    if (dc) memcpy(dc, s->dc, sizeof(double) * s->n);
+    if (eta) *eta = s->eta;
+    if (omega) *omega = s->omega0;
+    if (norm_a) *norm_a = s->norm_a;
+    if (norm_q) *norm_q = s->norm_q;
+    if (power_iters) *power_iters = s->power_iters;
+}
+
+void orc_scaled_vectors(const orc_ctx *s, double *c, double *lc, double *uc, double *lv,
+                        double *uv) {
+    if (c) memcpy(c, s->c, sizeof(double) * s->n);
+    if (lv) memcpy(lv, s->lv, sizeof(double) * s->n);
+    if (uv) memcpy(uv, s->uv, sizeof(double) * s->n);
+    if (lc) memcpy(lc, s->lc, sizeof(double) * s->m);
+    if (uc) memcpy(uc, s->uc, sizeof(double) * s->m);
+}
+
+/* ------------------------------------------------------------------------ */
+/* one iteration                                                             */
+
+/* Dual proximal step of eq. (pdhg-lp): with v = y/sigma - a,
+ * yhat = y - sigma a - sigma proj_[-u_c, -l_c](v) = sigma (v - proj(v)). */
+static double dual_prox(double y, double a, double sigma, double lc, double uc) {
+    double v = y / sigma - a;
+    double pr = clampd(v, -uc, -lc);
+    return sigma * (v - pr);
+}
+
+void orc_lp_step(const orc_ctx *s, const double *x, const double *y, const double *x0,
+                 const double *y0, int64_t k, double tau, double sigma, double gamma,
+                 double *xhat, double *yhat, double *xnew, double *ynew) {
+    const int32_t m = s->m, n = s->n;
+    double *aty = dalloc(n), *xh = dalloc(n), *xe = dalloc(n), *a = dalloc(m),
+           *yh = dalloc(m);
+    /* primal step: xhat = proj_X(x - tau (c - A'y)) */
+    at_mul(s, y, aty);
+    for (int32_t j = 0; j < n; ++j) {
+        xh[j] = clampd(x[j] - tau * (s->c[j] - aty[j]), s->lv[j], s->uv[j]);
+        xe[j] = 2.0 * xh[j] - x[j];
+    }
+    /* dual step with the extrapolated primal point 2 xhat - x */
+    a_mul(s, xe, a);
+    for (int32_t i = 0; i < m; ++i) yh[i] = dual_prox(y[i], a[i], sigma, s->lc[i], s->uc[i]);
+    /* Halpern step with reflection, eq. (hrpdhg) */
+    const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+    if (xnew)
+        for (int32_t j = 0; j < n; ++j)
+            xnew[j] = ak * ((1.0 + gamma) * xh[j] - gamma * x[j]) + bk * x0[j];
+    if (ynew)
+        for (int32_t i = 0; i < m; ++i)
+            ynew[i] = ak * ((1.0 + gamma) * yh[i] - gamma * y[i]) + bk * y0[i];
+    if (xhat) memcpy(xhat, xh, sizeof(double) * n);
+    if (yhat) memcpy(yhat, yh, sizeof(double) * m);
+    free(aty); free(xh); free(xe); free(a); free(yh);
+}
+
+/* rAPDHG step, Algorithm 2: beta_k = theta_k = 2/(k+2),
+ * 1/tau_k = omega/eta + 2 ||Q~|| / (k+1), sigma = eta omega. */
+void orc_qp_step(const orc_ctx *s, const double *x, const double *y, const double *xbar,
+                 const double *ybar, int64_t k, double omega, double *xn, double *yn,
+                 double *xbarn, double *ybarn) {
+    const int32_t m = s->m, n = s->n;
+    const double beta = 2.0 / (double)(k + 2), theta = beta;
+    const double tau = 1.0 / (omega / s->eta + 2.0 * s->norm_q / (double)(k + 1));
+    const double sigma = s->eta * omega;
+    double *v = dalloc(n), *qv = dalloc(n), *aty = dalloc(n), *xh = dalloc(n),
+           *xe = dalloc(n), *a = dalloc(m), *yh = dalloc(m);
+    for (int32_t j = 0; j < n; ++j) v[j] = (1.0 - beta) * xbar[j] + beta * x[j];
+    q_mul(s, v, qv);
+    at_mul(s, y, aty);
+    for (int32_t j = 0; j < n; ++j) {
+        xh[j] = clampd(x[j] - tau * (qv[j] + s->c[j] - aty[j]), s->lv[j], s->uv[j]);
+        xe[j] = 2.0 * xh[j] - x[j];
+    }
+    a_mul(s, xe, a);
+    for (int32_t i = 0; i < m; ++i) yh[i] = dual_prox(y[i], a[i], sigma, s->lc[i], s->uc[i]);
+    if (xbarn)
+        for (int32_t j = 0; j < n; ++j) xbarn[j] = (1.0 - theta) * xbar[j] + theta * xh[j];
+    if (ybarn)
+        for (int32_t i = 0; i < m; ++i) ybarn[i] = (1.0 - theta) * ybar[i] + theta * yh[i];
+    if (xn) memcpy(xn, xh, sizeof(double) * n);
+    if (yn) memcpy(yn, yh, sizeof(double) * m);
+    free(v); free(qv); free(aty); free(xh); free(xe); free(a); free(yh);
+}
+
+/* ||z - zhat||_M with M = [[I/tau, A~'], [A~, I/sigma]], the norm in which
+ * the PDHG operator is firmly non-expansive:
+ * r^2 = ||dx||^2/tau + ||dy||^2/sigma + 2 dy' A~ dx. */
+double orc_fixed_point_residual(const orc_ctx *s, const double *x, const double *y,
+                                const double *xhat, const double *yhat, double tau,
+                                double sigma) {
+    const int32_t m = s->m, n = s->n;
+    double *dx = dalloc(n), *dy = dalloc(m), *adx = dalloc(m);
+    for (int32_t j = 0; j < n; ++j) dx[j] = xhat[j] - x[j];
+    for (int32_t i = 0; i < m; ++i) dy[i] = yhat[i] - y[i];
+    a_mul(s, dx, adx);
+    ld r2 = sumsq(dx, n) / tau + sumsq(dy, m) / sigma + 2.0L * dot(dy, adx, m);
+    free(dx); free(dy); free(adx);
+    return r2 > 0.0L ? (double)sqrtl(r2) : 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* relative KKT error, original space                                        */
+
+void orc_kkt(const orc_problem *p, const double *x, const double *y, orc_result *r) {
+    const int32_t m = p->m, n = p->n;
+    double *ax = dalloc(m), *aty = dalloc(n), *qx = dalloc(n);
+    /* A x and A' y with the original matrix */
+    for (int32_t i = 0; i < m; ++i) {
+        ld acc = 0.0L;
+        if (p->dense) {
+            for (int32_t j = 0; j < n; ++j) acc += (ld)p->dense[(size_t)i * n + j] * (ld)x[j];
+        } else {
+            for (int32_t e = p->rowptr[i]; e < p->rowptr[i + 1]; ++e)
+                acc += (ld)p->val[e] * (ld)x[p->colidx[e]];
+        }
+        ax[i] = (double)acc;
+    }
+    {
+        ld *acc = lalloc(n);
+        for (int32_t i = 0; i < m; ++i) {
+            if (p->dense) {
+                for (int32_t j = 0; j < n; ++j) acc[j] += (ld)p->dense[(size_t)i * n + j] * (ld)y[i];
+            } else {
+                for (int32_t e = p->rowptr[i]; e < p->rowptr[i + 1]; ++e)
+                    acc[p->colidx[e]] += (ld)p->val[e] * (ld)y[i];
+            }
+        }
+        for (int32_t j = 0; j < n; ++j) aty[j] = (double)acc[j];
+        free(acc);
+    }
+    q_mul_orig(p, x, qx);
+    ld rp2 = 0.0L, rd2 = 0.0L, b2 = 0.0L, c2 = 0.0L;
+    ld xqx = 0.0L, cx = 0.0L, dual_b = 0.0L, dual_v = 0.0L;
+    for (int32_t i = 0; i < m; ++i) {
+        /* primal residual: distance of A x to [l_c, u_c] */
+        double rp = ax[i] - clampd(ax[i], p->lc[i], p->uc[i]);
+        rp2 += (ld)rp * rp;
+        double b = 0.0;
+        if (isfinite(p->lc[i])) b = fmax(b, fabs(p->lc[i]));
+        if (isfinite(p->uc[i])) b = fmax(b, fabs(p->uc[i]));
+        b2 += (ld)b * b;
+        /* -p(y) = l_c' y^+ - u_c' y^- (terms with infinite bounds are 0) */
+        if (isfinite(p->lc[i])) dual_b += (ld)p->lc[i] * (ld)fmax(y[i], 0.0);
+        if (isfinite(p->uc[i])) dual_b -= (ld)p->uc[i] * (ld)fmax(-y[i], 0.0);
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        /* gradient of the Lagrangian in x, and its part in the normal cone of X */
+        double g = qx[j] + p->c[j] - aty[j];
+        int lf = isfinite(p->lv[j]), uf = isfinite(p->uv[j]);
+        double lam;
+        if (!lf && !uf) lam = 0.0;
+        else if (lf && !uf) lam = fmax(g, 0.0);
+        else if (!lf && uf) lam = fmin(g, 0.0);
+        else lam = g;
+        double rd = g - lam;
+        rd2 += (ld)rd * rd;
+        c2 += (ld)p->c[j] * p->c[j];
+        xqx += (ld)x[j] * (ld)qx[j];
+        cx += (ld)p->c[j] * (ld)x[j];
+        if (lf) dual_v += (ld)p->lv[j] * (ld)fmax(lam, 0.0);
+        if (uf) dual_v -= (ld)p->uv[j] * (ld)fmax(-lam, 0.0);
+    }
+    ld P = 0.5L * xqx + cx;
+    ld D = -0.5L * xqx + dual_b + dual_v;
+    r->primal_obj = (double)P;
+    r->dual_obj = (double)D;
+    r->abs_primal = (double)sqrtl(rp2);
+    r->abs_dual = (double)sqrtl(rd2);
+    r->abs_gap = (double)fabsl(P - D);
+    r->rel_primal = (double)(sqrtl(rp2) / (1.0L + sqrtl(b2)));
+    r->rel_dual = (double)(sqrtl(rd2) / (1.0L + sqrtl(c2)));
+    r->rel_gap = (double)(fabsl(P - D) / (1.0L + fabsl(P) + fabsl(D)));
+    double k = r->rel_primal;
+    if (r->rel_dual > k || isnan(r->rel_dual)) k = r->rel_dual;
+    if (r->rel_gap > k || isnan(r->rel_gap)) k = r->rel_gap;
+    r->kkt = k;
+    free(ax); free(aty); free(qx);
+}
+
+/* ------------------------------------------------------------------------ */
+/* solver loops                                                              */
+
+static void unscale(const orc_ctx *s, const double *xs, const double *ys, double *x,
+                    double *y) {
+    for (int32_t j = 0; j < s->n; ++j) x[j] = s->dc[j] * xs[j];
+    for (int32_t i = 0; i < s->m; ++i) y[i] = s->dr[i] * ys[i];
+}
+
+/* projection onto Y (sign constraints of the dual, Section 2) */
+static double proj_y(double y, double lc, double uc) {
+    double lo = isfinite(uc) ? -INFINITY : 0.0;   /* no upper bound: y >= 0 */
+    double hi = isfinite(lc) ? INFINITY : 0.0;    /* no lower bound: y <= 0 */
+    return clampd(y, lo, hi);
+}
+
+static void init_point(const orc_ctx *s, const double *x_init, const double *y_init,
+                       double *x, double *y) {
+    for (int32_t j = 0; j < s->n; ++j)
+        x[j] = clampd(x_init ? x_init[j] / s->dc[j] : 0.0, s->lv[j], s->uv[j]);
+    for (int32_t i = 0; i < s->m; ++i)
+        y[i] = proj_y(y_init ? y_init[i] / s->dr[i] : 0.0, s->lc[i], s->uc[i]);
+}
+
+/* Restart test shared by both methods: sufficient decay, necessary decay
+ * without local progress, or an artificial restart after a long cycle. */
+static int restart_due(const orc_ctx *s, double r, double r_start, double r_prev,
+                       int64_t k, int64_t t) {
+    if (r <= s->o.restart_sufficient * r_start) return 1;
+    if (r <= s->o.restart_necessary * r_start && r > r_prev) return 1;
+    if ((double)k >= s->o.restart_artificial * (double)t) return 1;
+    return 0;
+}
+
+/* primal weight after a restart: log-smoothing (weight 1/2) towards dy/dx */
+static double new_weight(double omega, double dxr, double dyr) {
+    if (dxr > 1e-10 && dyr > 1e-10) return exp(0.5 * log(dyr / dxr) + 0.5 * log(omega));
+    return omega;
+}
+
+/* Core LP loop (Algorithm 1). When frozen != NULL the loop runs exactly T
+ * iterations and takes restarts / weights from the schedule instead of the
+ * tests; rec_* record the schedule actually used; masks (optional) record
+ * the projection state of every iteration for the reverse pass. */
+typedef struct {
+    const uint8_t *restart;   /* [T] or NULL */
+    const double *omega;      /* [T] or NULL */
+    uint8_t *rec_restart;     /* [T] or NULL */
+    double *rec_omega;        /* [T] or NULL */
+    uint8_t *xmask;           /* [T*n]: 1 if xhat strictly inside its box */
+    uint8_t *ymask;           /* [T*m]: 0 interior, 1 at -u_c, 2 at -l_c */
+    int64_t *kk;              /* [T]: inner counter */
+    int64_t T;
+} lp_trace;
+
+static int lp_loop(orc_ctx *s, const double *x_init, const double *y_init, double *x_out,
+                   double *y_out, orc_result *res, lp_trace *tr) {
+    const int32_t m = s->m, n = s->n;
+    double *x = dalloc(n), *y = dalloc(m), *x0 = dalloc(n), *y0 = dalloc(m);
+    double *xh = dalloc(n), *yh = dalloc(m), *xn = dalloc(n), *yn = dalloc(m);
+    double *xo = dalloc(n), *yo = dalloc(m);
+    init_point(s, x_init, y_init, x, y);
+    memcpy(x0, x, sizeof(double) * n);
+    memcpy(y0, y, sizeof(double) * m);
+    double omega = s->omega0, tau = s->eta / omega, sigma = s->eta * omega;
+    double r_start = 0.0, r_prev = 0.0;
+    int64_t k = 0, t = 0, nr = 0;
+    const int64_t limit = tr ? tr->T : s->o.iteration_limit;
+    int status = 0;
+    memset(res, 0, sizeof(*res));
+    for (;;) {
+        if (tr && tr->omega) {
+            omega = tr->omega[t];
+            tau = s->eta / omega;
+            sigma = s->eta * omega;
+        }
+        if (tr && tr->rec_omega) tr->rec_omega[t] = omega;
+        orc_lp_step(s, x, y, x0, y0, k, tau, sigma, s->o.gamma, xh, yh, xn, yn);
+        if (tr && tr->xmask) {
+            /* record the projection state for the reverse pass */
+            double *aty = dalloc(n), *xe = dalloc(n), *a = dalloc(m);
+            at_mul(s, y, aty);
+            for (int32_t j = 0; j < n; ++j) {
+                double u = x[j] - tau * (s->c[j] - aty[j]);
+                tr->xmask[t * n + j] = (u > s->lv[j] && u < s->uv[j]) ? 1 : 0;
+                xe[j] = 2.0 * xh[j] - x[j];
+            }
+            a_mul(s, xe, a);
+            for (int32_t i = 0; i < m; ++i) {
+                double v = y[i] / sigma - a[i];
+                tr->ymask[t * m + i] = v < -s->uc[i] ? 1 : (v > -s->lc[i] ? 2 : 0);
+            }
+            tr->kk[t] = k;
+            free(aty); free(xe); free(a);
+        }
+        const int is_check = (t % s->o.check_every) == 0;
+        const int is_last = (t + 1 >= limit);
+        if (!tr && (is_check || is_last)) {
+            unscale(s, xh, yh, xo, yo);
+            orc_kkt(&s->p, xo, yo, res);
+            if (s->o.verbose)
+                fprintf(stderr, "oracle t=%lld k=%lld nr=%lld omega=%.3e kkt=%.3e (%.2e %.2e %.2e)\n",
+                        (long long)t, (long long)k, (long long)nr, omega, res->kkt,
+                        res->rel_primal, res->rel_dual, res->rel_gap);
+            if (isnan(res->kkt)) { status = 6; break; }
+            if (res->kkt <= s->o.eps) { status = 1; break; }
+        }
+        if (is_last) { status = 4; break; }
+        int restart = 0;
+        double r = 0.0;
+        if (tr && tr->restart) {
+            restart = tr->restart[t];
+        } else if (is_check) {
+            r = orc_fixed_point_residual(s, x, y, xh, yh, tau, sigma);
+            if (t == 0) { r_start = r; r_prev = r; }
+            else if (restart_due(s, r, r_start, r_prev, k, t)) restart = 1;
+            else r_prev = r;
+        }
+        if (tr && tr->rec_restart) tr->rec_restart[t] = (uint8_t)restart;
+        if (restart) {
+            ld dx2 = 0.0L, dy2 = 0.0L;
+            for (int32_t j = 0; j < n; ++j) dx2 += (ld)(xh[j] - x0[j]) * (xh[j] - x0[j]);
+            for (int32_t i = 0; i < m; ++i) dy2 += (ld)(yh[i] - y0[i]) * (yh[i] - y0[i]);
+            memcpy(x, xh, sizeof(double) * n); memcpy(x0, xh, sizeof(double) * n);
+            memcpy(y, yh, sizeof(double) * m); memcpy(y0, yh, sizeof(double) * m);
+            if (!(tr && tr->omega)) {
+                omega = new_weight(omega, (double)sqrtl(dx2), (double)sqrtl(dy2));
+                tau = s->eta / omega;
+                sigma = s->eta * omega;
+            }
+            k = 0;
+            r_start = r;
+            r_prev = r;
+            ++nr;
+        } else {
+            memcpy(x, xn, sizeof(double) * n);
+            memcpy(y, yn, sizeof(double) * m);
+            ++k;
+        }
+        ++t;
+    }
+    unscale(s, xh, yh, x_out, y_out);
+    if (tr) orc_kkt(&s->p, x_out, y_out, res);
+    res->status = status;
+    res->iterations = t + 1;
+    res->restarts = nr;
+    res->eta = s->eta;
+    res->omega = omega;
+    res->norm_a = s->norm_a;
+    res->norm_q = s->norm_q;
+    res->power_iters = s->power_iters;
+    free(x); free(y); free(x0); free(y0); free(xh); free(yh); free(xn); free(yn);
+    free(xo); free(yo);
+    return status;
+}
+
+/* rAPDHG loop (Algorithm 2); the check uses the weighted KKT norm
+ * sqrt(omega ||r_p||^2 + ||r_d||^2 / omega + gap^2) as restart metric. */
+static int qp_loop(orc_ctx *s, const double *x_init, const double *y_init, double *x_out,
+                   double *y_out, orc_result *res) {
+    const int32_t m = s->m, n = s->n;
+    double *x = dalloc(n), *y = dalloc(m), *xb = dalloc(n), *yb = dalloc(m);
+    double *x0 = dalloc(n), *y0 = dalloc(m);
+    double *xn = dalloc(n), *yn = dalloc(m), *xbn = dalloc(n), *ybn = dalloc(m);
+    double *xo = dalloc(n), *yo = dalloc(m);
+    init_point(s, x_init, y_init, x, y);
+    memcpy(xb, x, sizeof(double) * n); memcpy(yb, y, sizeof(double) * m);
+    memcpy(x0, x, sizeof(double) * n); memcpy(y0, y, sizeof(double) * m);
+    double omega = s->omega0;
+    double r_start = 0.0, r_prev = 0.0;
+    int64_t k = 0, t = 0, nr = 0;
+    int status = 0;
+    memset(res, 0, sizeof(*res));
+    for (;;) {
+        orc_qp_step(s, x, y, xb, yb, k, omega, xn, yn, xbn, ybn);
+        memcpy(x, xn, sizeof(double) * n); memcpy(y, yn, sizeof(double) * m);
+        memcpy(xb, xbn, sizeof(double) * n); memcpy(yb, ybn, sizeof(double) * m);
+        const int is_check = (t % s->o.check_every) == 0;
+        const int is_last = (t + 1 >= s->o.iteration_limit);
+        double r = 0.0;
+        if (is_check || is_last) {
+            unscale(s, xb, yb, xo, yo);
+            orc_kkt(&s->p, xo, yo, res);
+            if (s->o.verbose)
+                fprintf(stderr, "oracle-qp t=%lld k=%lld nr=%lld omega=%.3e kkt=%.3e\n",
+                        (long long)t, (long long)k, (long long)nr, omega, res->kkt);
+            if (isnan(res->kkt)) { status = 6; break; }
+            if (res->kkt <= s->o.eps) { status = 1; break; }
+            r = sqrt(omega * res->abs_primal * res->abs_primal +
+                     res->abs_dual * res->abs_dual / omega + res->abs_gap * res->abs_gap);
+        }
+        if (is_last) { status = 4; break; }
+        int restart = 0;
+        if (is_check) {
+            if (t == 0) { r_start = r; r_prev = r; }
+            else if (restart_due(s, r, r_start, r_prev, k, t)) restart = 1;
+            else r_prev = r;
+        }
+        if (restart) {
+            ld dx2 = 0.0L, dy2 = 0.0L;
+            for (int32_t j = 0; j < n; ++j) dx2 += (ld)(xb[j] - x0[j]) * (xb[j] - x0[j]);
+            for (int32_t i = 0; i < m; ++i) dy2 += (ld)(yb[i] - y0[i]) * (yb[i] - y0[i]);
+            memcpy(x, xb, sizeof(double) * n); memcpy(x0, xb, sizeof(double) * n);
+            memcpy(y, yb, sizeof(double) * m); memcpy(y0, yb, sizeof(double) * m);
+            omega = new_weight(omega, (double)sqrtl(dx2), (double)sqrtl(dy2));
+            k = 0;
+            r_start = r;
+            r_prev = r;
+            ++nr;
+        } else {
+            ++k;
+        }
+        ++t;
+    }
+    unscale(s, xb, yb, x_out, y_out);
+    res->status = status;
+    res->iterations = t + 1;
+    res->restarts = nr;
+    res->eta = s->eta;
+    res->omega = omega;
+    res->norm_a = s->norm_a;
+    res->norm_q = s->norm_q;
+    res->power_iters = s->power_iters;
+    free(x); free(y); free(xb); free(yb); free(x0); free(y0);
+    free(xn); free(yn); free(xbn); free(ybn); free(xo); free(yo);
+    return status;
+}
+
+int orc_solve(orc_ctx *s, const double *x_init, const double *y_init, double *x_out,
+              double *y_out, orc_result *res) {
+    if (s->p.q_kind == 0) return lp_loop(s, x_init, y_init, x_out, y_out, res, NULL);
+    return qp_loop(s, x_init, y_init, x_out, y_out, res);
+}
+
+/* ------------------------------------------------------------------------ */
+/* unrolled LP and its reverse pass (frozen schedule)                         */
+
+int orc_unrolled_lp(orc_ctx *s, int64_t T, const uint8_t *sched_restart,
+                    const double *sched_omega, uint8_t *rec_restart, double *rec_omega,
+                    double *x_out, double *y_out) {
+    if (T < 1 || s->p.q_kind != 0) return -1;
+    lp_trace tr;
+    memset(&tr, 0, sizeof(tr));
+    tr.T = T;
+    tr.restart = sched_restart;
+    tr.omega = sched_omega;
+    tr.rec_restart = rec_restart;
+    tr.rec_omega = rec_omega;
+    orc_result res;
+    lp_loop(s, NULL, NULL, x_out, y_out, &res, &tr);
+    return 0;
+}
+
+/* Reverse pass of T iterations (Algorithm 1 unrolled) given the schedule.
+ * Per iteration, in reverse order of the forward equations:
+ *   Halpern:   x' = a_k((1+g) xh - g x) + b_k x0 (same for y), anchors carried
+ *   restart:   x' = x0' = xh, y' = y0' = yh
+ *   dual:      yh = sigma (v - clamp(v, -u_c, -l_c)), v = y/sigma - A~ xe
+ *   extrap.:   xe = 2 xh - x
+ *   primal:    xh = clamp(u, l_v, u_v), u = x - tau (c - A~'y)
+ * The projection states are recomputed by a forward replay. */
+int orc_unrolled_lp_backward(orc_ctx *s, int64_t T, const uint8_t *sched_restart,
+                             const double *sched_omega, const double *gx, const double *gy,
+                             double *gc, double *glc, double *guc) {
+    if (T < 1 || s->p.q_kind != 0 || !sched_restart || !sched_omega) return -1;
+    const int32_t m = s->m, n = s->n;
+    lp_trace tr;
+    memset(&tr, 0, sizeof(tr));
+    tr.T = T;
+    tr.restart = sched_restart;
+    tr.omega = sched_omega;
+    tr.xmask = (uint8_t *)calloc((size_t)T * n, 1);
+    tr.ymask = (uint8_t *)calloc((size_t)T * (m ? m : 1), 1);
+    tr.kk = (int64_t *)calloc((size_t)T, sizeof(int64_t));
+    double *xo = dalloc(n), *yo = dalloc(m);
+    orc_result res;
+    lp_loop(s, NULL, NULL, xo, yo, &res, &tr);
+    /* cotangents of the state (x, y, x0, y0) after iteration t, and of the
+     * PDHG point of the last iteration */
+    double *bx = dalloc(n), *by = dalloc(m), *bx0 = dalloc(n), *by0 = dalloc(m);
+    double *bxh = dalloc(n), *byh = dalloc(m), *bxe = dalloc(n), *ba = dalloc(m);
+    double *bu = dalloc(n), *tmp_n = dalloc(n), *tmp_m = dalloc(m);
+    ld *gcs = lalloc(n), *glcs = lalloc(m), *gucs = lalloc(m);
+    const double g = s->o.gamma;
+    for (int64_t t = T - 1; t >= 0; --t) {
+        const double omega = sched_omega[t];
+        const double tau = s->eta / omega, sigma = s->eta * omega;
+        const int64_t k = tr.kk[t];
+        memset(bxh, 0, sizeof(double) * n);
+        memset(byh, 0, sizeof(double) * m);
+        if (t == T - 1) {
+            /* output is the unscaled PDHG point of the last iteration */
+            for (int32_t j = 0; j < n; ++j) bxh[j] = s->dc[j] * gx[j];
+            for (int32_t i = 0; i < m; ++i) byh[i] = s->dr[i] * gy[i];
+        } else if (sched_restart[t]) {
+            for (int32_t j = 0; j < n; ++j) { bxh[j] = bx[j] + bx0[j]; bx[j] = 0.0; bx0[j] = 0.0; }
+            for (int32_t i = 0; i < m; ++i) { byh[i] = by[i] + by0[i]; by[i] = 0.0; by0[i] = 0.0; }
+        } else {
+            const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+            for (int32_t j = 0; j < n; ++j) {
+                bxh[j] = ak * (1.0 + g) * bx[j];
+                bx0[j] += bk * bx[j];
+                bx[j] = -ak * g * bx[j];
+            }
+            for (int32_t i = 0; i < m; ++i) {
+                byh[i] = ak * (1.0 + g) * by[i];
+                by0[i] += bk * by[i];
+                by[i] = -ak * g * by[i];
+            }
+        }
+        if (t == T - 1) {
+            memset(bx, 0, sizeof(double) * n); memset(by, 0, sizeof(double) * m);
+            memset(bx0, 0, sizeof(double) * n); memset(by0, 0, sizeof(double) * m);
+        }
+        /* dual step */
+        for (int32_t i = 0; i < m; ++i) {
+            const uint8_t st = tr.ymask[t * m + i];
+            double bv = 0.0;
+            if (st == 0) bv = 0.0;                          /* yhat = 0 */
+            else bv = sigma * byh[i];                        /* yhat = sigma (v + bound) */
+            if (st == 1) gucs[i] += (ld)(sigma * byh[i]);
+            if (st == 2) glcs[i] += (ld)(sigma * byh[i]);
+            by[i] += bv / sigma;
+            ba[i] = -bv;
+        }
+        at_mul(s, ba, bxe);
+        for (int32_t j = 0; j < n; ++j) {
+            bxh[j] += 2.0 * bxe[j];
+            bx[j] -= bxe[j];
+        }
+        /* primal step */
+        for (int32_t j = 0; j < n; ++j) {
+            bu[j] = tr.xmask[t * n + j] ? bxh[j] : 0.0;
+            bx[j] += bu[j];
+            gcs[j] += (ld)(-tau * bu[j]);
+            tmp_n[j] = tau * bu[j];
+        }
+        a_mul(s, tmp_n, tmp_m);
+        for (int32_t i = 0; i < m; ++i) by[i] += tmp_m[i];
+    }
+    /* back to original data: c~ = D_c c, l~_c = D_r l_c, u~_c = D_r u_c */
+    for (int32_t j = 0; j < n; ++j) gc[j] = s->dc[j] * (double)gcs[j];
+    for (int32_t i = 0; i < m; ++i) {
+        glc[i] = isfinite(s->p.lc[i]) ? s->dr[i] * (double)glcs[i] : 0.0;
+        guc[i] = isfinite(s->p.uc[i]) ? s->dr[i] * (double)gucs[i] : 0.0;
+    }
+    free(tr.xmask); free(tr.ymask); free(tr.kk); free(xo); free(yo);
+    free(bx); free(by); free(bx0); free(by0); free(bxh); free(byh); free(bxe); free(ba);
+    free(bu); free(tmp_n); free(tmp_m); free(gcs); free(glcs); free(gucs);
+    return 0;
+}
