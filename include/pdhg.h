@@ -1,0 +1,186 @@
+/*
+ * libpdhg: restarted Halpern PDHG (r2HPDHG) for linear programs and restarted
+ * accelerated PDHG (rAPDHG) for convex quadratic programs on AMD MI355X
+ * (gfx950), behind a plain C ABI.
+ *
+ * Problem (MPAX paper, Section 2, eq. (qp)):
+ *
+ *     min  1/2 x'Qx + c'x   s.t.  l_c <= A x <= u_c,   l_v <= x <= u_v
+ *
+ * with A (m x n), Q (n x n, convex), Q = 0 for an LP. Absent bounds are
+ * -INFINITY / +INFINITY. The solver works on the saddle form of eq.
+ * (primal-dual-qp); y >= 0 on rows with only a lower bound, y <= 0 on rows with
+ * only an upper bound, y free on two-sided rows.
+ *
+ * Conventions for every entry point below:
+ *  - Types: int32_t for m, n and indices; int64_t for nnz and counters; double
+ *    (FP64) for every value.
+ *  - Errors are returned as pdhg_err; nothing aborts or throws across the ABI.
+ *    pdhg_last_error() gives a message for the calling thread.
+ *  - Solve outcomes (optimal, limits, numerical trouble) are reported in
+ *    pdhg_result.status, separately from API errors.
+ *  - The caller owns every buffer it passes; the library owns its scaled
+ *    copies and workspace and frees them in pdhg_destroy / pdhg_batch_destroy.
+ *  - Vector arguments of solve / step / scaling calls are DEVICE pointers on
+ *    the GPU the handle was created on. Problem data handed to *_create may
+ *    live on the host or the device (pdhg_problem.mem).
+ *  - Work is ordered after the caller's stream (passed as void*, a hipStream_t)
+ *    and every call returns after its GPU work has completed.
+ *  - A handle must not be used from two threads at the same time.
+ */
+#ifndef PDHG_H
+#define PDHG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PDHG_OK = 0,
+    PDHG_ERR_INVALID_ARG = -1,   /* NULL pointer, negative size, bad option value */
+    PDHG_ERR_INVALID_INPUT = -2, /* NaN / inf data, l > u, malformed CSR */
+    PDHG_ERR_OOM = -3,           /* device allocation failed */
+    PDHG_ERR_HIP = -4,           /* a HIP runtime call failed */
+    PDHG_ERR_UNSUPPORTED = -5    /* valid but not supported combination */
+} pdhg_err;
+
+typedef enum {
+    PDHG_UNSOLVED = 0,
+    PDHG_OPTIMAL = 1,            /* relative KKT error <= eps */
+    PDHG_PRIMAL_INFEASIBLE = 2,  /* reserved */
+    PDHG_DUAL_INFEASIBLE = 3,    /* reserved */
+    PDHG_ITERATION_LIMIT = 4,
+    PDHG_TIME_LIMIT = 5,
+    PDHG_NUMERICAL_ERROR = 6     /* NaN in the KKT terms */
+} pdhg_status;
+
+enum { PDHG_FMT_NONE = 0, PDHG_FMT_CSR = 1, PDHG_FMT_DENSE = 2, PDHG_FMT_LOWRANK_DIAG = 3 };
+enum { PDHG_MEM_HOST = 0, PDHG_MEM_DEVICE = 1 };
+
+/* Problem data (eq. (qp)). CSR matrices must have rowptr[0] = 0, non-decreasing
+ * rowptr, rowptr[rows] = nnz, and strictly increasing column indices inside a
+ * row; dense matrices are row-major. The library copies what it needs during
+ * *_create; the caller may free the arrays afterwards. */
+typedef struct {
+    int32_t m, n;
+    int32_t a_format;            /* PDHG_FMT_CSR or PDHG_FMT_DENSE */
+    const int32_t *a_rowptr;     /* [m+1]  (CSR) */
+    const int32_t *a_colidx;     /* [nnz]  (CSR) */
+    const double *a_val;         /* [nnz]  (CSR) */
+    int64_t a_nnz;               /* must equal a_rowptr[m] (CSR) */
+    const double *a_dense;       /* [m*n]  (DENSE) */
+    const double *c;             /* [n] objective */
+    const double *lc, *uc;       /* [m] row bounds */
+    const double *lv, *uv;       /* [n] variable bounds */
+    int32_t q_format;            /* NONE, CSR, DENSE or LOWRANK_DIAG */
+    const int32_t *q_rowptr;     /* [n+1]  (CSR) */
+    const int32_t *q_colidx;     /* [q_nnz] (CSR) */
+    const double *q_val;         /* [q_nnz] (CSR) */
+    int64_t q_nnz;
+    const double *q_dense;       /* [n*n]  (DENSE) */
+    int32_t q_rank;              /* r (LOWRANK_DIAG): Q = F F' + diag(d) */
+    const double *q_factor;      /* [n*r] row-major F (LOWRANK_DIAG) */
+    const double *q_diag;        /* [n]   d (LOWRANK_DIAG) */
+    int32_t mem;                 /* PDHG_MEM_HOST or PDHG_MEM_DEVICE for all arrays */
+} pdhg_problem;
+
+/* Options. Defaults (pdhg_options_default) follow the paper's Appendix A where
+ * it gives a value (eps 1e-4, unlimited iterations, display every 10 checks)
+ * and the documented readings elsewhere. */
+typedef struct {
+    double eps;                  /* relative KKT tolerance (eps_abs = eps_rel) */
+    int64_t iteration_limit;     /* PDHG steps; INT64_MAX = none */
+    double time_limit_s;         /* <= 0: none */
+    int32_t check_every;         /* termination / restart cadence (iterations) */
+    int32_t ruiz_iters;          /* Ruiz passes */
+    int32_t pock_chambolle;      /* 1: one Pock-Chambolle (alpha = 1) pass */
+    double gamma;                /* reflection coefficient in [0, 1] */
+    double step_safety;          /* eta = step_safety / ||A~||_2 */
+    double restart_sufficient;   /* 0.2 */
+    double restart_necessary;    /* 0.8 */
+    double restart_artificial;   /* 0.36 */
+    double power_tol;            /* relative change stopping the power iteration */
+    int32_t power_max_iters;
+    int32_t verbose;             /* 1: one line per display_frequency checks */
+    int32_t display_frequency;   /* in checks */
+    int32_t use_graph;           /* 1: replay each check period as a HIP graph */
+    int32_t timing_chunk;        /* >= 0: time the iteration kernels of that
+                                    check period with HIP events (result.kernel_*) */
+} pdhg_options;
+
+typedef struct {
+    int32_t status;              /* pdhg_status */
+    int64_t iterations;          /* PDHG steps taken */
+    int64_t restarts;
+    double primal_obj, dual_obj;
+    double rel_primal_res, rel_dual_res, rel_gap, kkt_rel;
+    double solve_seconds;        /* pdhg_solve wall time */
+    double setup_seconds;        /* pdhg_create wall time (copied from the handle) */
+    double eta, omega, norm_a, norm_q;
+    int32_t power_iters;
+    /* HIP-event timings of one check period (timing_chunk), milliseconds */
+    int32_t kernel_samples;      /* number of timed plain iterations */
+    double kernel_primal_ms;     /* average primal-step kernel duration */
+    double kernel_dual_ms;       /* average dual-step kernel duration */
+} pdhg_result;
+
+typedef struct pdhg_handle pdhg_handle;
+
+void pdhg_options_default(pdhg_options *opt);
+
+/* Message of the last error on the calling thread (never NULL). */
+const char *pdhg_last_error(void);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t pdhg_version(void);
+
+/* Copy A (and Q) into library-owned device memory, apply the diagonal
+ * preconditioning of Section 3 (Ruiz, then Pock-Chambolle), estimate
+ * ||A~||_2 (and ||Q~||_2) by power iteration and set the step size and the
+ * initial primal weight. stream: hipStream_t whose prior work the call waits
+ * for (NULL = default stream). On success *out receives a handle that
+ * pdhg_destroy releases. Errors: INVALID_ARG, INVALID_INPUT, OOM, HIP. */
+pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *stream,
+                     pdhg_handle **out);
+
+/* Run r2HPDHG (Algorithm 1; rAPDHG, Algorithm 2, when Q != 0) to the relative
+ * KKT tolerance or a limit. x_init [n], y_init [m]: optional warm start in the
+ * original space (NULL = zeros, Section 3 "Warm start"); it is scaled and
+ * projected onto the bounds. x_out [n], y_out [m]: original-space solution
+ * (the last PDHG point for LP, the weighted average for QP), written in every
+ * outcome. res may be NULL. All vector pointers are device pointers. */
+pdhg_err pdhg_solve(pdhg_handle *h, const double *x_init, const double *y_init,
+                    double *x_out, double *y_out, pdhg_result *res);
+
+/* Replace c and the bounds of an existing handle (A, Q and the scaling stay);
+ * device pointers, NULL keeps the current vector. The step size stays; the
+ * initial primal weight is recomputed. */
+pdhg_err pdhg_update_data(pdhg_handle *h, const double *c, const double *lc,
+                          const double *uc, const double *lv, const double *uv);
+
+/* Exactly one LP iteration (eq. (pdhg-lp) then eq. (hrpdhg)) in the SCALED
+ * space, original variable order: from (x, y) with anchors (x0, y0), inner
+ * counter k, steps tau, sigma, writes the PDHG point (xhat, yhat) and the
+ * Halpern point (xnew, ynew). Uses the same kernels as pdhg_solve. Device
+ * pointers; outputs may be NULL. LP handles only (UNSUPPORTED otherwise). */
+pdhg_err pdhg_debug_step(pdhg_handle *h, const double *x, const double *y,
+                         const double *x0, const double *y0, int64_t k, double tau,
+                         double sigma, double *xhat, double *yhat, double *xnew,
+                         double *ynew);
+
+/* Scaling of Section 3 in the original order: D_r [m], D_c [n] (device
+ * pointers, may be NULL) with A~ = D_r A D_c; scalars (host pointer to 4
+ * doubles, may be NULL): eta, initial omega, ||A~||_2 estimate, ||Q~||_2
+ * estimate; power_iters (host, may be NULL). */
+pdhg_err pdhg_get_scaling(pdhg_handle *h, double *dr, double *dc, double *scalars,
+                          int32_t *power_iters);
+
+/* Release everything the handle owns. NULL is ignored. */
+void pdhg_destroy(pdhg_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PDHG_H */

@@ -275,10 +275,34 @@ static void scale(orc_ctx *s) {
 /* ------------------------------------------------------------------------ */
 /* power iteration for ||A~||_2 and ||Q~||_2                                 */
 
+/* SplitMix64 (Steele, Lea and Flood, 2014): output for counter x. */
+static uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* Start vector of the power iterations: v_j = 0.5 + u_j, u_j uniform in
+ * [0, 1) from SplitMix64 at counter j, scaled to unit length. (A constant
+ * start vector can lie in the null space, e.g. for node-arc incidence
+ * matrices, whose rows sum to zero.) */
+static void start_vector(double *v, int32_t n) {
+    for (int32_t j = 0; j < n; ++j)
+        v[j] = 0.5 + (double)(splitmix64((uint64_t)j) >> 11) * 0x1.0p-53;
+    double nv = (double)sqrtl(sumsq(v, n));
+    for (int32_t j = 0; j < n; ++j) v[j] = v[j] / nv;
+}
+
 static double power_norm_a(const orc_ctx *s, int32_t *iters) {
     const int32_t m = s->m, n = s->n;
+    const size_t nv = s->dense ? (size_t)m * n : (m > 0 ? (size_t)s->p.rowptr[m] : 0);
+    if (m == 0 || nv == 0) {   /* no constraint entries: ||A~|| = 0, no steps */
+        if (iters) *iters = 0;
+        return 0.0;
+    }
     double *v = dalloc(n), *w = dalloc(m), *u = dalloc(n);
-    for (int32_t j = 0; j < n; ++j) v[j] = 1.0 / sqrt((double)n);
+    start_vector(v, n);
     double lam = 0.0, lam_prev = 0.0;
     int32_t it = 0;
     for (it = 1; it <= s->o.power_max_iters; ++it) {
@@ -301,7 +325,7 @@ static double power_norm_q(const orc_ctx *s) {
     const int32_t n = s->n;
     if (s->p.q_kind == 0) return 0.0;
     double *v = dalloc(n), *w = dalloc(n);
-    for (int32_t j = 0; j < n; ++j) v[j] = 1.0 / sqrt((double)n);
+    start_vector(v, n);
     double lam = 0.0, lam_prev = 0.0;
     for (int32_t it = 1; it <= s->o.power_max_iters; ++it) {
         q_mul(s, v, w);
@@ -688,6 +712,9 @@ static int lp_loop(orc_ctx *s, const double *x_init, const double *y_init, doubl
             restart = tr->restart[t];
         } else if (is_check) {
             r = orc_fixed_point_residual(s, x, y, xh, yh, tau, sigma);
+            if (s->o.verbose)
+                fprintf(stderr, "oracle   r=%.17e r/r_start=%.17e r_prev=%.17e\n", r,
+                        r_start > 0 ? r / r_start : 0.0, r_prev);
             if (t == 0) { r_start = r; r_prev = r; }
             else if (restart_due(s, r, r_start, r_prev, k, t)) restart = 1;
             else r_prev = r;

@@ -1,0 +1,419 @@
+// C ABI of libpdhg and the device-resident solve driver.
+//
+// The solve runs in check periods of check_every iterations: one check
+// iteration (PDHG point kept, KKT and fixed-point residual, controller,
+// restart-or-Halpern) followed by check_every - 1 plain iterations (two fused
+// kernels each). A period is replayed as one HIP graph. Every kernel of a
+// period returns at once when the controller has set the done flag, so the
+// host can keep two periods in flight and poll a pinned status copy without
+// stalling the GPU.
+#include <chrono>
+#include <climits>
+#include <deque>
+#include <new>
+
+#include "common.hpp"
+
+namespace pdhg {
+
+static thread_local std::string g_err = "";
+
+void fail(pdhg_err code, const std::string &msg) { throw Error{code, msg}; }
+
+Handle::~Handle() {
+    if (chunk_exec) (void)hipGraphExecDestroy(chunk_exec);
+    if (chunk_graph) (void)hipGraphDestroy(chunk_graph);
+    if (st_host) (void)hipHostFree(st_host);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+template <class F>
+static pdhg_err guarded(F &&f) {
+    try {
+        f();
+        return PDHG_OK;
+    } catch (const Error &e) {
+        g_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return PDHG_ERR_OOM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return PDHG_ERR_HIP;
+    } catch (...) {
+        g_err = "unknown failure";
+        return PDHG_ERR_HIP;
+    }
+}
+
+static double now_s() {
+    using clk = std::chrono::steady_clock;
+    return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+// Make h.stream wait for the work already queued on the caller's stream.
+static void order_after(Handle &h, void *caller) {
+    PDHG_HIP(hipEventRecord(h.ev_in, reinterpret_cast<hipStream_t>(caller)));
+    PDHG_HIP(hipStreamWaitEvent(h.stream, h.ev_in, 0));
+}
+
+static void check_options(const pdhg_options &o) {
+    if (!(o.eps > 0.0) || o.iteration_limit < 1 || o.check_every < 1 || o.ruiz_iters < 0 ||
+        !(o.gamma >= 0.0 && o.gamma <= 1.0) || !(o.step_safety > 0.0 && o.step_safety <= 1.0) ||
+        o.power_max_iters < 1 || !(o.power_tol >= 0.0) || o.display_frequency < 1)
+        fail(PDHG_ERR_INVALID_ARG, "option out of range");
+}
+
+static void enqueue_check(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t last_status) {
+    launch_primal_check(h);
+    launch_dual_check(h);
+    launch_check_sums(h);
+    launch_controller(h, chunk_plain, is_last, last_status);
+    launch_apply(h);
+}
+
+static void enqueue_plain(Handle &h, int32_t j) {
+    launch_primal(h, j);
+    launch_dual(h, j);
+}
+
+static void build_graph(Handle &h) {
+    if (h.chunk_exec) return;
+    const int32_t C = h.opt.check_every;
+    PDHG_HIP(hipStreamBeginCapture(h.stream, hipStreamCaptureModeThreadLocal));
+    enqueue_check(h, C - 1, 0, 0);
+    for (int32_t j = 1; j < C; ++j) enqueue_plain(h, j);
+    hipGraph_t g = nullptr;
+    PDHG_HIP(hipStreamEndCapture(h.stream, &g));
+    h.chunk_graph = g;
+    PDHG_HIP(hipGraphInstantiate(&h.chunk_exec, g, nullptr, nullptr, 0));
+}
+
+static void print_check(const DevState &s) {
+    fprintf(stderr,
+            "pdhg t=%-8lld restarts=%-4lld omega=%.3e kkt=%.3e (p %.2e d %.2e g %.2e) obj=%.10e "
+            "r=%.17e r_start=%.17e r_prev=%.17e\n",
+            (long long)s.t_done, (long long)s.restarts, s.omega, s.kkt, s.rel_p, s.rel_d,
+            s.rel_g, s.pobj, s.last_r, s.r_start, s.r_prev);
+}
+
+static void run_solve(Handle &h, const double *x_init, const double *y_init, double *x_out,
+                      double *y_out, pdhg_result *res) {
+    const double t0 = now_s();
+    hipStream_t s = h.stream;
+    launch_reset_state(h);
+    launch_init_point(h, x_init, y_init);
+    const int32_t C = h.opt.check_every;
+    const int64_t L = h.opt.iteration_limit;
+    if (h.opt.use_graph) build_graph(h);
+
+    std::vector<hipEvent_t> tev;
+    int64_t timing_t = -1;
+    int timing_slot = -1;
+    std::vector<hipEvent_t> ring(h.st_ring);
+    for (auto &e : ring) PDHG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    std::deque<int> inflight;
+    int64_t t = 0, chunk = 0;
+    bool stop = false;
+    int64_t checks_seen = 0;
+    DevState timing_state{};
+    bool have_timing_state = false;
+    try {
+        while (!stop && t < L) {
+            bool final = false;
+            const bool time_up = h.opt.time_limit_s > 0.0 && now_s() - t0 > h.opt.time_limit_s;
+            int64_t plain = 0;
+            if (time_up) {
+                enqueue_check(h, 0, 1, PDHG_TIME_LIMIT);
+                final = true;
+            } else if (t == L - 1) {
+                enqueue_check(h, 0, 1, PDHG_ITERATION_LIMIT);
+                final = true;
+            } else {
+                plain = std::min<int64_t>(C - 1, L - 2 - t);
+                const bool timed = h.opt.timing_chunk >= 0 && chunk == h.opt.timing_chunk &&
+                                   plain == C - 1 && tev.empty();
+                if (plain == C - 1 && h.opt.use_graph && !timed) {
+                    PDHG_HIP(hipGraphLaunch(h.chunk_exec, s));
+                } else {
+                    enqueue_check(h, (int32_t)plain, 0, 0);
+                    if (timed) {
+                        tev.resize(3 * (size_t)plain);
+                        for (auto &e : tev) PDHG_HIP(hipEventCreate(&e));
+                        timing_t = t;
+                    }
+                    for (int32_t j = 1; j <= plain; ++j) {
+                        if (timed) PDHG_HIP(hipEventRecord(tev[3 * (j - 1)], s));
+                        launch_primal(h, j);
+                        if (timed) PDHG_HIP(hipEventRecord(tev[3 * (j - 1) + 1], s));
+                        launch_dual(h, j);
+                        if (timed) PDHG_HIP(hipEventRecord(tev[3 * (j - 1) + 2], s));
+                    }
+                }
+            }
+            const int slot = (int)(chunk % h.st_ring);
+            PDHG_HIP(hipMemcpyAsync(&h.st_host[slot], h.st.p, sizeof(DevState),
+                                    hipMemcpyDeviceToHost, s));
+            PDHG_HIP(hipEventRecord(ring[slot], s));
+            if (timing_t == t && timing_slot < 0) timing_slot = slot;
+            inflight.push_back(slot);
+            t += 1 + plain;
+            ++chunk;
+            const size_t depth = final ? 0 : 2;
+            while (inflight.size() > depth) {
+                const int q = inflight.front();
+                inflight.pop_front();
+                PDHG_HIP(hipEventSynchronize(ring[q]));
+                const DevState &sv = h.st_host[q];
+                if (q == timing_slot) {
+                    timing_state = sv;
+                    have_timing_state = true;
+                    timing_slot = -2;
+                }
+                ++checks_seen;
+                if (h.opt.verbose && (checks_seen % h.opt.display_frequency) == 0) print_check(sv);
+                if (sv.done) stop = true;
+            }
+            if (final) stop = true;
+        }
+        PDHG_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        for (auto &e : ring) (void)hipEventDestroy(e);
+        for (auto &e : tev) (void)hipEventDestroy(e);
+        throw;
+    }
+    DevState fin;
+    PDHG_HIP(hipMemcpy(&fin, h.st.p, sizeof(DevState), hipMemcpyDeviceToHost));
+    launch_finalize(h, x_out, y_out);
+    PDHG_HIP(hipStreamSynchronize(s));
+    if (h.opt.verbose) print_check(fin);
+    double kp = 0.0, kd = 0.0;
+    int32_t samples = 0;
+    // the timed period counts only if the solve was still running after its check
+    if (!tev.empty() && have_timing_state && !timing_state.done) {
+        for (size_t j = 0; j + 2 < tev.size(); j += 3) {
+            float a = 0.f, b = 0.f;
+            PDHG_HIP(hipEventElapsedTime(&a, tev[j], tev[j + 1]));
+            PDHG_HIP(hipEventElapsedTime(&b, tev[j + 1], tev[j + 2]));
+            kp += a;
+            kd += b;
+            ++samples;
+        }
+    }
+    for (auto &e : ring) (void)hipEventDestroy(e);
+    for (auto &e : tev) (void)hipEventDestroy(e);
+    if (res) {
+        memset(res, 0, sizeof(*res));
+        res->status = fin.done ? fin.status : PDHG_ITERATION_LIMIT;
+        res->iterations = fin.t_done + 1;
+        res->restarts = fin.restarts;
+        res->primal_obj = fin.pobj;
+        res->dual_obj = fin.dobj;
+        res->rel_primal_res = fin.rel_p;
+        res->rel_dual_res = fin.rel_d;
+        res->rel_gap = fin.rel_g;
+        res->kkt_rel = fin.kkt;
+        res->solve_seconds = now_s() - t0;
+        res->setup_seconds = h.setup_seconds;
+        res->eta = h.eta;
+        res->omega = fin.omega;
+        res->norm_a = h.norm_a;
+        res->norm_q = h.norm_q;
+        res->power_iters = h.power_iters;
+        res->kernel_samples = samples;
+        res->kernel_primal_ms = samples ? kp / samples : 0.0;
+        res->kernel_dual_ms = samples ? kd / samples : 0.0;
+    }
+}
+
+}  // namespace pdhg
+
+using namespace pdhg;
+
+struct pdhg_handle {
+    Handle h;
+};
+
+extern "C" {
+
+void pdhg_options_default(pdhg_options *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->eps = 1e-4;
+    o->iteration_limit = INT64_MAX;
+    o->time_limit_s = 0.0;
+    o->check_every = 64;
+    o->ruiz_iters = 10;
+    o->pock_chambolle = 1;
+    o->gamma = 1.0;
+    o->step_safety = 0.998;
+    o->restart_sufficient = 0.2;
+    o->restart_necessary = 0.8;
+    o->restart_artificial = 0.36;
+    o->power_tol = 1e-7;
+    o->power_max_iters = 2000;
+    o->verbose = 0;
+    o->display_frequency = 10;
+    o->use_graph = 1;
+    o->timing_chunk = -1;
+}
+
+const char *pdhg_last_error(void) { return g_err.c_str(); }
+
+int32_t pdhg_version(void) { return 100; }
+
+pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *stream,
+                     pdhg_handle **out) {
+    if (out) *out = nullptr;
+    pdhg_handle *ph = nullptr;
+    pdhg_err rc = guarded([&] {
+        if (!prob || !out) fail(PDHG_ERR_INVALID_ARG, "NULL problem or output pointer");
+        const pdhg_problem &p = *prob;
+        if (p.m < 0 || p.n < 1) fail(PDHG_ERR_INVALID_ARG, "need m >= 0 and n >= 1");
+        if (p.mem != PDHG_MEM_HOST && p.mem != PDHG_MEM_DEVICE)
+            fail(PDHG_ERR_INVALID_ARG, "mem must be PDHG_MEM_HOST or PDHG_MEM_DEVICE");
+        if (p.a_format != PDHG_FMT_CSR)
+            fail(PDHG_ERR_UNSUPPORTED, "only CSR constraint matrices are supported by pdhg_create");
+        if (p.q_format != PDHG_FMT_NONE)
+            fail(PDHG_ERR_UNSUPPORTED, "quadratic objectives are not supported by this entry point");
+        if (!p.a_rowptr || (p.a_nnz > 0 && (!p.a_colidx || !p.a_val)) || p.a_nnz < 0 ||
+            p.a_nnz >= INT32_MAX)
+            fail(PDHG_ERR_INVALID_ARG, "bad CSR arrays or nnz");
+        if (!p.c || !p.lv || !p.uv || (p.m > 0 && (!p.lc || !p.uc)))
+            fail(PDHG_ERR_INVALID_ARG, "NULL objective or bound vector");
+        pdhg_options o;
+        if (opt)
+            o = *opt;
+        else
+            pdhg_options_default(&o);
+        check_options(o);
+        const double t0 = now_s();
+        ph = new pdhg_handle();
+        Handle &h = ph->h;
+        h.m = p.m;
+        h.n = p.n;
+        h.opt = o;
+        PDHG_HIP(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
+        PDHG_HIP(hipEventCreateWithFlags(&h.ev_in, hipEventDisableTiming));
+        order_after(h, stream);
+        build_matrices(h, p);
+        validate_and_load_vectors(h, p);
+        scale_problem(h);
+        estimate_steps(h);
+        compute_weight(h);
+        h.pn.alloc((size_t)std::max(1, h.AT.nblocks()) * 6);
+        h.pm.alloc((size_t)std::max(1, h.A.nblocks()) * 4);
+        h.st.alloc(1);
+        PDHG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h.st_host),
+                               sizeof(DevState) * h.st_ring, hipHostMallocDefault));
+        memset(h.st_host, 0, sizeof(DevState) * h.st_ring);
+        PDHG_HIP(hipStreamSynchronize(h.stream));
+        h.setup_seconds = now_s() - t0;
+        *out = ph;
+    });
+    if (rc != PDHG_OK) delete ph;
+    return rc;
+}
+
+pdhg_err pdhg_solve(pdhg_handle *ph, const double *x_init, const double *y_init, double *x_out,
+                    double *y_out, pdhg_result *res) {
+    return guarded([&] {
+        if (!ph || !x_out || (ph->h.m > 0 && !y_out))
+            fail(PDHG_ERR_INVALID_ARG, "NULL handle or output pointer");
+        run_solve(ph->h, x_init, y_init, x_out, y_out, res);
+    });
+}
+
+pdhg_err pdhg_update_data(pdhg_handle *ph, const double *c, const double *lc, const double *uc,
+                          const double *lv, const double *uv) {
+    return guarded([&] {
+        if (!ph) fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+        Handle &h = ph->h;
+        hipStream_t s = h.stream;
+        DBuf<double> tc, tl, tu, tlv, tuv;
+        // validate the new data in original order before taking it
+        pdhg_problem p;
+        memset(&p, 0, sizeof(p));
+        p.m = h.m;
+        p.n = h.n;
+        p.mem = PDHG_MEM_DEVICE;
+        tc.alloc(h.n);
+        tlv.alloc(h.n);
+        tuv.alloc(h.n);
+        tl.alloc(h.m);
+        tu.alloc(h.m);
+        launch_scatter(s, h.perm_c.p, h.c_o.p, tc.p, h.n);
+        launch_scatter(s, h.perm_c.p, h.lv_o.p, tlv.p, h.n);
+        launch_scatter(s, h.perm_c.p, h.uv_o.p, tuv.p, h.n);
+        launch_scatter(s, h.perm_r.p, h.lc_o.p, tl.p, h.m);
+        launch_scatter(s, h.perm_r.p, h.uc_o.p, tu.p, h.m);
+        p.c = c ? c : tc.p;
+        p.lv = lv ? lv : tlv.p;
+        p.uv = uv ? uv : tuv.p;
+        p.lc = lc ? lc : tl.p;
+        p.uc = uc ? uc : tu.p;
+        validate_and_load_vectors(h, p);
+        // D_r, D_c and A~ are kept; only the transformed vectors change.
+        transform_vectors(h);
+        compute_weight(h);
+        PDHG_HIP(hipStreamSynchronize(s));
+    });
+}
+
+pdhg_err pdhg_debug_step(pdhg_handle *ph, const double *x, const double *y, const double *x0,
+                         const double *y0, int64_t k, double tau, double sigma, double *xhat,
+                         double *yhat, double *xnew, double *ynew) {
+    return guarded([&] {
+        if (!ph || !x || !x0 || (ph->h.m > 0 && (!y || !y0)))
+            fail(PDHG_ERR_INVALID_ARG, "NULL handle or state pointer");
+        if (!(tau > 0.0) || !(sigma > 0.0) || k < 0)
+            fail(PDHG_ERR_INVALID_ARG, "tau, sigma must be > 0 and k >= 0");
+        Handle &h = ph->h;
+        hipStream_t s = h.stream;
+        launch_reset_state(h);
+        launch_gather(s, h.perm_c.p, x, h.x.p, h.n);
+        launch_gather(s, h.perm_c.p, x0, h.x0.p, h.n);
+        launch_gather(s, h.perm_r.p, y, h.y.p, h.m);
+        launch_gather(s, h.perm_r.p, y0, h.y0.p, h.m);
+        launch_primal_check(h, tau);
+        launch_dual_check(h, sigma);
+        DBuf<double> xn, yn;
+        xn.alloc(h.n);
+        yn.alloc(h.m);
+        launch_debug_halpern(h, k, xn.p, yn.p);
+        if (xhat) launch_scatter(s, h.perm_c.p, h.xhat.p, xhat, h.n);
+        if (yhat) launch_scatter(s, h.perm_r.p, h.yhat.p, yhat, h.m);
+        if (xnew) launch_scatter(s, h.perm_c.p, xn.p, xnew, h.n);
+        if (ynew) launch_scatter(s, h.perm_r.p, yn.p, ynew, h.m);
+        PDHG_HIP(hipStreamSynchronize(s));
+    });
+}
+
+pdhg_err pdhg_get_scaling(pdhg_handle *ph, double *dr, double *dc, double *scalars,
+                          int32_t *power_iters) {
+    return guarded([&] {
+        if (!ph) fail(PDHG_ERR_INVALID_ARG, "NULL handle");
+        Handle &h = ph->h;
+        if (dr) launch_scatter(h.stream, h.perm_r.p, h.Dr.p, dr, h.m);
+        if (dc) launch_scatter(h.stream, h.perm_c.p, h.Dc.p, dc, h.n);
+        PDHG_HIP(hipStreamSynchronize(h.stream));
+        if (scalars) {
+            scalars[0] = h.eta;
+            scalars[1] = h.omega0;
+            scalars[2] = h.norm_a;
+            scalars[3] = h.norm_q;
+        }
+        if (power_iters) *power_iters = h.power_iters;
+    });
+}
+
+void pdhg_destroy(pdhg_handle *ph) {
+    if (!ph) return;
+    (void)hipStreamSynchronize(ph->h.stream);
+    delete ph;
+}
+
+}  // extern "C"

@@ -1,0 +1,197 @@
+// Internal declarations of libpdhg (not part of the public ABI).
+//
+// Layout in HBM: every vector is a contiguous FP64 array in the library's
+// INTERNAL order. Rows of A and of A' (= columns of A) are permuted so that
+// rows of similar length are adjacent (descending length class, stable inside
+// a class); a segment table then gives each run of rows a fixed number of
+// lanes per row. perm_r / perm_c map internal -> original indices.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pdhg.h"
+
+namespace pdhg {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kMaxSeg = 40;      // length classes per matrix
+constexpr int kShortMax = 64;    // rows up to this length go to SELL-64 slices
+
+struct Error {
+    pdhg_err code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(pdhg_err code, const std::string &msg);
+
+#define PDHG_HIP(expr)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            ::pdhg::fail(PDHG_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Owning device buffer.
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        size_t bytes = (count ? count : 1) * sizeof(T);
+        if (hipMalloc(reinterpret_cast<void **>(&p), bytes) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(PDHG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    T *get() const { return p; }
+};
+
+// A run of rows [row_begin, row_end) processed with 2^lanes_log2 lanes per
+// row, starting at workgroup block_begin.
+struct Seg {
+    int32_t row_begin, row_end, lanes_log2, block_begin;
+};
+struct SegTable {
+    Seg s[kMaxSeg];
+    int32_t nseg;
+    int32_t nblocks;
+};
+
+// Matrix in internal order, rows sorted by length (descending):
+//  - rows [0, R_long) longer than the short-row limit: CSR (rowptr over these
+//    rows, entries at the front of colidx/val), lane groups per the segment
+//    table;
+//  - rows [R_long, rows): SELL-64 slices. Slice s holds 64 consecutive rows;
+//    entry k of lane l sits at slice_ptr[s] + 64 k + l for k < width(s),
+//    width(s) = length of the slice's first (longest) row; shorter rows are
+//    padded with (column 0, value 0.0). One thread per row.
+struct HMat {
+    int32_t rows = 0, cols = 0;
+    int64_t nnz = 0;          // real entries
+    int64_t stored = 0;       // entries incl. padding
+    int32_t R_long = 0, nslices = 0;
+    DBuf<int32_t> rowptr, colidx, slice_ptr;
+    DBuf<double> val;
+    SegTable seg{};
+    int32_t nblocks() const { return seg.nblocks + (int32_t)((nslices + 3) / 4); }
+};
+
+// Kernel-argument view of an HMat.
+struct MatView {
+    const int32_t *rowptr;
+    const int32_t *colidx;
+    double *val;
+    const int32_t *slice_ptr;
+    int32_t rows, R_long, nslices, pad;
+    SegTable seg;
+};
+
+inline MatView view(const HMat &M) {
+    MatView v;
+    v.rowptr = M.rowptr.p;
+    v.colidx = M.colidx.p;
+    v.val = M.val.p;
+    v.slice_ptr = M.slice_ptr.p;
+    v.rows = M.rows;
+    v.R_long = M.R_long;
+    v.nslices = M.nslices;
+    v.pad = 0;
+    v.seg = M.seg;
+    return v;
+}
+
+// Solver scalars kept on the device; the controller kernel owns them.
+struct DevState {
+    double tau, sigma, omega, eta;
+    double r_start, r_prev;
+    double kkt, rel_p, rel_d, rel_g, pobj, dobj, abs_p, abs_d, abs_g;
+    double last_r;
+    int64_t t_next;      // iteration index of the next check
+    int64_t k_base;      // inner counter of the first plain iteration after a check
+    int64_t k_check;     // inner counter at the last check
+    int64_t plain_prev;  // plain iterations after the last check
+    int64_t restarts;
+    int64_t t_done;      // iteration index at which the solve stopped
+    int32_t done, status, action, first;
+};
+
+// Constants the controller needs.
+struct CtlConst {
+    double eps, bnorm, cnorm, eta;
+    double beta_suff, beta_nec, beta_art;
+    int32_t qp;
+    int32_t pad;
+};
+
+struct Handle {
+    int32_t m = 0, n = 0;
+    pdhg_options opt{};
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr;
+    HMat A, AT;
+    DBuf<int32_t> perm_r, perm_c;        // internal -> original
+    DBuf<double> Dr, Dc;                 // scaling, internal order
+    DBuf<double> c, lc, uc, lv, uv;      // scaled data
+    DBuf<double> c_o, lc_o, uc_o, lv_o, uv_o;  // original data, internal order
+    DBuf<double> x, y, x0, y0, xhat, yhat, xext, aty;
+    DBuf<double> pn, pm;                 // per-workgroup partial sums of a check
+    DBuf<double> scratch;                // reductions of setup / power iteration
+    DBuf<DevState> st;
+    DevState *st_host = nullptr;         // pinned ring of status copies
+    int st_ring = 4;
+    double eta = 1.0, omega0 = 1.0, norm_a = 0.0, norm_q = 0.0;
+    double cnorm = 0.0, bnorm = 0.0;
+    int32_t power_iters = 0;
+    double setup_seconds = 0.0;
+    hipGraphExec_t chunk_exec = nullptr;
+    hipGraph_t chunk_graph = nullptr;
+    ~Handle();
+};
+
+// ---- setup (setup.hip) ---------------------------------------------------
+void build_matrices(Handle &h, const pdhg_problem &p);
+void validate_and_load_vectors(Handle &h, const pdhg_problem &p);
+void scale_problem(Handle &h);
+void transform_vectors(Handle &h);
+void estimate_steps(Handle &h);
+void compute_weight(Handle &h);
+SegTable make_segments(const std::vector<int32_t> &class_count, int32_t rows);
+
+// ---- iteration kernels (lp_kernels.hip) -------------------------------------
+void launch_primal(Handle &h, int32_t j);
+void launch_dual(Handle &h, int32_t j);
+void launch_primal_check(Handle &h, double tau_override = -1.0);
+void launch_dual_check(Handle &h, double sigma_override = -1.0);
+void launch_check_sums(Handle &h);
+void launch_controller(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t last_status);
+void launch_apply(Handle &h);
+void launch_init_point(Handle &h, const double *x_init, const double *y_init);
+void launch_finalize(Handle &h, double *x_out, double *y_out);
+void launch_reset_state(Handle &h);
+void launch_debug_halpern(Handle &h, int64_t k, double *xnew_int, double *ynew_int);
+void launch_gather(hipStream_t s, const int32_t *perm, const double *src, double *dst, int32_t len);
+void launch_scatter(hipStream_t s, const int32_t *perm, const double *src, double *dst, int32_t len);
+void launch_scatter_scaled(hipStream_t s, const int32_t *perm, const double *scale,
+                           const double *src, double *dst, int32_t len);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace pdhg

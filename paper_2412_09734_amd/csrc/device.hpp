@@ -1,0 +1,249 @@
+// Device-side helpers shared by the kernels: row mapping of the binned CSR
+// layout, lane-group dot products and deterministic workgroup sums.
+#pragma once
+
+#include "common.hpp"
+
+namespace pdhg {
+
+struct RowCtx {
+    int32_t row;
+    int32_t lg;    // log2(lanes per row)
+    bool valid;    // row exists
+    bool lead;     // first lane of the row's lane group
+};
+
+// Workgroup blockIdx.x belongs to the last segment whose block_begin <= it.
+__device__ __forceinline__ RowCtx row_ctx(const SegTable &T) {
+    const int32_t b = blockIdx.x;
+    int32_t si = 0;
+#pragma unroll 1
+    for (int32_t q = 1; q < T.nseg; ++q) si = (b >= T.s[q].block_begin) ? q : si;
+    const int32_t lg = T.s[si].lanes_log2;
+    RowCtx r;
+    r.lg = lg;
+    r.row = T.s[si].row_begin + (b - T.s[si].block_begin) * (kBlock >> lg) +
+            (int32_t)(threadIdx.x >> lg);
+    r.valid = r.row < T.s[si].row_end;
+    r.lead = (threadIdx.x & ((1u << lg) - 1u)) == 0u;
+    return r;
+}
+
+// sum_e val[e] * v[colidx[e]] over the row, lanes strided; the lane-group
+// butterfly leaves the same total in every lane of the group.
+__device__ __forceinline__ double row_dot(const int32_t *__restrict__ rowptr,
+                                          const int32_t *__restrict__ colidx,
+                                          const double *__restrict__ val,
+                                          const double *__restrict__ v, const RowCtx &rc) {
+    double acc = 0.0;
+    const int32_t L = 1 << rc.lg;
+    if (rc.valid) {
+        const int32_t lane = (int32_t)(threadIdx.x & (uint32_t)(L - 1));
+        const int32_t e1 = rowptr[rc.row + 1];
+        for (int32_t e = rowptr[rc.row] + lane; e < e1; e += L)
+            acc = fma(__builtin_nontemporal_load(&val[e]), v[__builtin_nontemporal_load(&colidx[e])], acc);
+    }
+    for (int32_t off = L >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    return acc;
+}
+
+// Row reduction of |val| (max when MAXNORM, else sum) without a vector.
+template <bool MAXNORM>
+__device__ __forceinline__ double row_absnorm(const int32_t *__restrict__ rowptr,
+                                              const double *__restrict__ val, const RowCtx &rc) {
+    double acc = 0.0;
+    const int32_t L = 1 << rc.lg;
+    if (rc.valid) {
+        const int32_t lane = (int32_t)(threadIdx.x & (uint32_t)(L - 1));
+        const int32_t e1 = rowptr[rc.row + 1];
+        for (int32_t e = rowptr[rc.row] + lane; e < e1; e += L) {
+            const double a = fabs(val[e]);
+            acc = MAXNORM ? fmax(acc, a) : acc + a;
+        }
+    }
+    for (int32_t off = L >> 1; off > 0; off >>= 1) {
+        const double o = __shfl_xor(acc, off);
+        acc = MAXNORM ? fmax(acc, o) : acc + o;
+    }
+    return acc;
+}
+
+struct RowSum {
+    double s;
+    int32_t row;
+    bool valid;   // this thread owns an existing row and holds its full sum
+};
+
+// Index of the SELL-64 slice handled by this wave (wave-uniform), or -1 when
+// the workgroup belongs to the long-row part.
+__device__ __forceinline__ int32_t slice_of(const MatView &M) {
+    if ((int32_t)blockIdx.x < M.seg.nblocks) return -1;
+    return ((int32_t)blockIdx.x - M.seg.nblocks) * (kBlock / 64) + (int32_t)(threadIdx.x >> 6);
+}
+
+// Row sum of val * x[col] for the row owned by this thread (hybrid layout).
+// Long rows: lane groups with a butterfly; short rows: one thread per row,
+// entries walked in order with independent, coalesced loads.
+__device__ __forceinline__ RowSum mat_row_dot(const MatView &M, const double *__restrict__ x) {
+    RowSum r;
+    const int32_t sl = slice_of(M);
+    if (sl < 0) {
+        const RowCtx rc = row_ctx(M.seg);
+        r.s = row_dot(M.rowptr, M.colidx, M.val, x, rc);
+        r.row = rc.row;
+        r.valid = rc.valid && rc.lead;
+        return r;
+    }
+    const int32_t lane = (int32_t)(threadIdx.x & 63);
+    r.row = M.R_long + sl * 64 + lane;
+    r.valid = sl < M.nslices && r.row < M.rows;
+    double acc = 0.0;
+    if (sl < M.nslices) {
+        const int32_t b = __builtin_amdgcn_readfirstlane(M.slice_ptr[sl]);
+        const int32_t w = (__builtin_amdgcn_readfirstlane(M.slice_ptr[sl + 1]) - b) >> 6;
+        const int32_t *__restrict__ ci = M.colidx + b + lane;
+        const double *__restrict__ va = M.val + b + lane;
+        int32_t k = 0;
+        for (; k + 4 <= w; k += 4) {
+            const int32_t c0 = __builtin_nontemporal_load(ci + 64 * k);
+            const int32_t c1 = __builtin_nontemporal_load(ci + 64 * (k + 1));
+            const int32_t c2 = __builtin_nontemporal_load(ci + 64 * (k + 2));
+            const int32_t c3 = __builtin_nontemporal_load(ci + 64 * (k + 3));
+            const double a0 = __builtin_nontemporal_load(va + 64 * k);
+            const double a1 = __builtin_nontemporal_load(va + 64 * (k + 1));
+            const double a2 = __builtin_nontemporal_load(va + 64 * (k + 2));
+            const double a3 = __builtin_nontemporal_load(va + 64 * (k + 3));
+            const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+            acc = fma(a0, x0, acc);
+            acc = fma(a1, x1, acc);
+            acc = fma(a2, x2, acc);
+            acc = fma(a3, x3, acc);
+        }
+        for (; k < w; ++k)
+            acc = fma(__builtin_nontemporal_load(va + 64 * k), x[__builtin_nontemporal_load(ci + 64 * k)], acc);
+    }
+    r.s = acc;
+    return r;
+}
+
+// Row max (MAXNORM) or sum of |val| in the hybrid layout.
+template <bool MAXNORM>
+__device__ __forceinline__ RowSum mat_row_absnorm(const MatView &M) {
+    RowSum r;
+    const int32_t sl = slice_of(M);
+    if (sl < 0) {
+        const RowCtx rc = row_ctx(M.seg);
+        r.s = row_absnorm<MAXNORM>(M.rowptr, M.val, rc);
+        r.row = rc.row;
+        r.valid = rc.valid && rc.lead;
+        return r;
+    }
+    const int32_t lane = (int32_t)(threadIdx.x & 63);
+    r.row = M.R_long + sl * 64 + lane;
+    r.valid = sl < M.nslices && r.row < M.rows;
+    double acc = 0.0;
+    if (sl < M.nslices) {
+        const int32_t b = M.slice_ptr[sl];
+        const int32_t w = (M.slice_ptr[sl + 1] - b) >> 6;
+        for (int32_t k = 0; k < w; ++k) {
+            const double a = fabs(M.val[b + 64 * k + lane]);
+            acc = MAXNORM ? fmax(acc, a) : acc + a;
+        }
+    }
+    r.s = acc;
+    return r;
+}
+
+// val <- val / (rfac[i] * cfac[j]) for every stored entry (i, j) of the rows
+// of M; transposed: the rows of M are columns j and its column indices rows i.
+// Padding entries hold 0.0 and stay 0.0.
+__device__ __forceinline__ void mat_scale_entries(const MatView &M, const double *__restrict__ rfac,
+                                                  const double *__restrict__ cfac, bool transposed) {
+    const int32_t sl = slice_of(M);
+    if (sl < 0) {
+        const RowCtx rc = row_ctx(M.seg);
+        if (!rc.valid) return;
+        const int32_t L = 1 << rc.lg;
+        const int32_t lane = (int32_t)(threadIdx.x & (uint32_t)(L - 1));
+        for (int32_t e = M.rowptr[rc.row] + lane; e < M.rowptr[rc.row + 1]; e += L) {
+            const int32_t o = M.colidx[e];
+            const double ri = transposed ? rfac[o] : rfac[rc.row];
+            const double sj = transposed ? cfac[rc.row] : cfac[o];
+            M.val[e] = M.val[e] / (ri * sj);
+        }
+        return;
+    }
+    if (sl >= M.nslices) return;
+    const int32_t lane = (int32_t)(threadIdx.x & 63);
+    const int32_t row = M.R_long + sl * 64 + lane;
+    if (row >= M.rows) return;
+    const int32_t b = M.slice_ptr[sl];
+    const int32_t w = (M.slice_ptr[sl + 1] - b) >> 6;
+    for (int32_t k = 0; k < w; ++k) {
+        const int32_t e = b + 64 * k + lane;
+        const int32_t o = M.colidx[e];
+        const double ri = transposed ? rfac[o] : rfac[row];
+        const double sj = transposed ? cfac[row] : cfac[o];
+        M.val[e] = M.val[e] / (ri * sj);
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double s) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    return s;
+}
+
+// Deterministic workgroup sum of K values per thread: wave butterflies, then
+// the 4 wave totals in fixed order. Result written by threads 0..K-1 to out.
+template <int K>
+__device__ __forceinline__ void block_sum_store(const double (&v)[K], double *__restrict__ out) {
+    __shared__ double sh[K][kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) sh[q][wave] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += sh[threadIdx.x][w];
+        out[threadIdx.x] = s;
+    }
+}
+
+// Same, result broadcast to every thread.
+template <int K>
+__device__ __forceinline__ void block_sum_all(double (&v)[K]) {
+    __shared__ double sh[K][kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) sh[q][wave] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += sh[q][w];
+        v[q] = s;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double clampd(double v, double lo, double hi) {
+    return fmin(fmax(v, lo), hi);
+}
+
+// Dual proximal step of eq. (pdhg-lp): v = y/sigma - a,
+// yhat = sigma (v - proj_[-u_c, -l_c](v)); exactly 0 inside, exactly signed outside.
+__device__ __forceinline__ double dual_prox(double y, double a, double sigma, double lc, double uc) {
+    const double v = y / sigma - a;
+    return sigma * (v - clampd(v, -uc, -lc));
+}
+
+}  // namespace pdhg

@@ -1,0 +1,459 @@
+// r2HPDHG iteration kernels (MPAX paper, Algorithm 1 with eq. (pdhg-lp) and
+// eq. (hrpdhg)), all in the scaled space and internal order.
+//
+// Plain iteration = two launches:
+//   primal: s = A~'y (rows of A'), xhat = clamp(x - tau (c - s)), writes
+//           xext = 2 xhat - x and the Halpern point x <- a_k((1+g) xhat - g x) + b_k x0
+//   dual:   a = A~ xext (rows of A), yhat = dual prox, writes the Halpern point y.
+// Check iteration (every check_every steps) = primal/dual variants that keep
+// (xhat, yhat), two extra products A~'yhat and A~ xhat fused with the KKT and
+// fixed-point-residual sums, a one-workgroup controller and an apply kernel.
+#include "device.hpp"
+
+namespace pdhg {
+
+__global__ __launch_bounds__(kBlock) void k_primal(
+    MatView M, const double *__restrict__ y, double *__restrict__ x,
+    const double *__restrict__ x0, const double *__restrict__ c, const double *__restrict__ lv,
+    const double *__restrict__ uv, double *__restrict__ xext, const DevState *__restrict__ st,
+    int32_t j, double gamma) {
+    if (st->done) return;
+    const RowSum rs = mat_row_dot(M, y);
+    const double s = rs.s;
+    if (rs.valid) {
+        const int32_t r = rs.row;
+        const double tau = st->tau;
+        const int64_t k = st->k_base + (j - 1);
+        const double xr = x[r];
+        const double xh = clampd(xr - tau * (c[r] - s), lv[r], uv[r]);
+        const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+        xext[r] = 2.0 * xh - xr;
+        x[r] = ak * ((1.0 + gamma) * xh - gamma * xr) + bk * x0[r];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dual(
+    MatView M, const double *__restrict__ xext, double *__restrict__ y,
+    const double *__restrict__ y0, const double *__restrict__ lc, const double *__restrict__ uc,
+    const DevState *__restrict__ st, int32_t j, double gamma) {
+    if (st->done) return;
+    const RowSum rs = mat_row_dot(M, xext);
+    const double a = rs.s;
+    if (rs.valid) {
+        const int32_t r = rs.row;
+        const double sigma = st->sigma;
+        const int64_t k = st->k_base + (j - 1);
+        const double yr = y[r];
+        const double yh = dual_prox(yr, a, sigma, lc[r], uc[r]);
+        const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+        y[r] = ak * ((1.0 + gamma) * yh - gamma * yr) + bk * y0[r];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_primal_chk(
+    MatView M, const double *__restrict__ y, const double *__restrict__ x,
+    const double *__restrict__ c, const double *__restrict__ lv, const double *__restrict__ uv,
+    double *__restrict__ xhat, double *__restrict__ xext, double *__restrict__ aty,
+    const DevState *__restrict__ st, double tau_override) {
+    if (st->done) return;
+    const RowSum rs = mat_row_dot(M, y);
+    const double s = rs.s;
+    if (rs.valid) {
+        const int32_t r = rs.row;
+        const double tau = tau_override > 0.0 ? tau_override : st->tau;
+        const double xr = x[r];
+        const double xh = clampd(xr - tau * (c[r] - s), lv[r], uv[r]);
+        xhat[r] = xh;
+        xext[r] = 2.0 * xh - xr;
+        aty[r] = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dual_chk(
+    MatView M, const double *__restrict__ xext, const double *__restrict__ y,
+    const double *__restrict__ lc, const double *__restrict__ uc, double *__restrict__ yhat,
+    const DevState *__restrict__ st, double sigma_override) {
+    if (st->done) return;
+    const RowSum rs = mat_row_dot(M, xext);
+    const double a = rs.s;
+    if (rs.valid) {
+        const int32_t r = rs.row;
+        const double sigma = sigma_override > 0.0 ? sigma_override : st->sigma;
+        yhat[r] = dual_prox(y[r], a, sigma, lc[r], uc[r]);
+    }
+}
+
+// Column side of a check: q = A~'yhat. Sums (per workgroup):
+//  0 |xhat - x|^2   1 (q - A~'y)'(xhat - x)   2 |xhat - x0|^2
+//  3 |r_d|^2 (original space)   4 c'x (original)   5 l_v'lambda^+ - u_v'lambda^-
+__global__ __launch_bounds__(kBlock) void k_check_n(
+    MatView M, const double *__restrict__ yhat, const double *__restrict__ xhat,
+    const double *__restrict__ x, const double *__restrict__ x0, const double *__restrict__ aty,
+    const double *__restrict__ Dc, const double *__restrict__ c_o, const double *__restrict__ lv_o,
+    const double *__restrict__ uv_o, double *__restrict__ partials,
+    const DevState *__restrict__ st) {
+    if (st->done) return;
+    const RowSum rs = mat_row_dot(M, yhat);
+    const double q = rs.s;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (rs.valid) {
+        const int32_t r = rs.row;
+        const double xh = xhat[r];
+        const double dx = xh - x[r];
+        v[0] = dx * dx;
+        v[1] = (q - aty[r]) * dx;
+        const double d0 = xh - x0[r];
+        v[2] = d0 * d0;
+        const double d = Dc[r];
+        const double xo = d * xh;
+        const double g = c_o[r] - q / d;
+        const double lo = lv_o[r], hi = uv_o[r];
+        const bool lf = isfinite(lo), uf = isfinite(hi);
+        const double lam = (!lf && !uf) ? 0.0 : (lf && !uf) ? fmax(g, 0.0) : (!lf && uf) ? fmin(g, 0.0) : g;
+        const double rd = g - lam;
+        v[3] = rd * rd;
+        v[4] = c_o[r] * xo;
+        v[5] = (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
+    }
+    block_sum_store<6>(v, partials + (size_t)blockIdx.x * 6);
+}
+
+// Row side of a check: p = A~ xhat. Sums:
+//  0 |r_p|^2 (original)   1 l_c'y^+ - u_c'y^-   2 |yhat - y|^2   3 |yhat - y0|^2
+__global__ __launch_bounds__(kBlock) void k_check_m(
+    MatView M, const double *__restrict__ xhat, const double *__restrict__ yhat,
+    const double *__restrict__ y, const double *__restrict__ y0, const double *__restrict__ Dr,
+    const double *__restrict__ lc_o, const double *__restrict__ uc_o, double *__restrict__ partials,
+    const DevState *__restrict__ st) {
+    if (st->done) return;
+    const RowSum rs = mat_row_dot(M, xhat);
+    const double p = rs.s;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (rs.valid) {
+        const int32_t r = rs.row;
+        const double d = Dr[r];
+        const double ax = p / d;
+        const double lo = lc_o[r], hi = uc_o[r];
+        const double rpr = ax - clampd(ax, lo, hi);
+        v[0] = rpr * rpr;
+        const double yh = yhat[r];
+        const double yo = d * yh;
+        v[1] = (isfinite(lo) ? lo * fmax(yo, 0.0) : 0.0) - (isfinite(hi) ? hi * fmax(-yo, 0.0) : 0.0);
+        const double dy = yh - y[r];
+        v[2] = dy * dy;
+        const double d0 = yh - y0[r];
+        v[3] = d0 * d0;
+    }
+    block_sum_store<4>(v, partials + (size_t)blockIdx.x * 4);
+}
+
+// One workgroup: totals of the check sums in fixed order, relative KKT error,
+// fixed-point residual in the PDHG norm, termination and restart decisions,
+// primal-weight update.
+__global__ __launch_bounds__(kBlock) void k_controller(
+    DevState *__restrict__ st, const double *__restrict__ pn, int32_t nbn,
+    const double *__restrict__ pm, int32_t nbm, CtlConst K, int32_t chunk_plain,
+    int32_t is_last, int32_t last_status) {
+    if (st->done) return;
+    double vn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double vm[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int32_t b = threadIdx.x; b < nbn; b += kBlock)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) vn[q] += pn[(size_t)b * 6 + q];
+    for (int32_t b = threadIdx.x; b < nbm; b += kBlock)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vm[q] += pm[(size_t)b * 4 + q];
+    block_sum_all<6>(vn);
+    block_sum_all<4>(vm);
+    if (threadIdx.x != 0) return;
+
+    const int64_t t = st->t_next;
+    const int64_t k = st->first ? 0 : st->k_base + st->plain_prev;
+    const double P = vn[4];
+    const double D = vm[1] + vn[5];
+    const double abs_p = sqrt(vm[0]), abs_d = sqrt(vn[3]), abs_g = fabs(P - D);
+    const double rel_p = abs_p / (1.0 + K.bnorm);
+    const double rel_d = abs_d / (1.0 + K.cnorm);
+    const double rel_g = abs_g / (1.0 + fabs(P) + fabs(D));
+    double kkt = rel_p;
+    if (rel_d > kkt || isnan(rel_d)) kkt = rel_d;
+    if (rel_g > kkt || isnan(rel_g)) kkt = rel_g;
+    st->kkt = kkt;
+    st->rel_p = rel_p;
+    st->rel_d = rel_d;
+    st->rel_g = rel_g;
+    st->pobj = P;
+    st->dobj = D;
+    st->abs_p = abs_p;
+    st->abs_d = abs_d;
+    st->abs_g = abs_g;
+    st->k_check = k;
+    st->t_done = t;
+    st->first = 0;
+    st->plain_prev = chunk_plain;
+    st->t_next = t + 1 + chunk_plain;
+    if (isnan(kkt)) {
+        st->done = 1;
+        st->status = PDHG_NUMERICAL_ERROR;
+        st->action = 2;
+        return;
+    }
+    if (kkt <= K.eps) {
+        st->done = 1;
+        st->status = PDHG_OPTIMAL;
+        st->action = 2;
+        return;
+    }
+    if (is_last) {
+        st->done = 1;
+        st->status = last_status;
+        st->action = 2;
+        return;
+    }
+    const double tau = st->tau, sigma = st->sigma;
+    double r2 = vn[0] / tau + vm[2] / sigma + 2.0 * vn[1];
+    const double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+    st->last_r = r;
+    int restart = 0;
+    if (t == 0) {
+        st->r_start = r;
+        st->r_prev = r;
+    } else if (r <= K.beta_suff * st->r_start ||
+               (r <= K.beta_nec * st->r_start && r > st->r_prev) ||
+               (double)k >= K.beta_art * (double)t) {
+        restart = 1;
+    } else {
+        st->r_prev = r;
+    }
+    if (restart) {
+        const double dxr = sqrt(vn[2]), dyr = sqrt(vm[3]);
+        double omega = st->omega;
+        if (dxr > 1e-10 && dyr > 1e-10) omega = exp(0.5 * log(dyr / dxr) + 0.5 * log(omega));
+        st->omega = omega;
+        st->tau = K.eta / omega;
+        st->sigma = K.eta * omega;
+        st->r_start = r;
+        st->r_prev = r;
+        st->restarts += 1;
+        st->k_base = 0;
+        st->action = 1;
+    } else {
+        st->k_base = k + 1;
+        st->action = 0;
+    }
+}
+
+// Restart (z <- zhat, anchor <- zhat) or Halpern step at the check iteration.
+__global__ __launch_bounds__(kBlock) void k_apply(
+    const DevState *__restrict__ st, int32_t n, int32_t m, double *__restrict__ x,
+    double *__restrict__ x0, const double *__restrict__ xhat, double *__restrict__ y,
+    double *__restrict__ y0, const double *__restrict__ yhat, double gamma) {
+    if (st->done) return;
+    const int32_t act = st->action;
+    const int64_t k = st->k_check;
+    const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const double xh = xhat[i];
+        if (act == 1) {
+            x[i] = xh;
+            x0[i] = xh;
+        } else {
+            x[i] = ak * ((1.0 + gamma) * xh - gamma * x[i]) + bk * x0[i];
+        }
+    } else if (i - n < m) {
+        const int64_t r = i - n;
+        const double yh = yhat[r];
+        if (act == 1) {
+            y[r] = yh;
+            y0[r] = yh;
+        } else {
+            y[r] = ak * ((1.0 + gamma) * yh - gamma * y[r]) + bk * y0[r];
+        }
+    }
+}
+
+// Halpern point of a debug step with an explicit inner counter.
+__global__ __launch_bounds__(kBlock) void k_halpern_explicit(
+    int32_t n, int32_t m, int64_t k, const double *__restrict__ x, const double *__restrict__ x0,
+    const double *__restrict__ xhat, const double *__restrict__ y, const double *__restrict__ y0,
+    const double *__restrict__ yhat, double *__restrict__ xn, double *__restrict__ yn,
+    double gamma) {
+    const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        xn[i] = ak * ((1.0 + gamma) * xhat[i] - gamma * x[i]) + bk * x0[i];
+    } else if (i - n < m) {
+        const int64_t r = i - n;
+        yn[r] = ak * ((1.0 + gamma) * yhat[r] - gamma * y[r]) + bk * y0[r];
+    }
+}
+
+// Initial point: x = proj_X(x_init / D_c), y = proj_Y(y_init / D_r) (zeros when
+// no warm start), anchors equal to it.
+__global__ __launch_bounds__(kBlock) void k_init_point(
+    int32_t n, int32_t m, const int32_t *__restrict__ perm_c, const int32_t *__restrict__ perm_r,
+    const double *__restrict__ x_init, const double *__restrict__ y_init,
+    const double *__restrict__ Dc, const double *__restrict__ Dr, const double *__restrict__ lv,
+    const double *__restrict__ uv, const double *__restrict__ lc, const double *__restrict__ uc,
+    double *__restrict__ x, double *__restrict__ x0, double *__restrict__ y,
+    double *__restrict__ y0) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const double v = x_init ? x_init[perm_c[i]] / Dc[i] : 0.0;
+        const double xv = clampd(v, lv[i], uv[i]);
+        x[i] = xv;
+        x0[i] = xv;
+    } else if (i - n < m) {
+        const int64_t r = i - n;
+        const double v = y_init ? y_init[perm_r[r]] / Dr[r] : 0.0;
+        const double lo = isfinite(uc[r]) ? -INFINITY : 0.0;
+        const double hi = isfinite(lc[r]) ? INFINITY : 0.0;
+        const double yv = clampd(v, lo, hi);
+        y[r] = yv;
+        y0[r] = yv;
+    }
+}
+
+__global__ void k_reset_state(DevState *st, double eta, double omega) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    DevState s;
+    memset(&s, 0, sizeof(s));
+    s.eta = eta;
+    s.omega = omega;
+    s.tau = eta / omega;
+    s.sigma = eta * omega;
+    s.first = 1;
+    s.status = PDHG_UNSOLVED;
+    *st = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(const int32_t *__restrict__ perm,
+                                                   const double *__restrict__ src,
+                                                   double *__restrict__ dst, int32_t len) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) dst[i] = src[perm[i]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(const int32_t *__restrict__ perm,
+                                                    const double *__restrict__ src,
+                                                    double *__restrict__ dst, int32_t len) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) dst[perm[i]] = src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_scaled(const int32_t *__restrict__ perm,
+                                                           const double *__restrict__ scale,
+                                                           const double *__restrict__ src,
+                                                           double *__restrict__ dst, int32_t len) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) dst[perm[i]] = scale[i] * src[i];
+}
+
+// ---------------------------------------------------------------------------
+// host wrappers
+
+static inline dim3 grid_of(const HMat &M) { return dim3((unsigned)M.nblocks()); }
+
+void launch_primal(Handle &h, int32_t j) {
+    if (h.AT.nblocks() == 0) return;
+    k_primal<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
+        view(h.AT), h.y.p, h.x.p, h.x0.p, h.c.p, h.lv.p,
+        h.uv.p, h.xext.p, h.st.p, j, h.opt.gamma);
+}
+
+void launch_dual(Handle &h, int32_t j) {
+    if (h.A.nblocks() == 0) return;
+    k_dual<<<grid_of(h.A), kBlock, 0, h.stream>>>(view(h.A), h.xext.p, h.y.p, h.y0.p, h.lc.p,
+                                                  h.uc.p, h.st.p, j, h.opt.gamma);
+}
+
+void launch_primal_check(Handle &h, double tau_override) {
+    if (h.AT.nblocks() == 0) return;
+    k_primal_chk<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
+        view(h.AT), h.y.p, h.x.p, h.c.p, h.lv.p, h.uv.p,
+        h.xhat.p, h.xext.p, h.aty.p, h.st.p, tau_override);
+}
+
+void launch_dual_check(Handle &h, double sigma_override) {
+    if (h.A.nblocks() == 0) return;
+    k_dual_chk<<<grid_of(h.A), kBlock, 0, h.stream>>>(view(h.A), h.xext.p, h.y.p, h.lc.p,
+                                                      h.uc.p, h.yhat.p, h.st.p, sigma_override);
+}
+
+void launch_check_sums(Handle &h) {
+    if (h.AT.nblocks())
+        k_check_n<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
+            view(h.AT), h.yhat.p, h.xhat.p, h.x.p,
+            h.x0.p, h.aty.p, h.Dc.p, h.c_o.p, h.lv_o.p, h.uv_o.p, h.pn.p, h.st.p);
+    if (h.A.nblocks())
+        k_check_m<<<grid_of(h.A), kBlock, 0, h.stream>>>(
+            view(h.A), h.xhat.p, h.yhat.p, h.y.p, h.y0.p,
+            h.Dr.p, h.lc_o.p, h.uc_o.p, h.pm.p, h.st.p);
+}
+
+void launch_controller(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t last_status) {
+    CtlConst K;
+    K.eps = h.opt.eps;
+    K.bnorm = h.bnorm;
+    K.cnorm = h.cnorm;
+    K.eta = h.eta;
+    K.beta_suff = h.opt.restart_sufficient;
+    K.beta_nec = h.opt.restart_necessary;
+    K.beta_art = h.opt.restart_artificial;
+    K.qp = 0;
+    K.pad = 0;
+    k_controller<<<1, kBlock, 0, h.stream>>>(h.st.p, h.pn.p, h.AT.nblocks(), h.pm.p,
+                                              h.A.nblocks(), K, chunk_plain, is_last,
+                                              last_status);
+}
+
+void launch_apply(Handle &h) {
+    const int64_t tot = (int64_t)h.n + h.m;
+    k_apply<<<(unsigned)ceil_div(tot, kBlock), kBlock, 0, h.stream>>>(
+        h.st.p, h.n, h.m, h.x.p, h.x0.p, h.xhat.p, h.y.p, h.y0.p, h.yhat.p, h.opt.gamma);
+}
+
+void launch_debug_halpern(Handle &h, int64_t k, double *xnew_int, double *ynew_int) {
+    const int64_t tot = (int64_t)h.n + h.m;
+    k_halpern_explicit<<<(unsigned)ceil_div(tot, kBlock), kBlock, 0, h.stream>>>(
+        h.n, h.m, k, h.x.p, h.x0.p, h.xhat.p, h.y.p, h.y0.p, h.yhat.p, xnew_int, ynew_int,
+        h.opt.gamma);
+}
+
+void launch_init_point(Handle &h, const double *x_init, const double *y_init) {
+    const int64_t tot = (int64_t)h.n + h.m;
+    k_init_point<<<(unsigned)ceil_div(tot, kBlock), kBlock, 0, h.stream>>>(
+        h.n, h.m, h.perm_c.p, h.perm_r.p, x_init, y_init, h.Dc.p, h.Dr.p, h.lv.p, h.uv.p, h.lc.p,
+        h.uc.p, h.x.p, h.x0.p, h.y.p, h.y0.p);
+}
+
+void launch_finalize(Handle &h, double *x_out, double *y_out) {
+    if (h.n) launch_scatter_scaled(h.stream, h.perm_c.p, h.Dc.p, h.xhat.p, x_out, h.n);
+    if (h.m) launch_scatter_scaled(h.stream, h.perm_r.p, h.Dr.p, h.yhat.p, y_out, h.m);
+}
+
+void launch_reset_state(Handle &h) {
+    k_reset_state<<<1, 64, 0, h.stream>>>(h.st.p, h.eta, h.omega0);
+}
+
+void launch_gather(hipStream_t s, const int32_t *perm, const double *src, double *dst,
+                   int32_t len) {
+    if (len <= 0) return;
+    k_gather<<<(unsigned)ceil_div(len, kBlock), kBlock, 0, s>>>(perm, src, dst, len);
+}
+
+void launch_scatter(hipStream_t s, const int32_t *perm, const double *src, double *dst,
+                    int32_t len) {
+    if (len <= 0) return;
+    k_scatter<<<(unsigned)ceil_div(len, kBlock), kBlock, 0, s>>>(perm, src, dst, len);
+}
+
+void launch_scatter_scaled(hipStream_t s, const int32_t *perm, const double *scale,
+                           const double *src, double *dst, int32_t len) {
+    if (len <= 0) return;
+    k_scatter_scaled<<<(unsigned)ceil_div(len, kBlock), kBlock, 0, s>>>(perm, scale, src, dst,
+                                                                        len);
+}
+
+}  // namespace pdhg

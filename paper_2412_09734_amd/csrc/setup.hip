@@ -1,0 +1,755 @@
+// Setup on the device: validation, the length-binned internal layout of A and
+// A', the diagonal preconditioning of the MPAX paper's Section 3 (Ruiz
+// equilibration, then one Pock-Chambolle step with alpha = 1), the power
+// iteration for ||A~||_2 that sets the step size, and the initial primal
+// weight.
+#include <cstring>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include "device.hpp"
+
+namespace pdhg {
+
+// ---------------------------------------------------------------------------
+// validation
+
+__global__ __launch_bounds__(kBlock) void k_validate_rowptr(const int32_t *__restrict__ rowptr,
+                                                            int32_t m, int64_t nnz,
+                                                            uint8_t *__restrict__ rowstart,
+                                                            int32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i > m) return;
+    const int32_t a = rowptr[i];
+    if (i == 0 && a != 0) atomicOr(flag, 1);
+    if (i == m) {
+        if ((int64_t)a != nnz) atomicOr(flag, 1);
+        return;
+    }
+    const int32_t b = rowptr[i + 1];
+    if (b < a || a < 0 || (int64_t)b > nnz) {
+        atomicOr(flag, 1);
+        return;
+    }
+    if (b > a) rowstart[a] = 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_validate_entries(const int32_t *__restrict__ colidx,
+                                                             const double *__restrict__ val,
+                                                             int64_t nnz, int32_t n,
+                                                             const uint8_t *__restrict__ rowstart,
+                                                             int32_t *__restrict__ flag) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= nnz) return;
+    const int32_t j = colidx[e];
+    if (j < 0 || j >= n || !isfinite(val[e])) atomicOr(flag, 2);
+    if (e + 1 < nnz && !rowstart[e + 1] && colidx[e + 1] <= j) atomicOr(flag, 4);
+}
+
+// c finite; l <= u, no NaN, l != +inf, u != -inf.
+__global__ __launch_bounds__(kBlock) void k_validate_vectors(int32_t n, int32_t m,
+                                                             const double *__restrict__ c,
+                                                             const double *__restrict__ lv,
+                                                             const double *__restrict__ uv,
+                                                             const double *__restrict__ lc,
+                                                             const double *__restrict__ uc,
+                                                             int32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const double l = lv[i], u = uv[i];
+        if (!isfinite(c[i]) || isnan(l) || isnan(u) || l > u || l == INFINITY || u == -INFINITY)
+            atomicOr(flag, 8);
+    } else if (i - n < m) {
+        const int64_t r = i - n;
+        const double l = lc[r], u = uc[r];
+        if (isnan(l) || isnan(u) || l > u || l == INFINITY || u == -INFINITY) atomicOr(flag, 16);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// length classes and the internal layout
+
+// Sort key: descending exact length (ascending key).
+__global__ __launch_bounds__(kBlock) void k_row_keys(const int32_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ cnt, int32_t len,
+                                                     uint32_t kmax, uint32_t *__restrict__ key,
+                                                     int32_t *__restrict__ iota) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= len) return;
+    const int32_t l = rowptr ? rowptr[i + 1] - rowptr[i] : cnt[i];
+    key[i] = kmax - (uint32_t)l;
+    iota[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_col_count(const int32_t *__restrict__ colidx,
+                                                      int64_t nnz, int32_t *__restrict__ cnt) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < nnz) atomicAdd(&cnt[colidx[e]], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_inverse(const int32_t *__restrict__ perm, int32_t len,
+                                                    int32_t *__restrict__ inv) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) inv[perm[i]] = (int32_t)i;
+}
+
+// len_int[i'] = length of original row perm[i'] (rowptr form or count form);
+// len_int[len] = 0 so that an exclusive scan gives the full rowptr.
+__global__ __launch_bounds__(kBlock) void k_perm_lengths(const int32_t *__restrict__ perm,
+                                                         const int32_t *__restrict__ rowptr,
+                                                         const int32_t *__restrict__ counts,
+                                                         int32_t len, int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i > len) return;
+    if (i == len) {
+        out[i] = 0;
+        return;
+    }
+    const int32_t r = perm[i];
+    out[i] = rowptr ? rowptr[r + 1] - rowptr[r] : counts[r];
+}
+
+// One wave per internal row: copy the original row with relabelled columns.
+__global__ __launch_bounds__(kBlock) void k_fill_internal(
+    const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+    const double *__restrict__ val, const int32_t *__restrict__ perm_r,
+    const int32_t *__restrict__ inv_c, const int32_t *__restrict__ rp_int, int32_t m,
+    int32_t *__restrict__ ci_int, double *__restrict__ va_int, int32_t *__restrict__ row_of) {
+    const int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= m) return;
+    const int32_t src = perm_r[w];
+    const int32_t s0 = rowptr[src], s1 = rowptr[src + 1];
+    const int32_t d0 = rp_int[w];
+    for (int32_t e = s0 + lane; e < s1; e += 64) {
+        const int32_t d = d0 + (e - s0);
+        ci_int[d] = inv_c[colidx[e]];
+        va_int[d] = val[e];
+        row_of[d] = (int32_t)w;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_iota_u(int32_t *__restrict__ iota, int64_t len) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) iota[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_transpose(const int32_t *__restrict__ order,
+                                                           const int32_t *__restrict__ row_of,
+                                                           const double *__restrict__ va,
+                                                           int64_t nnz, int32_t *__restrict__ ci_t,
+                                                           double *__restrict__ va_t) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= nnz) return;
+    const int32_t e = order[p];
+    ci_t[p] = row_of[e];
+    va_t[p] = va[e];
+}
+
+// Number of leading rows longer than the short-row limit (rows sorted by
+// descending length) and the length histogram of those rows by class
+// (class c >= 1: length in (2^(c-1), 2^c]).
+__global__ __launch_bounds__(kBlock) void k_long_rows(const int32_t *__restrict__ rowptr,
+                                                      int32_t rows, int32_t limit,
+                                                      int32_t *__restrict__ out /*[1+32]*/) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= rows) return;
+    const int32_t l = rowptr[i + 1] - rowptr[i];
+    if (l > limit) {
+        const int32_t nl = (i + 1 < rows) ? rowptr[i + 2] - rowptr[i + 1] : 0;
+        if (nl <= limit) out[0] = (int32_t)(i + 1);
+        const int32_t cls = 32 - __clz(l - 1);
+        atomicAdd(&out[1 + (31 - cls)], 1);
+    }
+}
+
+// widths64[s] = 64 * length of the first row of slice s; widths64[ns] = 0.
+__global__ __launch_bounds__(kBlock) void k_slice_widths(const int32_t *__restrict__ rowptr,
+                                                         int32_t r_long, int32_t ns,
+                                                         int32_t *__restrict__ widths64) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s > ns) return;
+    if (s == ns) {
+        widths64[s] = 0;
+        return;
+    }
+    const int64_t r = r_long + s * 64;
+    widths64[s] = 64 * (rowptr[r + 1] - rowptr[r]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_add_offset(const int32_t *__restrict__ in, int32_t len,
+                                                       int32_t off, int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) out[i] = in[i] + off;
+}
+
+// Copy the short rows into their SELL-64 slices, padding with (0, 0.0).
+__global__ __launch_bounds__(kBlock) void k_fill_slices(const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ colidx,
+                                                        const double *__restrict__ val,
+                                                        int32_t r_long, int32_t rows, int32_t ns,
+                                                        const int32_t *__restrict__ slice_ptr,
+                                                        int32_t *__restrict__ ci_out,
+                                                        double *__restrict__ va_out) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = t >> 6;
+    const int32_t lane = (int32_t)(t & 63);
+    if (s >= ns) return;
+    const int64_t r = r_long + s * 64 + lane;
+    const int32_t b = slice_ptr[s];
+    const int32_t w = (slice_ptr[s + 1] - b) >> 6;
+    const int32_t e0 = r < rows ? rowptr[r] : 0;
+    const int32_t len = r < rows ? rowptr[r + 1] - e0 : 0;
+    for (int32_t k = 0; k < w; ++k) {
+        const int32_t d = b + 64 * k + lane;
+        ci_out[d] = k < len ? colidx[e0 + k] : 0;
+        va_out[d] = k < len ? val[e0 + k] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// scaling kernels
+
+template <bool MAXNORM>
+__global__ __launch_bounds__(kBlock) void k_row_absnorm(MatView M, double *__restrict__ out) {
+    const RowSum rs = mat_row_absnorm<MAXNORM>(M);
+    if (rs.valid) out[rs.row] = rs.s;
+}
+
+// factor f = sqrt(norm) (1 for an empty row / column); D <- D / f.
+__global__ __launch_bounds__(kBlock) void k_factors(double *__restrict__ norm_to_factor,
+                                                    double *__restrict__ D, int32_t len) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= len) return;
+    const double v = norm_to_factor[i];
+    const double f = v > 0.0 ? sqrt(v) : 1.0;
+    norm_to_factor[i] = f;
+    D[i] = D[i] / f;
+}
+
+// A~_ij <- A~_ij / (r_i s_j) for the rows of A (transposed = 0) or of A'.
+__global__ __launch_bounds__(kBlock) void k_scale_vals(MatView M, const double *__restrict__ rfac,
+                                                       const double *__restrict__ cfac,
+                                                       int32_t transposed) {
+    mat_scale_entries(M, rfac, cfac, transposed != 0);
+}
+
+// c~ = D_c c, l~_v = l_v / D_c, u~_v = u_v / D_c (columns); l~_c = D_r l_c,
+// u~_c = D_r u_c (rows).
+__global__ __launch_bounds__(kBlock) void k_transform(
+    int32_t n, int32_t m, const double *__restrict__ Dc, const double *__restrict__ Dr,
+    const double *__restrict__ c_o, const double *__restrict__ lv_o,
+    const double *__restrict__ uv_o, const double *__restrict__ lc_o,
+    const double *__restrict__ uc_o, double *__restrict__ c, double *__restrict__ lv,
+    double *__restrict__ uv, double *__restrict__ lc, double *__restrict__ uc) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const double d = Dc[i];
+        c[i] = d * c_o[i];
+        lv[i] = lv_o[i] / d;
+        uv[i] = uv_o[i] / d;
+    } else if (i - n < m) {
+        const int64_t r = i - n;
+        const double d = Dr[r];
+        lc[r] = d * lc_o[r];
+        uc[r] = d * uc_o[r];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(double *__restrict__ v, double value, int64_t len) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) v[i] = value;
+}
+
+// Sums for the norms: 0 |c~|^2, 1 |b~|^2 (scaled), 2 |c|^2, 3 |b|^2 (original),
+// with b_i the largest finite |bound| of row i.
+__global__ __launch_bounds__(kBlock) void k_norm_sums(int32_t n, int32_t m,
+                                                      const double *__restrict__ c,
+                                                      const double *__restrict__ lc,
+                                                      const double *__restrict__ uc,
+                                                      const double *__restrict__ c_o,
+                                                      const double *__restrict__ lc_o,
+                                                      const double *__restrict__ uc_o,
+                                                      double *__restrict__ partials) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)n + m; i += stride) {
+        if (i < n) {
+            v[0] += c[i] * c[i];
+            v[2] += c_o[i] * c_o[i];
+        } else {
+            const int64_t r = i - n;
+            double b = 0.0, bo = 0.0;
+            if (isfinite(lc[r])) b = fmax(b, fabs(lc[r]));
+            if (isfinite(uc[r])) b = fmax(b, fabs(uc[r]));
+            if (isfinite(lc_o[r])) bo = fmax(bo, fabs(lc_o[r]));
+            if (isfinite(uc_o[r])) bo = fmax(bo, fabs(uc_o[r]));
+            v[1] += b * b;
+            v[3] += bo * bo;
+        }
+    }
+    block_sum_store<4>(v, partials + (size_t)blockIdx.x * 4);
+}
+
+// out = A~ v on the rows of a matrix, partial sums of out^2.
+__global__ __launch_bounds__(kBlock) void k_spmv_sq(MatView M, const double *__restrict__ v,
+                                                    double *__restrict__ out,
+                                                    double *__restrict__ partials) {
+    const RowSum rs = mat_row_dot(M, v);
+    double q[1] = {0.0};
+    if (rs.valid) {
+        out[rs.row] = rs.s;
+        q[0] = rs.s * rs.s;
+    }
+    block_sum_store<1>(q, partials + blockIdx.x);
+}
+
+// Start vector of the power iteration: v_j = 0.5 + u_j with u_j uniform in
+// [0, 1) from SplitMix64 (Steele, Lea and Flood, 2014) at counter j, j the
+// ORIGINAL column index; also partial sums of v^2.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kBlock) void k_power_start(const int32_t *__restrict__ perm_c, int32_t n,
+                                                        double *__restrict__ v,
+                                                        double *__restrict__ partials) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double q[1] = {0.0};
+    if (i < n) {
+        const double u = (double)(splitmix64((uint64_t)perm_c[i]) >> 11) * 0x1.0p-53;
+        const double val = 0.5 + u;
+        v[i] = val;
+        q[0] = val * val;
+    }
+    block_sum_store<1>(q, partials + blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_div_sqrt(double *__restrict__ v, int32_t n,
+                                                     const double *__restrict__ tot) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) v[i] = v[i] / sqrt(tot[0]);
+}
+
+// Fixed-order total of K-wide partials, written to out[0..K-1].
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_total(const double *__restrict__ partials, int32_t nb,
+                                                  double *__restrict__ out) {
+    double v[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = 0.0;
+    for (int32_t b = threadIdx.x; b < nb; b += kBlock)
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[q] += partials[(size_t)b * K + q];
+    block_sum_all<K>(v);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < K; ++q) out[q] = v[q];
+}
+
+// v = u / |u|, |u|^2 = tot[0]; records lam (= |A~ v_prev|^2 = wtot[0]) and |u|.
+__global__ __launch_bounds__(kBlock) void k_power_normalize(const double *__restrict__ u,
+                                                            double *__restrict__ v, int32_t n,
+                                                            const double *__restrict__ wtot,
+                                                            const double *__restrict__ utot,
+                                                            double *__restrict__ hist, int32_t it) {
+    const double nu = sqrt(utot[0]);
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) {
+        hist[2 * it] = wtot[0];
+        hist[2 * it + 1] = nu;
+    }
+    if (i < n && nu > 0.0) v[i] = u[i] / nu;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+namespace {
+
+template <class F>
+void with_temp(hipStream_t s, F &&f) {
+    size_t bytes = 0;
+    PDHG_HIP(f(nullptr, bytes));
+    DBuf<uint8_t> tmp;
+    tmp.alloc(bytes);
+    PDHG_HIP(f(tmp.p, bytes));
+    (void)s;
+}
+
+void sort_pairs(hipStream_t s, const uint32_t *kin, uint32_t *kout, const int32_t *vin,
+                int32_t *vout, int64_t len, int bits) {
+    if (len <= 0) return;
+    with_temp(s, [&](void *tmp, size_t &bytes) {
+        return rocprim::radix_sort_pairs(tmp, bytes, kin, kout, vin, vout, (size_t)len, 0u,
+                                         (unsigned)bits, s);
+    });
+}
+
+void exclusive_scan(hipStream_t s, const int32_t *in, int32_t *out, int64_t len) {
+    with_temp(s, [&](void *tmp, size_t &bytes) {
+        return rocprim::exclusive_scan(tmp, bytes, in, out, 0, (size_t)len,
+                                       rocprim::plus<int32_t>(), s);
+    });
+}
+
+unsigned blocks_for(int64_t len) { return (unsigned)std::max<int64_t>(1, ceil_div(len, kBlock)); }
+
+}  // namespace
+
+SegTable make_segments(const std::vector<int32_t> &class_count, int32_t rows) {
+    SegTable T;
+    memset(&T, 0, sizeof(T));
+    int32_t begin = 0, blocks = 0;
+    for (int q = 0; q < 32; ++q) {
+        const int32_t cnt = class_count[q];
+        if (cnt <= 0) continue;
+        const int cls = 31 - q;
+        const int lg = std::min(6, std::max(0, cls - 2));
+        const int32_t rows_per_block = kBlock >> lg;
+        Seg sg;
+        sg.row_begin = begin;
+        sg.row_end = begin + cnt;
+        sg.lanes_log2 = lg;
+        sg.block_begin = blocks;
+        T.s[T.nseg++] = sg;
+        begin += cnt;
+        blocks += (int32_t)ceil_div(cnt, rows_per_block);
+    }
+    if (begin != rows) fail(PDHG_ERR_INVALID_INPUT, "internal: class counts do not add up");
+    T.nblocks = blocks;
+    return T;
+}
+
+static void check_flag(hipStream_t s, const int32_t *dflag, const char *what) {
+    int32_t f = 0;
+    PDHG_HIP(hipMemcpyAsync(&f, dflag, sizeof(f), hipMemcpyDeviceToHost, s));
+    PDHG_HIP(hipStreamSynchronize(s));
+    if (f) fail(PDHG_ERR_INVALID_INPUT, std::string(what) + " (code " + std::to_string(f) + ")");
+}
+
+// Device copy of a caller array (or a view when it already is on the device).
+template <class T>
+static const T *device_view(const T *src, size_t count, int mem, DBuf<T> &holder, hipStream_t s) {
+    if (mem == PDHG_MEM_DEVICE || count == 0) return src;
+    holder.alloc(count);
+    PDHG_HIP(hipMemcpyAsync(holder.p, src, count * sizeof(T), hipMemcpyHostToDevice, s));
+    return holder.p;
+}
+
+// Plain CSR in internal order (temporary, before conversion to the hybrid layout).
+struct PlainCsr {
+    int32_t rows = 0;
+    int64_t nnz = 0;
+    DBuf<int32_t> rowptr, colidx;
+    DBuf<double> val;
+};
+
+// Convert a plain CSR whose rows are sorted by descending length into the
+// hybrid layout (long rows as CSR with lane groups, the rest as SELL-64).
+static void to_hybrid(hipStream_t s, PlainCsr &P, int32_t cols, HMat &H) {
+    const int32_t R = P.rows;
+    H.rows = R;
+    H.cols = cols;
+    H.nnz = P.nnz;
+    DBuf<int32_t> info;
+    info.alloc(33);
+    PDHG_HIP(hipMemsetAsync(info.p, 0, 33 * sizeof(int32_t), s));
+    if (R > 0) k_long_rows<<<blocks_for(R), kBlock, 0, s>>>(P.rowptr.p, R, kShortMax, info.p);
+    int32_t hinfo[33];
+    PDHG_HIP(hipMemcpyAsync(hinfo, info.p, sizeof(hinfo), hipMemcpyDeviceToHost, s));
+    PDHG_HIP(hipStreamSynchronize(s));
+    const int32_t r_long = hinfo[0];
+    std::vector<int32_t> cls(hinfo + 1, hinfo + 33);
+    H.R_long = r_long;
+    H.seg = make_segments(cls, r_long);
+    const int32_t ns = (int32_t)ceil_div(R - r_long, 64);
+    H.nslices = ns;
+    int32_t nnz_long = 0;
+    if (r_long > 0)
+        PDHG_HIP(hipMemcpyAsync(&nnz_long, P.rowptr.p + r_long, sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+    DBuf<int32_t> widths, soff;
+    widths.alloc((size_t)ns + 1);
+    soff.alloc((size_t)ns + 1);
+    k_slice_widths<<<blocks_for((int64_t)ns + 1), kBlock, 0, s>>>(P.rowptr.p, r_long, ns, widths.p);
+    exclusive_scan(s, widths.p, soff.p, (int64_t)ns + 1);
+    int32_t short_total = 0;
+    PDHG_HIP(hipMemcpyAsync(&short_total, soff.p + ns, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    PDHG_HIP(hipStreamSynchronize(s));
+    if ((int64_t)nnz_long + short_total >= INT32_MAX)
+        fail(PDHG_ERR_UNSUPPORTED, "matrix too large for 32-bit entry offsets after padding");
+    H.stored = (int64_t)nnz_long + short_total;
+    H.colidx.alloc((size_t)H.stored);
+    H.val.alloc((size_t)H.stored);
+    H.rowptr.alloc((size_t)r_long + 1);
+    H.slice_ptr.alloc((size_t)ns + 1);
+    PDHG_HIP(hipMemcpyAsync(H.rowptr.p, P.rowptr.p, sizeof(int32_t) * ((size_t)r_long + 1),
+                            hipMemcpyDeviceToDevice, s));
+    if (nnz_long > 0) {
+        PDHG_HIP(hipMemcpyAsync(H.colidx.p, P.colidx.p, sizeof(int32_t) * (size_t)nnz_long,
+                                hipMemcpyDeviceToDevice, s));
+        PDHG_HIP(hipMemcpyAsync(H.val.p, P.val.p, sizeof(double) * (size_t)nnz_long,
+                                hipMemcpyDeviceToDevice, s));
+    }
+    k_add_offset<<<blocks_for((int64_t)ns + 1), kBlock, 0, s>>>(soff.p, ns + 1, nnz_long,
+                                                                H.slice_ptr.p);
+    if (ns > 0)
+        k_fill_slices<<<blocks_for((int64_t)ns * 64), kBlock, 0, s>>>(
+            P.rowptr.p, P.colidx.p, P.val.p, r_long, R, ns, H.slice_ptr.p, H.colidx.p, H.val.p);
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
+void build_matrices(Handle &h, const pdhg_problem &p) {
+    hipStream_t s = h.stream;
+    const int32_t m = p.m, n = p.n;
+    const int64_t nnz = p.a_nnz;
+    DBuf<int32_t> hrp, hci;
+    DBuf<double> hva;
+    const int32_t *rowptr = device_view(p.a_rowptr, (size_t)m + 1, p.mem, hrp, s);
+    const int32_t *colidx = device_view(p.a_colidx, (size_t)nnz, p.mem, hci, s);
+    const double *val = device_view(p.a_val, (size_t)nnz, p.mem, hva, s);
+
+    DBuf<int32_t> flag;
+    flag.alloc(1);
+    PDHG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+    {
+        DBuf<uint8_t> rowstart;
+        rowstart.alloc((size_t)nnz + 1);
+        PDHG_HIP(hipMemsetAsync(rowstart.p, 0, (size_t)nnz + 1, s));
+        k_validate_rowptr<<<blocks_for((int64_t)m + 1), kBlock, 0, s>>>(rowptr, m, nnz,
+                                                                         rowstart.p, flag.p);
+        check_flag(s, flag.p, "invalid CSR row pointers");
+        if (nnz > 0)
+            k_validate_entries<<<blocks_for(nnz), kBlock, 0, s>>>(colidx, val, nnz, n, rowstart.p,
+                                                                   flag.p);
+        check_flag(s, flag.p, "invalid CSR entries (column out of range, unsorted or duplicate "
+                              "column, or non-finite value)");
+    }
+
+    // permutations by descending exact length (stable)
+    h.perm_r.alloc(m);
+    h.perm_c.alloc(n);
+    int kbits = 1;
+    while ((1ll << kbits) <= (int64_t)std::max(m, n) + 1) ++kbits;
+    const uint32_t kmax = (uint32_t)((1ull << kbits) - 1);
+    {
+        DBuf<uint32_t> key, key_sorted;
+        DBuf<int32_t> iota, cnt;
+        key.alloc(std::max(m, n));
+        key_sorted.alloc(std::max(m, n));
+        iota.alloc(std::max(m, n));
+        cnt.alloc(n);
+        if (m > 0) {
+            k_row_keys<<<blocks_for(m), kBlock, 0, s>>>(rowptr, nullptr, m, kmax, key.p, iota.p);
+            sort_pairs(s, key.p, key_sorted.p, iota.p, h.perm_r.p, m, kbits);
+        }
+        PDHG_HIP(hipMemsetAsync(cnt.p, 0, (size_t)n * sizeof(int32_t), s));
+        if (nnz > 0) k_col_count<<<blocks_for(nnz), kBlock, 0, s>>>(colidx, nnz, cnt.p);
+        k_row_keys<<<blocks_for(n), kBlock, 0, s>>>(nullptr, cnt.p, n, kmax, key.p, iota.p);
+        sort_pairs(s, key.p, key_sorted.p, iota.p, h.perm_c.p, n, kbits);
+        key.release();
+        key_sorted.release();
+
+        DBuf<int32_t> inv_c, lens, row_of;
+        inv_c.alloc(n);
+        k_inverse<<<blocks_for(n), kBlock, 0, s>>>(h.perm_c.p, n, inv_c.p);
+
+        // plain internal A
+        PlainCsr PA;
+        PA.rows = m;
+        PA.nnz = nnz;
+        PA.rowptr.alloc((size_t)m + 1);
+        PA.colidx.alloc((size_t)nnz);
+        PA.val.alloc((size_t)nnz);
+        row_of.alloc((size_t)nnz);
+        lens.alloc((size_t)std::max(m, n) + 1);
+        k_perm_lengths<<<blocks_for((int64_t)m + 1), kBlock, 0, s>>>(h.perm_r.p, rowptr, nullptr, m,
+                                                                     lens.p);
+        exclusive_scan(s, lens.p, PA.rowptr.p, (int64_t)m + 1);
+        if (m > 0 && nnz > 0)
+            k_fill_internal<<<blocks_for((int64_t)m * 64), kBlock, 0, s>>>(
+                rowptr, colidx, val, h.perm_r.p, inv_c.p, PA.rowptr.p, m, PA.colidx.p, PA.val.p,
+                row_of.p);
+
+        // plain internal A' by a stable sort of the entries on their internal column
+        PlainCsr PT;
+        PT.rows = n;
+        PT.nnz = nnz;
+        PT.rowptr.alloc((size_t)n + 1);
+        PT.colidx.alloc((size_t)nnz);
+        PT.val.alloc((size_t)nnz);
+        k_perm_lengths<<<blocks_for((int64_t)n + 1), kBlock, 0, s>>>(h.perm_c.p, nullptr, cnt.p, n,
+                                                                     lens.p);
+        exclusive_scan(s, lens.p, PT.rowptr.p, (int64_t)n + 1);
+        if (nnz > 0) {
+            DBuf<uint32_t> ekey_sorted;
+            DBuf<int32_t> eid, order;
+            ekey_sorted.alloc((size_t)nnz);
+            eid.alloc((size_t)nnz);
+            order.alloc((size_t)nnz);
+            k_iota_u<<<blocks_for(nnz), kBlock, 0, s>>>(eid.p, nnz);
+            int bits = 1;
+            while ((1ll << bits) < (int64_t)n) ++bits;
+            sort_pairs(s, reinterpret_cast<const uint32_t *>(PA.colidx.p), ekey_sorted.p, eid.p,
+                       order.p, nnz, bits);
+            k_fill_transpose<<<blocks_for(nnz), kBlock, 0, s>>>(order.p, row_of.p, PA.val.p, nnz,
+                                                                PT.colidx.p, PT.val.p);
+        }
+        PDHG_HIP(hipStreamSynchronize(s));
+        to_hybrid(s, PA, n, h.A);
+        to_hybrid(s, PT, m, h.AT);
+    }
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
+void validate_and_load_vectors(Handle &h, const pdhg_problem &p) {
+    hipStream_t s = h.stream;
+    const int32_t m = h.m, n = h.n;
+    DBuf<double> hc, hlv, huv, hlc, huc;
+    const double *c = device_view(p.c, (size_t)n, p.mem, hc, s);
+    const double *lv = device_view(p.lv, (size_t)n, p.mem, hlv, s);
+    const double *uv = device_view(p.uv, (size_t)n, p.mem, huv, s);
+    const double *lc = device_view(p.lc, (size_t)m, p.mem, hlc, s);
+    const double *uc = device_view(p.uc, (size_t)m, p.mem, huc, s);
+    DBuf<int32_t> flag;
+    flag.alloc(1);
+    PDHG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+    k_validate_vectors<<<blocks_for((int64_t)n + m), kBlock, 0, s>>>(n, m, c, lv, uv, lc, uc,
+                                                                    flag.p);
+    check_flag(s, flag.p, "invalid objective or bounds (non-finite c, NaN bound, l > u)");
+    for (auto *b : {&h.c_o, &h.lv_o, &h.uv_o, &h.c, &h.lv, &h.uv, &h.Dc, &h.x, &h.x0, &h.xhat,
+                    &h.xext, &h.aty})
+        if (!b->p) b->alloc(n);
+    for (auto *b : {&h.lc_o, &h.uc_o, &h.lc, &h.uc, &h.Dr, &h.y, &h.y0, &h.yhat})
+        if (!b->p) b->alloc(m);
+    launch_gather(s, h.perm_c.p, c, h.c_o.p, n);
+    launch_gather(s, h.perm_c.p, lv, h.lv_o.p, n);
+    launch_gather(s, h.perm_c.p, uv, h.uv_o.p, n);
+    launch_gather(s, h.perm_r.p, lc, h.lc_o.p, m);
+    launch_gather(s, h.perm_r.p, uc, h.uc_o.p, m);
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
+void scale_problem(Handle &h) {
+    hipStream_t s = h.stream;
+    const int32_t m = h.m, n = h.n;
+    k_fill<<<blocks_for(n), kBlock, 0, s>>>(h.Dc.p, 1.0, n);
+    if (m > 0) k_fill<<<blocks_for(m), kBlock, 0, s>>>(h.Dr.p, 1.0, m);
+    const int passes = h.opt.ruiz_iters + (h.opt.pock_chambolle ? 1 : 0);
+    DBuf<double> rn, cn;
+    rn.alloc(m);
+    cn.alloc(n);
+    const MatView VA = view(h.A), VT = view(h.AT);
+    const int32_t nbA = h.A.nblocks(), nbT = h.AT.nblocks();
+    for (int pass = 0; pass < passes && h.A.nnz > 0; ++pass) {
+        const bool pc = pass >= h.opt.ruiz_iters;
+        if (nbA) {
+            if (pc) k_row_absnorm<false><<<nbA, kBlock, 0, s>>>(VA, rn.p);
+            else k_row_absnorm<true><<<nbA, kBlock, 0, s>>>(VA, rn.p);
+        }
+        if (nbT) {
+            if (pc) k_row_absnorm<false><<<nbT, kBlock, 0, s>>>(VT, cn.p);
+            else k_row_absnorm<true><<<nbT, kBlock, 0, s>>>(VT, cn.p);
+        }
+        if (m > 0) k_factors<<<blocks_for(m), kBlock, 0, s>>>(rn.p, h.Dr.p, m);
+        k_factors<<<blocks_for(n), kBlock, 0, s>>>(cn.p, h.Dc.p, n);
+        if (nbA) k_scale_vals<<<nbA, kBlock, 0, s>>>(VA, rn.p, cn.p, 0);
+        if (nbT) k_scale_vals<<<nbT, kBlock, 0, s>>>(VT, rn.p, cn.p, 1);
+    }
+    transform_vectors(h);
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
+void transform_vectors(Handle &h) {
+    const int32_t m = h.m, n = h.n;
+    k_transform<<<blocks_for((int64_t)n + m), kBlock, 0, h.stream>>>(
+        n, m, h.Dc.p, h.Dr.p, h.c_o.p, h.lv_o.p, h.uv_o.p, h.lc_o.p, h.uc_o.p, h.c.p, h.lv.p,
+        h.uv.p, h.lc.p, h.uc.p);
+}
+
+void estimate_steps(Handle &h) {
+    hipStream_t s = h.stream;
+    const int32_t m = h.m, n = h.n;
+    h.norm_a = 0.0;
+    h.power_iters = 0;
+    if (h.A.nnz > 0 && m > 0) {
+        // power iteration on A~'A~: lam_k = |A~ v_k|^2 with |v_k| = 1
+        const int maxit = std::max(1, h.opt.power_max_iters);
+        const int32_t nbA = h.A.nblocks(), nbT = h.AT.nblocks();
+        const MatView VA = view(h.A), VT = view(h.AT);
+        DBuf<double> v, w, u, pw, pu, tot, hist;
+        v.alloc(n);
+        w.alloc(m);
+        u.alloc(n);
+        pw.alloc(std::max<int64_t>(nbA, 1));
+        pu.alloc(std::max<int64_t>({(int64_t)nbT, (int64_t)blocks_for(n), 1}));
+        tot.alloc(2);
+        hist.alloc(2 * ((size_t)maxit + 2));
+        k_power_start<<<blocks_for(n), kBlock, 0, s>>>(h.perm_c.p, n, v.p, pu.p);
+        k_total<1><<<1, kBlock, 0, s>>>(pu.p, (int32_t)blocks_for(n), tot.p);
+        k_div_sqrt<<<blocks_for(n), kBlock, 0, s>>>(v.p, n, tot.p);
+        const int batch = 16;
+        std::vector<double> hh(2 * ((size_t)maxit + 2));
+        double lam = 0.0, lam_prev = 0.0;
+        int it_done = 0;
+        bool stop = false;
+        for (int it0 = 1; it0 <= maxit && !stop; it0 += batch) {
+            const int it1 = std::min(maxit, it0 + batch - 1);
+            for (int it = it0; it <= it1; ++it) {
+                k_spmv_sq<<<nbA, kBlock, 0, s>>>(VA, v.p, w.p, pw.p);
+                k_total<1><<<1, kBlock, 0, s>>>(pw.p, nbA, tot.p);
+                k_spmv_sq<<<nbT, kBlock, 0, s>>>(VT, w.p, u.p, pu.p);
+                k_total<1><<<1, kBlock, 0, s>>>(pu.p, nbT, tot.p + 1);
+                k_power_normalize<<<blocks_for(n), kBlock, 0, s>>>(u.p, v.p, n, tot.p,
+                                                                   tot.p + 1, hist.p, it);
+            }
+            PDHG_HIP(hipMemcpyAsync(hh.data() + 2 * it0, hist.p + 2 * it0,
+                                    sizeof(double) * 2 * (it1 - it0 + 1), hipMemcpyDeviceToHost,
+                                    s));
+            PDHG_HIP(hipStreamSynchronize(s));
+            for (int it = it0; it <= it1; ++it) {
+                lam = hh[2 * it];
+                const double nu = hh[2 * it + 1];
+                it_done = it;
+                if (!(nu > 0.0)) {
+                    lam = 0.0;
+                    stop = true;
+                    break;
+                }
+                if (it > 1 && fabs(lam - lam_prev) <= h.opt.power_tol * lam) {
+                    stop = true;
+                    break;
+                }
+                lam_prev = lam;
+            }
+        }
+        h.power_iters = it_done;
+        h.norm_a = sqrt(lam);
+    }
+    h.eta = h.norm_a > 0.0 ? h.opt.step_safety / h.norm_a : 1.0;
+}
+
+void compute_weight(Handle &h) {
+    hipStream_t s = h.stream;
+    const int32_t m = h.m, n = h.n;
+    const int nb = 64;
+    DBuf<double> part, tot;
+    part.alloc((size_t)nb * 4);
+    tot.alloc(4);
+    k_norm_sums<<<nb, kBlock, 0, s>>>(n, m, h.c.p, h.lc.p, h.uc.p, h.c_o.p, h.lc_o.p, h.uc_o.p,
+                                       part.p);
+    k_total<4><<<1, kBlock, 0, s>>>(part.p, nb, tot.p);
+    double t[4];
+    PDHG_HIP(hipMemcpyAsync(t, tot.p, sizeof(t), hipMemcpyDeviceToHost, s));
+    PDHG_HIP(hipStreamSynchronize(s));
+    const double cn = sqrt(t[0]), bn = sqrt(t[1]);
+    h.omega0 = (cn > 1e-10 && bn > 1e-10) ? cn / bn : 1.0;
+    h.cnorm = sqrt(t[2]);
+    h.bnorm = sqrt(t[3]);
+}
+
+}  // namespace pdhg

@@ -1,0 +1,231 @@
+"""GPU parity of the r2HPDHG path against the CPU oracle (through the C ABI).
+
+Bars: one iteration within 1e-12 relative (max-norm per output vector); the
+scaling vectors within 1e-12; a full solve reaches relative KKT <= 1e-4 with
+the objective within 1e-6 relative of the oracle's."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+from gpu_util import rel_inf, to_np
+
+pytestmark = pytest.mark.gpu
+
+STEP_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def pdhg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2412_09734_amd.solver as s
+    return s
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _step_case(pdhg, oracle_lib, lp, seeds=(0, 1), ks=(0, 5, 1000), compare_eta=True):
+    orc = oracle_lib.Oracle(lp) if compare_eta else oracle_lib.Oracle(lp, power_max_iters=1)
+    sc = orc.scaling()
+    with pdhg.Solver.from_lp(lp) as s:
+        gs = s.scaling()
+        assert rel_inf(to_np(gs["dc"]), sc["dc"]) <= STEP_TOL
+        if lp.m:
+            assert rel_inf(to_np(gs["dr"]), sc["dr"]) <= STEP_TOL
+        if compare_eta:
+            assert abs(gs["eta"] - sc["eta"]) <= 1e-10 * sc["eta"]
+            assert gs["power_iters"] == sc["power_iters"]
+        assert abs(gs["omega"] - sc["omega"]) <= 1e-10 * sc["omega"]
+        for seed in seeds:
+            rng = np.random.default_rng(seed)
+            x, y = rng.standard_normal(lp.n), rng.standard_normal(lp.m)
+            x0, y0 = rng.standard_normal(lp.n), rng.standard_normal(lp.m)
+            for k in ks:
+                tau, sigma = sc["eta"] / sc["omega"] * (1 + seed), sc["eta"] * sc["omega"]
+                got = s.debug_step(x, y, x0, y0, k, tau, sigma)
+                ref = orc.lp_step(x, y, x0, y0, k, tau, sigma)
+                for name, g, r in zip(("xhat", "yhat", "xnew", "ynew"), got, ref):
+                    err = rel_inf(to_np(g), r)
+                    assert err <= STEP_TOL, (name, seed, k, err)
+
+
+def test_step_parity_small_lp(pdhg, oracle_lib):
+    _say("case: step parity, planted m=200 n=400")
+    _step_case(pdhg, oracle_lib, gen.planted_sparse_lp(seed=0))
+
+
+def test_step_parity_mixed_bounds(pdhg, oracle_lib):
+    _say("case: step parity, boxed LP with every bound kind")
+    lp = gen.tiny_boxed_lp(37, 61, seed=3)
+    lp.lv[::5] = -np.inf
+    lp.uv[2::7] = np.inf
+    _step_case(pdhg, oracle_lib, lp)
+
+
+def _skewed_lp(seed=5):
+    """Rows and columns of very different lengths (every lane class, ragged
+    tails): a few dense rows/columns plus many 1-2 entry ones, empty rows and
+    columns, free rows."""
+    rng = np.random.default_rng(seed)
+    m, n = 1500, 3100
+    rows, cols = [], []
+    for i in range(m):
+        k = int(min(n, rng.zipf(1.6)))
+        if i % 97 == 0:
+            k = 0
+        rows += [i] * k
+        cols += list(rng.choice(n, size=k, replace=False))
+    dense_col = 7
+    rows += list(range(0, m, 2))
+    cols += [dense_col] * len(range(0, m, 2))
+    rows += [3] * 2500
+    cols += list(rng.choice(n, size=2500, replace=False))
+    key = np.unique(np.asarray(rows, np.int64) * n + np.asarray(cols, np.int64))
+    r, c = key // n, (key % n).astype(np.int32)
+    rowptr = np.zeros(m + 1, np.int32)
+    np.cumsum(np.bincount(r, minlength=m), out=rowptr[1:])
+    val = rng.standard_normal(len(c)) * 10.0 ** rng.uniform(-2, 2, len(c))
+    lc = np.where(rng.random(m) < 0.5, -rng.random(m), -np.inf)
+    uc = np.where(rng.random(m) < 0.5, rng.random(m), np.inf)
+    lc[::11] = -np.inf
+    uc[::11] = np.inf
+    lv = np.where(rng.random(n) < 0.7, 0.0, -np.inf)
+    uv = np.where(rng.random(n) < 0.3, 3.0, np.inf)
+    return gen.LP(m, n, rowptr, c, val, rng.standard_normal(n), lc, uc, lv, uv)
+
+
+def test_step_parity_skewed_lengths(pdhg, oracle_lib):
+    _say("case: step parity, skewed row/column lengths")
+    _step_case(pdhg, oracle_lib, _skewed_lp())
+
+
+def test_step_parity_grid_flow(pdhg, oracle_lib):
+    _say("case: step parity, grid min-cost flow")
+    _step_case(pdhg, oracle_lib, gen.grid_mincost_batch(batch=1, seed=3000).instance(0))
+
+
+def test_step_parity_no_rows(pdhg, oracle_lib):
+    _say("case: step parity, m=0")
+    n = 300
+    lp = gen.LP(0, n, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0),
+                np.linspace(-1, 1, n), np.zeros(0), np.zeros(0), np.full(n, -2.0), np.full(n, 5.0))
+    _step_case(pdhg, oracle_lib, lp, ks=(0, 3))
+
+
+def test_solve_parity_small_lp(pdhg, oracle_lib):
+    for seed in (0, 1, 2):
+        _say(f"case: full solve parity, planted m=200 n=400 seed={seed}")
+        lp = gen.planted_sparse_lp(seed=seed)
+        xo, yo, ro = oracle_lib.Oracle(lp).solve()
+        with pdhg.Solver.from_lp(lp) as s:
+            xg, yg, rg = s.solve()
+        _say(f"  iterations gpu={rg['iterations']} oracle={ro['iterations']} "
+             f"restarts gpu={rg['restarts']} oracle={ro['restarts']}")
+        assert rg["status_name"] == "optimal" and rg["kkt_rel"] <= 1e-4
+        assert ro["status"] == 1 and ro["kkt"] <= 1e-4
+        assert abs(rg["primal_obj"] - ro["primal_obj"]) <= 1e-6 * (1 + abs(ro["primal_obj"]))
+        # the reported KKT error is that of the returned point
+        kg = oracle_lib.kkt(lp, to_np(xg), to_np(yg))
+        assert abs(kg["kkt"] - rg["kkt_rel"]) <= 1e-9 + 1e-6 * kg["kkt"]
+
+
+def test_solve_parity_grid_flow(pdhg, oracle_lib):
+    g = gen.grid_mincost_batch(batch=2, seed=3000)
+    for b in range(2):
+        _say(f"case: full solve parity, grid min-cost flow instance {b}")
+        lp = g.instance(b)
+        xo, yo, ro = oracle_lib.Oracle(lp).solve()
+        with pdhg.Solver.from_lp(lp) as s:
+            xg, yg, rg = s.solve()
+        assert rg["status_name"] == "optimal"
+        assert abs(rg["primal_obj"] - ro["primal_obj"]) <= 1e-6 * (1 + abs(ro["primal_obj"]))
+
+
+def test_solve_is_deterministic(pdhg):
+    _say("case: bitwise determinism")
+    lp = gen.planted_sparse_lp(seed=1)
+    with pdhg.Solver.from_lp(lp) as s:
+        x1, y1, r1 = s.solve()
+        x1, y1 = to_np(x1), to_np(y1)
+        x2, y2, r2 = s.solve()
+    np.testing.assert_array_equal(x1, to_np(x2))
+    np.testing.assert_array_equal(y1, to_np(y2))
+    assert r1["iterations"] == r2["iterations"]
+
+
+def test_limits_and_warm_start(pdhg, oracle_lib):
+    _say("case: iteration limits and warm start")
+    lp = gen.planted_sparse_lp(seed=2)
+    for limit in (1, 10, 64, 65, 130):
+        xo, yo, ro = oracle_lib.Oracle(lp, iteration_limit=limit).solve()
+        with pdhg.Solver.from_lp(lp, iteration_limit=limit) as s:
+            xg, yg, rg = s.solve()
+        assert rg["status"] == ro["status"] == 4
+        assert rg["iterations"] == ro["iterations"] == limit
+        assert rel_inf(to_np(xg), xo) <= 1e-10 and rel_inf(to_np(yg), yo) <= 1e-10
+    with pdhg.Solver.from_lp(lp) as s:
+        xg, yg, rg = s.solve(lp.x_star, lp.y_star)
+    assert rg["status_name"] == "optimal" and rg["iterations"] == 1
+    # no graph replay: same iterates
+    with pdhg.Solver.from_lp(lp, use_graph=0) as s:
+        xa, ya, ra = s.solve()
+    with pdhg.Solver.from_lp(lp) as s:
+        xb, yb, rb = s.solve()
+    np.testing.assert_array_equal(to_np(xa), to_np(xb))
+
+
+def test_update_data_matches_fresh_handle(pdhg):
+    _say("case: update_data")
+    lp = gen.planted_sparse_lp(seed=3)
+    lp2 = gen.planted_sparse_lp(seed=3)
+    lp2.c = lp.c * 1.5 + 0.1
+    with pdhg.Solver.from_lp(lp) as s:
+        s.update_data(c=lp2.c)
+        xa, ya, ra = s.solve()
+    with pdhg.Solver.from_lp(lp2) as s:
+        xb, yb, rb = s.solve()
+    np.testing.assert_array_equal(to_np(xa), to_np(xb))
+    assert ra["iterations"] == rb["iterations"]
+
+
+def test_invalid_inputs_rejected(pdhg):
+    _say("case: invalid inputs")
+    from paper_2412_09734_amd._capi import PdhgError
+    lp = gen.planted_sparse_lp(seed=4)
+    bad = dict(m=lp.m, n=lp.n, rowptr=lp.rowptr, colidx=lp.colidx, val=lp.val, c=lp.c,
+               lc=lp.lc, uc=lp.uc, lv=lp.lv, uv=lp.uv)
+    c = lp.c.copy(); c[5] = np.nan
+    with pytest.raises(PdhgError) as e:
+        pdhg.Solver(**{**bad, "c": c})
+    assert e.value.code == -2
+    ci = lp.colidx.copy()
+    r = int(np.argmax(np.diff(lp.rowptr) >= 2))
+    ci[lp.rowptr[r]], ci[lp.rowptr[r] + 1] = ci[lp.rowptr[r] + 1], ci[lp.rowptr[r]]
+    with pytest.raises(PdhgError) as e:
+        pdhg.Solver(**{**bad, "colidx": ci})
+    assert e.value.code == -2
+    lv = lp.lv.copy(); lv[0] = 1.0
+    uv = lp.uv.copy(); uv[0] = 0.5
+    with pytest.raises(PdhgError) as e:
+        pdhg.Solver(**{**bad, "lv": lv, "uv": uv})
+    assert e.value.code == -2
+    v = lp.val.copy(); v[0] = np.inf
+    with pytest.raises(PdhgError) as e:
+        pdhg.Solver(**{**bad, "val": v})
+    assert e.value.code == -2
+
+
+@pytest.mark.timeout(600)
+def test_step_parity_large_zipf_lp(pdhg, oracle_lib):
+    """Full-size sparse LP (m=1e6, n=2e6, Zipf columns): one iteration and the
+    scaling, in the layout and launch configuration the benchmark times."""
+    _say("case: step parity at full size m=1e6 n=2e6 (generation + oracle take ~1 min)")
+    lp = gen.large_zipf_lp(seed=1000)
+    _say(f"  generated nnz={lp.nnz}")
+    _step_case(pdhg, oracle_lib, lp, seeds=(0,), ks=(7,), compare_eta=False)
