@@ -170,6 +170,16 @@ pdhg_err pdhg_debug_step(pdhg_handle *h, const double *x, const double *y,
                          double sigma, double *xhat, double *yhat, double *xnew,
                          double *ynew);
 
+/* Exactly one rAPDHG iteration (Algorithm 2) in the SCALED space, original
+ * variable order, for a handle with a quadratic term: from (x, y) and the
+ * averages (xbar, ybar) with inner counter k and primal weight omega
+ * (beta_k = theta_k = 2/(k+2), 1/tau_k = omega/eta + 2 ||Q~||_2/(k+1),
+ * sigma = eta omega), writes the new iterate (xn, yn) and averages (xbarn,
+ * ybarn). Device pointers; outputs may be NULL. UNSUPPORTED for LP handles. */
+pdhg_err pdhg_debug_qp_step(pdhg_handle *h, const double *x, const double *y,
+                            const double *xbar, const double *ybar, int64_t k, double omega,
+                            double *xn, double *yn, double *xbarn, double *ybarn);
+
 /* Scaling of Section 3 in the original order: D_r [m], D_c [n] (device
  * pointers, may be NULL) with A~ = D_r A D_c; scalars (host pointer to 4
  * doubles, may be NULL): eta, initial omega, ||A~||_2 estimate, ||Q~||_2
@@ -179,6 +189,88 @@ pdhg_err pdhg_get_scaling(pdhg_handle *h, double *dr, double *dc, double *scalar
 
 /* Release everything the handle owns. NULL is ignored. */
 void pdhg_destroy(pdhg_handle *h);
+
+/* ---------------------------------------------------------------------------
+ * Batched LPs (Section 3, "Batched solving"): many independent LPs solved in
+ * one persistent launch. Every instance runs its own r2HPDHG: own scaling
+ * (shared when A is shared, since it depends on A only), step size, primal
+ * weight, restarts and early exit, exactly as pdhg_solve would on that
+ * instance alone.
+ *
+ * shared_a = 1: all B instances use one A (m x n, CSR); per-instance vectors
+ *   are instance-major: c, lv, uv [B*n], lc, uc [B*m].
+ * shared_a = 0 (ragged): instance b owns rows [row_off[b], row_off[b+1]) and
+ *   columns [col_off[b], col_off[b+1]) of one block-diagonal CSR (m = total
+ *   rows, n = total columns, global column indices that must stay inside the
+ *   instance's column range); vectors are concatenated: c, lv, uv [n],
+ *   lc, uc [m].
+ */
+typedef struct {
+    int32_t batch;
+    int32_t shared_a;
+    int32_t m, n;
+    const int32_t *a_rowptr;
+    const int32_t *a_colidx;
+    const double *a_val;
+    int64_t a_nnz;
+    const int32_t *row_off, *col_off;   /* [batch+1] (ragged only) */
+    const double *c, *lc, *uc, *lv, *uv;
+    int32_t mem;                        /* PDHG_MEM_HOST or PDHG_MEM_DEVICE */
+} pdhg_batch_problem;
+
+typedef struct pdhg_batch pdhg_batch;
+
+/* Copy the batch, scale every instance and estimate its step size (one
+ * persistent launch). iteration_limit must be finite (at most 10^7) so that
+ * every workgroup of the persistent kernels ends. Errors as pdhg_create. */
+pdhg_err pdhg_batch_create(const pdhg_batch_problem *prob, const pdhg_options *opt,
+                           void *stream, pdhg_batch **out);
+
+/* Solve all instances in one persistent launch. x_init / y_init: optional
+ * warm starts laid out like c / lc (device pointers, may be NULL). x_out,
+ * y_out: device pointers laid out like c / lc. res: HOST array of `batch`
+ * results, may be NULL. */
+pdhg_err pdhg_batch_solve(pdhg_batch *b, const double *x_init, const double *y_init,
+                          double *x_out, double *y_out, pdhg_result *res);
+
+/* Launch shape of the persistent kernels: threads per instance (64, 128,
+ * 256, 512 or 1024) and the number of resident workgroups (<= 0: as many as
+ * the GPU holds). */
+pdhg_err pdhg_batch_set_launch(pdhg_batch *b, int32_t threads, int32_t workgroups);
+
+/* Time `iterations` iterations of every instance for each supported thread
+ * count and keep the fastest (written to *best_threads, may be NULL). The
+ * solver state is reset afterwards. */
+pdhg_err pdhg_batch_autotune(pdhg_batch *b, int32_t iterations, int32_t *best_threads);
+
+/* Replace the per-instance vectors (device pointers laid out as at create,
+ * NULL keeps the current one). Scaling and step sizes stay (they depend on A
+ * only); the initial primal weight is recomputed at the next solve. */
+pdhg_err pdhg_batch_update_data(pdhg_batch *b, const double *c, const double *lc,
+                                const double *uc, const double *lv, const double *uv);
+
+/* Differentiation by unrolling (Section 3 "Auto-differentiation"), LP
+ * batches: every instance runs exactly T iterations from zero with no
+ * termination test. replay = 0: restart and primal-weight decisions come
+ * from the regular tests and are recorded; replay = 1: the recorded schedule
+ * of the last replay = 0 call with the same T is reused (so the map from c
+ * and the row bounds to the output is piecewise affine and finite
+ * differences through it are meaningful). The projection state of every
+ * iteration is kept as bits for the reverse pass. x_out, y_out: the PDHG
+ * point of iteration T-1 in the original space (device, laid out like c /
+ * lc). T in [1, 10^6]. */
+pdhg_err pdhg_batch_unrolled_forward(pdhg_batch *b, int64_t T, int32_t replay, double *x_out,
+                                     double *y_out);
+
+/* Reverse pass of the last unrolled forward: given cotangents gx (like c) and
+ * gy (like lc, NULL = 0) of its outputs, writes the gradients with respect to
+ * the original c (gc) and row bounds (glc, guc; 0 for infinite bounds; NULL
+ * skips them). Two sparse products per reversed iteration. Device pointers. */
+pdhg_err pdhg_batch_unrolled_backward(pdhg_batch *b, const double *gx, const double *gy,
+                                      double *gc, double *glc, double *guc);
+
+/* Release everything the batch owns. NULL is ignored. */
+void pdhg_batch_destroy(pdhg_batch *b);
 
 #ifdef __cplusplus
 }

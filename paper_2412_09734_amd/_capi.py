@@ -57,6 +57,13 @@ class Result(C.Structure):
         return d
 
 
+class BatchProblem(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("shared_a", C.c_int32), ("m", C.c_int32), ("n", C.c_int32),
+                ("a_rowptr", P), ("a_colidx", P), ("a_val", P), ("a_nnz", C.c_int64),
+                ("row_off", P), ("col_off", P),
+                ("c", P), ("lc", P), ("uc", P), ("lv", P), ("uv", P), ("mem", C.c_int32)]
+
+
 # every symbol include/pdhg.h declares, with its ctypes signature
 SIGNATURES = {
     "pdhg_options_default": (None, [C.POINTER(Options)]),
@@ -67,7 +74,16 @@ SIGNATURES = {
     "pdhg_update_data": (C.c_int, [P, P, P, P, P, P]),
     "pdhg_debug_step": (C.c_int, [P, P, P, P, P, C.c_int64, C.c_double, C.c_double, P, P, P, P]),
     "pdhg_get_scaling": (C.c_int, [P, P, P, P, P]),
+    "pdhg_debug_qp_step": (C.c_int, [P, P, P, P, P, C.c_int64, C.c_double, P, P, P, P]),
     "pdhg_destroy": (None, [P]),
+    "pdhg_batch_create": (C.c_int, [C.POINTER(BatchProblem), C.POINTER(Options), P, C.POINTER(P)]),
+    "pdhg_batch_solve": (C.c_int, [P, P, P, P, P, P]),
+    "pdhg_batch_set_launch": (C.c_int, [P, C.c_int32, C.c_int32]),
+    "pdhg_batch_autotune": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int32)]),
+    "pdhg_batch_update_data": (C.c_int, [P, P, P, P, P, P]),
+    "pdhg_batch_unrolled_forward": (C.c_int, [P, C.c_int64, C.c_int32, P, P]),
+    "pdhg_batch_unrolled_backward": (C.c_int, [P, P, P, P, P, P]),
+    "pdhg_batch_destroy": (None, [P]),
 }
 
 _lib = None

@@ -48,18 +48,20 @@ static pdhg_err guarded(F &&f) {
     }
 }
 
-static double now_s() {
+double now_seconds() {
     using clk = std::chrono::steady_clock;
     return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
 }
+static double now_s() { return now_seconds(); }
 
-// Make h.stream wait for the work already queued on the caller's stream.
-static void order_after(Handle &h, void *caller) {
-    PDHG_HIP(hipEventRecord(h.ev_in, reinterpret_cast<hipStream_t>(caller)));
-    PDHG_HIP(hipStreamWaitEvent(h.stream, h.ev_in, 0));
+// Make `own` wait for the work already queued on the caller's stream.
+void order_after_stream(hipStream_t own, hipEvent_t ev, void *caller) {
+    PDHG_HIP(hipEventRecord(ev, reinterpret_cast<hipStream_t>(caller)));
+    PDHG_HIP(hipStreamWaitEvent(own, ev, 0));
 }
+static void order_after(Handle &h, void *caller) { order_after_stream(h.stream, h.ev_in, caller); }
 
-static void check_options(const pdhg_options &o) {
+void check_options(const pdhg_options &o) {
     if (!(o.eps > 0.0) || o.iteration_limit < 1 || o.check_every < 1 || o.ruiz_iters < 0 ||
         !(o.gamma >= 0.0 && o.gamma <= 1.0) || !(o.step_safety > 0.0 && o.step_safety <= 1.0) ||
         o.power_max_iters < 1 || !(o.power_tol >= 0.0) || o.display_frequency < 1)
@@ -67,6 +69,10 @@ static void check_options(const pdhg_options &o) {
 }
 
 static void enqueue_check(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t last_status) {
+    if (h.q_kind) {
+        launch_qp_check(h, chunk_plain, is_last, last_status);
+        return;
+    }
     launch_primal_check(h);
     launch_dual_check(h);
     launch_check_sums(h);
@@ -75,6 +81,10 @@ static void enqueue_check(Handle &h, int32_t chunk_plain, int32_t is_last, int32
 }
 
 static void enqueue_plain(Handle &h, int32_t j) {
+    if (h.q_kind) {
+        launch_qp_iteration(h, j);
+        return;
+    }
     launch_primal(h, j);
     launch_dual(h, j);
 }
@@ -105,6 +115,7 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
     hipStream_t s = h.stream;
     launch_reset_state(h);
     launch_init_point(h, x_init, y_init);
+    if (h.q_kind) launch_qp_init(h);
     const int32_t C = h.opt.check_every;
     const int64_t L = h.opt.iteration_limit;
     if (h.opt.use_graph) build_graph(h);
@@ -134,7 +145,7 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
             } else {
                 plain = std::min<int64_t>(C - 1, L - 2 - t);
                 const bool timed = h.opt.timing_chunk >= 0 && chunk == h.opt.timing_chunk &&
-                                   plain == C - 1 && tev.empty();
+                                   plain == C - 1 && tev.empty() && !h.q_kind;
                 if (plain == C - 1 && h.opt.use_graph && !timed) {
                     PDHG_HIP(hipGraphLaunch(h.chunk_exec, s));
                 } else {
@@ -145,11 +156,15 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
                         timing_t = t;
                     }
                     for (int32_t j = 1; j <= plain; ++j) {
-                        if (timed) PDHG_HIP(hipEventRecord(tev[3 * (j - 1)], s));
+                        if (!timed) {
+                            enqueue_plain(h, j);
+                            continue;
+                        }
+                        PDHG_HIP(hipEventRecord(tev[3 * (j - 1)], s));
                         launch_primal(h, j);
-                        if (timed) PDHG_HIP(hipEventRecord(tev[3 * (j - 1) + 1], s));
+                        PDHG_HIP(hipEventRecord(tev[3 * (j - 1) + 1], s));
                         launch_dual(h, j);
-                        if (timed) PDHG_HIP(hipEventRecord(tev[3 * (j - 1) + 2], s));
+                        PDHG_HIP(hipEventRecord(tev[3 * (j - 1) + 2], s));
                     }
                 }
             }
@@ -187,7 +202,10 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
     }
     DevState fin;
     PDHG_HIP(hipMemcpy(&fin, h.st.p, sizeof(DevState), hipMemcpyDeviceToHost));
-    launch_finalize(h, x_out, y_out);
+    if (h.q_kind)
+        launch_qp_finalize(h, x_out, y_out);
+    else
+        launch_finalize(h, x_out, y_out);
     PDHG_HIP(hipStreamSynchronize(s));
     if (h.opt.verbose) print_check(fin);
     double kp = 0.0, kd = 0.0;
@@ -277,8 +295,9 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
             fail(PDHG_ERR_INVALID_ARG, "mem must be PDHG_MEM_HOST or PDHG_MEM_DEVICE");
         if (p.a_format != PDHG_FMT_CSR)
             fail(PDHG_ERR_UNSUPPORTED, "only CSR constraint matrices are supported by pdhg_create");
-        if (p.q_format != PDHG_FMT_NONE)
-            fail(PDHG_ERR_UNSUPPORTED, "quadratic objectives are not supported by this entry point");
+        if (p.q_format != PDHG_FMT_NONE && p.q_format != PDHG_FMT_CSR &&
+            p.q_format != PDHG_FMT_DENSE && p.q_format != PDHG_FMT_LOWRANK_DIAG)
+            fail(PDHG_ERR_INVALID_ARG, "unknown q_format");
         if (!p.a_rowptr || (p.a_nnz > 0 && (!p.a_colidx || !p.a_val)) || p.a_nnz < 0 ||
             p.a_nnz >= INT32_MAX)
             fail(PDHG_ERR_INVALID_ARG, "bad CSR arrays or nnz");
@@ -299,14 +318,18 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
         PDHG_HIP(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
         PDHG_HIP(hipEventCreateWithFlags(&h.ev_in, hipEventDisableTiming));
         order_after(h, stream);
+        h.st.alloc(1);
         build_matrices(h, p);
         validate_and_load_vectors(h, p);
         scale_problem(h);
         estimate_steps(h);
         compute_weight(h);
+        if (p.q_format != PDHG_FMT_NONE) {
+            qp_build(h, p);
+            qp_estimate_norm(h);
+        }
         h.pn.alloc((size_t)std::max(1, h.AT.nblocks()) * 6);
         h.pm.alloc((size_t)std::max(1, h.A.nblocks()) * 4);
-        h.st.alloc(1);
         PDHG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h.st_host),
                                sizeof(DevState) * h.st_ring, hipHostMallocDefault));
         memset(h.st_host, 0, sizeof(DevState) * h.st_ring);
@@ -372,6 +395,7 @@ pdhg_err pdhg_debug_step(pdhg_handle *ph, const double *x, const double *y, cons
         if (!(tau > 0.0) || !(sigma > 0.0) || k < 0)
             fail(PDHG_ERR_INVALID_ARG, "tau, sigma must be > 0 and k >= 0");
         Handle &h = ph->h;
+        if (h.q_kind) fail(PDHG_ERR_UNSUPPORTED, "pdhg_debug_step is for LP handles");
         hipStream_t s = h.stream;
         launch_reset_state(h);
         launch_gather(s, h.perm_c.p, x, h.x.p, h.n);
@@ -388,6 +412,29 @@ pdhg_err pdhg_debug_step(pdhg_handle *ph, const double *x, const double *y, cons
         if (yhat) launch_scatter(s, h.perm_r.p, h.yhat.p, yhat, h.m);
         if (xnew) launch_scatter(s, h.perm_c.p, xn.p, xnew, h.n);
         if (ynew) launch_scatter(s, h.perm_r.p, yn.p, ynew, h.m);
+        PDHG_HIP(hipStreamSynchronize(s));
+    });
+}
+
+pdhg_err pdhg_debug_qp_step(pdhg_handle *ph, const double *x, const double *y,
+                            const double *xbar, const double *ybar, int64_t k, double omega,
+                            double *xn, double *yn, double *xbarn, double *ybarn) {
+    return guarded([&] {
+        if (!ph || !x || !xbar || (ph->h.m > 0 && (!y || !ybar)))
+            fail(PDHG_ERR_INVALID_ARG, "NULL handle or state pointer");
+        if (!(omega > 0.0) || k < 0) fail(PDHG_ERR_INVALID_ARG, "omega must be > 0 and k >= 0");
+        Handle &h = ph->h;
+        if (!h.q_kind) fail(PDHG_ERR_UNSUPPORTED, "pdhg_debug_qp_step is for QP handles");
+        hipStream_t s = h.stream;
+        launch_gather(s, h.perm_c.p, x, h.x.p, h.n);
+        launch_gather(s, h.perm_c.p, xbar, h.xbar.p, h.n);
+        launch_gather(s, h.perm_r.p, y, h.y.p, h.m);
+        launch_gather(s, h.perm_r.p, ybar, h.ybar.p, h.m);
+        launch_qp_debug_step(h, k, omega);
+        if (xn) launch_scatter(s, h.perm_c.p, h.x.p, xn, h.n);
+        if (yn) launch_scatter(s, h.perm_r.p, h.y.p, yn, h.m);
+        if (xbarn) launch_scatter(s, h.perm_c.p, h.xbar.p, xbarn, h.n);
+        if (ybarn) launch_scatter(s, h.perm_r.p, h.ybar.p, ybarn, h.m);
         PDHG_HIP(hipStreamSynchronize(s));
     });
 }
@@ -414,6 +461,79 @@ void pdhg_destroy(pdhg_handle *ph) {
     if (!ph) return;
     (void)hipStreamSynchronize(ph->h.stream);
     delete ph;
+}
+
+struct pdhg_batch {
+    BatchHandle *b;
+};
+
+pdhg_err pdhg_batch_create(const pdhg_batch_problem *prob, const pdhg_options *opt, void *stream,
+                           pdhg_batch **out) {
+    if (out) *out = nullptr;
+    return guarded([&] {
+        if (!prob || !out) fail(PDHG_ERR_INVALID_ARG, "NULL problem or output pointer");
+        pdhg_options o;
+        if (opt)
+            o = *opt;
+        else
+            pdhg_options_default(&o);
+        check_options(o);
+        BatchHandle *b = batch_create(*prob, o, stream);
+        *out = new pdhg_batch{b};
+    });
+}
+
+pdhg_err pdhg_batch_solve(pdhg_batch *pb, const double *x_init, const double *y_init,
+                          double *x_out, double *y_out, pdhg_result *res) {
+    return guarded([&] {
+        if (!pb || !x_out || !y_out) fail(PDHG_ERR_INVALID_ARG, "NULL batch or output pointer");
+        batch_solve(*pb->b, x_init, y_init, x_out, y_out, res);
+    });
+}
+
+pdhg_err pdhg_batch_set_launch(pdhg_batch *pb, int32_t threads, int32_t workgroups) {
+    return guarded([&] {
+        if (!pb) fail(PDHG_ERR_INVALID_ARG, "NULL batch");
+        batch_set_launch(*pb->b, threads, workgroups);
+    });
+}
+
+pdhg_err pdhg_batch_autotune(pdhg_batch *pb, int32_t iterations, int32_t *best_threads) {
+    return guarded([&] {
+        if (!pb || iterations < 1) fail(PDHG_ERR_INVALID_ARG, "NULL batch or iterations < 1");
+        const int32_t t = batch_autotune(*pb->b, iterations);
+        if (best_threads) *best_threads = t;
+    });
+}
+
+pdhg_err pdhg_batch_update_data(pdhg_batch *pb, const double *c, const double *lc,
+                                const double *uc, const double *lv, const double *uv) {
+    return guarded([&] {
+        if (!pb) fail(PDHG_ERR_INVALID_ARG, "NULL batch");
+        batch_update_data(*pb->b, c, lc, uc, lv, uv);
+    });
+}
+
+pdhg_err pdhg_batch_unrolled_forward(pdhg_batch *pb, int64_t T, int32_t replay, double *x_out,
+                                     double *y_out) {
+    return guarded([&] {
+        if (!pb || !x_out || !y_out) fail(PDHG_ERR_INVALID_ARG, "NULL batch or output pointer");
+        batch_unrolled_forward(*pb->b, T, replay, x_out, y_out);
+    });
+}
+
+pdhg_err pdhg_batch_unrolled_backward(pdhg_batch *pb, const double *gx, const double *gy,
+                                      double *gc, double *glc, double *guc) {
+    return guarded([&] {
+        if (!pb || !gx || !gc) fail(PDHG_ERR_INVALID_ARG, "NULL batch, gx or gc");
+        batch_backward(*pb->b, gx, gy, gc, glc, guc);
+    });
+}
+
+void pdhg_batch_destroy(pdhg_batch *pb) {
+    if (!pb) return;
+    batch_destroy(pb->b);
+    delete pb;
 }
 
 }  // extern "C"

@@ -1,0 +1,1256 @@
+// Batched r2HPDHG (MPAX paper, Section 3 "Batched solving"; Algorithm 1).
+//
+// One workgroup owns one LP instance at a time and runs its whole solve:
+// scaling and power iteration (setup kernel), then the iteration loop with
+// checks, restarts and early exit (solve kernel). Workgroups take instances
+// from a queue (an integer counter) until the batch is exhausted, so a launch
+// of as many workgroups as the GPU holds covers any batch size. Every
+// reduction is a fixed-order workgroup tree, so an instance's result does not
+// depend on which workgroup ran it.
+//
+// Matrices are plain CSR (rows in original order) with instance-local column
+// indices; row pointers hold global entry offsets. Per-instance vectors live
+// in HBM and stay in L2 while the instance runs.
+#include <algorithm>
+#include <climits>
+#include <memory>
+#include <vector>
+
+#include "device.hpp"
+
+namespace pdhg {
+
+struct BatchRes {
+    double pobj, dobj, rel_p, rel_d, rel_g, kkt, omega, eta;
+    int64_t iterations, restarts;
+    int32_t status, power_iters;
+};
+
+struct BOpts {
+    double eps, gamma, step_safety, beta_suff, beta_nec, beta_art, power_tol;
+    int64_t limit;
+    int32_t check_every, ruiz_iters, pock_chambolle, power_max_iters;
+};
+
+struct BArgs {
+    int32_t B, shared, m, n;
+    const int32_t *row_off, *col_off;
+    const int32_t *arp, *aci;
+    double *ava;
+    const int32_t *trp, *tci;
+    double *tva;
+    double *Dr, *Dc, *eta;
+    int32_t *power_iters;
+    const double *c_o, *lc_o, *uc_o, *lv_o, *uv_o;
+    double *c, *lc, *uc, *lv, *uv;
+    double *x, *x0, *xh, *xe, *aty, *y, *y0, *yh;
+    const double *x_init, *y_init;
+    double *x_out, *y_out;
+    BatchRes *res;
+    int32_t *queue;
+};
+
+// Geometry of instance b: matrix rows start at r0 (A) / c0 (A'); vectors at
+// vr / vc; scaling vectors at dr / dc.
+struct Geo {
+    int32_t m, n, r0, c0, vr, vc, dr, dc, sidx;
+};
+
+__device__ __forceinline__ Geo geometry(const BArgs &a, int32_t b) {
+    Geo g;
+    if (a.shared) {
+        g.m = a.m;
+        g.n = a.n;
+        g.r0 = 0;
+        g.c0 = 0;
+        g.vr = b * a.m;
+        g.vc = b * a.n;
+        g.dr = 0;
+        g.dc = 0;
+        g.sidx = 0;
+    } else {
+        g.r0 = a.row_off[b];
+        g.c0 = a.col_off[b];
+        g.m = a.row_off[b + 1] - g.r0;
+        g.n = a.col_off[b + 1] - g.c0;
+        g.vr = g.r0;
+        g.vc = g.c0;
+        g.dr = g.r0;
+        g.dc = g.c0;
+        g.sidx = b;
+    }
+    return g;
+}
+
+template <int BT, int K>
+__device__ __forceinline__ void wg_sum(double (&v)[K]) {
+    constexpr int NW = BT / 64;
+    __shared__ double sh[K][NW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) sh[q][wave] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += sh[q][w];
+        v[q] = s;
+    }
+    __syncthreads();
+}
+
+template <int BT>
+__device__ __forceinline__ int32_t next_instance(int32_t *queue) {
+    __shared__ int32_t id;
+    if (threadIdx.x == 0) id = atomicAdd(queue, 1);
+    __syncthreads();
+    const int32_t r = id;
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double csr_dot(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                          const double *__restrict__ va, int32_t row,
+                                          const double *__restrict__ v) {
+    double acc = 0.0;
+    const int32_t e1 = rp[row + 1];
+    for (int32_t e = rp[row]; e < e1; ++e) acc = fma(va[e], v[ci[e]], acc);
+    return acc;
+}
+
+__device__ __forceinline__ uint64_t splitmix64_b(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// setup: Ruiz + Pock-Chambolle scaling and the power iteration, per instance
+// (once for a shared matrix).
+
+template <int BT>
+__global__ __launch_bounds__(BT) void k_batch_setup(BArgs a, BOpts o, int32_t count) {
+    for (;;) {
+        const int32_t b = next_instance<BT>(a.queue);
+        if (b >= count) return;
+        const Geo g = geometry(a, b);
+        const int32_t *arp = a.arp + g.r0, *trp = a.trp + g.c0;
+        double *Dr = a.Dr + g.dr, *Dc = a.Dc + g.dc;
+        double *rs = a.yh + g.vr, *cs = a.xh + g.vc;   // factor scratch
+        for (int32_t i = threadIdx.x; i < g.m; i += BT) Dr[i] = 1.0;
+        for (int32_t j = threadIdx.x; j < g.n; j += BT) Dc[j] = 1.0;
+        const int passes = o.ruiz_iters + (o.pock_chambolle ? 1 : 0);
+        for (int pass = 0; pass < passes; ++pass) {
+            const bool pc = pass >= o.ruiz_iters;
+            __syncthreads();
+            for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+                double acc = 0.0;
+                for (int32_t e = arp[i]; e < arp[i + 1]; ++e)
+                    acc = pc ? acc + fabs(a.ava[e]) : fmax(acc, fabs(a.ava[e]));
+                rs[i] = acc > 0.0 ? sqrt(acc) : 1.0;
+            }
+            for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                double acc = 0.0;
+                for (int32_t e = trp[j]; e < trp[j + 1]; ++e)
+                    acc = pc ? acc + fabs(a.tva[e]) : fmax(acc, fabs(a.tva[e]));
+                cs[j] = acc > 0.0 ? sqrt(acc) : 1.0;
+            }
+            __syncthreads();
+            for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+                Dr[i] = Dr[i] / rs[i];
+                for (int32_t e = arp[i]; e < arp[i + 1]; ++e)
+                    a.ava[e] = a.ava[e] / (rs[i] * cs[a.aci[e]]);
+            }
+            for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                Dc[j] = Dc[j] / cs[j];
+                for (int32_t e = trp[j]; e < trp[j + 1]; ++e)
+                    a.tva[e] = a.tva[e] / (rs[a.tci[e]] * cs[j]);
+            }
+        }
+        __syncthreads();
+        // power iteration on A~'A~ from the SplitMix64 start vector
+        int64_t nnz = (int64_t)arp[g.m] - arp[0];
+        double lam = 0.0;
+        int32_t it = 0;
+        if (g.m > 0 && nnz > 0) {
+            double *v = a.xh + g.vc, *w = a.yh + g.vr, *u = a.xe + g.vc;
+            double q[1] = {0.0};
+            for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                const double val = 0.5 + (double)(splitmix64_b((uint64_t)j) >> 11) * 0x1.0p-53;
+                v[j] = val;
+                q[0] += val * val;
+            }
+            wg_sum<BT, 1>(q);
+            const double nv = sqrt(q[0]);
+            for (int32_t j = threadIdx.x; j < g.n; j += BT) v[j] = v[j] / nv;
+            __syncthreads();
+            double lam_prev = 0.0;
+            for (it = 1; it <= o.power_max_iters; ++it) {
+                double sw[1] = {0.0};
+                for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+                    const double s = csr_dot(arp, a.aci, a.ava, i, v);
+                    w[i] = s;
+                    sw[0] += s * s;
+                }
+                wg_sum<BT, 1>(sw);
+                lam = sw[0];
+                double su[1] = {0.0};
+                for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                    const double s = csr_dot(trp, a.tci, a.tva, j, w);
+                    u[j] = s;
+                    su[0] += s * s;
+                }
+                wg_sum<BT, 1>(su);
+                const double nu = sqrt(su[0]);
+                if (!(nu > 0.0)) {
+                    lam = 0.0;
+                    break;
+                }
+                for (int32_t j = threadIdx.x; j < g.n; j += BT) v[j] = u[j] / nu;
+                __syncthreads();
+                if (it > 1 && fabs(lam - lam_prev) <= o.power_tol * lam) break;
+                lam_prev = lam;
+            }
+            if (it > o.power_max_iters) it = o.power_max_iters;
+        }
+        if (threadIdx.x == 0) {
+            const double na = sqrt(lam);
+            a.eta[g.sidx] = na > 0.0 ? o.step_safety / na : 1.0;
+            a.power_iters[g.sidx] = it;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// solve
+
+template <int BT>
+__global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
+    for (;;) {
+        const int32_t b = next_instance<BT>(a.queue);
+        if (b >= a.B) return;
+        const Geo g = geometry(a, b);
+        const int32_t *arp = a.arp + g.r0, *trp = a.trp + g.c0;
+        const int32_t *aci = a.aci, *tci = a.tci;
+        const double *ava = a.ava, *tva = a.tva;
+        const double *Dr = a.Dr + g.dr, *Dc = a.Dc + g.dc;
+        const double *c_o = a.c_o + g.vc, *lv_o = a.lv_o + g.vc, *uv_o = a.uv_o + g.vc;
+        const double *lc_o = a.lc_o + g.vr, *uc_o = a.uc_o + g.vr;
+        double *c = a.c + g.vc, *lv = a.lv + g.vc, *uv = a.uv + g.vc;
+        double *lc = a.lc + g.vr, *uc = a.uc + g.vr;
+        double *x = a.x + g.vc, *x0 = a.x0 + g.vc, *xh = a.xh + g.vc, *xe = a.xe + g.vc;
+        double *aty = a.aty + g.vc;
+        double *y = a.y + g.vr, *y0 = a.y0 + g.vr, *yh = a.yh + g.vr;
+        const double eta = a.eta[g.sidx];
+        const double gam = o.gamma;
+
+        // scaled data, norms, initial point
+        double nrm[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+            const double d = Dc[j];
+            const double cj = d * c_o[j];
+            c[j] = cj;
+            lv[j] = lv_o[j] / d;
+            uv[j] = uv_o[j] / d;
+            nrm[0] += cj * cj;
+            nrm[2] += c_o[j] * c_o[j];
+        }
+        for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+            const double d = Dr[i];
+            const double l = d * lc_o[i], u = d * uc_o[i];
+            lc[i] = l;
+            uc[i] = u;
+            double bb = 0.0, bo = 0.0;
+            if (isfinite(l)) bb = fmax(bb, fabs(l));
+            if (isfinite(u)) bb = fmax(bb, fabs(u));
+            if (isfinite(lc_o[i])) bo = fmax(bo, fabs(lc_o[i]));
+            if (isfinite(uc_o[i])) bo = fmax(bo, fabs(uc_o[i]));
+            nrm[1] += bb * bb;
+            nrm[3] += bo * bo;
+        }
+        wg_sum<BT, 4>(nrm);
+        const double cn = sqrt(nrm[0]), bn = sqrt(nrm[1]);
+        const double cnorm = sqrt(nrm[2]), bnorm = sqrt(nrm[3]);
+        double omega = (cn > 1e-10 && bn > 1e-10) ? cn / bn : 1.0;
+        double tau = eta / omega, sigma = eta * omega;
+        for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+            const double v0 = a.x_init ? a.x_init[g.vc + j] / Dc[j] : 0.0;
+            const double xv = clampd(v0, lv[j], uv[j]);
+            x[j] = xv;
+            x0[j] = xv;
+        }
+        for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+            const double v0 = a.y_init ? a.y_init[g.vr + i] / Dr[i] : 0.0;
+            const double lo = isfinite(uc[i]) ? -INFINITY : 0.0;
+            const double hi = isfinite(lc[i]) ? INFINITY : 0.0;
+            const double yv = clampd(v0, lo, hi);
+            y[i] = yv;
+            y0[i] = yv;
+        }
+        __syncthreads();
+
+        int64_t t = 0, k = 0, restarts = 0;
+        double r_start = 0.0, r_prev = 0.0;
+        int32_t status = 0;
+        double kkt = 0.0, rel_p = 0.0, rel_d = 0.0, rel_g = 0.0, P = 0.0, D = 0.0;
+        for (;;) {
+            const bool check = (t % o.check_every) == 0;
+            const bool last = t + 1 >= o.limit;
+            const bool keep = check || last;
+            const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+            // primal step over the rows of A'
+            for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                const double s = csr_dot(trp, tci, tva, j, y);
+                const double xr = x[j];
+                const double xhat = clampd(xr - tau * (c[j] - s), lv[j], uv[j]);
+                xe[j] = 2.0 * xhat - xr;
+                if (keep) {
+                    xh[j] = xhat;
+                    aty[j] = s;
+                } else {
+                    x[j] = ak * ((1.0 + gam) * xhat - gam * xr) + bk * x0[j];
+                }
+            }
+            __syncthreads();
+            // dual step over the rows of A
+            for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+                const double av = csr_dot(arp, aci, ava, i, xe);
+                const double yr = y[i];
+                const double yhat = dual_prox(yr, av, sigma, lc[i], uc[i]);
+                if (keep)
+                    yh[i] = yhat;
+                else
+                    y[i] = ak * ((1.0 + gam) * yhat - gam * yr) + bk * y0[i];
+            }
+            __syncthreads();
+            if (!keep) {
+                ++k;
+                ++t;
+                continue;
+            }
+            // check: KKT in the original space and the fixed-point residual
+            double v[10];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) v[q] = 0.0;
+            for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                const double q = csr_dot(trp, tci, tva, j, yh);
+                const double xhv = xh[j];
+                const double dx = xhv - x[j];
+                v[0] += dx * dx;
+                v[1] += (q - aty[j]) * dx;
+                const double d0 = xhv - x0[j];
+                v[2] += d0 * d0;
+                const double d = Dc[j];
+                const double gr = c_o[j] - q / d;
+                const double lo = lv_o[j], hi = uv_o[j];
+                const bool lf = isfinite(lo), uf = isfinite(hi);
+                const double lam = (!lf && !uf) ? 0.0 : (lf && !uf) ? fmax(gr, 0.0) : (!lf && uf) ? fmin(gr, 0.0) : gr;
+                const double rd = gr - lam;
+                v[3] += rd * rd;
+                v[4] += c_o[j] * (d * xhv);
+                v[5] += (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
+            }
+            for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+                const double p = csr_dot(arp, aci, ava, i, xh);
+                const double d = Dr[i];
+                const double ax = p / d;
+                const double lo = lc_o[i], hi = uc_o[i];
+                const double rpr = ax - clampd(ax, lo, hi);
+                v[6] += rpr * rpr;
+                const double yhv = yh[i];
+                const double yo = d * yhv;
+                v[7] += (isfinite(lo) ? lo * fmax(yo, 0.0) : 0.0) - (isfinite(hi) ? hi * fmax(-yo, 0.0) : 0.0);
+                const double dy = yhv - y[i];
+                v[8] += dy * dy;
+                const double d0 = yhv - y0[i];
+                v[9] += d0 * d0;
+            }
+            wg_sum<BT, 10>(v);
+            P = v[4];
+            D = v[7] + v[5];
+            rel_p = sqrt(v[6]) / (1.0 + bnorm);
+            rel_d = sqrt(v[3]) / (1.0 + cnorm);
+            rel_g = fabs(P - D) / (1.0 + fabs(P) + fabs(D));
+            kkt = rel_p;
+            if (rel_d > kkt || isnan(rel_d)) kkt = rel_d;
+            if (rel_g > kkt || isnan(rel_g)) kkt = rel_g;
+            if (isnan(kkt)) {
+                status = PDHG_NUMERICAL_ERROR;
+                break;
+            }
+            if (kkt <= o.eps) {
+                status = PDHG_OPTIMAL;
+                break;
+            }
+            if (last) {
+                status = PDHG_ITERATION_LIMIT;
+                break;
+            }
+            const double r2 = v[0] / tau + v[8] / sigma + 2.0 * v[1];
+            const double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+            bool restart = false;
+            if (t == 0) {
+                r_start = r;
+                r_prev = r;
+            } else if (r <= o.beta_suff * r_start || (r <= o.beta_nec * r_start && r > r_prev) ||
+                       (double)k >= o.beta_art * (double)t) {
+                restart = true;
+            } else {
+                r_prev = r;
+            }
+            if (restart) {
+                const double dxr = sqrt(v[2]), dyr = sqrt(v[9]);
+                if (dxr > 1e-10 && dyr > 1e-10) omega = exp(0.5 * log(dyr / dxr) + 0.5 * log(omega));
+                tau = eta / omega;
+                sigma = eta * omega;
+                for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                    x[j] = xh[j];
+                    x0[j] = xh[j];
+                }
+                for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+                    y[i] = yh[i];
+                    y0[i] = yh[i];
+                }
+                k = 0;
+                r_start = r;
+                r_prev = r;
+                ++restarts;
+            } else {
+                for (int32_t j = threadIdx.x; j < g.n; j += BT)
+                    x[j] = ak * ((1.0 + gam) * xh[j] - gam * x[j]) + bk * x0[j];
+                for (int32_t i = threadIdx.x; i < g.m; i += BT)
+                    y[i] = ak * ((1.0 + gam) * yh[i] - gam * y[i]) + bk * y0[i];
+                ++k;
+            }
+            ++t;
+            __syncthreads();
+        }
+        // original-space output of the last PDHG point
+        for (int32_t j = threadIdx.x; j < g.n; j += BT) a.x_out[g.vc + j] = Dc[j] * xh[j];
+        for (int32_t i = threadIdx.x; i < g.m; i += BT) a.y_out[g.vr + i] = Dr[i] * yh[i];
+        if (threadIdx.x == 0) {
+            BatchRes r;
+            r.pobj = P;
+            r.dobj = D;
+            r.rel_p = rel_p;
+            r.rel_d = rel_d;
+            r.rel_g = rel_g;
+            r.kkt = kkt;
+            r.omega = omega;
+            r.eta = eta;
+            r.iterations = t + 1;
+            r.restarts = restarts;
+            r.status = status;
+            r.power_iters = a.power_iters[g.sidx];
+            a.res[b] = r;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// unrolled iterations with a frozen schedule, and their reverse pass
+
+struct UArgs {
+    int64_t T;
+    int32_t replay;                       // 1: take restarts / weights from the schedule
+    uint8_t *restart;                     // [B][T]
+    double *omega;                        // [B][T]
+    int32_t *kk;                          // [B][T]
+    uint64_t *xmask, *ymask;              // bit-packed projection states
+    const int64_t *xm_off, *ym_off;       // per-instance word offsets
+    const double *gx, *gy;                // cotangents of the outputs
+    double *gc, *glc, *guc;               // gradients (original space)
+    double *ba;                           // scratch, like lc
+};
+
+// Exactly T iterations of Algorithm 1 per instance. Restart tests run at the
+// check cadence (no termination test) unless replayed; every iteration
+// records omega, k, the restart flag, the set of x inside its box and the
+// clamp state of every row (bit 0: at -u_c, bit 1: at -l_c).
+template <int BT>
+__global__ __launch_bounds__(BT) void k_batch_unrolled(BArgs a, BOpts o, UArgs u) {
+    for (;;) {
+        const int32_t b = next_instance<BT>(a.queue);
+        if (b >= a.B) return;
+        const Geo g = geometry(a, b);
+        const int32_t *arp = a.arp + g.r0, *trp = a.trp + g.c0;
+        const int32_t *aci = a.aci, *tci = a.tci;
+        const double *ava = a.ava, *tva = a.tva;
+        const double *Dr = a.Dr + g.dr, *Dc = a.Dc + g.dc;
+        const double *c_o = a.c_o + g.vc, *lv_o = a.lv_o + g.vc, *uv_o = a.uv_o + g.vc;
+        const double *lc_o = a.lc_o + g.vr, *uc_o = a.uc_o + g.vr;
+        double *c = a.c + g.vc, *lv = a.lv + g.vc, *uv = a.uv + g.vc;
+        double *lc = a.lc + g.vr, *uc = a.uc + g.vr;
+        double *x = a.x + g.vc, *x0 = a.x0 + g.vc, *xh = a.xh + g.vc, *xe = a.xe + g.vc;
+        double *aty = a.aty + g.vc;
+        double *y = a.y + g.vr, *y0 = a.y0 + g.vr, *yh = a.yh + g.vr;
+        uint8_t *rs_ = u.restart + (size_t)b * u.T;
+        double *om_ = u.omega + (size_t)b * u.T;
+        int32_t *kk_ = u.kk + (size_t)b * u.T;
+        uint64_t *xm = u.xmask + u.xm_off[b], *ym = u.ymask + u.ym_off[b];
+        const int32_t xw = (g.n + 63) >> 6, yw = (g.m + 63) >> 6;
+        const double eta = a.eta[g.sidx];
+        const double gam = o.gamma;
+        double nrm[2] = {0.0, 0.0};
+        for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+            const double d = Dc[j];
+            const double cj = d * c_o[j];
+            c[j] = cj;
+            lv[j] = lv_o[j] / d;
+            uv[j] = uv_o[j] / d;
+            nrm[0] += cj * cj;
+        }
+        for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+            const double d = Dr[i];
+            const double l = d * lc_o[i], uu = d * uc_o[i];
+            lc[i] = l;
+            uc[i] = uu;
+            double bb = 0.0;
+            if (isfinite(l)) bb = fmax(bb, fabs(l));
+            if (isfinite(uu)) bb = fmax(bb, fabs(uu));
+            nrm[1] += bb * bb;
+        }
+        wg_sum<BT, 2>(nrm);
+        const double cn = sqrt(nrm[0]), bn = sqrt(nrm[1]);
+        double omega = (cn > 1e-10 && bn > 1e-10) ? cn / bn : 1.0;
+        for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+            const double xv = clampd(0.0, lv[j], uv[j]);
+            x[j] = xv;
+            x0[j] = xv;
+        }
+        for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+            const double lo = isfinite(uc[i]) ? -INFINITY : 0.0;
+            const double hi = isfinite(lc[i]) ? INFINITY : 0.0;
+            const double yv = clampd(0.0, lo, hi);
+            y[i] = yv;
+            y0[i] = yv;
+        }
+        __syncthreads();
+        int64_t k = 0;
+        double r_start = 0.0, r_prev = 0.0;
+        for (int64_t t = 0; t < u.T; ++t) {
+            if (u.replay) omega = om_[t];
+            const double tau = eta / omega, sigma = eta * omega;
+            const bool last = t + 1 >= u.T;
+            const bool check = !u.replay && (t % o.check_every) == 0 && !last;
+            const bool keep = true;   // restart decisions need the PDHG point
+            const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+            (void)keep;
+            uint64_t *xmt = xm + (size_t)t * xw;
+            uint64_t *ymt = ym + (size_t)t * 2 * yw;
+            for (int32_t j0 = 0; j0 < g.n; j0 += BT) {
+                const int32_t j = j0 + (int32_t)threadIdx.x;
+                bool inside = false;
+                if (j < g.n) {
+                    const double s = csr_dot(trp, tci, tva, j, y);
+                    const double xr = x[j];
+                    const double uu = xr - tau * (c[j] - s);
+                    inside = uu > lv[j] && uu < uv[j];
+                    const double xhat = clampd(uu, lv[j], uv[j]);
+                    xe[j] = 2.0 * xhat - xr;
+                    xh[j] = xhat;
+                    aty[j] = s;
+                }
+                const uint64_t bits = __ballot(inside);
+                if ((threadIdx.x & 63) == 0 && j < g.n) xmt[j >> 6] = bits;
+            }
+            __syncthreads();
+            for (int32_t i0 = 0; i0 < g.m; i0 += BT) {
+                const int32_t i = i0 + (int32_t)threadIdx.x;
+                bool at_u = false, at_l = false;
+                if (i < g.m) {
+                    const double av = csr_dot(arp, aci, ava, i, xe);
+                    const double vv = y[i] / sigma - av;
+                    at_u = vv < -uc[i];
+                    at_l = vv > -lc[i];
+                    yh[i] = sigma * (vv - clampd(vv, -uc[i], -lc[i]));
+                }
+                const uint64_t bu = __ballot(at_u), bl = __ballot(at_l);
+                if ((threadIdx.x & 63) == 0 && i < g.m) {
+                    ymt[2 * (i >> 6)] = bu;
+                    ymt[2 * (i >> 6) + 1] = bl;
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                om_[t] = omega;
+                kk_[t] = (int32_t)k;
+            }
+            if (last) break;
+            bool restart = u.replay ? rs_[t] != 0 : false;
+            double v2[10];
+            if (check) {
+#pragma unroll
+                for (int q = 0; q < 10; ++q) v2[q] = 0.0;
+                for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                    const double dx = xh[j] - x[j];
+                    v2[0] += dx * dx;
+                    const double d0 = xh[j] - x0[j];
+                    v2[2] += d0 * d0;
+                }
+                for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+                    const double dy = yh[i] - y[i];
+                    v2[8] += dy * dy;
+                    const double d0 = yh[i] - y0[i];
+                    v2[9] += d0 * d0;
+                    // cross term dy' A~ dx
+                    double adx = 0.0;
+                    for (int32_t e = arp[i]; e < arp[i + 1]; ++e)
+                        adx = fma(ava[e], xh[aci[e]] - x[aci[e]], adx);
+                    v2[1] += dy * adx;
+                }
+                wg_sum<BT, 10>(v2);
+                const double r2 = v2[0] / tau + v2[8] / sigma + 2.0 * v2[1];
+                const double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+                if (t == 0) {
+                    r_start = r;
+                    r_prev = r;
+                } else if (r <= o.beta_suff * r_start || (r <= o.beta_nec * r_start && r > r_prev) ||
+                           (double)k >= o.beta_art * (double)t) {
+                    restart = true;
+                } else {
+                    r_prev = r;
+                }
+                if (restart) {
+                    const double dxr = sqrt(v2[2]), dyr = sqrt(v2[9]);
+                    if (dxr > 1e-10 && dyr > 1e-10) omega = exp(0.5 * log(dyr / dxr) + 0.5 * log(omega));
+                    r_start = r;
+                    r_prev = r;
+                }
+            }
+            if (threadIdx.x == 0 && !u.replay) rs_[t] = restart ? 1 : 0;
+            if (restart) {
+                for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                    x[j] = xh[j];
+                    x0[j] = xh[j];
+                }
+                for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+                    y[i] = yh[i];
+                    y0[i] = yh[i];
+                }
+                k = 0;
+            } else {
+                for (int32_t j = threadIdx.x; j < g.n; j += BT)
+                    x[j] = ak * ((1.0 + gam) * xh[j] - gam * x[j]) + bk * x0[j];
+                for (int32_t i = threadIdx.x; i < g.m; i += BT)
+                    y[i] = ak * ((1.0 + gam) * yh[i] - gam * y[i]) + bk * y0[i];
+                ++k;
+            }
+            __syncthreads();
+        }
+        if (u.replay == 0 && threadIdx.x == 0) rs_[u.T - 1] = 0;
+        for (int32_t j = threadIdx.x; j < g.n; j += BT) a.x_out[g.vc + j] = Dc[j] * xh[j];
+        for (int32_t i = threadIdx.x; i < g.m; i += BT) a.y_out[g.vr + i] = Dr[i] * yh[i];
+        __syncthreads();
+    }
+}
+
+// Reverse pass of k_batch_unrolled with its recorded schedule and masks.
+template <int BT>
+__global__ __launch_bounds__(BT) void k_batch_backward(BArgs a, BOpts o, UArgs u) {
+    for (;;) {
+        const int32_t b = next_instance<BT>(a.queue);
+        if (b >= a.B) return;
+        const Geo g = geometry(a, b);
+        const int32_t *arp = a.arp + g.r0, *trp = a.trp + g.c0;
+        const int32_t *aci = a.aci, *tci = a.tci;
+        const double *ava = a.ava, *tva = a.tva;
+        const double *Dr = a.Dr + g.dr, *Dc = a.Dc + g.dc;
+        const uint8_t *rs_ = u.restart + (size_t)b * u.T;
+        const double *om_ = u.omega + (size_t)b * u.T;
+        const int32_t *kk_ = u.kk + (size_t)b * u.T;
+        const uint64_t *xm = u.xmask + u.xm_off[b], *ym = u.ymask + u.ym_off[b];
+        const int32_t xw = (g.n + 63) >> 6, yw = (g.m + 63) >> 6;
+        const double eta = a.eta[g.sidx];
+        const double gam = o.gamma;
+        // cotangents: bx, bx0, bxh (x, x0, xh), tmp (xe); by, by0, byh (y, y0, yh), ba
+        double *bx = a.x + g.vc, *bx0 = a.x0 + g.vc, *bxh = a.xh + g.vc, *tmp = a.xe + g.vc;
+        double *by = a.y + g.vr, *by0 = a.y0 + g.vr, *byh = a.yh + g.vr, *ba = u.ba + g.vr;
+        double *gc = u.gc + g.vc, *glc = u.glc + g.vr, *guc = u.guc + g.vr;
+        for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+            bx[j] = 0.0;
+            bx0[j] = 0.0;
+            bxh[j] = Dc[j] * u.gx[g.vc + j];
+            gc[j] = 0.0;
+        }
+        for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+            by[i] = 0.0;
+            by0[i] = 0.0;
+            byh[i] = Dr[i] * u.gy[g.vr + i];
+            glc[i] = 0.0;
+            guc[i] = 0.0;
+        }
+        __syncthreads();
+        for (int64_t t = u.T - 1; t >= 0; --t) {
+            const double omega = om_[t];
+            const double tau = eta / omega, sigma = eta * omega;
+            if (t < u.T - 1) {
+                if (rs_[t]) {
+                    for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                        bxh[j] = bx[j] + bx0[j];
+                        bx[j] = 0.0;
+                        bx0[j] = 0.0;
+                    }
+                    for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+                        byh[i] = by[i] + by0[i];
+                        by[i] = 0.0;
+                        by0[i] = 0.0;
+                    }
+                } else {
+                    const int64_t k = kk_[t];
+                    const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+                    for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                        const double v = bx[j];
+                        bxh[j] = ak * (1.0 + gam) * v;
+                        bx0[j] += bk * v;
+                        bx[j] = -ak * gam * v;
+                    }
+                    for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+                        const double v = by[i];
+                        byh[i] = ak * (1.0 + gam) * v;
+                        by0[i] += bk * v;
+                        by[i] = -ak * gam * v;
+                    }
+                }
+            }
+            // dual step: yhat = sigma (v - clamp(v, -u_c, -l_c)), v = y/sigma - A~ xext
+            const uint64_t *ymt = ym + (size_t)t * 2 * yw;
+            for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+                const uint64_t bit = 1ull << (i & 63);
+                const bool at_u = (ymt[2 * (i >> 6)] & bit) != 0;
+                const bool at_l = (ymt[2 * (i >> 6) + 1] & bit) != 0;
+                const double bv = (at_u || at_l) ? sigma * byh[i] : 0.0;
+                if (at_u) guc[i] += sigma * byh[i];
+                if (at_l) glc[i] += sigma * byh[i];
+                by[i] += bv / sigma;
+                ba[i] = -bv;
+            }
+            __syncthreads();
+            // xext = 2 xhat - x, then the primal step xhat = clamp(x - tau (c - A~'y))
+            const uint64_t *xmt = xm + (size_t)t * xw;
+            for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                const double bxe = csr_dot(trp, tci, tva, j, ba);
+                const double bh = bxh[j] + 2.0 * bxe;
+                bx[j] -= bxe;
+                const bool inside = (xmt[j >> 6] >> (j & 63)) & 1ull;
+                const double bu = inside ? bh : 0.0;
+                bx[j] += bu;
+                gc[j] += -tau * bu;
+                tmp[j] = tau * bu;
+            }
+            __syncthreads();
+            for (int32_t i = threadIdx.x; i < g.m; i += BT) by[i] += csr_dot(arp, aci, ava, i, tmp);
+            __syncthreads();
+        }
+        // c~ = D_c c, l~_c = D_r l_c, u~_c = D_r u_c
+        for (int32_t j = threadIdx.x; j < g.n; j += BT) gc[j] = Dc[j] * gc[j];
+        for (int32_t i = threadIdx.x; i < g.m; i += BT) {
+            glc[i] = isfinite(a.lc_o[g.vr + i]) ? Dr[i] * glc[i] : 0.0;
+            guc[i] = isfinite(a.uc_o[g.vr + i]) ? Dr[i] * guc[i] : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// layout kernels
+
+// Instance-local column indices of A and the row -> instance map check.
+__global__ __launch_bounds__(kBlock) void k_batch_localize(const int32_t *__restrict__ row_off,
+                                                           const int32_t *__restrict__ col_off,
+                                                           int32_t B, const int32_t *__restrict__ rowptr,
+                                                           int32_t *__restrict__ colidx,
+                                                           int32_t *__restrict__ flag) {
+    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (b >= B) return;
+    const int32_t c0 = col_off[b], c1 = col_off[b + 1];
+    if (row_off[b + 1] < row_off[b] || c1 <= c0) {
+        atomicOr(flag, 32);
+        return;
+    }
+    for (int32_t i = row_off[b]; i < row_off[b + 1]; ++i)
+        for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            const int32_t j = colidx[e];
+            if (j < c0 || j >= c1) atomicOr(flag, 64);
+            colidx[e] = j - c0;
+        }
+}
+
+// Column indices of A' (global rows) made instance-local.
+__global__ __launch_bounds__(kBlock) void k_batch_localize_t(const int32_t *__restrict__ row_off,
+                                                             const int32_t *__restrict__ col_off,
+                                                             int32_t B, const int32_t *__restrict__ trp,
+                                                             int32_t *__restrict__ tci) {
+    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (b >= B) return;
+    const int32_t r0 = row_off[b];
+    for (int32_t j = col_off[b]; j < col_off[b + 1]; ++j)
+        for (int32_t e = trp[j]; e < trp[j + 1]; ++e) tci[e] -= r0;
+}
+
+}  // namespace pdhg
+
+// ---------------------------------------------------------------------------
+// host side
+
+namespace pdhg {
+
+struct BatchHandle {
+    int32_t B = 0, shared = 0, m = 0, n = 0;   // shared: per-instance m, n; ragged: totals
+    int64_t nnz = 0;
+    int32_t vec_m = 0, vec_n = 0;              // lengths of the row / column vectors
+    pdhg_options opt{};
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    DBuf<int32_t> row_off, col_off, arp, aci, trp, tci, power_iters, queue;
+    DBuf<double> ava, tva, Dr, Dc, eta;
+    DBuf<double> c_o, lc_o, uc_o, lv_o, uv_o, c, lc, uc, lv, uv;
+    DBuf<double> x, x0, xh, xe, aty, y, y0, yh;
+    DBuf<BatchRes> res;
+    int32_t threads = 256;
+    int32_t workgroups = 0;
+    double setup_seconds = 0.0;
+    const double *x_init_ = nullptr, *y_init_ = nullptr;
+    double *x_out_ = nullptr, *y_out_ = nullptr;
+    std::vector<int32_t> row_off_h, col_off_h;
+    // unrolled iterations: schedule, masks and reverse-pass scratch
+    int64_t unrolled_T = 0;
+    DBuf<uint8_t> u_restart;
+    DBuf<double> u_omega, u_ba;
+    DBuf<int32_t> u_kk;
+    DBuf<uint64_t> u_xmask, u_ymask;
+    DBuf<int64_t> u_xoff, u_yoff;
+    ~BatchHandle() {
+        if (ev) (void)hipEventDestroy(ev);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+static BOpts batch_opts(const pdhg_options &o) {
+    BOpts b;
+    b.eps = o.eps;
+    b.gamma = o.gamma;
+    b.step_safety = o.step_safety;
+    b.beta_suff = o.restart_sufficient;
+    b.beta_nec = o.restart_necessary;
+    b.beta_art = o.restart_artificial;
+    b.power_tol = o.power_tol;
+    b.limit = std::min<int64_t>(o.iteration_limit, 10000000);
+    b.check_every = o.check_every;
+    b.ruiz_iters = o.ruiz_iters;
+    b.pock_chambolle = o.pock_chambolle;
+    b.power_max_iters = o.power_max_iters;
+    return b;
+}
+
+static BArgs batch_args(BatchHandle &h) {
+    BArgs a;
+    memset(&a, 0, sizeof(a));
+    a.B = h.B;
+    a.shared = h.shared;
+    a.m = h.m;
+    a.n = h.n;
+    a.row_off = h.row_off.p;
+    a.col_off = h.col_off.p;
+    a.arp = h.arp.p;
+    a.aci = h.aci.p;
+    a.ava = h.ava.p;
+    a.trp = h.trp.p;
+    a.tci = h.tci.p;
+    a.tva = h.tva.p;
+    a.Dr = h.Dr.p;
+    a.Dc = h.Dc.p;
+    a.eta = h.eta.p;
+    a.power_iters = h.power_iters.p;
+    a.c_o = h.c_o.p;
+    a.lc_o = h.lc_o.p;
+    a.uc_o = h.uc_o.p;
+    a.lv_o = h.lv_o.p;
+    a.uv_o = h.uv_o.p;
+    a.c = h.c.p;
+    a.lc = h.lc.p;
+    a.uc = h.uc.p;
+    a.lv = h.lv.p;
+    a.uv = h.uv.p;
+    a.x = h.x.p;
+    a.x0 = h.x0.p;
+    a.xh = h.xh.p;
+    a.xe = h.xe.p;
+    a.aty = h.aty.p;
+    a.y = h.y.p;
+    a.y0 = h.y0.p;
+    a.yh = h.yh.p;
+    a.res = h.res.p;
+    a.queue = h.queue.p;
+    a.x_init = h.x_init_;
+    a.y_init = h.y_init_;
+    a.x_out = h.x_out_;
+    a.y_out = h.y_out_;
+    return a;
+}
+
+template <int BT>
+static int32_t resident(const void *kernel) {
+    int dev = 0, per_cu = 0;
+    PDHG_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    PDHG_HIP(hipGetDeviceProperties(&prop, dev));
+    PDHG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, BT, 0));
+    return std::max(1, per_cu) * prop.multiProcessorCount;
+}
+
+template <int BT>
+static void launch_setup_t(BatchHandle &h, int32_t count) {
+    BArgs a = batch_args(h);
+    const BOpts o = batch_opts(h.opt);
+    int32_t wg = std::min(count, resident<BT>(reinterpret_cast<const void *>(&k_batch_setup<BT>)));
+    if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
+    PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
+    k_batch_setup<BT><<<wg, BT, 0, h.stream>>>(a, o, count);
+    PDHG_HIP(hipGetLastError());
+}
+
+template <int BT>
+static void launch_solve_t(BatchHandle &h, const BOpts &o) {
+    BArgs a = batch_args(h);
+    int32_t wg = std::min(h.B, resident<BT>(reinterpret_cast<const void *>(&k_batch_solve<BT>)));
+    if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
+    PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
+    k_batch_solve<BT><<<wg, BT, 0, h.stream>>>(a, o);
+    PDHG_HIP(hipGetLastError());
+}
+
+static void dispatch_setup(BatchHandle &h, int32_t count) {
+    switch (h.threads) {
+        case 64: launch_setup_t<64>(h, count); break;
+        case 128: launch_setup_t<128>(h, count); break;
+        case 512: launch_setup_t<512>(h, count); break;
+        case 1024: launch_setup_t<1024>(h, count); break;
+        default: launch_setup_t<256>(h, count); break;
+    }
+}
+
+static void dispatch_solve(BatchHandle &h, const BOpts &o) {
+    switch (h.threads) {
+        case 64: launch_solve_t<64>(h, o); break;
+        case 128: launch_solve_t<128>(h, o); break;
+        case 512: launch_solve_t<512>(h, o); break;
+        case 1024: launch_solve_t<1024>(h, o); break;
+        default: launch_solve_t<256>(h, o); break;
+    }
+}
+
+template <class T>
+static void load(DBuf<T> &dst, const T *src, size_t count, int mem, hipStream_t s) {
+    dst.alloc(count);
+    if (count == 0) return;
+    PDHG_HIP(hipMemcpyAsync(dst.p, src, count * sizeof(T),
+                            mem == PDHG_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                   : hipMemcpyHostToDevice,
+                            s));
+}
+
+BatchHandle *batch_create(const pdhg_batch_problem &p, const pdhg_options &o, void *stream) {
+    if (p.batch < 1 || (p.shared_a != 0 && p.shared_a != 1) || p.m < 0 || p.n < 1)
+        fail(PDHG_ERR_INVALID_ARG, "need batch >= 1, shared_a in {0,1}, m >= 0, n >= 1");
+    if (p.mem != PDHG_MEM_HOST && p.mem != PDHG_MEM_DEVICE)
+        fail(PDHG_ERR_INVALID_ARG, "mem must be PDHG_MEM_HOST or PDHG_MEM_DEVICE");
+    if (!p.a_rowptr || (p.a_nnz > 0 && (!p.a_colidx || !p.a_val)) || p.a_nnz < 0 ||
+        p.a_nnz >= INT32_MAX)
+        fail(PDHG_ERR_INVALID_ARG, "bad CSR arrays or nnz");
+    if (!p.c || !p.lv || !p.uv || (p.m > 0 && (!p.lc || !p.uc)))
+        fail(PDHG_ERR_INVALID_ARG, "NULL objective or bound vector");
+    if (!p.shared_a && (!p.row_off || !p.col_off))
+        fail(PDHG_ERR_INVALID_ARG, "ragged batches need row_off and col_off");
+    if (p.shared_a && ((int64_t)p.batch * p.n >= INT32_MAX || (int64_t)p.batch * p.m >= INT32_MAX))
+        fail(PDHG_ERR_UNSUPPORTED, "batch vectors exceed 32-bit indexing");
+    auto hp = std::make_unique<BatchHandle>();
+    BatchHandle &h = *hp;
+    const double t0 = now_seconds();
+    h.B = p.batch;
+    h.shared = p.shared_a;
+    h.m = p.m;
+    h.n = p.n;
+    h.nnz = p.a_nnz;
+    h.opt = o;
+    h.vec_m = h.shared ? h.B * h.m : h.m;
+    h.vec_n = h.shared ? h.B * h.n : h.n;
+    PDHG_HIP(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
+    PDHG_HIP(hipEventCreateWithFlags(&h.ev, hipEventDisableTiming));
+    order_after_stream(h.stream, h.ev, stream);
+    hipStream_t s = h.stream;
+
+    load(h.arp, p.a_rowptr, (size_t)h.m + 1, p.mem, s);
+    load(h.aci, p.a_colidx, (size_t)h.nnz, p.mem, s);
+    load(h.ava, p.a_val, (size_t)h.nnz, p.mem, s);
+    validate_csr(s, h.arp.p, h.aci.p, h.ava.p, h.m, h.n, h.nnz);
+    if (!h.shared) {
+        std::vector<int32_t> ro((size_t)h.B + 1), co((size_t)h.B + 1);
+        if (p.mem == PDHG_MEM_DEVICE) {
+            PDHG_HIP(hipMemcpy(ro.data(), p.row_off, ro.size() * 4, hipMemcpyDeviceToHost));
+            PDHG_HIP(hipMemcpy(co.data(), p.col_off, co.size() * 4, hipMemcpyDeviceToHost));
+        } else {
+            memcpy(ro.data(), p.row_off, ro.size() * 4);
+            memcpy(co.data(), p.col_off, co.size() * 4);
+        }
+        if (ro[0] != 0 || co[0] != 0 || ro[h.B] != h.m || co[h.B] != h.n)
+            fail(PDHG_ERR_INVALID_INPUT, "row_off / col_off must start at 0 and end at m / n");
+        for (int32_t b = 0; b < h.B; ++b)
+            if (ro[b + 1] < ro[b] || co[b + 1] <= co[b])
+                fail(PDHG_ERR_INVALID_INPUT, "instance offsets must increase (>= 1 column each)");
+        load(h.row_off, ro.data(), ro.size(), PDHG_MEM_HOST, s);
+        load(h.col_off, co.data(), co.size(), PDHG_MEM_HOST, s);
+        h.row_off_h = ro;
+        h.col_off_h = co;
+    } else {
+        h.row_off.alloc(1);
+        h.col_off.alloc(1);
+    }
+    // A' from the global matrix, then instance-local indices on both
+    h.trp.alloc((size_t)h.n + 1);
+    h.tci.alloc((size_t)h.nnz);
+    h.tva.alloc((size_t)h.nnz);
+    plain_transpose(s, h.m, h.n, h.nnz, h.arp.p, h.aci.p, h.ava.p, h.trp.p, h.tci.p, h.tva.p);
+    if (!h.shared) {
+        DBuf<int32_t> flag;
+        flag.alloc(1);
+        PDHG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+        const unsigned nb = (unsigned)std::max<int64_t>(1, ceil_div(h.B, kBlock));
+        k_batch_localize<<<nb, kBlock, 0, s>>>(h.row_off.p, h.col_off.p, h.B, h.arp.p, h.aci.p,
+                                                flag.p);
+        check_flag(s, flag.p, "a ragged instance has entries outside its column range");
+        k_batch_localize_t<<<nb, kBlock, 0, s>>>(h.row_off.p, h.col_off.p, h.B, h.trp.p, h.tci.p);
+    }
+    load(h.c_o, p.c, (size_t)h.vec_n, p.mem, s);
+    load(h.lv_o, p.lv, (size_t)h.vec_n, p.mem, s);
+    load(h.uv_o, p.uv, (size_t)h.vec_n, p.mem, s);
+    load(h.lc_o, p.lc, (size_t)h.vec_m, p.mem, s);
+    load(h.uc_o, p.uc, (size_t)h.vec_m, p.mem, s);
+    validate_vectors(s, h.vec_n, h.vec_m, h.c_o.p, h.lv_o.p, h.uv_o.p, h.lc_o.p, h.uc_o.p);
+    for (auto *b : {&h.c, &h.lv, &h.uv, &h.x, &h.x0, &h.xh, &h.xe, &h.aty}) b->alloc((size_t)h.vec_n);
+    for (auto *b : {&h.lc, &h.uc, &h.y, &h.y0, &h.yh}) b->alloc((size_t)h.vec_m);
+    h.Dr.alloc((size_t)h.m);
+    h.Dc.alloc((size_t)h.n);
+    const int32_t nscal = h.shared ? 1 : h.B;
+    h.eta.alloc((size_t)nscal);
+    h.power_iters.alloc((size_t)nscal);
+    h.res.alloc((size_t)h.B);
+    h.queue.alloc(1);
+    dispatch_setup(h, nscal);
+    PDHG_HIP(hipStreamSynchronize(s));
+    h.setup_seconds = now_seconds() - t0;
+    return hp.release();
+}
+
+void batch_solve(BatchHandle &h, const double *x_init, const double *y_init, double *x_out,
+                 double *y_out, pdhg_result *res) {
+    const double t0 = now_seconds();
+    BOpts o = batch_opts(h.opt);
+    // pointers of this call go in through the argument block
+    h.x_init_ = x_init;
+    h.y_init_ = y_init;
+    h.x_out_ = x_out;
+    h.y_out_ = y_out;
+    dispatch_solve(h, o);
+    PDHG_HIP(hipStreamSynchronize(h.stream));
+    const double el = now_seconds() - t0;
+    if (res) {
+        std::vector<BatchRes> r((size_t)h.B);
+        PDHG_HIP(hipMemcpy(r.data(), h.res.p, sizeof(BatchRes) * h.B, hipMemcpyDeviceToHost));
+        for (int32_t b = 0; b < h.B; ++b) {
+            pdhg_result &q = res[b];
+            memset(&q, 0, sizeof(q));
+            q.status = r[b].status;
+            q.iterations = r[b].iterations;
+            q.restarts = r[b].restarts;
+            q.primal_obj = r[b].pobj;
+            q.dual_obj = r[b].dobj;
+            q.rel_primal_res = r[b].rel_p;
+            q.rel_dual_res = r[b].rel_d;
+            q.rel_gap = r[b].rel_g;
+            q.kkt_rel = r[b].kkt;
+            q.solve_seconds = el;
+            q.setup_seconds = h.setup_seconds;
+            q.eta = r[b].eta;
+            q.omega = r[b].omega;
+            q.norm_a = r[b].eta > 0.0 ? h.opt.step_safety / r[b].eta : 0.0;
+            q.power_iters = r[b].power_iters;
+        }
+    }
+}
+
+void batch_set_launch(BatchHandle &h, int32_t threads, int32_t workgroups) {
+    if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
+        fail(PDHG_ERR_INVALID_ARG, "threads must be 64, 128, 256, 512 or 1024");
+    h.threads = threads;
+    h.workgroups = workgroups;
+}
+
+int32_t batch_autotune(BatchHandle &h, int32_t iterations) {
+    BOpts o = batch_opts(h.opt);
+    o.limit = iterations;
+    DBuf<double> xo, yo;
+    xo.alloc((size_t)h.vec_n);
+    yo.alloc((size_t)h.vec_m);
+    h.x_out_ = xo.p;
+    h.y_out_ = yo.p;
+    h.x_init_ = nullptr;
+    h.y_init_ = nullptr;
+    int32_t best = h.threads;
+    double best_t = 1e300;
+    for (int32_t t : {64, 128, 256, 512, 1024}) {
+        h.threads = t;
+        dispatch_solve(h, o);   // warm-up
+        PDHG_HIP(hipStreamSynchronize(h.stream));
+        const double t0 = now_seconds();
+        dispatch_solve(h, o);
+        PDHG_HIP(hipStreamSynchronize(h.stream));
+        const double el = now_seconds() - t0;
+        if (el < best_t) {
+            best_t = el;
+            best = t;
+        }
+    }
+    h.threads = best;
+    return best;
+}
+
+static UArgs unrolled_args(BatchHandle &h) {
+    UArgs u;
+    memset(&u, 0, sizeof(u));
+    u.T = h.unrolled_T;
+    u.restart = h.u_restart.p;
+    u.omega = h.u_omega.p;
+    u.kk = h.u_kk.p;
+    u.xmask = h.u_xmask.p;
+    u.ymask = h.u_ymask.p;
+    u.xm_off = h.u_xoff.p;
+    u.ym_off = h.u_yoff.p;
+    u.ba = h.u_ba.p;
+    return u;
+}
+
+template <int BT>
+static void launch_unrolled_t(BatchHandle &h, const UArgs &u) {
+    BArgs a = batch_args(h);
+    const BOpts o = batch_opts(h.opt);
+    int32_t wg = std::min(h.B, resident<BT>(reinterpret_cast<const void *>(&k_batch_unrolled<BT>)));
+    if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
+    PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
+    k_batch_unrolled<BT><<<wg, BT, 0, h.stream>>>(a, o, u);
+    PDHG_HIP(hipGetLastError());
+}
+
+template <int BT>
+static void launch_backward_t(BatchHandle &h, const UArgs &u) {
+    BArgs a = batch_args(h);
+    const BOpts o = batch_opts(h.opt);
+    int32_t wg = std::min(h.B, resident<BT>(reinterpret_cast<const void *>(&k_batch_backward<BT>)));
+    if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
+    PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
+    k_batch_backward<BT><<<wg, BT, 0, h.stream>>>(a, o, u);
+    PDHG_HIP(hipGetLastError());
+}
+
+void batch_unrolled_forward(BatchHandle &h, int64_t T, int32_t replay, double *x_out,
+                            double *y_out) {
+    if (T < 1 || T > 1000000) fail(PDHG_ERR_INVALID_ARG, "T must be in [1, 10^6]");
+    if (replay && h.unrolled_T != T)
+        fail(PDHG_ERR_INVALID_ARG, "replay needs a recorded schedule of the same length T");
+    if (h.unrolled_T != T) {
+        // per-instance mask offsets (64-bit words)
+        std::vector<int64_t> xo((size_t)h.B + 1, 0), yo((size_t)h.B + 1, 0);
+        for (int32_t b = 0; b < h.B; ++b) {
+            const int64_t n_b = h.shared ? h.n : h.col_off_h[b + 1] - h.col_off_h[b];
+            const int64_t m_b = h.shared ? h.m : h.row_off_h[b + 1] - h.row_off_h[b];
+            xo[b + 1] = xo[b] + ((n_b + 63) / 64) * T;
+            yo[b + 1] = yo[b] + 2 * ((m_b + 63) / 64) * T;
+        }
+        h.u_xoff.alloc(xo.size());
+        h.u_yoff.alloc(yo.size());
+        PDHG_HIP(hipMemcpy(h.u_xoff.p, xo.data(), xo.size() * 8, hipMemcpyHostToDevice));
+        PDHG_HIP(hipMemcpy(h.u_yoff.p, yo.data(), yo.size() * 8, hipMemcpyHostToDevice));
+        h.u_xmask.alloc((size_t)std::max<int64_t>(1, xo[h.B]));
+        h.u_ymask.alloc((size_t)std::max<int64_t>(1, yo[h.B]));
+        h.u_restart.alloc((size_t)h.B * T);
+        h.u_omega.alloc((size_t)h.B * T);
+        h.u_kk.alloc((size_t)h.B * T);
+        h.u_ba.alloc((size_t)std::max(1, h.vec_m));
+        h.unrolled_T = T;
+    }
+    h.x_out_ = x_out;
+    h.y_out_ = y_out;
+    UArgs u = unrolled_args(h);
+    u.replay = replay;
+    switch (h.threads) {
+        case 64: launch_unrolled_t<64>(h, u); break;
+        case 128: launch_unrolled_t<128>(h, u); break;
+        case 512: launch_unrolled_t<512>(h, u); break;
+        case 1024: launch_unrolled_t<1024>(h, u); break;
+        default: launch_unrolled_t<256>(h, u); break;
+    }
+    PDHG_HIP(hipStreamSynchronize(h.stream));
+}
+
+void batch_backward(BatchHandle &h, const double *gx, const double *gy, double *gc, double *glc,
+                    double *guc) {
+    if (h.unrolled_T < 1) fail(PDHG_ERR_INVALID_ARG, "run pdhg_batch_unrolled_forward first");
+    DBuf<double> zm, lcs, ucs;
+    zm.alloc((size_t)std::max(1, h.vec_m));
+    PDHG_HIP(hipMemsetAsync(zm.p, 0, sizeof(double) * std::max(1, h.vec_m), h.stream));
+    // gradients of rows without bounds are written to scratch when not requested
+    lcs.alloc((size_t)std::max(1, h.vec_m));
+    ucs.alloc((size_t)std::max(1, h.vec_m));
+    UArgs u = unrolled_args(h);
+    u.gx = gx;
+    u.gy = gy ? gy : zm.p;
+    u.gc = gc;
+    u.glc = glc ? glc : lcs.p;
+    u.guc = guc ? guc : ucs.p;
+    switch (h.threads) {
+        case 64: launch_backward_t<64>(h, u); break;
+        case 128: launch_backward_t<128>(h, u); break;
+        case 512: launch_backward_t<512>(h, u); break;
+        case 1024: launch_backward_t<1024>(h, u); break;
+        default: launch_backward_t<256>(h, u); break;
+    }
+    PDHG_HIP(hipStreamSynchronize(h.stream));
+}
+
+void batch_update_data(BatchHandle &h, const double *c, const double *lc, const double *uc,
+                       const double *lv, const double *uv) {
+    hipStream_t s = h.stream;
+    DBuf<double> nc, nlc, nuc, nlv, nuv;
+    auto take = [&](DBuf<double> &dst, const double *src, const DBuf<double> &cur, int32_t len) {
+        dst.alloc((size_t)std::max(1, len));
+        PDHG_HIP(hipMemcpyAsync(dst.p, src ? src : cur.p, sizeof(double) * (size_t)len,
+                                hipMemcpyDeviceToDevice, s));
+    };
+    take(nc, c, h.c_o, h.vec_n);
+    take(nlv, lv, h.lv_o, h.vec_n);
+    take(nuv, uv, h.uv_o, h.vec_n);
+    take(nlc, lc, h.lc_o, h.vec_m);
+    take(nuc, uc, h.uc_o, h.vec_m);
+    validate_vectors(s, h.vec_n, h.vec_m, nc.p, nlv.p, nuv.p, nlc.p, nuc.p);
+    std::swap(h.c_o.p, nc.p);
+    std::swap(h.lv_o.p, nlv.p);
+    std::swap(h.uv_o.p, nuv.p);
+    std::swap(h.lc_o.p, nlc.p);
+    std::swap(h.uc_o.p, nuc.p);
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
+void batch_destroy(BatchHandle *h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+}  // namespace pdhg

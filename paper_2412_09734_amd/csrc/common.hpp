@@ -137,6 +137,7 @@ struct DevState {
 struct CtlConst {
     double eps, bnorm, cnorm, eta;
     double beta_suff, beta_nec, beta_art;
+    double norm_q;
     int32_t qp;
     int32_t pad;
 };
@@ -163,6 +164,12 @@ struct Handle {
     double setup_seconds = 0.0;
     hipGraphExec_t chunk_exec = nullptr;
     hipGraph_t chunk_graph = nullptr;
+    // quadratic term Q~ = D_c Q D_c (rAPDHG), internal order
+    int32_t q_kind = 0;                  // 0 none, PDHG_FMT_CSR, PDHG_FMT_DENSE, PDHG_FMT_LOWRANK_DIAG
+    int32_t q_rank = 0;
+    DBuf<int32_t> q_rp, q_ci;            // CSR
+    DBuf<double> q_va, q_dense, q_f, q_d;  // CSR values, dense n x n, factor n x r, diagonal
+    DBuf<double> xbar, ybar, qv_in, qv, qpart, qt;
     ~Handle();
 };
 
@@ -174,6 +181,43 @@ void transform_vectors(Handle &h);
 void estimate_steps(Handle &h);
 void compute_weight(Handle &h);
 SegTable make_segments(const std::vector<int32_t> &class_count, int32_t rows);
+void validate_csr(hipStream_t s, const int32_t *rowptr, const int32_t *colidx, const double *val,
+                  int32_t m, int32_t n, int64_t nnz);
+void validate_vectors(hipStream_t s, int32_t n, int32_t m, const double *c, const double *lv,
+                      const double *uv, const double *lc, const double *uc);
+void plain_transpose(hipStream_t s, int32_t rows, int32_t cols, int64_t nnz, const int32_t *rowptr,
+                     const int32_t *colidx, const double *val, int32_t *rowptr_t,
+                     int32_t *colidx_t, double *val_t);
+void check_flag(hipStream_t s, const int32_t *dflag, const char *what);
+void permute_csr(hipStream_t s, int32_t rows, int32_t cols, int64_t nnz, const int32_t *rowptr,
+                 const int32_t *colidx, const double *val, const int32_t *perm_r,
+                 const int32_t *perm_c, int32_t *out_rp, int32_t *out_ci, double *out_va);
+double now_seconds();
+void order_after_stream(hipStream_t own, hipEvent_t ev, void *caller);
+void check_options(const pdhg_options &o);
+
+// ---- rAPDHG (qp_kernels.hip) -------------------------------------------------
+void qp_build(Handle &h, const pdhg_problem &p);
+void qp_estimate_norm(Handle &h);
+void launch_qp_iteration(Handle &h, int32_t j);
+void launch_qp_check(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t last_status);
+void launch_qp_finalize(Handle &h, double *x_out, double *y_out);
+void launch_qp_init(Handle &h);
+void launch_qp_debug_step(Handle &h, int64_t k, double omega);
+
+// ---- batched solver (batch.hip) ---------------------------------------------
+struct BatchHandle;
+BatchHandle *batch_create(const pdhg_batch_problem &p, const pdhg_options &o, void *stream);
+void batch_solve(BatchHandle &b, const double *x_init, const double *y_init, double *x_out,
+                 double *y_out, pdhg_result *res);
+void batch_set_launch(BatchHandle &b, int32_t threads, int32_t workgroups);
+int32_t batch_autotune(BatchHandle &b, int32_t iterations);
+void batch_unrolled_forward(BatchHandle &b, int64_t T, int32_t replay, double *x_out, double *y_out);
+void batch_backward(BatchHandle &b, const double *gx, const double *gy, double *gc, double *glc,
+                    double *guc);
+void batch_update_data(BatchHandle &b, const double *c, const double *lc, const double *uc,
+                       const double *lv, const double *uv);
+void batch_destroy(BatchHandle *b);
 
 // ---- iteration kernels (lp_kernels.hip) -------------------------------------
 void launch_primal(Handle &h, int32_t j);

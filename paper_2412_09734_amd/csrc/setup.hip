@@ -129,6 +129,15 @@ __global__ __launch_bounds__(kBlock) void k_fill_internal(
     }
 }
 
+// row id of every entry of a plain CSR (one wave per row)
+__global__ __launch_bounds__(kBlock) void k_row_of(const int32_t *__restrict__ rowptr, int32_t rows,
+                                                   int32_t *__restrict__ row_of) {
+    const int64_t w = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (w >= rows) return;
+    for (int32_t e = rowptr[w] + lane; e < rowptr[w + 1]; e += 64) row_of[e] = (int32_t)w;
+}
+
 __global__ __launch_bounds__(kBlock) void k_iota_u(int32_t *__restrict__ iota, int64_t len) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < len) iota[i] = (int32_t)i;
@@ -424,7 +433,7 @@ SegTable make_segments(const std::vector<int32_t> &class_count, int32_t rows) {
     return T;
 }
 
-static void check_flag(hipStream_t s, const int32_t *dflag, const char *what) {
+void check_flag(hipStream_t s, const int32_t *dflag, const char *what) {
     int32_t f = 0;
     PDHG_HIP(hipMemcpyAsync(&f, dflag, sizeof(f), hipMemcpyDeviceToHost, s));
     PDHG_HIP(hipStreamSynchronize(s));
@@ -500,6 +509,77 @@ static void to_hybrid(hipStream_t s, PlainCsr &P, int32_t cols, HMat &H) {
     if (ns > 0)
         k_fill_slices<<<blocks_for((int64_t)ns * 64), kBlock, 0, s>>>(
             P.rowptr.p, P.colidx.p, P.val.p, r_long, R, ns, H.slice_ptr.p, H.colidx.p, H.val.p);
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
+void validate_csr(hipStream_t s, const int32_t *rowptr, const int32_t *colidx,
+                  const double *val, int32_t m, int32_t n, int64_t nnz) {
+    DBuf<int32_t> flag;
+    flag.alloc(1);
+    PDHG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+    DBuf<uint8_t> rowstart;
+    rowstart.alloc((size_t)nnz + 1);
+    PDHG_HIP(hipMemsetAsync(rowstart.p, 0, (size_t)nnz + 1, s));
+    k_validate_rowptr<<<blocks_for((int64_t)m + 1), kBlock, 0, s>>>(rowptr, m, nnz, rowstart.p,
+                                                                     flag.p);
+    check_flag(s, flag.p, "invalid CSR row pointers");
+    if (nnz > 0)
+        k_validate_entries<<<blocks_for(nnz), kBlock, 0, s>>>(colidx, val, nnz, n, rowstart.p,
+                                                               flag.p);
+    check_flag(s, flag.p, "invalid CSR entries (column out of range, unsorted or duplicate "
+                          "column, or non-finite value)");
+}
+
+void validate_vectors(hipStream_t s, int32_t n, int32_t m, const double *c, const double *lv,
+                      const double *uv, const double *lc, const double *uc) {
+    DBuf<int32_t> flag;
+    flag.alloc(1);
+    PDHG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+    k_validate_vectors<<<blocks_for((int64_t)n + m), kBlock, 0, s>>>(n, m, c, lv, uv, lc, uc,
+                                                                    flag.p);
+    check_flag(s, flag.p, "invalid objective or bounds (non-finite c, NaN bound, l > u)");
+}
+
+void plain_transpose(hipStream_t s, int32_t rows, int32_t cols, int64_t nnz,
+                     const int32_t *rowptr, const int32_t *colidx, const double *val,
+                     int32_t *rowptr_t, int32_t *colidx_t, double *val_t) {
+    DBuf<int32_t> cnt, row_of;
+    cnt.alloc((size_t)cols + 1);
+    PDHG_HIP(hipMemsetAsync(cnt.p, 0, ((size_t)cols + 1) * sizeof(int32_t), s));
+    if (nnz > 0) k_col_count<<<blocks_for(nnz), kBlock, 0, s>>>(colidx, nnz, cnt.p);
+    exclusive_scan(s, cnt.p, rowptr_t, (int64_t)cols + 1);
+    if (nnz == 0) return;
+    row_of.alloc((size_t)nnz);
+    if (rows > 0) k_row_of<<<blocks_for((int64_t)rows * 64), kBlock, 0, s>>>(rowptr, rows, row_of.p);
+    DBuf<uint32_t> ekey_sorted;
+    DBuf<int32_t> eid, order;
+    ekey_sorted.alloc((size_t)nnz);
+    eid.alloc((size_t)nnz);
+    order.alloc((size_t)nnz);
+    k_iota_u<<<blocks_for(nnz), kBlock, 0, s>>>(eid.p, nnz);
+    int bits = 1;
+    while ((1ll << bits) < (int64_t)cols) ++bits;
+    sort_pairs(s, reinterpret_cast<const uint32_t *>(colidx), ekey_sorted.p, eid.p, order.p, nnz,
+               bits);
+    k_fill_transpose<<<blocks_for(nnz), kBlock, 0, s>>>(order.p, row_of.p, val, nnz, colidx_t,
+                                                        val_t);
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
+void permute_csr(hipStream_t s, int32_t rows, int32_t cols, int64_t nnz, const int32_t *rowptr,
+                 const int32_t *colidx, const double *val, const int32_t *perm_r,
+                 const int32_t *perm_c, int32_t *out_rp, int32_t *out_ci, double *out_va) {
+    DBuf<int32_t> inv_c, lens, row_of;
+    inv_c.alloc(cols);
+    k_inverse<<<blocks_for(cols), kBlock, 0, s>>>(perm_c, cols, inv_c.p);
+    lens.alloc((size_t)rows + 1);
+    k_perm_lengths<<<blocks_for((int64_t)rows + 1), kBlock, 0, s>>>(perm_r, rowptr, nullptr, rows,
+                                                                    lens.p);
+    exclusive_scan(s, lens.p, out_rp, (int64_t)rows + 1);
+    row_of.alloc((size_t)nnz);
+    if (rows > 0 && nnz > 0)
+        k_fill_internal<<<blocks_for((int64_t)rows * 64), kBlock, 0, s>>>(
+            rowptr, colidx, val, perm_r, inv_c.p, out_rp, rows, out_ci, out_va, row_of.p);
     PDHG_HIP(hipStreamSynchronize(s));
 }
 

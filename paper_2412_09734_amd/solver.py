@@ -53,10 +53,13 @@ class Solver:
     device, handed to pdhg_create (which keeps its own scaled copy) and
     released."""
 
-    def __init__(self, m, n, rowptr, colidx, val, c, lc, uc, lv, uv, *, device=None, **opts):
+    def __init__(self, m, n, rowptr, colidx, val, c, lc, uc, lv, uv, *, q_format="none",
+                 q_rowptr=None, q_colidx=None, q_val=None, q_dense=None, q_factor=None,
+                 q_diag=None, device=None, **opts):
         self.dev = _device(device)
         self.m, self.n = int(m), int(n)
         self._opts = options(**opts)
+        self.qp = q_format != "none"
         with torch.cuda.device(self.dev):
             t = dict(rowptr=_to_dev(rowptr, torch.int32, self.dev),
                      colidx=_to_dev(colidx, torch.int32, self.dev),
@@ -74,6 +77,24 @@ class Solver:
             p.c, p.lc, p.uc = t["c"].data_ptr(), t["lc"].data_ptr(), t["uc"].data_ptr()
             p.lv, p.uv = t["lv"].data_ptr(), t["uv"].data_ptr()
             p.q_format = capi.FMT_NONE
+            if q_format == "csr":
+                t["qr"], t["qc"], t["qv"] = (_to_dev(q_rowptr, torch.int32, self.dev),
+                                             _to_dev(q_colidx, torch.int32, self.dev),
+                                             _to_dev(q_val, torch.float64, self.dev))
+                p.q_format, p.q_rowptr, p.q_colidx, p.q_val = (capi.FMT_CSR, t["qr"].data_ptr(),
+                                                               t["qc"].data_ptr(), t["qv"].data_ptr())
+                p.q_nnz = int(t["qc"].numel())
+            elif q_format == "dense":
+                t["qd"] = _to_dev(q_dense, torch.float64, self.dev)
+                p.q_format, p.q_dense = capi.FMT_DENSE, t["qd"].data_ptr()
+            elif q_format == "lowrank":
+                t["qf"] = _to_dev(q_factor, torch.float64, self.dev)
+                t["qg"] = _to_dev(q_diag, torch.float64, self.dev)
+                p.q_format, p.q_factor, p.q_diag = (capi.FMT_LOWRANK_DIAG, t["qf"].data_ptr(),
+                                                    t["qg"].data_ptr())
+                p.q_rank = int(t["qf"].shape[1]) if t["qf"].dim() == 2 else 1
+            elif q_format != "none":
+                raise ValueError(f"unknown q_format {q_format}")
             p.mem = capi.MEM_DEVICE
             h = C.c_void_p()
             rc = capi.lib().pdhg_create(C.byref(p), C.byref(self._opts), _stream_ptr(), C.byref(h))
@@ -83,8 +104,18 @@ class Solver:
 
     @classmethod
     def from_lp(cls, lp, **opts) -> "Solver":
-        """From any object with m, n, rowptr, colidx, val, c, lc, uc, lv, uv."""
-        return cls(lp.m, lp.n, lp.rowptr, lp.colidx, lp.val, lp.c, lp.lc, lp.uc, lp.lv, lp.uv, **opts)
+        """From any object with m, n, rowptr, colidx, val, c, lc, uc, lv, uv
+        (and optionally q_kind 'csr' / 'lowrank' with its Q arrays)."""
+        q = {}
+        kind = getattr(lp, "q_kind", "none")
+        if kind == "csr":
+            q = dict(q_format="csr", q_rowptr=lp.q_rowptr, q_colidx=lp.q_colidx, q_val=lp.q_val)
+        elif kind == "lowrank":
+            q = dict(q_format="lowrank", q_factor=lp.q_factor, q_diag=lp.q_diag)
+        elif kind == "dense":
+            q = dict(q_format="dense", q_dense=lp.q_dense)
+        return cls(lp.m, lp.n, lp.rowptr, lp.colidx, lp.val, lp.c, lp.lc, lp.uc, lp.lv, lp.uv,
+                   **q, **opts)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -138,6 +169,21 @@ class Solver:
         capi.check(rc, "pdhg_debug_step")
         return outs[0], outs[1][: self.m], outs[2], outs[3][: self.m]
 
+    def debug_qp_step(self, x, y, xbar, ybar, k, omega):
+        """One rAPDHG iteration in the scaled space (original order)."""
+        z = lambda: torch.zeros(1, dtype=torch.float64, device=self.dev)  # noqa: E731
+        x, xbar = self._vec(x, self.n), self._vec(xbar, self.n)
+        y = self._vec(y, self.m) if self.m else z()
+        ybar = self._vec(ybar, self.m) if self.m else z()
+        outs = [torch.empty(self.n, dtype=torch.float64, device=self.dev),
+                torch.empty(max(self.m, 1), dtype=torch.float64, device=self.dev),
+                torch.empty(self.n, dtype=torch.float64, device=self.dev),
+                torch.empty(max(self.m, 1), dtype=torch.float64, device=self.dev)]
+        rc = capi.lib().pdhg_debug_qp_step(self._h, _ptr(x), _ptr(y), _ptr(xbar), _ptr(ybar),
+                                           int(k), float(omega), *[_ptr(o) for o in outs])
+        capi.check(rc, "pdhg_debug_qp_step")
+        return outs[0], outs[1][: self.m], outs[2], outs[3][: self.m]
+
     def scaling(self) -> dict:
         dr = torch.empty(max(self.m, 1), dtype=torch.float64, device=self.dev)
         dc = torch.empty(self.n, dtype=torch.float64, device=self.dev)
@@ -153,3 +199,185 @@ class Solver:
              self._vec(lv, self.n), self._vec(uv, self.n)]
         rc = capi.lib().pdhg_update_data(self._h, *[_ptr(a) for a in t])
         capi.check(rc, "pdhg_update_data")
+
+
+class BatchSolver:
+    """Many LPs solved in one persistent launch (pdhg_batch_*).
+
+    Shared A: `c, lv, uv` are [B, n] and `lc, uc` [B, m]. Ragged: one
+    block-diagonal CSR with `row_off`, `col_off` ([B+1]) and concatenated
+    vectors (see `from_lps`)."""
+
+    def __init__(self, *, shared_a, batch, m, n, rowptr, colidx, val, c, lc, uc, lv, uv,
+                 row_off=None, col_off=None, device=None, threads=None, **opts):
+        self.dev = _device(device)
+        self.shared = bool(shared_a)
+        self.batch, self.m, self.n = int(batch), int(m), int(n)
+        self._opts = options(**opts)
+        f64 = lambda a: _to_dev(a, torch.float64, self.dev).reshape(-1)  # noqa: E731
+        i32 = lambda a: _to_dev(a, torch.int32, self.dev).reshape(-1)  # noqa: E731
+        with torch.cuda.device(self.dev):
+            t = dict(rowptr=i32(rowptr), colidx=i32(colidx), val=f64(val), c=f64(c), lc=f64(lc),
+                     uc=f64(uc), lv=f64(lv), uv=f64(uv))
+            if not self.shared:
+                t["row_off"], t["col_off"] = i32(row_off), i32(col_off)
+            p = capi.BatchProblem()
+            p.batch, p.shared_a, p.m, p.n = self.batch, int(self.shared), self.m, self.n
+            p.a_rowptr, p.a_colidx, p.a_val = (t["rowptr"].data_ptr(), t["colidx"].data_ptr(),
+                                               t["val"].data_ptr())
+            p.a_nnz = int(t["colidx"].numel())
+            if not self.shared:
+                p.row_off, p.col_off = t["row_off"].data_ptr(), t["col_off"].data_ptr()
+            p.c, p.lc, p.uc = t["c"].data_ptr(), t["lc"].data_ptr(), t["uc"].data_ptr()
+            p.lv, p.uv = t["lv"].data_ptr(), t["uv"].data_ptr()
+            p.mem = capi.MEM_DEVICE
+            h = C.c_void_p()
+            rc = capi.lib().pdhg_batch_create(C.byref(p), C.byref(self._opts), _stream_ptr(),
+                                              C.byref(h))
+            capi.check(rc, "pdhg_batch_create")
+            self._h = h
+            self.vec_n = int(t["c"].numel())
+            self.vec_m = int(t["lc"].numel())
+            if not self.shared:
+                self.row_off = np.asarray(row_off, dtype=np.int64)
+                self.col_off = np.asarray(col_off, dtype=np.int64)
+        if threads is not None:
+            self.set_launch(threads)
+
+    @classmethod
+    def from_shared(cls, sb, **opts) -> "BatchSolver":
+        """From an object with m, n, rowptr, colidx, val and [B, .] vectors."""
+        return cls(shared_a=True, batch=sb.c.shape[0], m=sb.m, n=sb.n, rowptr=sb.rowptr,
+                   colidx=sb.colidx, val=sb.val, c=sb.c, lc=sb.lc, uc=sb.uc, lv=sb.lv, uv=sb.uv,
+                   **opts)
+
+    @classmethod
+    def from_lps(cls, lps, **opts) -> "BatchSolver":
+        """Ragged batch from a list of LP objects (block-diagonal concatenation)."""
+        ms = np.array([lp.m for lp in lps], dtype=np.int64)
+        ns = np.array([lp.n for lp in lps], dtype=np.int64)
+        row_off = np.concatenate([[0], np.cumsum(ms)])
+        col_off = np.concatenate([[0], np.cumsum(ns)])
+        nnz_off = np.concatenate([[0], np.cumsum([int(lp.rowptr[-1]) for lp in lps])])
+        rowptr = np.concatenate([lp.rowptr[:-1].astype(np.int64) + nnz_off[b] for b, lp in enumerate(lps)]
+                                + [[nnz_off[-1]]])
+        colidx = np.concatenate([lp.colidx.astype(np.int64) + col_off[b] for b, lp in enumerate(lps)])
+        cat = lambda f: np.concatenate([getattr(lp, f) for lp in lps])  # noqa: E731
+        return cls(shared_a=False, batch=len(lps), m=int(row_off[-1]), n=int(col_off[-1]),
+                   rowptr=rowptr, colidx=colidx, val=cat("val"), c=cat("c"), lc=cat("lc"),
+                   uc=cat("uc"), lv=cat("lv"), uv=cat("uv"), row_off=row_off, col_off=col_off,
+                   **opts)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            capi.lib().pdhg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def set_launch(self, threads, workgroups=0):
+        capi.check(capi.lib().pdhg_batch_set_launch(self._h, int(threads), int(workgroups)),
+                   "pdhg_batch_set_launch")
+
+    def autotune(self, iterations=256) -> int:
+        best = C.c_int32()
+        capi.check(capi.lib().pdhg_batch_autotune(self._h, int(iterations), C.byref(best)),
+                   "pdhg_batch_autotune")
+        return best.value
+
+    def solve(self, x_init=None, y_init=None):
+        """Returns (x, y, results): x [B, n] / y [B, m] for a shared A, flat
+        concatenated vectors for a ragged batch; results is a list of dicts."""
+        xi = None if x_init is None else _to_dev(x_init, torch.float64, self.dev).reshape(-1)
+        yi = None if y_init is None else _to_dev(y_init, torch.float64, self.dev).reshape(-1)
+        x = torch.empty(self.vec_n, dtype=torch.float64, device=self.dev)
+        y = torch.empty(max(self.vec_m, 1), dtype=torch.float64, device=self.dev)
+        res = (capi.Result * self.batch)()
+        rc = capi.lib().pdhg_batch_solve(self._h, _ptr(xi), _ptr(yi), _ptr(x), _ptr(y), res)
+        capi.check(rc, "pdhg_batch_solve")
+        out = [r.as_dict() for r in res]
+        y = y[: self.vec_m]
+        if self.shared:
+            return x.reshape(self.batch, self.n), y.reshape(self.batch, self.m), out
+        return x, y, out
+
+    def instance_slices(self, b):
+        """(column slice, row slice) of instance b in the flat ragged vectors."""
+        return (slice(int(self.col_off[b]), int(self.col_off[b + 1])),
+                slice(int(self.row_off[b]), int(self.row_off[b + 1])))
+
+    # -- differentiation by unrolling (LP batches) ---------------------------
+
+    def update_data(self, c=None, lc=None, uc=None, lv=None, uv=None):
+        """New per-instance vectors, laid out as at construction."""
+        def dev(a, length):
+            if a is None:
+                return None
+            t = _to_dev(a, torch.float64, self.dev).reshape(-1)
+            if t.numel() != length:
+                raise ValueError(f"expected {length} values, got {t.numel()}")
+            return t
+        t = [dev(c, self.vec_n), dev(lc, self.vec_m), dev(uc, self.vec_m),
+             dev(lv, self.vec_n), dev(uv, self.vec_n)]
+        rc = capi.lib().pdhg_batch_update_data(self._h, *[_ptr(a) for a in t])
+        capi.check(rc, "pdhg_batch_update_data")
+
+    def unrolled(self, T, replay=False):
+        """Exactly T iterations per instance; returns the PDHG point of the
+        last one (shaped like solve()). replay=True reuses the schedule of the
+        last replay=False call."""
+        x = torch.empty(self.vec_n, dtype=torch.float64, device=self.dev)
+        y = torch.empty(max(self.vec_m, 1), dtype=torch.float64, device=self.dev)
+        rc = capi.lib().pdhg_batch_unrolled_forward(self._h, int(T), int(bool(replay)), _ptr(x), _ptr(y))
+        capi.check(rc, "pdhg_batch_unrolled_forward")
+        y = y[: self.vec_m]
+        if self.shared:
+            return x.reshape(self.batch, self.n), y.reshape(self.batch, self.m)
+        return x, y
+
+    def backward(self, gx, gy=None):
+        """Gradients (gc, glc, guc) of <gx, x_T> + <gy, y_T> for the last unrolled call."""
+        gxt = _to_dev(gx, torch.float64, self.dev).reshape(-1)
+        gyt = None if gy is None else _to_dev(gy, torch.float64, self.dev).reshape(-1)
+        gc = torch.empty(self.vec_n, dtype=torch.float64, device=self.dev)
+        glc = torch.empty(max(self.vec_m, 1), dtype=torch.float64, device=self.dev)
+        guc = torch.empty(max(self.vec_m, 1), dtype=torch.float64, device=self.dev)
+        rc = capi.lib().pdhg_batch_unrolled_backward(self._h, _ptr(gxt), _ptr(gyt), _ptr(gc),
+                                                     _ptr(glc), _ptr(guc))
+        capi.check(rc, "pdhg_batch_unrolled_backward")
+        glc, guc = glc[: self.vec_m], guc[: self.vec_m]
+        if self.shared:
+            return (gc.reshape(self.batch, self.n), glc.reshape(self.batch, self.m),
+                    guc.reshape(self.batch, self.m))
+        return gc, glc, guc
+
+
+class UnrolledLP(torch.autograd.Function):
+    """x_T(c): T unrolled r2HPDHG iterations of a batch, differentiable in c.
+
+    forward(c, solver, T) sets the batch objective to c, runs the unrolled
+    iterations (recording the schedule) and returns x_T; backward runs the
+    hand-written adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, c, solver, T):
+        solver.update_data(c=c.detach())
+        x, _ = solver.unrolled(T)
+        ctx.solver = solver
+        ctx.shape = c.shape
+        return x.reshape(c.shape)
+
+    @staticmethod
+    def backward(ctx, gx):
+        gc, _, _ = ctx.solver.backward(gx.detach().contiguous())
+        return gc.reshape(ctx.shape), None, None

@@ -1,0 +1,96 @@
+"""GPU parity of the batched solver (one persistent launch): every instance
+against the CPU oracle and against the plain GPU solver on that instance."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+from gpu_util import to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pdhg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2412_09734_amd.solver as s
+    return s
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _close(a, b, tol=1e-6):
+    return abs(a - b) <= tol * (1 + abs(b))
+
+
+def test_shared_grid_batch_matches_oracle_and_plain(pdhg, oracle_lib):
+    _say("case: shared-A batch, 12x12 grid min-cost flow, B=24")
+    sb = gen.grid_mincost_batch(batch=24, rows=12, cols=12, seed=3100)
+    with pdhg.BatchSolver.from_shared(sb) as bs:
+        x, y, res = bs.solve()
+    for b in range(sb.batch):
+        lp = sb.instance(b)
+        _, _, ro = oracle_lib.Oracle(lp).solve()
+        with pdhg.Solver.from_lp(lp) as s:
+            _, _, rp = s.solve()
+        rb = res[b]
+        assert rb["status_name"] == "optimal" and rb["kkt_rel"] <= 1e-4, (b, rb)
+        assert _close(rb["primal_obj"], ro["primal_obj"]), (b, rb["primal_obj"], ro["primal_obj"])
+        assert _close(rb["primal_obj"], rp["primal_obj"]), (b, rb["primal_obj"], rp["primal_obj"])
+        kb = oracle_lib.kkt(lp, to_np(x[b]), to_np(y[b]))
+        assert kb["kkt"] <= 1e-4 * (1 + 1e-6)
+    _say(f"  iterations: {[r['iterations'] for r in res[:8]]}")
+
+
+def test_ragged_batch_matches_oracle(pdhg, oracle_lib):
+    _say("case: ragged batch of planted LPs, B=12, m in 50..150")
+    lps = gen.ragged_planted_batch(batch=12, m_lo=50, m_hi=150, seed=3600)
+    with pdhg.BatchSolver.from_lps(lps) as bs:
+        x, y, res = bs.solve()
+        for b, lp in enumerate(lps):
+            _, _, ro = oracle_lib.Oracle(lp).solve()
+            cs, rs = bs.instance_slices(b)
+            rb = res[b]
+            assert rb["status_name"] == "optimal", (b, rb)
+            assert _close(rb["primal_obj"], ro["primal_obj"]), (b, rb["primal_obj"], ro["primal_obj"])
+            assert rb["iterations"] == ro["iterations"], (b, rb["iterations"], ro["iterations"])
+            kb = oracle_lib.kkt(lp, to_np(x[cs]), to_np(y[rs]))
+            assert abs(kb["kkt"] - rb["kkt_rel"]) <= 1e-9 + 1e-6 * kb["kkt"]
+
+
+def test_batch_determinism_and_launch_shapes(pdhg):
+    _say("case: batch determinism across launches and thread counts")
+    sb = gen.grid_mincost_batch(batch=40, rows=8, cols=8, seed=3200)
+    with pdhg.BatchSolver.from_shared(sb) as bs:
+        x1, y1, r1 = bs.solve()
+        x1 = to_np(x1)
+        x2, y2, r2 = bs.solve()
+        np.testing.assert_array_equal(x1, to_np(x2))
+        objs = {}
+        for t in (64, 128, 512):
+            bs.set_launch(t, workgroups=7)
+            _, _, r = bs.solve()
+            objs[t] = [q["primal_obj"] for q in r]
+        best = bs.autotune(64)
+        assert best in (64, 128, 256, 512, 1024)
+    for t, o in objs.items():
+        for a, b in zip(o, [q["primal_obj"] for q in r1]):
+            assert _close(a, b), (t, a, b)
+
+
+def test_batch_iteration_limit(pdhg, oracle_lib):
+    _say("case: batch iteration limit")
+    lps = gen.ragged_planted_batch(batch=4, m_lo=40, m_hi=60, seed=3700)
+    with pdhg.BatchSolver.from_lps(lps, iteration_limit=70) as bs:
+        x, y, res = bs.solve()
+        for b, lp in enumerate(lps):
+            xo, yo, ro = oracle_lib.Oracle(lp, iteration_limit=70).solve()
+            cs, rs = bs.instance_slices(b)
+            assert res[b]["iterations"] == 70 and res[b]["status"] == 4
+            assert np.abs(to_np(x[cs]) - xo).max() <= 1e-10 * max(1.0, np.abs(xo).max())
