@@ -293,13 +293,18 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
         if (p.m < 0 || p.n < 1) fail(PDHG_ERR_INVALID_ARG, "need m >= 0 and n >= 1");
         if (p.mem != PDHG_MEM_HOST && p.mem != PDHG_MEM_DEVICE)
             fail(PDHG_ERR_INVALID_ARG, "mem must be PDHG_MEM_HOST or PDHG_MEM_DEVICE");
-        if (p.a_format != PDHG_FMT_CSR)
-            fail(PDHG_ERR_UNSUPPORTED, "only CSR constraint matrices are supported by pdhg_create");
+        if (p.a_format != PDHG_FMT_CSR && p.a_format != PDHG_FMT_DENSE)
+            fail(PDHG_ERR_INVALID_ARG, "a_format must be PDHG_FMT_CSR or PDHG_FMT_DENSE");
+        if (p.a_format == PDHG_FMT_DENSE && p.q_format != PDHG_FMT_NONE)
+            fail(PDHG_ERR_UNSUPPORTED, "quadratic objectives need a CSR constraint matrix");
+        if (p.a_format == PDHG_FMT_DENSE && p.m > 0 && !p.a_dense)
+            fail(PDHG_ERR_INVALID_ARG, "NULL dense matrix");
         if (p.q_format != PDHG_FMT_NONE && p.q_format != PDHG_FMT_CSR &&
             p.q_format != PDHG_FMT_DENSE && p.q_format != PDHG_FMT_LOWRANK_DIAG)
             fail(PDHG_ERR_INVALID_ARG, "unknown q_format");
-        if (!p.a_rowptr || (p.a_nnz > 0 && (!p.a_colidx || !p.a_val)) || p.a_nnz < 0 ||
-            p.a_nnz >= INT32_MAX)
+        if (p.a_format == PDHG_FMT_CSR &&
+            (!p.a_rowptr || (p.a_nnz > 0 && (!p.a_colidx || !p.a_val)) || p.a_nnz < 0 ||
+             p.a_nnz >= INT32_MAX))
             fail(PDHG_ERR_INVALID_ARG, "bad CSR arrays or nnz");
         if (!p.c || !p.lv || !p.uv || (p.m > 0 && (!p.lc || !p.uc)))
             fail(PDHG_ERR_INVALID_ARG, "NULL objective or bound vector");
@@ -319,7 +324,16 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
         PDHG_HIP(hipEventCreateWithFlags(&h.ev_in, hipEventDisableTiming));
         order_after(h, stream);
         h.st.alloc(1);
-        build_matrices(h, p);
+        h.dense = p.a_format == PDHG_FMT_DENSE;
+        if (h.dense) {
+            dense_build(h, p);
+            h.nbn = dense_col_blocks(h);
+            h.nbm = h.m > 0 ? dense_row_blocks(h) : 0;
+        } else {
+            build_matrices(h, p);
+            h.nbn = h.AT.nblocks();
+            h.nbm = h.A.nblocks();
+        }
         validate_and_load_vectors(h, p);
         scale_problem(h);
         estimate_steps(h);
@@ -328,8 +342,8 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
             qp_build(h, p);
             qp_estimate_norm(h);
         }
-        h.pn.alloc((size_t)std::max(1, h.AT.nblocks()) * 6);
-        h.pm.alloc((size_t)std::max(1, h.A.nblocks()) * 4);
+        h.pn.alloc((size_t)std::max(1, h.nbn) * 6);
+        h.pm.alloc((size_t)std::max(1, h.nbm) * 4);
         PDHG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h.st_host),
                                sizeof(DevState) * h.st_ring, hipHostMallocDefault));
         memset(h.st_host, 0, sizeof(DevState) * h.st_ring);

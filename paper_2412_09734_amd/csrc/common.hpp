@@ -170,6 +170,10 @@ struct Handle {
     DBuf<int32_t> q_rp, q_ci;            // CSR
     DBuf<double> q_va, q_dense, q_f, q_d;  // CSR values, dense n x n, factor n x r, diagonal
     DBuf<double> xbar, ybar, qv_in, qv, qpart, qt;
+    // dense constraint matrix (row-major, scaled in place) and column-pass partials
+    bool dense = false;
+    DBuf<double> Ad, dpart;
+    int32_t nbn = 0, nbm = 0;            // workgroups of the column / row check passes
     ~Handle();
 };
 
@@ -195,6 +199,20 @@ void permute_csr(hipStream_t s, int32_t rows, int32_t cols, int64_t nnz, const i
 double now_seconds();
 void order_after_stream(hipStream_t own, hipEvent_t ev, void *caller);
 void check_options(const pdhg_options &o);
+
+// ---- dense matrices (dense_kernels.hip) --------------------------------------
+void dense_build(Handle &h, const pdhg_problem &p);
+void dense_scale(Handle &h);
+void dense_primal(Handle &h, int32_t j);
+void dense_dual(Handle &h, int32_t j);
+void dense_primal_check(Handle &h, double tau_override);
+void dense_dual_check(Handle &h, double sigma_override);
+void dense_check_sums(Handle &h);
+void dense_rows_sq(Handle &h, const double *v, double *out, double *partials);
+void dense_cols_sq(Handle &h, const double *w, double *out, double *partials);
+int32_t dense_row_blocks(const Handle &h);
+int32_t dense_col_blocks(const Handle &h);
+void launch_factors(Handle &h, double *rn, double *cn);
 
 // ---- rAPDHG (qp_kernels.hip) -------------------------------------------------
 void qp_build(Handle &h, const pdhg_problem &p);

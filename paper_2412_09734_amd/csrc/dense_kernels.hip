@@ -1,0 +1,423 @@
+// Dense constraint matrices (row-major, m x n): the r2HPDHG iteration of
+// eq. (pdhg-lp) / eq. (hrpdhg) with the two products done as HBM-streaming
+// passes over A~ (FP64 GEMV has 0.25 flop per byte, far below the FP64 ridge,
+// so the vector units keep up with HBM and matrix cores would not help):
+//   rows pass    : a_i = A~_i . v, one wave per row, fused with the dual step
+//   columns pass : partial sums of A~' w over 256-column tiles and row splits,
+//                  then a finalize kernel that adds the splits in fixed order
+//                  and applies the primal step.
+// The epilogues repeat the formulas of the sparse kernels exactly.
+#include "device.hpp"
+
+namespace pdhg {
+
+constexpr int kDenseSplits = 16;
+
+enum RowMode : int32_t {
+    ROW_DUAL = 0,      // y <- Halpern(prox)
+    ROW_DUAL_CHK = 1,  // yhat <- prox
+    ROW_CHECK_M = 2,   // check sums over rows
+    ROW_STORE_SQ = 3,  // out = a, partial sum of a^2
+    ROW_ABSMAX = 4,    // out = max |A_i.|
+    ROW_ABSSUM = 5     // out = sum |A_i.|
+};
+
+enum ColMode : int32_t {
+    COL_PRIMAL = 0,
+    COL_PRIMAL_CHK = 1,
+    COL_CHECK_N = 2,
+    COL_STORE_SQ = 3,
+    COL_ABSMAX = 4,
+    COL_ABSSUM = 5
+};
+
+struct DenseVecs {
+    const double *x, *x0, *xhat, *aty, *c, *lv, *uv, *Dc, *c_o, *lv_o, *uv_o;
+    double *xw, *xext, *xhat_w, *aty_w;
+    const double *y, *y0, *yhat, *lc, *uc, *Dr, *lc_o, *uc_o;
+    double *yw, *yhat_w;
+    double *out, *partials;
+    const DevState *st;
+    int32_t j;
+    double gamma, tau_o, sigma_o;
+};
+
+// One wave per row: a = sum_c A[i][c] v[c] (lanes strided, butterfly), or |A| norms.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict__ A, int32_t m,
+                                                       int32_t n, const double *__restrict__ v,
+                                                       DenseVecs d) {
+    if (d.st && d.st->done) return;
+    const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+    const int32_t lane = threadIdx.x & 63;
+    double acc = 0.0;
+    if (row < m) {
+        const double *__restrict__ Ar = A + (size_t)row * n;
+        if (MODE == ROW_ABSMAX || MODE == ROW_ABSSUM) {
+            for (int32_t c = lane; c < n; c += 64) {
+                const double a = fabs(Ar[c]);
+                acc = MODE == ROW_ABSMAX ? fmax(acc, a) : acc + a;
+            }
+        } else {
+            int32_t c = lane;
+            for (; c + 192 < n; c += 256) {
+                const double a0 = __builtin_nontemporal_load(Ar + c);
+                const double a1 = __builtin_nontemporal_load(Ar + c + 64);
+                const double a2 = __builtin_nontemporal_load(Ar + c + 128);
+                const double a3 = __builtin_nontemporal_load(Ar + c + 192);
+                acc = fma(a0, v[c], acc);
+                acc = fma(a1, v[c + 64], acc);
+                acc = fma(a2, v[c + 128], acc);
+                acc = fma(a3, v[c + 192], acc);
+            }
+            for (; c < n; c += 64) acc = fma(__builtin_nontemporal_load(Ar + c), v[c], acc);
+        }
+    }
+    if (MODE == ROW_ABSMAX) {
+        for (int off = 32; off > 0; off >>= 1) acc = fmax(acc, __shfl_xor(acc, off));
+    } else {
+        acc = wave_sum(acc);
+    }
+    const bool own = row < m && lane == 0;
+    if (MODE == ROW_CHECK_M || MODE == ROW_STORE_SQ) {
+        double vals[4] = {0.0, 0.0, 0.0, 0.0};
+        if (own) {
+            const int64_t r = row;
+            if (MODE == ROW_STORE_SQ) {
+                d.out[r] = acc;
+                vals[0] = acc * acc;
+            } else {
+                const double dr = d.Dr[r];
+                const double ax = acc / dr;
+                const double lo = d.lc_o[r], hi = d.uc_o[r];
+                const double rpr = ax - clampd(ax, lo, hi);
+                vals[0] = rpr * rpr;
+                const double yh = d.yhat[r];
+                const double yo = dr * yh;
+                vals[1] = (isfinite(lo) ? lo * fmax(yo, 0.0) : 0.0) - (isfinite(hi) ? hi * fmax(-yo, 0.0) : 0.0);
+                const double dy = yh - d.y[r];
+                vals[2] = dy * dy;
+                const double d0 = yh - d.y0[r];
+                vals[3] = d0 * d0;
+            }
+        }
+        if (MODE == ROW_STORE_SQ) {
+            double q[1] = {vals[0]};
+            block_sum_store<1>(q, d.partials + blockIdx.x);
+        } else {
+            block_sum_store<4>(vals, d.partials + (size_t)blockIdx.x * 4);
+        }
+        return;
+    }
+    if (!own) return;
+    const int64_t r = row;
+    if (MODE == ROW_ABSMAX || MODE == ROW_ABSSUM) {
+        d.out[r] = acc;
+    } else if (MODE == ROW_DUAL) {
+        const double sigma = d.st->sigma;
+        const int64_t k = d.st->k_base + (d.j - 1);
+        const double yr = d.y[r];
+        const double yh = dual_prox(yr, acc, sigma, d.lc[r], d.uc[r]);
+        const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+        d.yw[r] = ak * ((1.0 + d.gamma) * yh - d.gamma * yr) + bk * d.y0[r];
+    } else if (MODE == ROW_DUAL_CHK) {
+        const double sigma = d.sigma_o > 0.0 ? d.sigma_o : d.st->sigma;
+        d.yhat_w[r] = dual_prox(d.y[r], acc, sigma, d.lc[r], d.uc[r]);
+    }
+}
+
+// Partial column sums: partials[split][c] = sum over the split's rows of A[i][c] w[i].
+template <bool ABSMAX, bool ABSSUM>
+__global__ __launch_bounds__(kBlock) void k_dense_cols_partial(const double *__restrict__ A,
+                                                               int32_t m, int32_t n,
+                                                               const double *__restrict__ w,
+                                                               double *__restrict__ partials,
+                                                               const DevState *__restrict__ st) {
+    if (st && st->done) return;
+    const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int32_t split = blockIdx.y;
+    const int32_t rows_per = (m + kDenseSplits - 1) / kDenseSplits;
+    const int32_t r0 = split * rows_per, r1 = min(m, r0 + rows_per);
+    if (col >= n) return;
+    double acc = 0.0;
+    const double *__restrict__ Ac = A + col;
+    int32_t i = r0;
+    if (ABSMAX || ABSSUM) {
+        for (; i < r1; ++i) {
+            const double a = fabs(Ac[(size_t)i * n]);
+            acc = ABSMAX ? fmax(acc, a) : acc + a;
+        }
+    } else {
+        for (; i + 3 < r1; i += 4) {
+            const double a0 = __builtin_nontemporal_load(Ac + (size_t)i * n);
+            const double a1 = __builtin_nontemporal_load(Ac + (size_t)(i + 1) * n);
+            const double a2 = __builtin_nontemporal_load(Ac + (size_t)(i + 2) * n);
+            const double a3 = __builtin_nontemporal_load(Ac + (size_t)(i + 3) * n);
+            acc = fma(a0, w[i], acc);
+            acc = fma(a1, w[i + 1], acc);
+            acc = fma(a2, w[i + 2], acc);
+            acc = fma(a3, w[i + 3], acc);
+        }
+        for (; i < r1; ++i) acc = fma(__builtin_nontemporal_load(Ac + (size_t)i * n), w[i], acc);
+    }
+    partials[(size_t)split * n + col] = acc;
+}
+
+// Splits added in order 0..S-1, then the column epilogue.
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_dense_cols_final(int32_t n, const double *__restrict__ part,
+                                                             DenseVecs d) {
+    if (d.st && d.st->done) return;
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double s = 0.0;
+    if (r < n) {
+        for (int q = 0; q < kDenseSplits; ++q) {
+            const double p = part[(size_t)q * n + r];
+            s = MODE == COL_ABSMAX ? fmax(s, p) : s + p;
+        }
+    }
+    if (MODE == COL_CHECK_N || MODE == COL_STORE_SQ) {
+        double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (r < n) {
+            if (MODE == COL_STORE_SQ) {
+                d.out[r] = s;
+                v[0] = s * s;
+            } else {
+                const double q = s;
+                const double xh = d.xhat[r];
+                const double dx = xh - d.x[r];
+                v[0] = dx * dx;
+                v[1] = (q - d.aty[r]) * dx;
+                const double d0 = xh - d.x0[r];
+                v[2] = d0 * d0;
+                const double dd = d.Dc[r];
+                const double xo = dd * xh;
+                const double g = d.c_o[r] - q / dd;
+                const double lo = d.lv_o[r], hi = d.uv_o[r];
+                const bool lf = isfinite(lo), uf = isfinite(hi);
+                const double lam = (!lf && !uf) ? 0.0 : (lf && !uf) ? fmax(g, 0.0) : (!lf && uf) ? fmin(g, 0.0) : g;
+                const double rd = g - lam;
+                v[3] = rd * rd;
+                v[4] = d.c_o[r] * xo;
+                v[5] = (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
+            }
+        }
+        if (MODE == COL_STORE_SQ) {
+            double q1[1] = {v[0]};
+            block_sum_store<1>(q1, d.partials + blockIdx.x);
+        } else {
+            block_sum_store<6>(v, d.partials + (size_t)blockIdx.x * 6);
+        }
+        return;
+    }
+    if (r >= n) return;
+    if (MODE == COL_ABSMAX || MODE == COL_ABSSUM) {
+        d.out[r] = s;
+    } else if (MODE == COL_PRIMAL) {
+        const double tau = d.st->tau;
+        const int64_t k = d.st->k_base + (d.j - 1);
+        const double xr = d.x[r];
+        const double xh = clampd(xr - tau * (d.c[r] - s), d.lv[r], d.uv[r]);
+        const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+        d.xext[r] = 2.0 * xh - xr;
+        d.xw[r] = ak * ((1.0 + d.gamma) * xh - d.gamma * xr) + bk * d.x0[r];
+    } else if (MODE == COL_PRIMAL_CHK) {
+        const double tau = d.tau_o > 0.0 ? d.tau_o : d.st->tau;
+        const double xr = d.x[r];
+        const double xh = clampd(xr - tau * (d.c[r] - s), d.lv[r], d.uv[r]);
+        d.xhat_w[r] = xh;
+        d.xext[r] = 2.0 * xh - xr;
+        d.aty_w[r] = s;
+    }
+}
+
+// A~_ij <- A~_ij / (r_i s_j) elementwise; also finite check of the input.
+__global__ __launch_bounds__(kBlock) void k_dense_scale(double *__restrict__ A, int32_t m, int32_t n,
+                                                        const double *__restrict__ rf,
+                                                        const double *__restrict__ cf) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t total = (int64_t)m * n;
+    for (int64_t e = t; e < total; e += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = e / n, j = e - i * n;
+        A[e] = A[e] / (rf[i] * cf[j]);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dense_finite(const double *__restrict__ A, int64_t total,
+                                                         int32_t *__restrict__ flag) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (int64_t e = t; e < total; e += (int64_t)gridDim.x * kBlock)
+        if (!isfinite(A[e])) atomicOr(flag, 2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_iota(int32_t *__restrict__ p, int32_t len) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) p[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+static unsigned dblk(int64_t len) { return (unsigned)std::max<int64_t>(1, ceil_div(len, kBlock)); }
+
+static DenseVecs dvecs(Handle &h, int32_t j) {
+    DenseVecs d;
+    memset(&d, 0, sizeof(d));
+    d.x = h.x.p;
+    d.x0 = h.x0.p;
+    d.xhat = h.xhat.p;
+    d.aty = h.aty.p;
+    d.c = h.c.p;
+    d.lv = h.lv.p;
+    d.uv = h.uv.p;
+    d.Dc = h.Dc.p;
+    d.c_o = h.c_o.p;
+    d.lv_o = h.lv_o.p;
+    d.uv_o = h.uv_o.p;
+    d.xw = h.x.p;
+    d.xext = h.xext.p;
+    d.xhat_w = h.xhat.p;
+    d.aty_w = h.aty.p;
+    d.y = h.y.p;
+    d.y0 = h.y0.p;
+    d.yhat = h.yhat.p;
+    d.lc = h.lc.p;
+    d.uc = h.uc.p;
+    d.Dr = h.Dr.p;
+    d.lc_o = h.lc_o.p;
+    d.uc_o = h.uc_o.p;
+    d.yw = h.y.p;
+    d.yhat_w = h.yhat.p;
+    d.st = h.st.p;
+    d.j = j;
+    d.gamma = h.opt.gamma;
+    d.tau_o = -1.0;
+    d.sigma_o = -1.0;
+    return d;
+}
+
+static unsigned row_blocks(int32_t m) { return dblk((int64_t)m * 64); }
+static unsigned col_blocks(int32_t n) { return dblk(n); }
+
+int32_t dense_row_blocks(const Handle &h) { return (int32_t)row_blocks(h.m); }
+int32_t dense_col_blocks(const Handle &h) { return (int32_t)col_blocks(h.n); }
+
+static void cols_partial(Handle &h, const double *w, const DevState *st) {
+    dim3 grid(col_blocks(h.n), kDenseSplits);
+    k_dense_cols_partial<false, false><<<grid, kBlock, 0, h.stream>>>(h.Ad.p, h.m, h.n, w, h.dpart.p, st);
+}
+
+void dense_primal(Handle &h, int32_t j) {
+    cols_partial(h, h.y.p, h.st.p);
+    k_dense_cols_final<COL_PRIMAL><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, h.dpart.p, dvecs(h, j));
+}
+
+void dense_dual(Handle &h, int32_t j) {
+    if (h.m == 0) return;
+    k_dense_rows<ROW_DUAL><<<row_blocks(h.m), kBlock, 0, h.stream>>>(h.Ad.p, h.m, h.n, h.xext.p, dvecs(h, j));
+}
+
+void dense_primal_check(Handle &h, double tau_override) {
+    cols_partial(h, h.y.p, h.st.p);
+    DenseVecs d = dvecs(h, 0);
+    d.tau_o = tau_override;
+    k_dense_cols_final<COL_PRIMAL_CHK><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, h.dpart.p, d);
+}
+
+void dense_dual_check(Handle &h, double sigma_override) {
+    if (h.m == 0) return;
+    DenseVecs d = dvecs(h, 0);
+    d.sigma_o = sigma_override;
+    k_dense_rows<ROW_DUAL_CHK><<<row_blocks(h.m), kBlock, 0, h.stream>>>(h.Ad.p, h.m, h.n, h.xext.p, d);
+}
+
+void dense_check_sums(Handle &h) {
+    cols_partial(h, h.yhat.p, h.st.p);
+    DenseVecs d = dvecs(h, 0);
+    d.partials = h.pn.p;
+    k_dense_cols_final<COL_CHECK_N><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, h.dpart.p, d);
+    if (h.m > 0) {
+        DenseVecs e = dvecs(h, 0);
+        e.partials = h.pm.p;
+        k_dense_rows<ROW_CHECK_M><<<row_blocks(h.m), kBlock, 0, h.stream>>>(h.Ad.p, h.m, h.n, h.xhat.p, e);
+    }
+}
+
+// out = A~ v with partial sums of out^2 (rows), for the power iteration
+void dense_rows_sq(Handle &h, const double *v, double *out, double *partials) {
+    DenseVecs d = dvecs(h, 0);
+    d.st = nullptr;
+    d.out = out;
+    d.partials = partials;
+    k_dense_rows<ROW_STORE_SQ><<<row_blocks(h.m), kBlock, 0, h.stream>>>(h.Ad.p, h.m, h.n, v, d);
+}
+
+// out = A~' w with partial sums of out^2 (columns)
+void dense_cols_sq(Handle &h, const double *w, double *out, double *partials) {
+    cols_partial(h, w, nullptr);
+    DenseVecs d = dvecs(h, 0);
+    d.st = nullptr;
+    d.out = out;
+    d.partials = partials;
+    k_dense_cols_final<COL_STORE_SQ><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, h.dpart.p, d);
+}
+
+void dense_build(Handle &h, const pdhg_problem &p) {
+    hipStream_t s = h.stream;
+    const int64_t total = (int64_t)h.m * h.n;
+    h.Ad.alloc((size_t)std::max<int64_t>(1, total));
+    if (total > 0)
+        PDHG_HIP(hipMemcpyAsync(h.Ad.p, p.a_dense, sizeof(double) * (size_t)total,
+                                p.mem == PDHG_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                         : hipMemcpyHostToDevice,
+                                s));
+    DBuf<int32_t> flag;
+    flag.alloc(1);
+    PDHG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+    if (total > 0) k_dense_finite<<<4096, kBlock, 0, s>>>(h.Ad.p, total, flag.p);
+    check_flag(s, flag.p, "non-finite entry in the dense matrix");
+    h.perm_r.alloc(h.m);
+    h.perm_c.alloc(h.n);
+    if (h.m) k_iota<<<dblk(h.m), kBlock, 0, s>>>(h.perm_r.p, h.m);
+    k_iota<<<dblk(h.n), kBlock, 0, s>>>(h.perm_c.p, h.n);
+    h.dpart.alloc((size_t)kDenseSplits * h.n);
+    h.A.rows = h.m;
+    h.A.cols = h.n;
+    h.A.nnz = total;
+    h.AT.rows = h.n;
+    h.AT.cols = h.m;
+    h.AT.nnz = total;
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
+void dense_scale(Handle &h) {
+    hipStream_t s = h.stream;
+    const int32_t m = h.m, n = h.n;
+    DBuf<double> rn, cn;
+    rn.alloc(m);
+    cn.alloc(n);
+    const int passes = h.opt.ruiz_iters + (h.opt.pock_chambolle ? 1 : 0);
+    for (int pass = 0; pass < passes && m > 0; ++pass) {
+        const bool pc = pass >= h.opt.ruiz_iters;
+        DenseVecs d = dvecs(h, 0);
+        d.st = nullptr;
+        d.out = rn.p;
+        dim3 grid(col_blocks(n), kDenseSplits);
+        if (pc) {
+            k_dense_rows<ROW_ABSSUM><<<row_blocks(m), kBlock, 0, s>>>(h.Ad.p, m, n, nullptr, d);
+            k_dense_cols_partial<false, true><<<grid, kBlock, 0, s>>>(h.Ad.p, m, n, nullptr, h.dpart.p, nullptr);
+            d.out = cn.p;
+            k_dense_cols_final<COL_ABSSUM><<<col_blocks(n), kBlock, 0, s>>>(n, h.dpart.p, d);
+        } else {
+            k_dense_rows<ROW_ABSMAX><<<row_blocks(m), kBlock, 0, s>>>(h.Ad.p, m, n, nullptr, d);
+            k_dense_cols_partial<true, false><<<grid, kBlock, 0, s>>>(h.Ad.p, m, n, nullptr, h.dpart.p, nullptr);
+            d.out = cn.p;
+            k_dense_cols_final<COL_ABSMAX><<<col_blocks(n), kBlock, 0, s>>>(n, h.dpart.p, d);
+        }
+        launch_factors(h, rn.p, cn.p);
+        k_dense_scale<<<8192, kBlock, 0, s>>>(h.Ad.p, m, n, rn.p, cn.p);
+    }
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace pdhg

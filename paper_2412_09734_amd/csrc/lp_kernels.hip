@@ -356,6 +356,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter_scaled(const int32_t *__rest
 static inline dim3 grid_of(const HMat &M) { return dim3((unsigned)M.nblocks()); }
 
 void launch_primal(Handle &h, int32_t j) {
+    if (h.dense) {
+        dense_primal(h, j);
+        return;
+    }
     if (h.AT.nblocks() == 0) return;
     k_primal<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
         view(h.AT), h.y.p, h.x.p, h.x0.p, h.c.p, h.lv.p,
@@ -363,12 +367,20 @@ void launch_primal(Handle &h, int32_t j) {
 }
 
 void launch_dual(Handle &h, int32_t j) {
+    if (h.dense) {
+        dense_dual(h, j);
+        return;
+    }
     if (h.A.nblocks() == 0) return;
     k_dual<<<grid_of(h.A), kBlock, 0, h.stream>>>(view(h.A), h.xext.p, h.y.p, h.y0.p, h.lc.p,
                                                   h.uc.p, h.st.p, j, h.opt.gamma);
 }
 
 void launch_primal_check(Handle &h, double tau_override) {
+    if (h.dense) {
+        dense_primal_check(h, tau_override);
+        return;
+    }
     if (h.AT.nblocks() == 0) return;
     k_primal_chk<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
         view(h.AT), h.y.p, h.x.p, h.c.p, h.lv.p, h.uv.p,
@@ -376,12 +388,20 @@ void launch_primal_check(Handle &h, double tau_override) {
 }
 
 void launch_dual_check(Handle &h, double sigma_override) {
+    if (h.dense) {
+        dense_dual_check(h, sigma_override);
+        return;
+    }
     if (h.A.nblocks() == 0) return;
     k_dual_chk<<<grid_of(h.A), kBlock, 0, h.stream>>>(view(h.A), h.xext.p, h.y.p, h.lc.p,
                                                       h.uc.p, h.yhat.p, h.st.p, sigma_override);
 }
 
 void launch_check_sums(Handle &h) {
+    if (h.dense) {
+        dense_check_sums(h);
+        return;
+    }
     if (h.AT.nblocks())
         k_check_n<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
             view(h.AT), h.yhat.p, h.xhat.p, h.x.p,
@@ -403,8 +423,8 @@ void launch_controller(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t 
     K.beta_art = h.opt.restart_artificial;
     K.qp = 0;
     K.pad = 0;
-    k_controller<<<1, kBlock, 0, h.stream>>>(h.st.p, h.pn.p, h.AT.nblocks(), h.pm.p,
-                                              h.A.nblocks(), K, chunk_plain, is_last,
+    k_controller<<<1, kBlock, 0, h.stream>>>(h.st.p, h.pn.p, h.nbn, h.pm.p,
+                                              h.nbm, K, chunk_plain, is_last,
                                               last_status);
 }
 

@@ -489,7 +489,7 @@ void launch_qp_check(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t la
     K.norm_q = h.norm_q;
     K.qp = 1;
     K.pad = 0;
-    k_qp_controller<<<1, kBlock, 0, s>>>(h.st.p, h.pn.p, h.AT.nblocks(), h.pm.p, h.A.nblocks(), K,
+    k_qp_controller<<<1, kBlock, 0, s>>>(h.st.p, h.pn.p, h.nbn, h.pm.p, h.nbm, K,
                                          chunk_plain, is_last, last_status);
     k_qp_apply<<<nblk((int64_t)h.n + h.m), kBlock, 0, s>>>(h.st.p, h.n, h.m, h.x.p, h.x0.p,
                                                           h.xbar.p, h.y.p, h.y0.p, h.ybar.p);

@@ -714,6 +714,11 @@ void validate_and_load_vectors(Handle &h, const pdhg_problem &p) {
     PDHG_HIP(hipStreamSynchronize(s));
 }
 
+void launch_factors(Handle &h, double *rn, double *cn) {
+    if (h.m > 0) k_factors<<<blocks_for(h.m), kBlock, 0, h.stream>>>(rn, h.Dr.p, h.m);
+    k_factors<<<blocks_for(h.n), kBlock, 0, h.stream>>>(cn, h.Dc.p, h.n);
+}
+
 void scale_problem(Handle &h) {
     hipStream_t s = h.stream;
     const int32_t m = h.m, n = h.n;
@@ -725,6 +730,12 @@ void scale_problem(Handle &h) {
     cn.alloc(n);
     const MatView VA = view(h.A), VT = view(h.AT);
     const int32_t nbA = h.A.nblocks(), nbT = h.AT.nblocks();
+    if (h.dense) {
+        dense_scale(h);
+        transform_vectors(h);
+        PDHG_HIP(hipStreamSynchronize(s));
+        return;
+    }
     for (int pass = 0; pass < passes && h.A.nnz > 0; ++pass) {
         const bool pc = pass >= h.opt.ruiz_iters;
         if (nbA) {
@@ -759,8 +770,16 @@ void estimate_steps(Handle &h) {
     if (h.A.nnz > 0 && m > 0) {
         // power iteration on A~'A~: lam_k = |A~ v_k|^2 with |v_k| = 1
         const int maxit = std::max(1, h.opt.power_max_iters);
-        const int32_t nbA = h.A.nblocks(), nbT = h.AT.nblocks();
+        const int32_t nbA = h.nbm, nbT = h.nbn;
         const MatView VA = view(h.A), VT = view(h.AT);
+        auto mul_a = [&](const double *vin, double *wout, double *part) {
+            if (h.dense) dense_rows_sq(h, vin, wout, part);
+            else k_spmv_sq<<<nbA, kBlock, 0, s>>>(VA, vin, wout, part);
+        };
+        auto mul_at = [&](const double *win, double *uout, double *part) {
+            if (h.dense) dense_cols_sq(h, win, uout, part);
+            else k_spmv_sq<<<nbT, kBlock, 0, s>>>(VT, win, uout, part);
+        };
         DBuf<double> v, w, u, pw, pu, tot, hist;
         v.alloc(n);
         w.alloc(m);
@@ -780,9 +799,9 @@ void estimate_steps(Handle &h) {
         for (int it0 = 1; it0 <= maxit && !stop; it0 += batch) {
             const int it1 = std::min(maxit, it0 + batch - 1);
             for (int it = it0; it <= it1; ++it) {
-                k_spmv_sq<<<nbA, kBlock, 0, s>>>(VA, v.p, w.p, pw.p);
+                mul_a(v.p, w.p, pw.p);
                 k_total<1><<<1, kBlock, 0, s>>>(pw.p, nbA, tot.p);
-                k_spmv_sq<<<nbT, kBlock, 0, s>>>(VT, w.p, u.p, pu.p);
+                mul_at(w.p, u.p, pu.p);
                 k_total<1><<<1, kBlock, 0, s>>>(pu.p, nbT, tot.p + 1);
                 k_power_normalize<<<blocks_for(n), kBlock, 0, s>>>(u.p, v.p, n, tot.p,
                                                                    tot.p + 1, hist.p, it);

@@ -55,15 +55,18 @@ class Solver:
 
     def __init__(self, m, n, rowptr, colidx, val, c, lc, uc, lv, uv, *, q_format="none",
                  q_rowptr=None, q_colidx=None, q_val=None, q_dense=None, q_factor=None,
-                 q_diag=None, device=None, **opts):
+                 q_diag=None, a_dense=None, device=None, **opts):
         self.dev = _device(device)
         self.m, self.n = int(m), int(n)
         self._opts = options(**opts)
         self.qp = q_format != "none"
         with torch.cuda.device(self.dev):
-            t = dict(rowptr=_to_dev(rowptr, torch.int32, self.dev),
-                     colidx=_to_dev(colidx, torch.int32, self.dev),
-                     val=_to_dev(val, torch.float64, self.dev),
+            dense = a_dense is not None
+            z32 = torch.zeros(1, dtype=torch.int32, device=self.dev)
+            z64 = torch.zeros(1, dtype=torch.float64, device=self.dev)
+            t = dict(rowptr=z32 if dense else _to_dev(rowptr, torch.int32, self.dev),
+                     colidx=z32 if dense else _to_dev(colidx, torch.int32, self.dev),
+                     val=z64 if dense else _to_dev(val, torch.float64, self.dev),
                      c=_to_dev(c, torch.float64, self.dev),
                      lc=_to_dev(lc, torch.float64, self.dev),
                      uc=_to_dev(uc, torch.float64, self.dev),
@@ -74,6 +77,9 @@ class Solver:
             p.a_format = capi.FMT_CSR
             p.a_rowptr, p.a_colidx, p.a_val = t["rowptr"].data_ptr(), t["colidx"].data_ptr(), t["val"].data_ptr()
             p.a_nnz = int(t["colidx"].numel())
+            if dense:
+                t["dense"] = _to_dev(a_dense, torch.float64, self.dev)
+                p.a_format, p.a_dense, p.a_nnz = capi.FMT_DENSE, t["dense"].data_ptr(), 0
             p.c, p.lc, p.uc = t["c"].data_ptr(), t["lc"].data_ptr(), t["uc"].data_ptr()
             p.lv, p.uv = t["lv"].data_ptr(), t["uv"].data_ptr()
             p.q_format = capi.FMT_NONE
@@ -114,6 +120,8 @@ class Solver:
             q = dict(q_format="lowrank", q_factor=lp.q_factor, q_diag=lp.q_diag)
         elif kind == "dense":
             q = dict(q_format="dense", q_dense=lp.q_dense)
+        if getattr(lp, "dense", None) is not None:
+            q["a_dense"] = lp.dense
         return cls(lp.m, lp.n, lp.rowptr, lp.colidx, lp.val, lp.c, lp.lc, lp.uc, lp.lv, lp.uv,
                    **q, **opts)
 
