@@ -94,6 +94,11 @@ def lib():
         L.orc_unrolled_lp.restype = C.c_int
         L.orc_unrolled_lp_backward.argtypes = [P, C.c_int64, P, P, P, P, P, P, P]
         L.orc_unrolled_lp_backward.restype = C.c_int
+        L.orc_pin_steps.argtypes = [P, C.c_double, C.c_double]
+        L.orc_unrolled_qp.argtypes = [P, C.c_int64, P, P, P, P, P, P]
+        L.orc_unrolled_qp.restype = C.c_int
+        L.orc_unrolled_qp_backward.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, P]
+        L.orc_unrolled_qp_backward.restype = C.c_int
         _lib = L
     return _lib
 
@@ -195,6 +200,9 @@ class Oracle:
         return dict(dr=dr[: self.m], dc=dc, eta=vals[0].value, omega=vals[1].value,
                     norm_a=vals[2].value, norm_q=vals[3].value, power_iters=it.value)
 
+    def pin_steps(self, eta, norm_q):
+        lib().orc_pin_steps(self._ctx, float(eta), float(norm_q))
+
     def scaled_vectors(self) -> dict:
         out = dict(c=np.zeros(self.n), lc=np.zeros(max(self.m, 1)), uc=np.zeros(max(self.m, 1)),
                    lv=np.zeros(self.n), uv=np.zeros(self.n))
@@ -246,6 +254,33 @@ class Oracle:
         if rc != 0:
             raise ValueError("unrolled forward rejected")
         return x, y[: self.m], rec_r, rec_w
+
+    def unrolled_qp(self, T, sched_restart=None, sched_omega=None):
+        x = np.zeros(self.n)
+        y = np.zeros(max(self.m, 1))
+        rec_r = np.zeros(T, dtype=np.uint8)
+        rec_w = np.zeros(T)
+        sr = None if sched_restart is None else np.ascontiguousarray(sched_restart, dtype=np.uint8)
+        sw = _f64(sched_omega)
+        rc = lib().orc_unrolled_qp(self._ctx, int(T), _ptr(sr), _ptr(sw), _ptr(rec_r), _ptr(rec_w),
+                                   _ptr(x), _ptr(y))
+        if rc != 0:
+            raise ValueError("unrolled QP forward rejected")
+        return x, y[: self.m], rec_r, rec_w
+
+    def backward_qp(self, T, sched_restart, sched_omega, gx, gy):
+        sr = np.ascontiguousarray(sched_restart, dtype=np.uint8)
+        sw = _f64(sched_omega)
+        gx = _f64(gx)
+        gy = _f64(gy) if self.m else np.zeros(1)
+        gc, gd = np.zeros(self.n), np.zeros(self.n)
+        glc = np.zeros(max(self.m, 1))
+        guc = np.zeros(max(self.m, 1))
+        rc = lib().orc_unrolled_qp_backward(self._ctx, int(T), _ptr(sr), _ptr(sw), _ptr(gx),
+                                            _ptr(gy), _ptr(gc), _ptr(glc), _ptr(guc), _ptr(gd))
+        if rc != 0:
+            raise ValueError("unrolled QP backward rejected")
+        return gc, glc[: self.m], guc[: self.m], gd
 
     def backward(self, T, sched_restart, sched_omega, gx, gy):
         sr = np.ascontiguousarray(sched_restart, dtype=np.uint8)

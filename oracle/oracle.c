@@ -426,6 +426,11 @@ void orc_scaling(const orc_ctx *s, double *dr, double *dc, double *eta, double *
     if (power_iters) *power_iters = s->power_iters;
 }
 
+void orc_pin_steps(orc_ctx *s, double eta, double norm_q) {
+    s->eta = eta;
+    s->norm_q = norm_q;
+}
+
 void orc_scaled_vectors(const orc_ctx *s, double *c, double *lc, double *uc, double *lv,
                         double *uv) {
     if (c) memcpy(c, s->c, sizeof(double) * s->n);
@@ -950,5 +955,187 @@ int orc_unrolled_lp_backward(orc_ctx *s, int64_t T, const uint8_t *sched_restart
     free(tr.xmask); free(tr.ymask); free(tr.kk); free(xo); free(yo);
     free(bx); free(by); free(bx0); free(by0); free(bxh); free(byh); free(bxe); free(ba);
     free(bu); free(tmp_n); free(tmp_m); free(gcs); free(glcs); free(gucs);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* unrolled rAPDHG and its reverse pass (frozen schedule)                     */
+
+/* Forward of T iterations; when `keep` is given, stores per iteration the
+ * momentum point v, the box-interior mask of x and the clamp state of y, and
+ * the inner counter. */
+typedef struct {
+    double *v;        /* [T*n] */
+    uint8_t *xmask;   /* [T*n] */
+    uint8_t *ymask;   /* [T*m] */
+    int64_t *kk;      /* [T] */
+} qp_trace;
+
+static void qp_unrolled_core(orc_ctx *s, int64_t T, const uint8_t *sched_restart,
+                             const double *sched_omega, uint8_t *rec_restart, double *rec_omega,
+                             double *x_out, double *y_out, qp_trace *keep) {
+    const int32_t m = s->m, n = s->n;
+    double *x = dalloc(n), *y = dalloc(m), *xb = dalloc(n), *yb = dalloc(m);
+    double *x0 = dalloc(n), *y0 = dalloc(m);
+    double *v = dalloc(n), *qv = dalloc(n), *aty = dalloc(n), *xe = dalloc(n), *a = dalloc(m);
+    double *xo = dalloc(n), *yo = dalloc(m);
+    init_point(s, NULL, NULL, x, y);
+    memcpy(xb, x, sizeof(double) * n); memcpy(yb, y, sizeof(double) * m);
+    memcpy(x0, x, sizeof(double) * n); memcpy(y0, y, sizeof(double) * m);
+    double omega = s->omega0, r_start = 0.0, r_prev = 0.0;
+    int64_t k = 0;
+    orc_result res;
+    for (int64_t t = 0; t < T; ++t) {
+        if (sched_omega) omega = sched_omega[t];
+        if (rec_omega) rec_omega[t] = omega;
+        const double beta = 2.0 / (double)(k + 2), theta = beta;
+        const double tau = 1.0 / (omega / s->eta + 2.0 * s->norm_q / (double)(k + 1));
+        const double sigma = s->eta * omega;
+        for (int32_t j = 0; j < n; ++j) v[j] = (1.0 - beta) * xb[j] + beta * x[j];
+        q_mul(s, v, qv);
+        at_mul(s, y, aty);
+        for (int32_t j = 0; j < n; ++j) {
+            double u = x[j] - tau * (qv[j] + s->c[j] - aty[j]);
+            double xp = clampd(u, s->lv[j], s->uv[j]);
+            if (keep) {
+                keep->v[t * n + j] = v[j];
+                keep->xmask[t * n + j] = (u > s->lv[j] && u < s->uv[j]) ? 1 : 0;
+            }
+            xe[j] = 2.0 * xp - x[j];
+            x[j] = xp;
+            xb[j] = (1.0 - theta) * xb[j] + theta * xp;
+        }
+        a_mul(s, xe, a);
+        for (int32_t i = 0; i < m; ++i) {
+            double w = y[i] / sigma - a[i];
+            if (keep) keep->ymask[t * m + i] = w < -s->uc[i] ? 1 : (w > -s->lc[i] ? 2 : 0);
+            double yp = sigma * (w - clampd(w, -s->uc[i], -s->lc[i]));
+            y[i] = yp;
+            yb[i] = (1.0 - theta) * yb[i] + theta * yp;
+        }
+        if (keep) keep->kk[t] = k;
+        if (t + 1 >= T) break;
+        int restart = 0;
+        if (sched_restart) {
+            restart = sched_restart[t];
+        } else if ((t % s->o.check_every) == 0) {
+            unscale(s, xb, yb, xo, yo);
+            orc_kkt(&s->p, xo, yo, &res);
+            double r = sqrt(omega * res.abs_primal * res.abs_primal +
+                            res.abs_dual * res.abs_dual / omega + res.abs_gap * res.abs_gap);
+            if (t == 0) { r_start = r; r_prev = r; }
+            else if (restart_due(s, r, r_start, r_prev, k, t)) restart = 1;
+            else r_prev = r;
+            if (restart) {
+                ld dx2 = 0.0L, dy2 = 0.0L;
+                for (int32_t j = 0; j < n; ++j) dx2 += (ld)(xb[j] - x0[j]) * (xb[j] - x0[j]);
+                for (int32_t i = 0; i < m; ++i) dy2 += (ld)(yb[i] - y0[i]) * (yb[i] - y0[i]);
+                omega = new_weight(omega, (double)sqrtl(dx2), (double)sqrtl(dy2));
+                r_start = r;
+                r_prev = r;
+            }
+        }
+        if (rec_restart) rec_restart[t] = (uint8_t)restart;
+        if (restart) {
+            memcpy(x, xb, sizeof(double) * n); memcpy(x0, xb, sizeof(double) * n);
+            memcpy(y, yb, sizeof(double) * m); memcpy(y0, yb, sizeof(double) * m);
+            k = 0;
+        } else {
+            ++k;
+        }
+    }
+    if (x_out) unscale(s, xb, yb, x_out, y_out);
+    free(x); free(y); free(xb); free(yb); free(x0); free(y0); free(v); free(qv); free(aty);
+    free(xe); free(a); free(xo); free(yo);
+}
+
+int orc_unrolled_qp(orc_ctx *s, int64_t T, const uint8_t *sched_restart, const double *sched_omega,
+                    uint8_t *rec_restart, double *rec_omega, double *x_out, double *y_out) {
+    if (T < 1 || s->p.q_kind == 0) return -1;
+    qp_unrolled_core(s, T, sched_restart, sched_omega, rec_restart, rec_omega, x_out, y_out, NULL);
+    return 0;
+}
+
+/* Reverse of Algorithm 2 per iteration (restarts and weights frozen):
+ *   xbar+ = (1-th) xbar + th x+,  ybar+ likewise
+ *   y+ = sigma (w - clamp(w, -u_c, -l_c)),  w = y/sigma - A~ xe,  xe = 2x+ - x
+ *   x+ = clamp(u),  u = x - tau (Q~ v + c - A~'y),  v = (1-beta) xbar + beta x
+ *   Q~ v = F~ (F~' v) + d~ v  (d~ = D_c^2 d) or a general symmetric Q~
+ * A restart after iteration t makes the next iteration start from
+ * (xbar+, ybar+, xbar+, ybar+). */
+int orc_unrolled_qp_backward(orc_ctx *s, int64_t T, const uint8_t *sched_restart,
+                             const double *sched_omega, const double *gx, const double *gy,
+                             double *gc, double *glc, double *guc, double *gd) {
+    if (T < 1 || s->p.q_kind == 0 || !sched_restart || !sched_omega) return -1;
+    const int32_t m = s->m, n = s->n;
+    qp_trace tr;
+    tr.v = dalloc((size_t)T * n);
+    tr.xmask = (uint8_t *)calloc((size_t)T * n, 1);
+    tr.ymask = (uint8_t *)calloc((size_t)T * (m ? m : 1), 1);
+    tr.kk = (int64_t *)calloc((size_t)T, sizeof(int64_t));
+    qp_unrolled_core(s, T, sched_restart, sched_omega, NULL, NULL, NULL, NULL, &tr);
+    double *bx = dalloc(n), *by = dalloc(m), *bxb = dalloc(n), *byb = dalloc(m);
+    double *bxp = dalloc(n), *byp = dalloc(m), *bw = dalloc(m), *bxe = dalloc(n);
+    double *bqv = dalloc(n), *bv = dalloc(n), *tmp = dalloc(n), *tm = dalloc(m);
+    ld *gcs = lalloc(n), *gds = lalloc(n), *glcs = lalloc(m), *gucs = lalloc(m);
+    /* cotangent of the output (unscaled averages after iteration T-1) */
+    for (int32_t j = 0; j < n; ++j) bxb[j] = s->dc[j] * gx[j];
+    for (int32_t i = 0; i < m; ++i) byb[i] = s->dr[i] * gy[i];
+    for (int64_t t = T - 1; t >= 0; --t) {
+        if (t < T - 1 && sched_restart[t]) {
+            for (int32_t j = 0; j < n; ++j) { bxb[j] += bx[j]; bx[j] = 0.0; }
+            for (int32_t i = 0; i < m; ++i) { byb[i] += by[i]; by[i] = 0.0; }
+        }
+        const int64_t k = tr.kk[t];
+        const double omega = sched_omega[t];
+        const double beta = 2.0 / (double)(k + 2), theta = beta;
+        const double tau = 1.0 / (omega / s->eta + 2.0 * s->norm_q / (double)(k + 1));
+        const double sigma = s->eta * omega;
+        /* averages */
+        for (int32_t j = 0; j < n; ++j) { bxp[j] = bx[j] + theta * bxb[j]; bxb[j] = (1.0 - theta) * bxb[j]; }
+        for (int32_t i = 0; i < m; ++i) { byp[i] = by[i] + theta * byb[i]; byb[i] = (1.0 - theta) * byb[i]; }
+        /* dual step */
+        for (int32_t i = 0; i < m; ++i) {
+            const uint8_t st = tr.ymask[t * m + i];
+            bw[i] = st ? sigma * byp[i] : 0.0;
+            if (st == 1) gucs[i] += (ld)(sigma * byp[i]);
+            if (st == 2) glcs[i] += (ld)(sigma * byp[i]);
+            by[i] = bw[i] / sigma;       /* w depends on the input y */
+            tm[i] = -bw[i];
+        }
+        at_mul(s, tm, bxe);              /* d w / d xe = -A~ */
+        for (int32_t j = 0; j < n; ++j) {
+            bxp[j] += 2.0 * bxe[j];
+            bx[j] = -bxe[j];
+        }
+        /* primal step */
+        for (int32_t j = 0; j < n; ++j) {
+            const double bu = tr.xmask[t * n + j] ? bxp[j] : 0.0;
+            bx[j] += bu;
+            bqv[j] = -tau * bu;
+            gcs[j] += (ld)(-tau * bu);
+            tmp[j] = tau * bu;
+        }
+        a_mul(s, tmp, tm);
+        for (int32_t i = 0; i < m; ++i) by[i] += tm[i];
+        /* Q~ v is symmetric: bv = Q~ bqv; d~ term */
+        q_mul(s, bqv, bv);
+        for (int32_t j = 0; j < n; ++j) {
+            gds[j] += (ld)bqv[j] * (ld)tr.v[t * n + j];
+            bxb[j] += (1.0 - beta) * bv[j];
+            bx[j] += beta * bv[j];
+        }
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        gc[j] = s->dc[j] * (double)gcs[j];
+        if (gd) gd[j] = (s->p.q_kind == 2) ? (s->dc[j] * s->dc[j]) * (double)gds[j] : 0.0;
+    }
+    for (int32_t i = 0; i < m; ++i) {
+        glc[i] = isfinite(s->p.lc[i]) ? s->dr[i] * (double)glcs[i] : 0.0;
+        guc[i] = isfinite(s->p.uc[i]) ? s->dr[i] * (double)gucs[i] : 0.0;
+    }
+    free(tr.v); free(tr.xmask); free(tr.ymask); free(tr.kk);
+    free(bx); free(by); free(bxb); free(byb); free(bxp); free(byp); free(bw); free(bxe);
+    free(bqv); free(bv); free(tmp); free(tm); free(gcs); free(gds); free(glcs); free(gucs);
     return 0;
 }

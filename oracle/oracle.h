@@ -76,6 +76,11 @@ void orc_destroy(orc_ctx *ctx);
 void orc_scaling(const orc_ctx *ctx, double *dr, double *dc, double *eta,
                  double *omega, double *norm_a, double *norm_q, int32_t *power_iters);
 
+/* Pin the step-size constants (eta, ||Q~||_2) to given values, e.g. those of
+ * a base problem, so that an unrolled run with perturbed data follows the
+ * same frozen map. */
+void orc_pin_steps(orc_ctx *ctx, double eta, double norm_q);
+
 /* Scaled data: c~ [n], l~_c u~_c [m], l~_v u~_v [n]. */
 void orc_scaled_vectors(const orc_ctx *ctx, double *c, double *lc, double *uc,
                         double *lv, double *uv);
@@ -123,6 +128,20 @@ int orc_unrolled_lp(orc_ctx *ctx, int64_t T, const uint8_t *sched_restart,
 int orc_unrolled_lp_backward(orc_ctx *ctx, int64_t T, const uint8_t *sched_restart,
                              const double *sched_omega, const double *gx,
                              const double *gy, double *gc, double *glc, double *guc);
+
+/* Unrolled rAPDHG (Algorithm 2) with a frozen schedule: exactly T iterations
+ * from zero; restarts / weights from the tests (recorded) or from sched_*.
+ * Output: the unscaled averages (xbar, ybar) after iteration T-1. */
+int orc_unrolled_qp(orc_ctx *ctx, int64_t T, const uint8_t *sched_restart,
+                    const double *sched_omega, uint8_t *rec_restart, double *rec_omega,
+                    double *x_out, double *y_out);
+
+/* Reverse pass of orc_unrolled_qp: gradients with respect to the original c,
+ * l_c, u_c and the diagonal d of Q (low-rank + diagonal Q only; gd may be
+ * NULL otherwise). */
+int orc_unrolled_qp_backward(orc_ctx *ctx, int64_t T, const uint8_t *sched_restart,
+                             const double *sched_omega, const double *gx, const double *gy,
+                             double *gc, double *glc, double *guc, double *gd);
 
 #ifdef __cplusplus
 }

@@ -496,3 +496,52 @@ def test_unrolled_envelope_gradient(oracle_lib):
     gc, _, _ = o.backward(T, sr, sw, lp.c, np.zeros(lp.m))
     grad = x + gc
     assert np.abs(grad - xs).max() <= 1e-4 * (1 + np.abs(xs).max())
+
+
+def test_unrolled_qp_backward_matches_finite_differences(oracle_lib):
+    """Reverse pass of unrolled rAPDHG (frozen schedule) against central
+    differences in c and in the diagonal d of Q = F F' + diag(d)."""
+    p = gen.portfolio_qp_batch(batch=1, n=12, rank=3, seed=4800)
+    base = gen.portfolio_instance(p, 0)
+    T = 120
+    o = _orc(base)
+    x, y, sr, sw = o.unrolled_qp(T)
+    assert sr.sum() >= 1          # the schedule contains restarts
+    rng = np.random.default_rng(2)
+    wx, wy = rng.standard_normal(base.n), rng.standard_normal(base.m)
+    gc, glc, guc, gd = o.backward_qp(T, sr, sw, wx, wy)
+    h = 1e-6
+
+    sc = o.scaling()
+
+    def loss(c=None, d=None):
+        q = gen.portfolio_instance(p, 0)
+        if c is not None: q.c = c
+        if d is not None: q.q_diag = d
+        oq = _orc(q)
+        oq.pin_steps(sc["eta"], sc["norm_q"])   # frozen step sizes
+        xx, yy, _, _ = oq.unrolled_qp(T, sr, sw)
+        return wx @ xx + wy @ yy
+
+    for j in range(base.n):
+        e = np.zeros(base.n); e[j] = h
+        fd = (loss(c=base.c + e) - loss(c=base.c - e)) / (2 * h)
+        assert abs(fd - gc[j]) <= 1e-6 * (1 + abs(fd)), ("c", j, fd, gc[j])
+        fd = (loss(d=base.q_diag + e) - loss(d=base.q_diag - e)) / (2 * h)
+        assert abs(fd - gd[j]) <= 1e-6 * (1 + abs(fd)), ("d", j, fd, gd[j])
+
+
+def test_unrolled_qp_envelope(oracle_lib):
+    """At convergence d(V)/dc = x* and d(V)/dd = x*^2 / 2 for
+    V = 1/2 x'Qx + c'x (envelope theorem)."""
+    p = gen.portfolio_qp_batch(batch=1, n=30, rank=4, seed=4900)
+    lp = gen.portfolio_instance(p, 0)
+    xs, ys, r = _orc(lp, eps=1e-10).solve()
+    T = int(r["iterations"]) + 300
+    o = _orc(lp)
+    x, y, sr, sw = o.unrolled_qp(T)
+    qx = lp.q_factor @ (lp.q_factor.T @ x) + lp.q_diag * x
+    # dV/dx_T = Q x_T + c; chain through the reverse pass, plus the explicit terms
+    gc, _, _, gd = o.backward_qp(T, sr, sw, qx + lp.c, np.zeros(lp.m))
+    np.testing.assert_allclose(gc + x, xs, atol=2e-4)
+    np.testing.assert_allclose(gd + 0.5 * x * x, 0.5 * xs * xs, atol=2e-4)
