@@ -215,6 +215,12 @@ typedef struct {
     int64_t a_nnz;
     const int32_t *row_off, *col_off;   /* [batch+1] (ragged only) */
     const double *c, *lc, *uc, *lv, *uv;
+    /* Optional quadratic term (shared A only, rAPDHG): Q_b = F F' + diag(d_b)
+     * with F [n*q_rank] row-major shared by the batch and d [B*n] per instance;
+     * q_rank = 0 for LP batches, at most 32. */
+    int32_t q_rank;
+    const double *q_factor;
+    const double *q_diag;
     int32_t mem;                        /* PDHG_MEM_HOST or PDHG_MEM_DEVICE */
 } pdhg_batch_problem;
 
@@ -249,8 +255,8 @@ pdhg_err pdhg_batch_autotune(pdhg_batch *b, int32_t iterations, int32_t *best_th
 pdhg_err pdhg_batch_update_data(pdhg_batch *b, const double *c, const double *lc,
                                 const double *uc, const double *lv, const double *uv);
 
-/* Differentiation by unrolling (Section 3 "Auto-differentiation"), LP
- * batches: every instance runs exactly T iterations from zero with no
+/* Differentiation by unrolling (Section 3 "Auto-differentiation"): every
+ * instance (LP or QP batch) runs exactly T iterations from zero with no
  * termination test. replay = 0: restart and primal-weight decisions come
  * from the regular tests and are recorded; replay = 1: the recorded schedule
  * of the last replay = 0 call with the same T is reused (so the map from c
@@ -264,10 +270,13 @@ pdhg_err pdhg_batch_unrolled_forward(pdhg_batch *b, int64_t T, int32_t replay, d
 
 /* Reverse pass of the last unrolled forward: given cotangents gx (like c) and
  * gy (like lc, NULL = 0) of its outputs, writes the gradients with respect to
- * the original c (gc) and row bounds (glc, guc; 0 for infinite bounds; NULL
- * skips them). Two sparse products per reversed iteration. Device pointers. */
+ * the original c (gc), row bounds (glc, guc; 0 for infinite bounds) and, for
+ * QP batches, the diagonal d of Q (gd); NULL skips glc / guc / gd. Two sparse
+ * products per reversed iteration. QP batches (rAPDHG, whose output is the
+ * average) keep the state every 50 iterations during the forward pass and
+ * recompute each segment to get the momentum points. Device pointers. */
 pdhg_err pdhg_batch_unrolled_backward(pdhg_batch *b, const double *gx, const double *gy,
-                                      double *gc, double *glc, double *guc);
+                                      double *gc, double *glc, double *guc, double *gd);
 
 /* Release everything the batch owns. NULL is ignored. */
 void pdhg_batch_destroy(pdhg_batch *b);

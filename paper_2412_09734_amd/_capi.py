@@ -61,7 +61,8 @@ class BatchProblem(C.Structure):
     _fields_ = [("batch", C.c_int32), ("shared_a", C.c_int32), ("m", C.c_int32), ("n", C.c_int32),
                 ("a_rowptr", P), ("a_colidx", P), ("a_val", P), ("a_nnz", C.c_int64),
                 ("row_off", P), ("col_off", P),
-                ("c", P), ("lc", P), ("uc", P), ("lv", P), ("uv", P), ("mem", C.c_int32)]
+                ("c", P), ("lc", P), ("uc", P), ("lv", P), ("uv", P),
+                ("q_rank", C.c_int32), ("q_factor", P), ("q_diag", P), ("mem", C.c_int32)]
 
 
 # every symbol include/pdhg.h declares, with its ctypes signature
@@ -82,7 +83,7 @@ SIGNATURES = {
     "pdhg_batch_autotune": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int32)]),
     "pdhg_batch_update_data": (C.c_int, [P, P, P, P, P, P]),
     "pdhg_batch_unrolled_forward": (C.c_int, [P, C.c_int64, C.c_int32, P, P]),
-    "pdhg_batch_unrolled_backward": (C.c_int, [P, P, P, P, P, P]),
+    "pdhg_batch_unrolled_backward": (C.c_int, [P, P, P, P, P, P, P]),
     "pdhg_batch_destroy": (None, [P]),
 }
 

@@ -537,10 +537,10 @@ pdhg_err pdhg_batch_unrolled_forward(pdhg_batch *pb, int64_t T, int32_t replay, 
 }
 
 pdhg_err pdhg_batch_unrolled_backward(pdhg_batch *pb, const double *gx, const double *gy,
-                                      double *gc, double *glc, double *guc) {
+                                      double *gc, double *glc, double *guc, double *gd) {
     return guarded([&] {
         if (!pb || !gx || !gc) fail(PDHG_ERR_INVALID_ARG, "NULL batch, gx or gc");
-        batch_backward(*pb->b, gx, gy, gc, glc, guc);
+        batch_backward(*pb->b, gx, gy, gc, glc, guc, gd);
     });
 }
 

@@ -17,14 +17,9 @@
 #include <vector>
 
 #include "device.hpp"
+#include "batch_internal.hpp"
 
 namespace pdhg {
-
-struct BatchRes {
-    double pobj, dobj, rel_p, rel_d, rel_g, kkt, omega, eta;
-    int64_t iterations, restarts;
-    int32_t status, power_iters;
-};
 
 struct BOpts {
     double eps, gamma, step_safety, beta_suff, beta_nec, beta_art, power_tol;
@@ -802,37 +797,6 @@ __global__ __launch_bounds__(kBlock) void k_batch_localize_t(const int32_t *__re
 
 namespace pdhg {
 
-struct BatchHandle {
-    int32_t B = 0, shared = 0, m = 0, n = 0;   // shared: per-instance m, n; ragged: totals
-    int64_t nnz = 0;
-    int32_t vec_m = 0, vec_n = 0;              // lengths of the row / column vectors
-    pdhg_options opt{};
-    hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
-    DBuf<int32_t> row_off, col_off, arp, aci, trp, tci, power_iters, queue;
-    DBuf<double> ava, tva, Dr, Dc, eta;
-    DBuf<double> c_o, lc_o, uc_o, lv_o, uv_o, c, lc, uc, lv, uv;
-    DBuf<double> x, x0, xh, xe, aty, y, y0, yh;
-    DBuf<BatchRes> res;
-    int32_t threads = 256;
-    int32_t workgroups = 0;
-    double setup_seconds = 0.0;
-    const double *x_init_ = nullptr, *y_init_ = nullptr;
-    double *x_out_ = nullptr, *y_out_ = nullptr;
-    std::vector<int32_t> row_off_h, col_off_h;
-    // unrolled iterations: schedule, masks and reverse-pass scratch
-    int64_t unrolled_T = 0;
-    DBuf<uint8_t> u_restart;
-    DBuf<double> u_omega, u_ba;
-    DBuf<int32_t> u_kk;
-    DBuf<uint64_t> u_xmask, u_ymask;
-    DBuf<int64_t> u_xoff, u_yoff;
-    ~BatchHandle() {
-        if (ev) (void)hipEventDestroy(ev);
-        if (stream) (void)hipStreamDestroy(stream);
-    }
-};
-
 static BOpts batch_opts(const pdhg_options &o) {
     BOpts b;
     b.eps = o.eps;
@@ -1045,12 +1009,17 @@ BatchHandle *batch_create(const pdhg_batch_problem &p, const pdhg_options &o, vo
     h.queue.alloc(1);
     dispatch_setup(h, nscal);
     PDHG_HIP(hipStreamSynchronize(s));
+    if (p.q_rank > 0) bqp_create(h, p);
     h.setup_seconds = now_seconds() - t0;
     return hp.release();
 }
 
 void batch_solve(BatchHandle &h, const double *x_init, const double *y_init, double *x_out,
                  double *y_out, pdhg_result *res) {
+    if (h.q_rank > 0) {
+        bqp_solve(h, x_init, y_init, x_out, y_out, res);
+        return;
+    }
     const double t0 = now_seconds();
     BOpts o = batch_opts(h.opt);
     // pointers of this call go in through the argument block
@@ -1094,6 +1063,7 @@ void batch_set_launch(BatchHandle &h, int32_t threads, int32_t workgroups) {
 }
 
 int32_t batch_autotune(BatchHandle &h, int32_t iterations) {
+    if (h.q_rank > 0) fail(PDHG_ERR_UNSUPPORTED, "autotune is for LP batches");
     BOpts o = batch_opts(h.opt);
     o.limit = iterations;
     DBuf<double> xo, yo;
@@ -1161,6 +1131,10 @@ static void launch_backward_t(BatchHandle &h, const UArgs &u) {
 
 void batch_unrolled_forward(BatchHandle &h, int64_t T, int32_t replay, double *x_out,
                             double *y_out) {
+    if (h.q_rank > 0) {
+        bqp_unrolled(h, T, replay, x_out, y_out);
+        return;
+    }
     if (T < 1 || T > 1000000) fail(PDHG_ERR_INVALID_ARG, "T must be in [1, 10^6]");
     if (replay && h.unrolled_T != T)
         fail(PDHG_ERR_INVALID_ARG, "replay needs a recorded schedule of the same length T");
@@ -1200,7 +1174,11 @@ void batch_unrolled_forward(BatchHandle &h, int64_t T, int32_t replay, double *x
 }
 
 void batch_backward(BatchHandle &h, const double *gx, const double *gy, double *gc, double *glc,
-                    double *guc) {
+                    double *guc, double *gd) {
+    if (h.q_rank > 0) {
+        bqp_backward(h, gx, gy, gc, glc, guc, gd);
+        return;
+    }
     if (h.unrolled_T < 1) fail(PDHG_ERR_INVALID_ARG, "run pdhg_batch_unrolled_forward first");
     DBuf<double> zm, lcs, ucs;
     zm.alloc((size_t)std::max(1, h.vec_m));

@@ -232,7 +232,7 @@ void batch_set_launch(BatchHandle &b, int32_t threads, int32_t workgroups);
 int32_t batch_autotune(BatchHandle &b, int32_t iterations);
 void batch_unrolled_forward(BatchHandle &b, int64_t T, int32_t replay, double *x_out, double *y_out);
 void batch_backward(BatchHandle &b, const double *gx, const double *gy, double *gc, double *glc,
-                    double *guc);
+                    double *guc, double *gd);
 void batch_update_data(BatchHandle &b, const double *c, const double *lc, const double *uc,
                        const double *lv, const double *uv);
 void batch_destroy(BatchHandle *b);

@@ -214,10 +214,12 @@ class BatchSolver:
 
     Shared A: `c, lv, uv` are [B, n] and `lc, uc` [B, m]. Ragged: one
     block-diagonal CSR with `row_off`, `col_off` ([B+1]) and concatenated
-    vectors (see `from_lps`)."""
+    vectors (see `from_lps`). QPs (shared A only, rAPDHG): `q_factor` F [n, r]
+    shared and `q_diag` d [B, n], Q_b = F F' + diag(d_b)."""
 
     def __init__(self, *, shared_a, batch, m, n, rowptr, colidx, val, c, lc, uc, lv, uv,
-                 row_off=None, col_off=None, device=None, threads=None, **opts):
+                 row_off=None, col_off=None, q_factor=None, q_diag=None, device=None,
+                 threads=None, **opts):
         self.dev = _device(device)
         self.shared = bool(shared_a)
         self.batch, self.m, self.n = int(batch), int(m), int(n)
@@ -238,6 +240,12 @@ class BatchSolver:
                 p.row_off, p.col_off = t["row_off"].data_ptr(), t["col_off"].data_ptr()
             p.c, p.lc, p.uc = t["c"].data_ptr(), t["lc"].data_ptr(), t["uc"].data_ptr()
             p.lv, p.uv = t["lv"].data_ptr(), t["uv"].data_ptr()
+            self.qp = q_factor is not None
+            if self.qp:
+                t["qf"] = _to_dev(q_factor, torch.float64, self.dev)
+                t["qd"] = f64(q_diag)
+                p.q_rank = int(t["qf"].shape[1]) if t["qf"].dim() == 2 else 1
+                p.q_factor, p.q_diag = t["qf"].data_ptr(), t["qd"].data_ptr()
             p.mem = capi.MEM_DEVICE
             h = C.c_void_p()
             rc = capi.lib().pdhg_batch_create(C.byref(p), C.byref(self._opts), _stream_ptr(),
@@ -254,10 +262,14 @@ class BatchSolver:
 
     @classmethod
     def from_shared(cls, sb, **opts) -> "BatchSolver":
-        """From an object with m, n, rowptr, colidx, val and [B, .] vectors."""
+        """From an object with m, n, rowptr, colidx, val and [B, .] vectors
+        (and optionally q_factor [n, r] and q_diag [B, n])."""
+        q = {}
+        if getattr(sb, "q_factor", None) is not None:
+            q = dict(q_factor=sb.q_factor, q_diag=sb.q_diag)
         return cls(shared_a=True, batch=sb.c.shape[0], m=sb.m, n=sb.n, rowptr=sb.rowptr,
                    colidx=sb.colidx, val=sb.val, c=sb.c, lc=sb.lc, uc=sb.uc, lv=sb.lv, uv=sb.uv,
-                   **opts)
+                   **q, **opts)
 
     @classmethod
     def from_lps(cls, lps, **opts) -> "BatchSolver":
@@ -342,8 +354,9 @@ class BatchSolver:
 
     def unrolled(self, T, replay=False):
         """Exactly T iterations per instance; returns the PDHG point of the
-        last one (shaped like solve()). replay=True reuses the schedule of the
-        last replay=False call."""
+        last one for LPs, the averages (xbar, ybar) for QPs (shaped like
+        solve()). replay=True reuses the schedule of the last replay=False
+        call."""
         x = torch.empty(self.vec_n, dtype=torch.float64, device=self.dev)
         y = torch.empty(max(self.vec_m, 1), dtype=torch.float64, device=self.dev)
         rc = capi.lib().pdhg_batch_unrolled_forward(self._h, int(T), int(bool(replay)), _ptr(x), _ptr(y))
@@ -354,19 +367,24 @@ class BatchSolver:
         return x, y
 
     def backward(self, gx, gy=None):
-        """Gradients (gc, glc, guc) of <gx, x_T> + <gy, y_T> for the last unrolled call."""
+        """Gradients (gc, glc, guc) of <gx, x_T> + <gy, y_T> for the last
+        unrolled call; QP batches return (gc, glc, guc, gd)."""
         gxt = _to_dev(gx, torch.float64, self.dev).reshape(-1)
         gyt = None if gy is None else _to_dev(gy, torch.float64, self.dev).reshape(-1)
         gc = torch.empty(self.vec_n, dtype=torch.float64, device=self.dev)
         glc = torch.empty(max(self.vec_m, 1), dtype=torch.float64, device=self.dev)
         guc = torch.empty(max(self.vec_m, 1), dtype=torch.float64, device=self.dev)
+        gd = torch.empty(self.vec_n, dtype=torch.float64, device=self.dev) if self.qp else None
         rc = capi.lib().pdhg_batch_unrolled_backward(self._h, _ptr(gxt), _ptr(gyt), _ptr(gc),
-                                                     _ptr(glc), _ptr(guc))
+                                                     _ptr(glc), _ptr(guc), _ptr(gd))
         capi.check(rc, "pdhg_batch_unrolled_backward")
         glc, guc = glc[: self.vec_m], guc[: self.vec_m]
         if self.shared:
-            return (gc.reshape(self.batch, self.n), glc.reshape(self.batch, self.m),
-                    guc.reshape(self.batch, self.m))
+            out = (gc.reshape(self.batch, self.n), glc.reshape(self.batch, self.m),
+                   guc.reshape(self.batch, self.m))
+            if self.qp:
+                out = out + (gd.reshape(self.batch, self.n),)
+            return out
         return gc, glc, guc
 
 
@@ -387,5 +405,5 @@ class UnrolledLP(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, gx):
-        gc, _, _ = ctx.solver.backward(gx.detach().contiguous())
+        gc = ctx.solver.backward(gx.detach().contiguous())[0]
         return gc.reshape(ctx.shape), None, None
