@@ -56,7 +56,12 @@ def test_unrolled_forward_and_backward_match_oracle(pdhg, oracle_lib):
 
 
 def test_adjoint_matches_finite_differences(pdhg):
-    _say("case: adjoint vs central differences (h=1e-6) through the frozen schedule")
+    """The frozen map is piecewise linear in c (the projection patterns switch
+    at kinks), so a difference quotient only matches the adjoint when no kink
+    lies inside the step: each coordinate is checked with a central quotient
+    (h = 1e-7) and the two one-sided ones (h = 1e-8), one of which must agree.
+    A wrong adjoint fails all three."""
+    _say("case: adjoint vs difference quotients through the frozen schedule")
     lps = _small_lps()[:3]
     T = 200
     rng = np.random.default_rng(7)
@@ -66,7 +71,6 @@ def test_adjoint_matches_finite_differences(pdhg):
         wx, wy = rng.standard_normal(bs.vec_n), rng.standard_normal(bs.vec_m)
         gc, _, _ = bs.backward(wx, wy)
         gc = to_np(gc)
-        h = 1e-6
 
         def loss(c):
             bs.update_data(c=c)
@@ -75,27 +79,41 @@ def test_adjoint_matches_finite_differences(pdhg):
             return np.array([wx[cs] @ xx[cs] + wy[rs] @ yy[rs]
                              for cs, rs in (bs.instance_slices(b) for b in range(bs.batch))])
 
+        l0 = loss(c0)
         n_max = max(lp.n for lp in lps)
-        for j in range(0, n_max, 7):
-            e = np.zeros(bs.vec_n)
-            for b in range(bs.batch):
-                cs, _ = bs.instance_slices(b)
-                if j < cs.stop - cs.start:
-                    e[cs.start + j] = h
-            fd = (loss(c0 + e) - loss(c0 - e)) / (2 * h)
+        checked = 0
+        for j in range(0, n_max, 5):
+            def unit(h):
+                e = np.zeros(bs.vec_n)
+                for b in range(bs.batch):
+                    cs, _ = bs.instance_slices(b)
+                    if j < cs.stop - cs.start:
+                        e[cs.start + j] = h
+                return e
+            central = (loss(c0 + unit(1e-7)) - loss(c0 - unit(1e-7))) / 2e-7
+            fwd = (loss(c0 + unit(1e-8)) - l0) / 1e-8
+            bwd = (l0 - loss(c0 - unit(1e-8))) / 1e-8
             for b in range(bs.batch):
                 cs, _ = bs.instance_slices(b)
                 if j < cs.stop - cs.start:
                     g = gc[cs.start + j]
-                    assert abs(fd[b] - g) <= 1e-6 * (1 + abs(fd[b])), (b, j, fd[b], g)
+                    err = min(abs(central[b] - g), abs(fwd[b] - g), abs(bwd[b] - g))
+                    assert err <= 2e-5 * (1 + abs(g)), (b, j, central[b], fwd[b], bwd[b], g)
+                    checked += 1
+        assert checked > 20
         bs.update_data(c=c0)
 
 
 def test_envelope_gradients_at_convergence(pdhg, oracle_lib):
-    """d(c'x*)/dc = x* and, on equality rows of a planted LP, d(c'x*)/db = y*."""
+    """d(c'x*)/dc = x* and, on equality rows of a planted LP, d(c'x*)/db = y*.
+    The second identity needs a unique dual solution; some planted instances
+    are degenerate, so the seed is one whose three duals are unique (checked
+    with the oracle's reverse pass)."""
     _say("case: envelope gradients, planted LPs")
-    lps = gen.ragged_planted_batch(batch=3, m_lo=30, m_hi=40, density=0.15, seed=3900)
-    T = 4000
+    lps = gen.ragged_planted_batch(batch=3, m_lo=30, m_hi=40, density=0.15, seed=3904)
+    # T past the oracle's iteration count at eps 1e-10 for every instance, so
+    # the unrolled output sits at the solution
+    T = max(oracle_lib.Oracle(lp, eps=1e-10).solve()[2]["iterations"] for lp in lps) + 200
     with pdhg.BatchSolver.from_lps(lps) as bs:
         x, y = bs.unrolled(T)
         c = np.concatenate([lp.c for lp in lps])
@@ -105,10 +123,10 @@ def test_envelope_gradients_at_convergence(pdhg, oracle_lib):
             cs, rs = bs.instance_slices(b)
             xs, ys, r = oracle_lib.Oracle(lp, eps=1e-10).solve()
             grad_c = x[cs] + gc[cs]
-            assert np.abs(grad_c - xs).max() <= 2e-3 * (1 + np.abs(xs).max())
+            assert np.abs(grad_c - xs).max() <= 1e-6 * (1 + np.abs(xs).max())
             eq = np.isfinite(lp.lc) & (lp.lc == lp.uc)
             grad_b = glc[rs] + guc[rs]
-            assert np.abs(grad_b[eq] - ys[eq]).max() <= 2e-3 * (1 + np.abs(ys[eq]).max())
+            assert np.abs(grad_b[eq] - ys[eq]).max() <= 1e-6 * (1 + np.abs(ys[eq]).max())
 
 
 def test_autograd_function(pdhg):
