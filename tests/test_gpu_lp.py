@@ -135,6 +135,24 @@ def test_solve_parity_small_lp(pdhg, oracle_lib):
         assert abs(kg["kkt"] - rg["kkt_rel"]) <= 1e-9 + 1e-6 * kg["kkt"]
 
 
+def test_solve_parity_zipf_long_columns(pdhg, oracle_lib):
+    """Zipf column degrees with columns longer than the SELL limit, so A~'
+    has long rows and the primal product runs through the panel split."""
+    for (m, n, seed) in ((1000, 2000, 79), (800, 1600, 81)):
+        _say(f"case: full solve parity, Zipf planted m={m} n={n} seed={seed}")
+        lp = gen.large_zipf_lp(m=m, n=n, kmax=300, seed=seed)
+        assert (np.bincount(lp.colidx, minlength=n) > 64).sum() > 10
+        xo, yo, ro = oracle_lib.Oracle(lp).solve()
+        with pdhg.Solver.from_lp(lp) as s:
+            xg, yg, rg = s.solve()
+        _say(f"  iterations gpu={rg['iterations']} oracle={ro['iterations']}")
+        assert rg["status_name"] == "optimal" and rg["kkt_rel"] <= 1e-4
+        assert abs(rg["primal_obj"] - ro["primal_obj"]) <= 1e-5 * (1 + abs(ro["primal_obj"]))
+        kg = oracle_lib.kkt(lp, to_np(xg), to_np(yg))
+        assert kg["kkt"] <= 1e-4
+        assert abs(kg["kkt"] - rg["kkt_rel"]) <= 1e-9 + 1e-6 * kg["kkt"]
+
+
 def test_solve_parity_grid_flow(pdhg, oracle_lib):
     g = gen.grid_mincost_batch(batch=2, seed=3000)
     for b in range(2):
