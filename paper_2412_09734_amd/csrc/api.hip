@@ -336,7 +336,6 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
         }
         validate_and_load_vectors(h, p);
         scale_problem(h);
-        if (!h.dense) build_panels(h.stream, h.AT, kPanels);
         estimate_steps(h);
         compute_weight(h);
         if (p.q_format != PDHG_FMT_NONE) {

@@ -22,7 +22,6 @@ namespace pdhg {
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kMaxSeg = 40;      // length classes per matrix
 constexpr int kShortMax = 64;    // rows up to this length go to SELL-64 slices
-constexpr int kPanels = 8;       // column panels of the split long rows (one per XCD)
 
 struct Error {
     pdhg_err code;
@@ -84,15 +83,6 @@ struct SegTable {
 //    entry k of lane l sits at slice_ptr[s] + 64 k + l for k < width(s),
 //    width(s) = length of the slice's first (longest) row; shorter rows are
 //    padded with (column 0, value 0.0). One thread per row.
-//
-// Optionally (build_panels, after scaling) the long rows are also kept split
-// by column panels: panel p holds the entries whose column lies in
-// [p W, (p + 1) W), W = ceil(cols / npanel); sub-row (p, r) is
-// [prow[p R_long + r], prow[p R_long + r + 1]) of pcol / pval. Workgroup b of
-// the split part works on panel b % npanel, so with npanel = 8 every XCD
-// gathers from one eighth of the vector, which stays in its own L2. Partial
-// sums go to part[p R_long + r] and are added in fixed panel order by a
-// second pass.
 struct HMat {
     int32_t rows = 0, cols = 0;
     int64_t nnz = 0;          // real entries
@@ -101,14 +91,7 @@ struct HMat {
     DBuf<int32_t> rowptr, colidx, slice_ptr;
     DBuf<double> val;
     SegTable seg{};
-    std::vector<int32_t> long_classes;   // rows per length class (as make_segments)
-    int32_t npanel = 0;
-    DBuf<int32_t> prow, pcol;
-    DBuf<double> pval, part;
-    SegTable pseg{};
     int32_t nblocks() const { return seg.nblocks + (int32_t)((nslices + 3) / 4); }
-    int32_t panel_long_blocks() const { return npanel * pseg.nblocks; }
-    int32_t panel_nblocks() const { return panel_long_blocks() + (int32_t)((nslices + 3) / 4); }
 };
 
 // Kernel-argument view of an HMat.
@@ -120,27 +103,6 @@ struct MatView {
     int32_t rows, R_long, nslices, pad;
     SegTable seg;
 };
-
-// Kernel-argument view of the panel split of an HMat's long rows.
-struct PanelView {
-    const int32_t *prow, *pcol;
-    const double *pval;
-    double *part;
-    int32_t npanel, nblocks_long;
-    SegTable pseg;
-};
-
-inline PanelView panel_view(const HMat &M) {
-    PanelView v;
-    v.prow = M.prow.p;
-    v.pcol = M.pcol.p;
-    v.pval = M.pval.p;
-    v.part = M.part.p;
-    v.npanel = M.npanel;
-    v.nblocks_long = M.panel_long_blocks();
-    v.pseg = M.pseg;
-    return v;
-}
 
 inline MatView view(const HMat &M) {
     MatView v;
@@ -222,8 +184,7 @@ void scale_problem(Handle &h);
 void transform_vectors(Handle &h);
 void estimate_steps(Handle &h);
 void compute_weight(Handle &h);
-SegTable make_segments(const std::vector<int32_t> &class_count, int32_t rows, int shift = 0);
-void build_panels(hipStream_t s, HMat &M, int32_t npanel);
+SegTable make_segments(const std::vector<int32_t> &class_count, int32_t rows);
 void validate_csr(hipStream_t s, const int32_t *rowptr, const int32_t *colidx, const double *val,
                   int32_t m, int32_t n, int64_t nnz);
 void validate_vectors(hipStream_t s, int32_t n, int32_t m, const double *c, const double *lv,

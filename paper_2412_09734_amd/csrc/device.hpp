@@ -13,8 +13,9 @@ struct RowCtx {
     bool lead;     // first lane of the row's lane group
 };
 
-// Workgroup b belongs to the last segment whose block_begin <= b.
-__device__ __forceinline__ RowCtx row_ctx_b(const SegTable &T, int32_t b) {
+// Workgroup blockIdx.x belongs to the last segment whose block_begin <= it.
+__device__ __forceinline__ RowCtx row_ctx(const SegTable &T) {
+    const int32_t b = blockIdx.x;
     int32_t si = 0;
 #pragma unroll 1
     for (int32_t q = 1; q < T.nseg; ++q) si = (b >= T.s[q].block_begin) ? q : si;
@@ -27,8 +28,6 @@ __device__ __forceinline__ RowCtx row_ctx_b(const SegTable &T, int32_t b) {
     r.lead = (threadIdx.x & ((1u << lg) - 1u)) == 0u;
     return r;
 }
-
-__device__ __forceinline__ RowCtx row_ctx(const SegTable &T) { return row_ctx_b(T, (int32_t)blockIdx.x); }
 
 // sum_e val[e] * v[colidx[e]] over the row, lanes strided; the lane-group
 // butterfly leaves the same total in every lane of the group.
@@ -82,11 +81,19 @@ __device__ __forceinline__ int32_t slice_of(const MatView &M) {
     return ((int32_t)blockIdx.x - M.seg.nblocks) * (kBlock / 64) + (int32_t)(threadIdx.x >> 6);
 }
 
-// Row sum over SELL-64 slice sl (wave-uniform) for the row of this lane:
+// Row sum of val * x[col] for the row owned by this thread (hybrid layout).
+// Long rows: lane groups with a butterfly; short rows: one thread per row,
 // entries walked in order with independent, coalesced loads.
-__device__ __forceinline__ RowSum sell_row_dot(const MatView &M, const double *__restrict__ x,
-                                               int32_t sl) {
+__device__ __forceinline__ RowSum mat_row_dot(const MatView &M, const double *__restrict__ x) {
     RowSum r;
+    const int32_t sl = slice_of(M);
+    if (sl < 0) {
+        const RowCtx rc = row_ctx(M.seg);
+        r.s = row_dot(M.rowptr, M.colidx, M.val, x, rc);
+        r.row = rc.row;
+        r.valid = rc.valid && rc.lead;
+        return r;
+    }
     const int32_t lane = (int32_t)(threadIdx.x & 63);
     r.row = M.R_long + sl * 64 + lane;
     r.valid = sl < M.nslices && r.row < M.rows;
@@ -117,48 +124,6 @@ __device__ __forceinline__ RowSum sell_row_dot(const MatView &M, const double *_
     }
     r.s = acc;
     return r;
-}
-
-// Row sum of val * x[col] for the row owned by this thread (hybrid layout).
-// Long rows: lane groups with a butterfly; short rows: one thread per row.
-__device__ __forceinline__ RowSum mat_row_dot(const MatView &M, const double *__restrict__ x) {
-    const int32_t sl = slice_of(M);
-    if (sl < 0) {
-        RowSum r;
-        const RowCtx rc = row_ctx(M.seg);
-        r.s = row_dot(M.rowptr, M.colidx, M.val, x, rc);
-        r.row = rc.row;
-        r.valid = rc.valid && rc.lead;
-        return r;
-    }
-    return sell_row_dot(M, x, sl);
-}
-
-// Same with the long rows split by column panels: workgroups
-// [0, P.nblocks_long) store the sub-row sums of panel b % npanel in P.part and
-// own no row (valid = false); the others cover the SELL-64 slices.
-__device__ __forceinline__ RowSum panel_row_dot(const MatView &M, const PanelView &P,
-                                                const double *__restrict__ x) {
-    const int32_t b = (int32_t)blockIdx.x;
-    if (b < P.nblocks_long) {
-        const int32_t panel = b % P.npanel;
-        const RowCtx rc = row_ctx_b(P.pseg, b / P.npanel);
-        const double s = row_dot(P.prow + (size_t)panel * M.R_long, P.pcol, P.pval, x, rc);
-        if (rc.valid && rc.lead) P.part[(size_t)panel * M.R_long + rc.row] = s;
-        RowSum r;
-        r.s = 0.0;
-        r.row = 0;
-        r.valid = false;
-        return r;
-    }
-    return sell_row_dot(M, x, (b - P.nblocks_long) * (kBlock / 64) + (int32_t)(threadIdx.x >> 6));
-}
-
-// Full sum of split long row r: panel partials added in panel order.
-__device__ __forceinline__ double panel_sum(const PanelView &P, int32_t R_long, int32_t r) {
-    double s = 0.0;
-    for (int32_t p = 0; p < P.npanel; ++p) s += P.part[(size_t)p * R_long + r];
-    return s;
 }
 
 // Row max (MAXNORM) or sum of |val| in the hybrid layout.

@@ -12,43 +12,24 @@
 
 namespace pdhg {
 
-// Primal update of row r given s = (A~' y)_r: PDHG point, extrapolation and
-// the Halpern step (Algorithm 1).
-__device__ __forceinline__ void primal_update(int32_t r, double s, double *__restrict__ x,
-                                              const double *__restrict__ x0,
-                                              const double *__restrict__ c,
-                                              const double *__restrict__ lv,
-                                              const double *__restrict__ uv,
-                                              double *__restrict__ xext, const DevState *st,
-                                              int32_t j, double gamma) {
-    const double tau = st->tau;
-    const int64_t k = st->k_base + (j - 1);
-    const double xr = x[r];
-    const double xh = clampd(xr - tau * (c[r] - s), lv[r], uv[r]);
-    const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
-    xext[r] = 2.0 * xh - xr;
-    x[r] = ak * ((1.0 + gamma) * xh - gamma * xr) + bk * x0[r];
-}
-
 __global__ __launch_bounds__(kBlock) void k_primal(
-    MatView M, PanelView P, const double *__restrict__ y, double *__restrict__ x,
+    MatView M, const double *__restrict__ y, double *__restrict__ x,
     const double *__restrict__ x0, const double *__restrict__ c, const double *__restrict__ lv,
     const double *__restrict__ uv, double *__restrict__ xext, const DevState *__restrict__ st,
     int32_t j, double gamma) {
     if (st->done) return;
-    const RowSum rs = P.npanel ? panel_row_dot(M, P, y) : mat_row_dot(M, y);
-    if (rs.valid) primal_update(rs.row, rs.s, x, x0, c, lv, uv, xext, st, j, gamma);
-}
-
-// Long rows of a panel-split A~': add the partials, then the primal update.
-__global__ __launch_bounds__(kBlock) void k_primal_long(
-    PanelView P, int32_t R_long, double *__restrict__ x, const double *__restrict__ x0,
-    const double *__restrict__ c, const double *__restrict__ lv, const double *__restrict__ uv,
-    double *__restrict__ xext, const DevState *__restrict__ st, int32_t j, double gamma) {
-    if (st->done) return;
-    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (r >= R_long) return;
-    primal_update(r, panel_sum(P, R_long, r), x, x0, c, lv, uv, xext, st, j, gamma);
+    const RowSum rs = mat_row_dot(M, y);
+    const double s = rs.s;
+    if (rs.valid) {
+        const int32_t r = rs.row;
+        const double tau = st->tau;
+        const int64_t k = st->k_base + (j - 1);
+        const double xr = x[r];
+        const double xh = clampd(xr - tau * (c[r] - s), lv[r], uv[r]);
+        const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+        xext[r] = 2.0 * xh - xr;
+        x[r] = ak * ((1.0 + gamma) * xh - gamma * xr) + bk * x0[r];
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_dual(
@@ -69,42 +50,23 @@ __global__ __launch_bounds__(kBlock) void k_dual(
     }
 }
 
-__device__ __forceinline__ void primal_check_update(int32_t r, double s,
-                                                    const double *__restrict__ x,
-                                                    const double *__restrict__ c,
-                                                    const double *__restrict__ lv,
-                                                    const double *__restrict__ uv,
-                                                    double *__restrict__ xhat,
-                                                    double *__restrict__ xext,
-                                                    double *__restrict__ aty, const DevState *st,
-                                                    double tau_override) {
-    const double tau = tau_override > 0.0 ? tau_override : st->tau;
-    const double xr = x[r];
-    const double xh = clampd(xr - tau * (c[r] - s), lv[r], uv[r]);
-    xhat[r] = xh;
-    xext[r] = 2.0 * xh - xr;
-    aty[r] = s;
-}
-
 __global__ __launch_bounds__(kBlock) void k_primal_chk(
-    MatView M, PanelView P, const double *__restrict__ y, const double *__restrict__ x,
+    MatView M, const double *__restrict__ y, const double *__restrict__ x,
     const double *__restrict__ c, const double *__restrict__ lv, const double *__restrict__ uv,
     double *__restrict__ xhat, double *__restrict__ xext, double *__restrict__ aty,
     const DevState *__restrict__ st, double tau_override) {
     if (st->done) return;
-    const RowSum rs = P.npanel ? panel_row_dot(M, P, y) : mat_row_dot(M, y);
-    if (rs.valid) primal_check_update(rs.row, rs.s, x, c, lv, uv, xhat, xext, aty, st, tau_override);
-}
-
-__global__ __launch_bounds__(kBlock) void k_primal_chk_long(
-    PanelView P, int32_t R_long, const double *__restrict__ x, const double *__restrict__ c,
-    const double *__restrict__ lv, const double *__restrict__ uv, double *__restrict__ xhat,
-    double *__restrict__ xext, double *__restrict__ aty, const DevState *__restrict__ st,
-    double tau_override) {
-    if (st->done) return;
-    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (r >= R_long) return;
-    primal_check_update(r, panel_sum(P, R_long, r), x, c, lv, uv, xhat, xext, aty, st, tau_override);
+    const RowSum rs = mat_row_dot(M, y);
+    const double s = rs.s;
+    if (rs.valid) {
+        const int32_t r = rs.row;
+        const double tau = tau_override > 0.0 ? tau_override : st->tau;
+        const double xr = x[r];
+        const double xh = clampd(xr - tau * (c[r] - s), lv[r], uv[r]);
+        xhat[r] = xh;
+        xext[r] = 2.0 * xh - xr;
+        aty[r] = s;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_dual_chk(
@@ -399,13 +361,9 @@ void launch_primal(Handle &h, int32_t j) {
         return;
     }
     if (h.AT.nblocks() == 0) return;
-    const PanelView P = panel_view(h.AT);
-    const unsigned grid = (unsigned)(P.npanel ? h.AT.panel_nblocks() : h.AT.nblocks());
-    k_primal<<<grid, kBlock, 0, h.stream>>>(view(h.AT), P, h.y.p, h.x.p, h.x0.p, h.c.p, h.lv.p,
-                                            h.uv.p, h.xext.p, h.st.p, j, h.opt.gamma);
-    if (P.npanel)
-        k_primal_long<<<(unsigned)ceil_div(h.AT.R_long, kBlock), kBlock, 0, h.stream>>>(
-            P, h.AT.R_long, h.x.p, h.x0.p, h.c.p, h.lv.p, h.uv.p, h.xext.p, h.st.p, j, h.opt.gamma);
+    k_primal<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
+        view(h.AT), h.y.p, h.x.p, h.x0.p, h.c.p, h.lv.p,
+        h.uv.p, h.xext.p, h.st.p, j, h.opt.gamma);
 }
 
 void launch_dual(Handle &h, int32_t j) {
@@ -424,15 +382,9 @@ void launch_primal_check(Handle &h, double tau_override) {
         return;
     }
     if (h.AT.nblocks() == 0) return;
-    const PanelView P = panel_view(h.AT);
-    const unsigned grid = (unsigned)(P.npanel ? h.AT.panel_nblocks() : h.AT.nblocks());
-    k_primal_chk<<<grid, kBlock, 0, h.stream>>>(view(h.AT), P, h.y.p, h.x.p, h.c.p, h.lv.p,
-                                                h.uv.p, h.xhat.p, h.xext.p, h.aty.p, h.st.p,
-                                                tau_override);
-    if (P.npanel)
-        k_primal_chk_long<<<(unsigned)ceil_div(h.AT.R_long, kBlock), kBlock, 0, h.stream>>>(
-            P, h.AT.R_long, h.x.p, h.c.p, h.lv.p, h.uv.p, h.xhat.p, h.xext.p, h.aty.p, h.st.p,
-            tau_override);
+    k_primal_chk<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
+        view(h.AT), h.y.p, h.x.p, h.c.p, h.lv.p, h.uv.p,
+        h.xhat.p, h.xext.p, h.aty.p, h.st.p, tau_override);
 }
 
 void launch_dual_check(Handle &h, double sigma_override) {

@@ -409,10 +409,7 @@ unsigned blocks_for(int64_t len) { return (unsigned)std::max<int64_t>(1, ceil_di
 
 }  // namespace
 
-// One segment per length class; rows of class cls (lengths in
-// (2^(cls-1), 2^cls]) get 2^(cls-2-shift) lanes (1 to 64), about 4 entries
-// per lane for rows of length ~2^(cls-shift) (shift 3: sub-rows of 8 panels).
-SegTable make_segments(const std::vector<int32_t> &class_count, int32_t rows, int shift) {
+SegTable make_segments(const std::vector<int32_t> &class_count, int32_t rows) {
     SegTable T;
     memset(&T, 0, sizeof(T));
     int32_t begin = 0, blocks = 0;
@@ -420,7 +417,7 @@ SegTable make_segments(const std::vector<int32_t> &class_count, int32_t rows, in
         const int32_t cnt = class_count[q];
         if (cnt <= 0) continue;
         const int cls = 31 - q;
-        const int lg = std::min(6, std::max(0, cls - 2 - shift));
+        const int lg = std::min(6, std::max(0, cls - 2));
         const int32_t rows_per_block = kBlock >> lg;
         Seg sg;
         sg.row_begin = begin;
@@ -434,67 +431,6 @@ SegTable make_segments(const std::vector<int32_t> &class_count, int32_t rows, in
     if (begin != rows) fail(PDHG_ERR_INVALID_INPUT, "internal: class counts do not add up");
     T.nblocks = blocks;
     return T;
-}
-
-// cnt[p R + r] = entries of long row r whose column lies in panel p.
-__global__ __launch_bounds__(kBlock) void k_panel_count(const int32_t *__restrict__ rowptr,
-                                                        const int32_t *__restrict__ colidx,
-                                                        int32_t R, int32_t P, int32_t W,
-                                                        int32_t *__restrict__ cnt) {
-    const int32_t r = blockIdx.x * kBlock + threadIdx.x;
-    if (r >= R) return;
-    for (int32_t p = 0; p < P; ++p) {
-        int32_t c = 0;
-        for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) c += (colidx[e] / W == p) ? 1 : 0;
-        cnt[(size_t)p * R + r] = c;
-    }
-}
-
-// Copy each long row's entries into its panel sub-rows, keeping their order.
-__global__ __launch_bounds__(kBlock) void k_panel_fill(const int32_t *__restrict__ rowptr,
-                                                       const int32_t *__restrict__ colidx,
-                                                       const double *__restrict__ val, int32_t R,
-                                                       int32_t P, int32_t W,
-                                                       const int32_t *__restrict__ prow,
-                                                       int32_t *__restrict__ pcol,
-                                                       double *__restrict__ pval) {
-    const int32_t r = blockIdx.x * kBlock + threadIdx.x;
-    if (r >= R) return;
-    for (int32_t p = 0; p < P; ++p) {
-        int32_t o = prow[(size_t)p * R + r];
-        for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-            const int32_t c = colidx[e];
-            if (c / W == p) {
-                pcol[o] = c;
-                pval[o] = val[e];
-                ++o;
-            }
-        }
-    }
-}
-
-void build_panels(hipStream_t s, HMat &M, int32_t npanel) {
-    M.npanel = 0;
-    if (M.R_long == 0 || npanel < 2 || M.cols < npanel) return;
-    const int32_t R = M.R_long, W = (int32_t)ceil_div(M.cols, npanel);
-    const int64_t cells = (int64_t)npanel * R;
-    DBuf<int32_t> cnt;
-    cnt.alloc((size_t)cells + 1);
-    PDHG_HIP(hipMemsetAsync(cnt.p + cells, 0, sizeof(int32_t), s));
-    k_panel_count<<<blocks_for(R), kBlock, 0, s>>>(M.rowptr.p, M.colidx.p, R, npanel, W, cnt.p);
-    M.prow.alloc((size_t)cells + 1);
-    exclusive_scan(s, cnt.p, M.prow.p, cells + 1);
-    int32_t total = 0;
-    PDHG_HIP(hipMemcpyAsync(&total, M.prow.p + cells, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    PDHG_HIP(hipStreamSynchronize(s));
-    M.pcol.alloc((size_t)std::max(1, total));
-    M.pval.alloc((size_t)std::max(1, total));
-    M.part.alloc((size_t)cells);
-    k_panel_fill<<<blocks_for(R), kBlock, 0, s>>>(M.rowptr.p, M.colidx.p, M.val.p, R, npanel, W,
-                                                  M.prow.p, M.pcol.p, M.pval.p);
-    M.pseg = make_segments(M.long_classes, R, 3);
-    M.npanel = npanel;
-    PDHG_HIP(hipStreamSynchronize(s));
 }
 
 void check_flag(hipStream_t s, const int32_t *dflag, const char *what) {
@@ -539,7 +475,6 @@ static void to_hybrid(hipStream_t s, PlainCsr &P, int32_t cols, HMat &H) {
     std::vector<int32_t> cls(hinfo + 1, hinfo + 33);
     H.R_long = r_long;
     H.seg = make_segments(cls, r_long);
-    H.long_classes = cls;
     const int32_t ns = (int32_t)ceil_div(R - r_long, 64);
     H.nslices = ns;
     int32_t nnz_long = 0;
