@@ -101,11 +101,15 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (counter calibration)")
     ap.add_argument("--workload", default="sparse",
-                    choices=["sparse", "dense", "batch-grid", "batch-ragged"],
+                    choices=["sparse", "dense", "batch-grid", "batch-ragged", "learn-grid",
+                             "qp-portfolio"],
                     help="sparse (default, the headline line), dense 20k x 40k, "
                          "batched grid min-cost flows (2,048 x 32x32 grid) or the ragged batch "
                          "(1,024 planted LPs); the batched modes also time the plain solver "
-                         "looped one instance at a time on a subset")
+                         "looped one instance at a time on a subset; learn-grid: training steps "
+                         "of the shortest-path cost model through 1,000 unrolled iterations "
+                         "(256 grids); qp-portfolio: 512 portfolio QPs, solve and unrolled "
+                         "gradient")
     ap.add_argument("--batch", type=int, default=0, help="batch size override (batched modes)")
     ap.add_argument("--loop-sample", type=int, default=16,
                     help="instances solved one at a time for the looped comparison")
@@ -135,6 +139,10 @@ def main():
         return bench_batch(args)
     if args.workload == "dense":
         return bench_dense(args)
+    if args.workload == "learn-grid":
+        return bench_learn(args)
+    if args.workload == "qp-portfolio":
+        return bench_qp(args)
 
     log(f"bench: generating sparse LP m={args.m} n={args.n}")
     t = time.perf_counter()
@@ -321,6 +329,120 @@ def bench_dense(args):
                       "primal_obj": last["primal_obj"], "planted_obj": lp.v_star,
                       "iter_ms_kernels": round(prim + dual, 4)},
            "roofline": roof}
+    print(json.dumps(out), flush=True)
+
+
+def bench_learn(args):
+    """One training step of the shortest-path cost model: c_hat = f W on the
+    device, 1,000 unrolled iterations of the batch, regret under the true
+    costs, reverse pass, weight gradient (all in libpdhg kernels), then a
+    host-side gradient step on the 5 weights. value = LPs differentiated per
+    second (batch / step time)."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2412_09734_amd import heads
+    from paper_2412_09734_amd.solver import BatchSolver
+
+    B = args.batch or 256
+    T = 1000
+    sb, f, w_star, W = gen.shortest_path_learning(batch=B, seed=gen.seed_for(4, 0))
+    dev = torch.device("cuda:0")
+    fd = torch.from_numpy(f).to(dev)
+    ct = torch.from_numpy(sb.c).to(dev)
+    with BatchSolver.from_shared(sb, eps=1e-8) as bs:
+        _, _, res = bs.solve()                       # optimal values under the true costs
+    vstar = torch.tensor([r["primal_obj"] for r in res], dtype=torch.float64, device=dev)
+    lr = 0.05
+    with BatchSolver.from_shared(sb) as bs:
+        def step(Wv):
+            chat = heads.linear_costs(fd, Wv)
+            bs.update_data(c=chat)
+            x, _ = bs.unrolled(T)
+            loss = heads.regret(ct, x, vstar)
+            gc = bs.backward(ct)[0]
+            gW = heads.linear_costs_backward(fd, gc)
+            return float(loss.mean()), gW.cpu().numpy() / B
+        for _ in range(args.warmup):
+            step(W)
+        torch.cuda.synchronize()
+        losses = []
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            l, g = step(W)
+            W = W - lr * g
+            losses.append(l)
+            log(f"bench: learn step {k}: mean regret {l:.4f}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    out = {"metric": METRIC, "value": round(args.steps * B / el, 2), "unit": "LPs/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(el / args.steps * 1e3, 2), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"learning step: {B} grid shortest-path LPs (32x32), linear cost "
+                                  f"model on 5 features, {T} unrolled r2HPDHG iterations + reverse pass",
+                      "batch": B, "unrolled_iterations": T, "mean_regret_first": losses[0],
+                      "mean_regret_last": losses[-1]}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_qp(args):
+    """512 portfolio QPs (n=500, Q = F F' + diag d, F shared, rank 20):
+    batched rAPDHG solve to 1e-4 (QPs/s), then 1,000 unrolled iterations with
+    the reverse pass for the gradient of the value in (c, d)."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2412_09734_amd import heads
+    from paper_2412_09734_amd.solver import BatchSolver
+    from types import SimpleNamespace
+
+    B = args.batch or 512
+    T = 1000
+    p = gen.portfolio_qp_batch(batch=B, seed=gen.seed_for(4, 500))
+    sb = SimpleNamespace(m=p["m"], n=p["n"], rowptr=p["rowptr"], colidx=p["colidx"], val=p["val"],
+                         c=p["c"], lc=np.tile(p["lc"], (B, 1)), uc=np.tile(p["uc"], (B, 1)),
+                         lv=np.tile(p["lv"], (B, 1)), uv=np.tile(p["uv"], (B, 1)),
+                         q_factor=p["F"], q_diag=p["d"])
+    dev = torch.device("cuda:0")
+    with BatchSolver.from_shared(sb) as bs:
+        for _ in range(args.warmup):
+            bs.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x, y, res = bs.solve()
+        torch.cuda.synchronize()
+        t_solve = (time.perf_counter() - t0) / args.steps
+        solved = sum(r["status"] == 1 for r in res)
+        iters = [r["iterations"] for r in res]
+        Fd = torch.from_numpy(p["F"]).to(dev)
+        dd = torch.from_numpy(p["d"]).to(dev)
+        cd = torch.from_numpy(p["c"]).to(dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            xT, _ = bs.unrolled(T)
+            val, gx = heads.qp_value(Fd, dd, cd, xT)
+            gc, _, _, gd = bs.backward(gx)
+        torch.cuda.synchronize()
+        t_grad = (time.perf_counter() - t1) / args.steps
+        # envelope check: dV/dc = x*, dV/dd = x*^2 / 2 (at convergence)
+        gc_tot = (gc + xT).cpu().numpy()
+        xs = x.cpu().numpy()
+        env_c = float(np.abs(gc_tot - xs).max())
+    out = {"metric": METRIC, "value": round(solved / t_solve, 2), "unit": "QPs/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(t_solve * 1e3, 2), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"batched rAPDHG, {B} portfolio QPs n=500, Q = F F' + diag(d), "
+                                  f"F rank 20 shared", "batch": B, "solved": int(solved),
+                      "iterations_mean": float(np.mean(iters)), "iterations_max": int(np.max(iters)),
+                      "unrolled_iterations": T, "grad_ms": round(t_grad * 1e3, 2),
+                      "qps_per_s_with_gradient": round(B / t_grad, 2),
+                      "envelope_c_max_abs_err": env_c}}
     print(json.dumps(out), flush=True)
 
 

@@ -16,6 +16,7 @@ from .lp import (  # noqa: F401
     dense_planted_lp,
     grid_incidence,
     grid_mincost_batch,
+    shortest_path_learning,
     ragged_planted_batch,
     tiny_boxed_lp,
     portfolio_qp_batch,

@@ -342,6 +342,26 @@ def grid_mincost_batch(batch: int = 2048, rows: int = 32, cols: int = 32,
                                  tails=tails, heads=heads, grid=(rows, cols), seed=seed))
 
 
+def shortest_path_learning(batch: int = 256, rows: int = 32, cols: int = 32, p: int = 5,
+                           seed: int = 4000):
+    """Learning-to-route workload: grid min-cost flows whose arc costs come
+    from features. Per arc a of instance b: features f ~ N(0, I_p); the true
+    cost is c_true = 1 + 9 sigmoid(w*' f) with w* ~ N(0, I_p) fixed by the
+    seed (costs in [1, 10] as in the grid batch); the learner's initial
+    weights W0 ~ N(0, 0.1^2). Capacities >= 5 >= supply never bind, so the
+    optimum under c_true is supply x (shortest path).
+
+    Returns (SharedBatch with c = c_true, features [batch, n, p], w_star, W0)."""
+    rng = np.random.default_rng(seed)
+    w_star = rng.normal(0.0, 1.0, size=p)
+    W0 = rng.normal(0.0, 0.1, size=p)
+    m, n, *_ = grid_incidence(rows, cols)
+    feats = rng.normal(0.0, 1.0, size=(batch, n, p))
+    c_true = 1.0 + 9.0 / (1.0 + np.exp(-(feats @ w_star)))
+    sb = grid_mincost_batch(batch=batch, rows=rows, cols=cols, seed=seed + 1, costs=c_true)
+    return sb, feats, w_star, W0
+
+
 def ragged_planted_batch(batch: int = 1024, m_lo: int = 50, m_hi: int = 500,
                          density: float = 0.05, seed: int = 3500):
     """Planted sparse LPs of uneven size: m ~ U{m_lo..m_hi}, n = 2m."""

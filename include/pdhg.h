@@ -264,7 +264,8 @@ pdhg_err pdhg_batch_update_data(pdhg_batch *b, const double *c, const double *lc
  * differences through it are meaningful). The projection state of every
  * iteration is kept as bits for the reverse pass. x_out, y_out: the PDHG
  * point of iteration T-1 in the original space (device, laid out like c /
- * lc). T in [1, 10^6]. */
+ * lc); for QP batches (rAPDHG) the averages (xbar, ybar) of iteration T-1.
+ * T in [1, 10^6]. */
 pdhg_err pdhg_batch_unrolled_forward(pdhg_batch *b, int64_t T, int32_t replay, double *x_out,
                                      double *y_out);
 
@@ -280,6 +281,38 @@ pdhg_err pdhg_batch_unrolled_backward(pdhg_batch *b, const double *gx, const dou
 
 /* Release everything the batch owns. NULL is ignored. */
 void pdhg_batch_destroy(pdhg_batch *b);
+
+/* ---- Loss heads of the end-to-end learning pipelines (Section 4: the
+ * shortest-path experiment with a regret loss, and differentiating QP
+ * solutions). Device pointers, work enqueued on `stream` (a hipStream_t, NULL
+ * = default stream); the functions return once the work is enqueued, except
+ * pdhg_linear_costs_backward, which also waits for it. Sums are deterministic
+ * (fixed-order workgroup trees). Errors: PDHG_ERR_INVALID_ARG for bad sizes
+ * or NULL arrays. ---- */
+
+/* Linear cost model on features: c_hat[i] = sum_k W[k] f[i p + k] for the
+ * N = B n variables (f row-major [B n][p], 1 <= p <= 64). */
+pdhg_err pdhg_linear_costs(int32_t B, int32_t n, int32_t p, const double *f, const double *W,
+                           double *c_hat, void *stream);
+
+/* Regret of decisions x [B n] under the true costs: loss[b] = c_true_b' x_b
+ * - v_star[b], v_star the optimal value under c_true. Its gradient in x_b is
+ * c_true_b, the cotangent to hand to pdhg_batch_unrolled_backward. */
+pdhg_err pdhg_regret(int32_t B, int32_t n, const double *c_true, const double *x,
+                     const double *v_star, double *loss, void *stream);
+
+/* Weight gradient of the linear cost model: gW[k] = sum_i gc[i] f[i p + k]
+ * for a cotangent gc [B n] of c_hat (e.g. the gc of the unrolled reverse
+ * pass). gW has p entries. */
+pdhg_err pdhg_linear_costs_backward(int32_t B, int32_t n, int32_t p, const double *f,
+                                    const double *gc, double *gW, void *stream);
+
+/* Objective value of B QPs with Q_b = F F' + diag(d_b) (F [n r] row-major,
+ * shared, r <= 32; d, c, x [B n]): value[b] = 1/2 x_b' Q_b x_b + c_b' x_b and,
+ * when gx is not NULL, its gradient gx_b = Q_b x_b + c_b. */
+pdhg_err pdhg_qp_value(int32_t B, int32_t n, int32_t r, const double *F, const double *d,
+                       const double *c, const double *x, double *value, double *gx,
+                       void *stream);
 
 #ifdef __cplusplus
 }

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIB_DIR, "libpdhg.so")
 
-SOURCES = ["api.hip", "lp_kernels.hip", "setup.hip", "batch.hip", "qp_kernels.hip", "dense_kernels.hip", "batch_qp.hip"]
+SOURCES = ["api.hip", "lp_kernels.hip", "setup.hip", "batch.hip", "qp_kernels.hip", "dense_kernels.hip", "batch_qp.hip", "heads.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -84,6 +84,10 @@ SIGNATURES = {
     "pdhg_batch_update_data": (C.c_int, [P, P, P, P, P, P]),
     "pdhg_batch_unrolled_forward": (C.c_int, [P, C.c_int64, C.c_int32, P, P]),
     "pdhg_batch_unrolled_backward": (C.c_int, [P, P, P, P, P, P, P]),
+    "pdhg_linear_costs": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, P, P]),
+    "pdhg_regret": (C.c_int, [C.c_int32, C.c_int32, P, P, P, P, P]),
+    "pdhg_linear_costs_backward": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, P, P]),
+    "pdhg_qp_value": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P]),
     "pdhg_batch_destroy": (None, [P]),
 }
 

@@ -551,3 +551,42 @@ void pdhg_batch_destroy(pdhg_batch *pb) {
 }
 
 }  // extern "C"
+
+// ---- loss heads --------------------------------------------------------------
+
+pdhg_err pdhg_linear_costs(int32_t B, int32_t n, int32_t p, const double *f, const double *W,
+                           double *c_hat, void *stream) {
+    return guarded([&] {
+        if (B < 0 || n < 0 || p < 1 || p > 64) fail(PDHG_ERR_INVALID_ARG, "need B, n >= 0, 1 <= p <= 64");
+        if ((int64_t)B * n > 0 && (!f || !W || !c_hat)) fail(PDHG_ERR_INVALID_ARG, "NULL array");
+        head_linear_costs(reinterpret_cast<hipStream_t>(stream), B, n, p, f, W, c_hat);
+    });
+}
+
+pdhg_err pdhg_regret(int32_t B, int32_t n, const double *c_true, const double *x,
+                     const double *v_star, double *loss, void *stream) {
+    return guarded([&] {
+        if (B < 0 || n < 0) fail(PDHG_ERR_INVALID_ARG, "need B, n >= 0");
+        if (B > 0 && (!c_true || !x || !v_star || !loss)) fail(PDHG_ERR_INVALID_ARG, "NULL array");
+        head_regret(reinterpret_cast<hipStream_t>(stream), B, n, c_true, x, v_star, loss);
+    });
+}
+
+pdhg_err pdhg_linear_costs_backward(int32_t B, int32_t n, int32_t p, const double *f,
+                                    const double *gc, double *gW, void *stream) {
+    return guarded([&] {
+        if (B < 0 || n < 0 || p < 1 || p > 64) fail(PDHG_ERR_INVALID_ARG, "need B, n >= 0, 1 <= p <= 64");
+        if (!gW || ((int64_t)B * n > 0 && (!f || !gc))) fail(PDHG_ERR_INVALID_ARG, "NULL array");
+        head_linear_costs_backward(reinterpret_cast<hipStream_t>(stream), B, n, p, f, gc, gW);
+    });
+}
+
+pdhg_err pdhg_qp_value(int32_t B, int32_t n, int32_t r, const double *F, const double *d,
+                       const double *c, const double *x, double *value, double *gx, void *stream) {
+    return guarded([&] {
+        if (B < 0 || n < 0 || r < 0 || r > 32) fail(PDHG_ERR_INVALID_ARG, "need B, n >= 0, 0 <= r <= 32");
+        if (B > 0 && (!d || !c || !x || !value || (r > 0 && !F)))
+            fail(PDHG_ERR_INVALID_ARG, "NULL array");
+        head_qp_value(reinterpret_cast<hipStream_t>(stream), B, n, r, F, d, c, x, value, gx);
+    });
+}

@@ -177,6 +177,16 @@ struct Handle {
     ~Handle();
 };
 
+// ---- loss heads (heads.hip) ---------------------------------------------
+void head_linear_costs(hipStream_t s, int32_t B, int32_t n, int32_t p, const double *f,
+                       const double *W, double *c);
+void head_regret(hipStream_t s, int32_t B, int32_t n, const double *ct, const double *x,
+                 const double *vs, double *loss);
+void head_linear_costs_backward(hipStream_t s, int32_t B, int32_t n, int32_t p, const double *f,
+                                const double *gc, double *gW);
+void head_qp_value(hipStream_t s, int32_t B, int32_t n, int32_t r, const double *F,
+                   const double *d, const double *c, const double *x, double *value, double *gx);
+
 // ---- setup (setup.hip) ---------------------------------------------------
 void build_matrices(Handle &h, const pdhg_problem &p);
 void validate_and_load_vectors(Handle &h, const pdhg_problem &p);

@@ -1,0 +1,128 @@
+// Loss heads around the unrolled solver for end-to-end learning (Section 4,
+// the shortest-path and portfolio pipelines): a linear cost model on
+// per-variable features, the regret of the decisions under the true costs,
+// the weight gradient of the cost model, and the value / gradient of a
+// low-rank-plus-diagonal QP objective. All sums are deterministic
+// workgroup trees in a fixed order.
+#include <algorithm>
+
+#include "device.hpp"
+
+namespace pdhg {
+
+constexpr int kHeadChunks = 64;   // column chunks of the weight-gradient reduction
+constexpr int kHeadRmax = 32;     // largest factor rank of pdhg_qp_value
+
+__global__ __launch_bounds__(kBlock) void k_linear_costs(int64_t N, int32_t p,
+                                                         const double *__restrict__ f,
+                                                         const double *__restrict__ W,
+                                                         double *__restrict__ c) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+    double s = 0.0;
+    for (int32_t k = 0; k < p; ++k) s = fma(W[k], f[i * p + k], s);
+    c[i] = s;
+}
+
+// One workgroup per instance: loss[b] = c_true_b' x_b - v_star[b].
+__global__ __launch_bounds__(kBlock) void k_regret(int32_t n, const double *__restrict__ ct,
+                                                   const double *__restrict__ x,
+                                                   const double *__restrict__ vs,
+                                                   double *__restrict__ loss) {
+    const int32_t b = blockIdx.x;
+    const size_t o = (size_t)b * n;
+    double v[1] = {0.0};
+    for (int32_t a = threadIdx.x; a < n; a += kBlock) v[0] = fma(ct[o + a], x[o + a], v[0]);
+    block_sum_all<1>(v);
+    if (threadIdx.x == 0) loss[b] = v[0] - vs[b];
+}
+
+// Partial weight gradients: workgroup (k, chunk) sums gc[i] f[i, k] over
+// chunk `chunk` of the N = B n entries into part[k * kHeadChunks + chunk].
+__global__ __launch_bounds__(kBlock) void k_costs_grad_part(int64_t N, int32_t p,
+                                                            const double *__restrict__ f,
+                                                            const double *__restrict__ gc,
+                                                            double *__restrict__ part) {
+    const int32_t k = blockIdx.x / kHeadChunks, chunk = blockIdx.x % kHeadChunks;
+    const int64_t len = (N + kHeadChunks - 1) / kHeadChunks;
+    const int64_t i0 = chunk * len, i1 = std::min(N, i0 + len);
+    double v[1] = {0.0};
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) v[0] = fma(gc[i], f[i * p + k], v[0]);
+    block_sum_store<1>(v, part + (size_t)k * kHeadChunks + chunk);
+}
+
+__global__ __launch_bounds__(64) void k_costs_grad_final(int32_t p, const double *__restrict__ part,
+                                                         double *__restrict__ gW) {
+    const int32_t k = threadIdx.x;
+    if (k >= p) return;
+    double s = 0.0;
+    for (int32_t q = 0; q < kHeadChunks; ++q) s += part[(size_t)k * kHeadChunks + q];
+    gW[k] = s;
+}
+
+// One workgroup per instance: t = F' x, Qx = F t + d x, value and gradient.
+__global__ __launch_bounds__(kBlock) void k_qp_value(int32_t n, int32_t r, const double *__restrict__ F,
+                                                     const double *__restrict__ d,
+                                                     const double *__restrict__ c,
+                                                     const double *__restrict__ x,
+                                                     double *__restrict__ value,
+                                                     double *__restrict__ gx) {
+    const int32_t b = blockIdx.x;
+    const size_t o = (size_t)b * n;
+    double t[kHeadRmax];
+#pragma unroll
+    for (int k = 0; k < kHeadRmax; ++k) t[k] = 0.0;
+    for (int32_t j = threadIdx.x; j < n; j += kBlock) {
+        const double xj = x[o + j];
+        for (int32_t k = 0; k < r; ++k) t[k] = fma(F[(size_t)j * r + k], xj, t[k]);
+    }
+    block_sum_all<kHeadRmax>(t);
+    double v[1] = {0.0};
+    for (int32_t j = threadIdx.x; j < n; j += kBlock) {
+        double qx = d[o + j] * x[o + j];
+        for (int32_t k = 0; k < r; ++k) qx = fma(F[(size_t)j * r + k], t[k], qx);
+        const double g = qx + c[o + j];
+        if (gx) gx[o + j] = g;
+        v[0] += x[o + j] * (0.5 * qx + c[o + j]);
+    }
+    block_sum_all<1>(v);
+    if (threadIdx.x == 0) value[b] = v[0];
+}
+
+static unsigned grid1(int64_t N) { return (unsigned)std::max<int64_t>(1, ceil_div(N, kBlock)); }
+
+void head_linear_costs(hipStream_t s, int32_t B, int32_t n, int32_t p, const double *f,
+                       const double *W, double *c) {
+    const int64_t N = (int64_t)B * n;
+    if (N == 0) return;
+    k_linear_costs<<<grid1(N), kBlock, 0, s>>>(N, p, f, W, c);
+    PDHG_HIP(hipGetLastError());
+}
+
+void head_regret(hipStream_t s, int32_t B, int32_t n, const double *ct, const double *x,
+                 const double *vs, double *loss) {
+    if (B == 0) return;
+    k_regret<<<(unsigned)B, kBlock, 0, s>>>(n, ct, x, vs, loss);
+    PDHG_HIP(hipGetLastError());
+}
+
+void head_linear_costs_backward(hipStream_t s, int32_t B, int32_t n, int32_t p, const double *f,
+                                const double *gc, double *gW) {
+    const int64_t N = (int64_t)B * n;
+    DBuf<double> part;
+    part.alloc((size_t)p * kHeadChunks);
+    k_costs_grad_part<<<(unsigned)(p * kHeadChunks), kBlock, 0, s>>>(N, p, f, gc, part.p);
+    k_costs_grad_final<<<1, 64, 0, s>>>(p, part.p, gW);
+    PDHG_HIP(hipGetLastError());
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
+void head_qp_value(hipStream_t s, int32_t B, int32_t n, int32_t r, const double *F,
+                   const double *d, const double *c, const double *x, double *value, double *gx) {
+    if (B == 0) return;
+    if (r > kHeadRmax) fail(PDHG_ERR_UNSUPPORTED, "factor rank above 32");
+    k_qp_value<<<(unsigned)B, kBlock, 0, s>>>(n, r, F, d, c, x, value, gx);
+    PDHG_HIP(hipGetLastError());
+}
+
+}  // namespace pdhg
