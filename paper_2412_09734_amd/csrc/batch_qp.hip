@@ -19,9 +19,11 @@ namespace pdhg {
 
 constexpr int kRmax = 32;   // largest supported rank of F
 constexpr int kCkpt = 50;   // checkpoint spacing of the unrolled QP
+constexpr int kWaveRowsMax = 256;   // row limit of the wave-per-row mode
 
 struct QArgs {
     int32_t B, m, n, r;
+    int32_t wave_rows;      // 1: each constraint row is reduced by one wave (few, long rows)
     const int32_t *arp, *aci, *trp, *tci;
     const double *ava, *tva, *Dr, *Dc;
     double eta;
@@ -92,6 +94,16 @@ __device__ __forceinline__ double qdot(const int32_t *__restrict__ rp, const int
     double acc = 0.0;
     for (int32_t e = rp[row]; e < rp[row + 1]; ++e) acc = fma(va[e], v[ci[e]], acc);
     return acc;
+}
+
+// Row dot by one wave: lanes stride over the row, butterfly sum (all lanes).
+__device__ __forceinline__ double qdot_wave(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                            const double *__restrict__ va, int32_t row,
+                                            const double *__restrict__ v) {
+    double acc = 0.0;
+    for (int32_t e = rp[row] + (int32_t)(threadIdx.x & 63); e < rp[row + 1]; e += 64)
+        acc = fma(va[e], v[ci[e]], acc);
+    return wave_sum(acc);
 }
 
 // Per-instance pointers.
@@ -217,6 +229,35 @@ __device__ __forceinline__ void qstep(const QArgs &a, const QI &q, int64_t k, do
         }
     }
     __syncthreads();
+    if (a.wave_rows) {
+        // few long rows: one wave per row, projection states staged in LDS
+        __shared__ uint8_t flags[kWaveRowsMax];
+        for (int32_t i = (int32_t)(threadIdx.x >> 6); i < a.m; i += BT / 64) {
+            const double av = qdot_wave(a.arp, a.aci, a.ava, i, q.xe);
+            if ((threadIdx.x & 63) == 0) {
+                const double w = q.y[i] / sigma - av;
+                const bool at_u = w < -q.uc[i], at_l = w > -q.lc[i];
+                const double yp = sigma * (w - clampd(w, -q.uc[i], -q.lc[i]));
+                q.y[i] = yp;
+                q.yb[i] = (1.0 - theta) * q.yb[i] + theta * yp;
+                flags[i] = (uint8_t)((at_u ? 1 : 0) | (at_l ? 2 : 0));
+            }
+        }
+        __syncthreads();
+        if (ymt) {
+            for (int32_t i0 = 0; i0 < a.m; i0 += BT) {
+                const int32_t i = i0 + (int32_t)threadIdx.x;
+                const uint8_t fl = i < a.m ? flags[i] : (uint8_t)0;
+                const uint64_t bu = __ballot((fl & 1) != 0), bl = __ballot((fl & 2) != 0);
+                if ((threadIdx.x & 63) == 0 && i < a.m) {
+                    ymt[2 * (i >> 6)] = bu;
+                    ymt[2 * (i >> 6) + 1] = bl;
+                }
+            }
+        }
+        __syncthreads();
+        return;
+    }
     for (int32_t i0 = 0; i0 < a.m; i0 += BT) {
         const int32_t i = i0 + (int32_t)threadIdx.x;
         bool at_u = false, at_l = false;
@@ -266,8 +307,11 @@ __device__ __forceinline__ void qcheck(const QArgs &a, const QI &q, double (&v)[
         v[3] += q.c_o[j] * xo;
         v[4] += (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
     }
-    for (int32_t i = threadIdx.x; i < a.m; i += BT) {
-        const double p = qdot(a.arp, a.aci, a.ava, i, q.xb);
+    const bool wr = a.wave_rows != 0;
+    for (int32_t i = wr ? (int32_t)(threadIdx.x >> 6) : (int32_t)threadIdx.x; i < a.m;
+         i += wr ? BT / 64 : BT) {
+        const double p = wr ? qdot_wave(a.arp, a.aci, a.ava, i, q.xb) : qdot(a.arp, a.aci, a.ava, i, q.xb);
+        if (wr && (threadIdx.x & 63) != 0) continue;
         const double d = a.Dr[i];
         const double ax = p / d;
         const double lo = q.lc_o[i], hi = q.uc_o[i];
@@ -610,7 +654,14 @@ __global__ __launch_bounds__(BT) void k_bqp_backward(QArgs a, QOpts o) {
                     q.xe[j] = tau * bu;
                 }
                 __syncthreads();
-                for (int32_t i = threadIdx.x; i < a.m; i += BT) by[i] += qdot(a.arp, a.aci, a.ava, i, q.xe);
+                if (a.wave_rows) {
+                    for (int32_t i = (int32_t)(threadIdx.x >> 6); i < a.m; i += BT / 64) {
+                        const double s = qdot_wave(a.arp, a.aci, a.ava, i, q.xe);
+                        if ((threadIdx.x & 63) == 0) by[i] += s;
+                    }
+                } else {
+                    for (int32_t i = threadIdx.x; i < a.m; i += BT) by[i] += qdot(a.arp, a.aci, a.ava, i, q.xe);
+                }
                 // Q~ v: bv = F~ (F~' bqv) + d~ bqv, gradient in d~
                 double t2[kRmax];
                 qt_of<BT>(a, bqv, t2);
@@ -679,6 +730,8 @@ static QArgs qargs(BatchHandle &h) {
     a.m = h.m;
     a.n = h.n;
     a.r = h.q_rank;
+    // one wave per row when the rows are few and long (e.g. a budget row)
+    a.wave_rows = (h.m <= kWaveRowsMax && h.m > 0 && h.nnz >= (int64_t)32 * h.m) ? 1 : 0;
     a.arp = h.arp.p;
     a.aci = h.aci.p;
     a.trp = h.trp.p;

@@ -35,6 +35,57 @@ def _batch(p):
                            q_factor=p["F"], q_diag=p["d"])
 
 
+def _with_group_limits(p, groups=40, size=5, cap=0.3, seed=0):
+    """The portfolio plus `groups` rows sum_{j in S} x_j <= cap over random
+    asset groups S: many short rows, so the per-thread row path runs."""
+    rng = np.random.default_rng(seed)
+    n = p["n"]
+    rows = [np.arange(n)] + [np.sort(rng.choice(n, size=size, replace=False)) for _ in range(groups)]
+    rowptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    q = dict(p)
+    q.update(m=1 + groups, rowptr=rowptr, colidx=np.concatenate(rows).astype(np.int32),
+             val=np.ones(rowptr[-1]), lc=np.r_[1.0, np.full(groups, -np.inf)],
+             uc=np.r_[1.0, np.full(groups, cap)])
+    return q
+
+
+def _instance(p, b):
+    lp = gen.portfolio_instance(p, b)
+    lp.m, lp.rowptr, lp.colidx, lp.val = p["m"], p["rowptr"], p["colidx"], p["val"]
+    lp.lc, lp.uc = p["lc"].copy(), p["uc"].copy()
+    return lp
+
+
+@pytest.mark.parametrize("rows", ["budget", "groups"])
+def test_batch_qp_rows_paths_match_oracle(pdhg, oracle_lib, rows):
+    _say(f"case: batched rAPDHG unrolled + adjoint, constraint rows '{rows}'")
+    p = gen.portfolio_qp_batch(batch=3, n=60, rank=3, seed=4750)
+    if rows == "groups":
+        p = _with_group_limits(p)
+    T = 160
+    rng = np.random.default_rng(5)
+    with pdhg.BatchSolver.from_shared(_batch(p)) as bs:
+        x, y = bs.unrolled(T)
+        gx = rng.standard_normal((3, p["n"]))
+        gy = rng.standard_normal((3, p["m"]))
+        gc, glc, guc, gd = bs.backward(gx, gy)
+        xs, ys, res = bs.solve()
+        for b in range(3):
+            o = oracle_lib.Oracle(_instance(p, b))
+            xo, yo, sr, sw = o.unrolled_qp(T)
+            assert rel_inf(to_np(x[b]), xo) <= 1e-10
+            assert rel_inf(to_np(y[b]), yo) <= 1e-10
+            gco, glco, guco, gdo = o.backward_qp(T, sr, sw, gx[b], gy[b])
+            assert rel_inf(to_np(gc[b]), gco) <= 1e-9
+            assert rel_inf(to_np(glc[b]), glco) <= 1e-9
+            assert rel_inf(to_np(guc[b]), guco) <= 1e-9
+            assert rel_inf(to_np(gd[b]), gdo) <= 1e-9
+            xso, yso, ro = o.solve()
+            assert res[b]["status"] == 1 and ro["status"] == 1
+            assert abs(res[b]["iterations"] - ro["iterations"]) <= 64
+            assert abs(res[b]["primal_obj"] - ro["primal_obj"]) <= 1e-5 * (1 + abs(ro["primal_obj"]))
+
+
 def test_batch_qp_solve_matches_oracle(pdhg, oracle_lib):
     _say("case: batched rAPDHG solve, 6 portfolio QPs n=90 rank 6, eps 1e-6")
     p = gen.portfolio_qp_batch(batch=6, n=90, rank=6, seed=4700)
