@@ -67,13 +67,13 @@ def measured_traffic(kernel: str):
 
 
 def cpu_baseline(lp, gpu_iters: int, gpu_power_iters: int) -> dict:
-    """The oracle on a bounded sample of the same LP: its scaling, then 65
+    """The oracle on a bounded sample of the same LP: its scaling, then 40
     iterations (checks at the first and last), timed on one host core; the
     per-LP time is extrapolated to the GPU's power-iteration and iteration
     counts (each power step costs about one iteration's two products)."""
     import oracle
     oracle.build(force=False)
-    sample_iters = 65
+    sample_iters = 40
     t0 = time.perf_counter()
     orc = oracle.Oracle(lp, power_max_iters=1, iteration_limit=sample_iters)
     t_setup = time.perf_counter() - t0
