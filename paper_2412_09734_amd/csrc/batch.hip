@@ -43,6 +43,9 @@ struct BArgs {
     double *x_out, *y_out;
     BatchRes *res;
     int32_t *queue;
+    // SELL-64 copies (entry k of local row i at sp[sfirst + i/64] + 64 k + i%64)
+    const int32_t *asp, *asci, *asfirst, *tsp, *tsci, *tsfirst;
+    const double *asva, *tsva;
 };
 
 // Geometry of instance b: matrix rows start at r0 (A) / c0 (A'); vectors at
@@ -77,10 +80,15 @@ __device__ __forceinline__ Geo geometry(const BArgs &a, int32_t b) {
     return g;
 }
 
+// Deterministic workgroup sum of K values per thread, result in every thread:
+// wave butterflies, then thread q adds the wave totals of value q in wave
+// order (one value per thread keeps the register footprint independent of
+// the workgroup size).
 template <int BT, int K>
 __device__ __forceinline__ void wg_sum(double (&v)[K]) {
     constexpr int NW = BT / 64;
     __shared__ double sh[K][NW];
+    __shared__ double tot[K];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
@@ -88,13 +96,14 @@ __device__ __forceinline__ void wg_sum(double (&v)[K]) {
         if (lane == 0) sh[q][wave] = s;
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
+    if ((int)threadIdx.x < K) {
         double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) s += sh[q][w];
-        v[q] = s;
+        for (int w = 0; w < NW; ++w) s += sh[threadIdx.x][w];
+        tot[threadIdx.x] = s;
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = tot[q];
     __syncthreads();
 }
 
@@ -114,6 +123,32 @@ __device__ __forceinline__ double csr_dot(const int32_t *__restrict__ rp, const 
     double acc = 0.0;
     const int32_t e1 = rp[row + 1];
     for (int32_t e = rp[row]; e < e1; ++e) acc = fma(va[e], v[ci[e]], acc);
+    return acc;
+}
+
+// Row sum of a SELL-64 slice row: lane `lane` of slice `sl`; entries walked in
+// row order (padding entries are (column 0, value 0.0)).
+__device__ __forceinline__ double sell_dot(const int32_t *__restrict__ sp, const int32_t *__restrict__ ci,
+                                           const double *__restrict__ va, int32_t sl, int32_t lane,
+                                           const double *__restrict__ v) {
+    const int32_t b = sp[sl], w = (sp[sl + 1] - b) >> 6;
+    double acc = 0.0;
+    for (int32_t k = 0; k < w; ++k) {
+        const int32_t e = b + 64 * k + lane;
+        acc = fma(va[e], v[ci[e]], acc);
+    }
+    return acc;
+}
+
+// Same with the slice's first entry and width already known.
+__device__ __forceinline__ double sell_dot_bw(const int32_t *__restrict__ ci, const double *__restrict__ va,
+                                              int32_t base, int32_t w, int32_t lane,
+                                              const double *__restrict__ v) {
+    double acc = 0.0;
+    for (int32_t k = 0; k < w; ++k) {
+        const int32_t e = base + 64 * k + lane;
+        acc = fma(va[e], v[ci[e]], acc);
+    }
     return acc;
 }
 
@@ -429,6 +464,299 @@ __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
         // original-space output of the last PDHG point
         for (int32_t j = threadIdx.x; j < g.n; j += BT) a.x_out[g.vc + j] = Dc[j] * xh[j];
         for (int32_t i = threadIdx.x; i < g.m; i += BT) a.y_out[g.vr + i] = Dr[i] * yh[i];
+        if (threadIdx.x == 0) {
+            BatchRes r;
+            r.pobj = P;
+            r.dobj = D;
+            r.rel_p = rel_p;
+            r.rel_d = rel_d;
+            r.rel_g = rel_g;
+            r.kkt = kkt;
+            r.omega = omega;
+            r.eta = eta;
+            r.iterations = t + 1;
+            r.restarts = restarts;
+            r.status = status;
+            r.power_iters = a.power_iters[g.sidx];
+            a.res[b] = r;
+        }
+        __syncthreads();
+    }
+}
+
+// Same iteration with the gathered vectors held on chip: y (for A~'y) and
+// x_ext (for A~x_ext; at checks the PDHG points) live in LDS, and each thread
+// keeps the row pointers of its S columns and S rows in registers. The
+// per-element data (iterate, anchors, c~, bounds) are read and written by
+// their owner only; those loads do not depend on the gathers and overlap
+// them, so an iteration costs about one round trip for the shared matrix
+// entries plus LDS instead of a chain of memory round trips. Same arithmetic
+// and summation order as k_batch_solve.
+template <int BT, int S>
+__global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_t nmax) {
+    extern __shared__ double lds[];
+    double *sx = lds;          // x_ext, at checks x^
+    double *sy = lds + nmax;   // y, at checks y^
+    for (;;) {
+        const int32_t b = next_instance<BT>(a.queue);
+        if (b >= a.B) return;
+        const Geo g = geometry(a, b);
+        const int32_t as0 = a.shared ? 0 : a.asfirst[b], ts0 = a.shared ? 0 : a.tsfirst[b];
+        const int32_t lane = (int32_t)(threadIdx.x & 63);
+        const double *Dr = a.Dr + g.dr, *Dc = a.Dc + g.dc;
+        const double *c_o = a.c_o + g.vc, *lv_o = a.lv_o + g.vc, *uv_o = a.uv_o + g.vc;
+        const double *lc_o = a.lc_o + g.vr, *uc_o = a.uc_o + g.vr;
+        double *__restrict__ lc = a.lc + g.vr;
+        double *__restrict__ uc = a.uc + g.vr;
+        double *__restrict__ xh = a.xh + g.vc;
+        double *__restrict__ aty = a.aty + g.vc;
+        double *__restrict__ y = a.y + g.vr;
+        double *__restrict__ y0 = a.y0 + g.vr;
+        double *__restrict__ yh = a.yh + g.vr;
+        const int32_t *__restrict__ tsci = a.tsci;
+        const int32_t *__restrict__ asci = a.asci;
+        const double *__restrict__ tsva = a.tsva;
+        const double *__restrict__ asva = a.asva;
+        const double eta = a.eta[g.sidx];
+        const double gam = o.gamma;
+
+        // slice start and width of each owned column / row (iteration invariant)
+        int32_t tbase[S], tw[S], abase[S], aw[S];
+        // per-column iterate, anchor, cost and bounds stay in registers
+        double xr[S], x0r[S], cr[S], lvr[S], uvr[S];
+        double nrm[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int32_t j = threadIdx.x + q * BT;
+            tbase[q] = tw[q] = abase[q] = aw[q] = 0;
+            xr[q] = x0r[q] = cr[q] = lvr[q] = uvr[q] = 0.0;
+            if (j < g.n) {
+                const int32_t sl = ts0 + (j >> 6);
+                tbase[q] = a.tsp[sl];
+                tw[q] = (a.tsp[sl + 1] - tbase[q]) >> 6;
+            }
+            if (j < g.m) {
+                const int32_t sl = as0 + (j >> 6);
+                abase[q] = a.asp[sl];
+                aw[q] = (a.asp[sl + 1] - abase[q]) >> 6;
+            }
+            if (j < g.n) {
+                const double d = Dc[j];
+                const double cj = d * c_o[j];
+                const double l = lv_o[j] / d, u = uv_o[j] / d;
+                cr[q] = cj;
+                lvr[q] = l;
+                uvr[q] = u;
+                nrm[0] += cj * cj;
+                nrm[2] += c_o[j] * c_o[j];
+                const double v0 = a.x_init ? a.x_init[g.vc + j] / d : 0.0;
+                xr[q] = clampd(v0, l, u);
+                x0r[q] = xr[q];
+            }
+            const int32_t i = j;
+            if (i < g.m) {
+                const double d = Dr[i];
+                const double l = d * lc_o[i], u = d * uc_o[i];
+                lc[i] = l;
+                uc[i] = u;
+                double bb = 0.0, bo = 0.0;
+                if (isfinite(l)) bb = fmax(bb, fabs(l));
+                if (isfinite(u)) bb = fmax(bb, fabs(u));
+                if (isfinite(lc_o[i])) bo = fmax(bo, fabs(lc_o[i]));
+                if (isfinite(uc_o[i])) bo = fmax(bo, fabs(uc_o[i]));
+                nrm[1] += bb * bb;
+                nrm[3] += bo * bo;
+                const double v0 = a.y_init ? a.y_init[g.vr + i] / d : 0.0;
+                const double lo = isfinite(u) ? -INFINITY : 0.0;
+                const double hi = isfinite(l) ? INFINITY : 0.0;
+                const double yv = clampd(v0, lo, hi);
+                sy[i] = yv;
+                y0[i] = yv;
+            }
+        }
+        wg_sum<BT, 4>(nrm);
+        const double cn = sqrt(nrm[0]), bn = sqrt(nrm[1]);
+        const double cnorm = sqrt(nrm[2]), bnorm = sqrt(nrm[3]);
+        double omega = (cn > 1e-10 && bn > 1e-10) ? cn / bn : 1.0;
+        double tau = eta / omega, sigma = eta * omega;
+
+        int64_t t = 0, k = 0, restarts = 0;
+        double r_start = 0.0, r_prev = 0.0;
+        int32_t status = 0;
+        double kkt = 0.0, rel_p = 0.0, rel_d = 0.0, rel_g = 0.0, P = 0.0, D = 0.0;
+        for (;;) {
+            // an opaque copy of the thread index: the element addresses are
+            // recomputed each iteration (two VALU ops) instead of being hoisted
+            // into ~40 registers per slot, which would spill
+            int32_t tid = (int32_t)threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            const bool check = (t % o.check_every) == 0;
+            const bool last = t + 1 >= o.limit;
+            const bool keep = check || last;
+            const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int32_t j = tid + q * BT;
+                if (j < g.n) {
+                    const double s = sell_dot_bw(tsci, tsva, tbase[q], tw[q], lane, sy);
+                    const double xhat = clampd(xr[q] - tau * (cr[q] - s), lvr[q], uvr[q]);
+                    sx[j] = 2.0 * xhat - xr[q];
+                    if (keep) {
+                        xh[j] = xhat;
+                        aty[j] = s;
+                    } else {
+                        xr[q] = ak * ((1.0 + gam) * xhat - gam * xr[q]) + bk * x0r[q];
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int32_t i = tid + q * BT;
+                if (i < g.m) {
+                    const double li = lc[i], ui = uc[i];
+                    const double av = sell_dot_bw(asci, asva, abase[q], aw[q], lane, sx);
+                    const double yv = sy[i];
+                    const double yhat = dual_prox(yv, av, sigma, li, ui);
+                    if (keep) {
+                        yh[i] = yhat;
+                        y[i] = yv;
+                    } else {
+                        sy[i] = ak * ((1.0 + gam) * yhat - gam * yv) + bk * y0[i];
+                    }
+                }
+            }
+            __syncthreads();
+            if (!keep) {
+                ++k;
+                ++t;
+                continue;
+            }
+            // check: the PDHG points replace x_ext and y in LDS for the products
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int32_t j = tid + q * BT;
+                if (j < g.n) sx[j] = xh[j];
+                if (j < g.m) sy[j] = yh[j];
+            }
+            __syncthreads();
+            double v[10];
+#pragma unroll
+            for (int q = 0; q < 10; ++q) v[q] = 0.0;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int32_t j = tid + q * BT;
+                if (j < g.n) {
+                    const double qq = sell_dot_bw(tsci, tsva, tbase[q], tw[q], lane, sy);
+                    const double xhv = xh[j];
+                    const double dx = xhv - xr[q];
+                    v[0] += dx * dx;
+                    v[1] += (qq - aty[j]) * dx;
+                    const double d0 = xhv - x0r[q];
+                    v[2] += d0 * d0;
+                    const double d = Dc[j];
+                    const double gr = c_o[j] - qq / d;
+                    const double lo = lv_o[j], hi = uv_o[j];
+                    const bool lf = isfinite(lo), uf = isfinite(hi);
+                    const double lam = (!lf && !uf) ? 0.0 : (lf && !uf) ? fmax(gr, 0.0) : (!lf && uf) ? fmin(gr, 0.0) : gr;
+                    const double rd = gr - lam;
+                    v[3] += rd * rd;
+                    v[4] += c_o[j] * (d * xhv);
+                    v[5] += (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int32_t i = tid + q * BT;
+                if (i < g.m) {
+                    const double p = sell_dot_bw(asci, asva, abase[q], aw[q], lane, sx);
+                    const double d = Dr[i];
+                    const double ax = p / d;
+                    const double lo = lc_o[i], hi = uc_o[i];
+                    const double rpr = ax - clampd(ax, lo, hi);
+                    v[6] += rpr * rpr;
+                    const double yhv = yh[i];
+                    const double yo = d * yhv;
+                    v[7] += (isfinite(lo) ? lo * fmax(yo, 0.0) : 0.0) - (isfinite(hi) ? hi * fmax(-yo, 0.0) : 0.0);
+                    const double dy = yhv - y[i];
+                    v[8] += dy * dy;
+                    const double d0 = yhv - y0[i];
+                    v[9] += d0 * d0;
+                }
+            }
+            wg_sum<BT, 10>(v);
+            P = v[4];
+            D = v[7] + v[5];
+            rel_p = sqrt(v[6]) / (1.0 + bnorm);
+            rel_d = sqrt(v[3]) / (1.0 + cnorm);
+            rel_g = fabs(P - D) / (1.0 + fabs(P) + fabs(D));
+            kkt = rel_p;
+            if (rel_d > kkt || isnan(rel_d)) kkt = rel_d;
+            if (rel_g > kkt || isnan(rel_g)) kkt = rel_g;
+            if (isnan(kkt)) {
+                status = PDHG_NUMERICAL_ERROR;
+                break;
+            }
+            if (kkt <= o.eps) {
+                status = PDHG_OPTIMAL;
+                break;
+            }
+            if (last) {
+                status = PDHG_ITERATION_LIMIT;
+                break;
+            }
+            const double r2 = v[0] / tau + v[8] / sigma + 2.0 * v[1];
+            const double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+            bool restart = false;
+            if (t == 0) {
+                r_start = r;
+                r_prev = r;
+            } else if (r <= o.beta_suff * r_start || (r <= o.beta_nec * r_start && r > r_prev) ||
+                       (double)k >= o.beta_art * (double)t) {
+                restart = true;
+            } else {
+                r_prev = r;
+            }
+            if (restart) {
+                const double dxr = sqrt(v[2]), dyr = sqrt(v[9]);
+                if (dxr > 1e-10 && dyr > 1e-10) omega = exp(0.5 * log(dyr / dxr) + 0.5 * log(omega));
+                tau = eta / omega;
+                sigma = eta * omega;
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const int32_t j = tid + q * BT;
+                    if (j < g.n) {
+                        xr[q] = xh[j];
+                        x0r[q] = xr[q];
+                    }
+                    if (j < g.m) {
+                        sy[j] = yh[j];
+                        y0[j] = yh[j];
+                    }
+                }
+                k = 0;
+                r_start = r;
+                r_prev = r;
+                ++restarts;
+            } else {
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const int32_t j = tid + q * BT;
+                    if (j < g.n) xr[q] = ak * ((1.0 + gam) * xh[j] - gam * xr[q]) + bk * x0r[q];
+                    if (j < g.m) sy[j] = ak * ((1.0 + gam) * yh[j] - gam * y[j]) + bk * y0[j];
+                }
+                ++k;
+            }
+            ++t;
+            __syncthreads();
+        }
+        // original-space output of the last PDHG point
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int32_t j = threadIdx.x + q * BT;
+            if (j < g.n) a.x_out[g.vc + j] = Dc[j] * xh[j];
+            if (j < g.m) a.y_out[g.vr + j] = Dr[j] * yh[j];
+        }
         if (threadIdx.x == 0) {
             BatchRes r;
             r.pobj = P;
@@ -855,6 +1183,14 @@ static BArgs batch_args(BatchHandle &h) {
     a.queue = h.queue.p;
     a.x_init = h.x_init_;
     a.y_init = h.y_init_;
+    a.asp = h.asp.p;
+    a.asci = h.asci.p;
+    a.asva = h.asva.p;
+    a.asfirst = h.asfirst.p;
+    a.tsp = h.tsp.p;
+    a.tsci = h.tsci.p;
+    a.tsva = h.tsva.p;
+    a.tsfirst = h.tsfirst.p;
     a.x_out = h.x_out_;
     a.y_out = h.y_out_;
     return a;
@@ -881,9 +1217,98 @@ static void launch_setup_t(BatchHandle &h, int32_t count) {
     PDHG_HIP(hipGetLastError());
 }
 
+template <int BT, int S>
+static void launch_solve_lds_t(BatchHandle &h, const BOpts &o, BArgs a, size_t lds) {
+    const void *kern = reinterpret_cast<const void *>(&k_batch_solve_lds<BT, S>);
+    int dev = 0, per_cu = 0;
+    PDHG_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    PDHG_HIP(hipGetDeviceProperties(&prop, dev));
+    PDHG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BT, lds));
+    int32_t wg = std::min(h.B, std::max(1, per_cu) * prop.multiProcessorCount);
+    if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
+    PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
+    k_batch_solve_lds<BT, S><<<wg, BT, lds, h.stream>>>(a, o, h.nmax);
+    PDHG_HIP(hipGetLastError());
+}
+
+template <class T>
+static void load(DBuf<T> &dst, const T *src, size_t count, int mem, hipStream_t s);
+
+// SELL-64 copy of a batch matrix (rows of every instance padded to whole
+// slices): built on the host from the scaled CSR after the setup kernel.
+static void build_batch_sell(hipStream_t s, int32_t nb, const std::vector<int32_t> &roff,
+                             const DBuf<int32_t> &rp, const DBuf<int32_t> &ci, const DBuf<double> &va,
+                             int64_t nnz, DBuf<int32_t> &sp, DBuf<int32_t> &sci, DBuf<double> &sva,
+                             DBuf<int32_t> &sfirst) {
+    const int32_t rows = roff[nb];
+    std::vector<int32_t> hrp((size_t)rows + 1), hci((size_t)std::max<int64_t>(nnz, 1));
+    std::vector<double> hva((size_t)std::max<int64_t>(nnz, 1));
+    PDHG_HIP(hipMemcpyAsync(hrp.data(), rp.p, hrp.size() * 4, hipMemcpyDeviceToHost, s));
+    if (nnz > 0) {
+        PDHG_HIP(hipMemcpyAsync(hci.data(), ci.p, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
+        PDHG_HIP(hipMemcpyAsync(hva.data(), va.p, (size_t)nnz * 8, hipMemcpyDeviceToHost, s));
+    }
+    PDHG_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> first((size_t)nb + 1), off(1, 0);
+    int64_t total = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        first[b] = (int32_t)off.size() - 1;
+        for (int32_t r0 = roff[b]; r0 < roff[b + 1]; r0 += 64) {
+            int32_t w = 0;
+            for (int32_t r = r0; r < std::min(r0 + 64, roff[b + 1]); ++r) w = std::max(w, hrp[r + 1] - hrp[r]);
+            total += 64 * (int64_t)w;
+            if (total >= INT32_MAX) fail(PDHG_ERR_UNSUPPORTED, "batch matrix too large for 32-bit offsets");
+            off.push_back((int32_t)total);
+        }
+    }
+    first[nb] = (int32_t)off.size() - 1;
+    std::vector<int32_t> oci((size_t)std::max<int64_t>(total, 1), 0);
+    std::vector<double> ova((size_t)std::max<int64_t>(total, 1), 0.0);
+    for (int32_t b = 0; b < nb; ++b)
+        for (int32_t r = roff[b]; r < roff[b + 1]; ++r) {
+            const int32_t loc = r - roff[b], sl = first[b] + loc / 64, l = loc % 64;
+            for (int32_t e = hrp[r]; e < hrp[r + 1]; ++e) {
+                const int64_t o = off[sl] + 64 * (int64_t)(e - hrp[r]) + l;
+                oci[o] = hci[e];
+                ova[o] = hva[e];
+            }
+        }
+    load(sp, off.data(), off.size(), PDHG_MEM_HOST, s);
+    load(sci, oci.data(), oci.size(), PDHG_MEM_HOST, s);
+    load(sva, ova.data(), ova.size(), PDHG_MEM_HOST, s);
+    load(sfirst, first.data(), first.size(), PDHG_MEM_HOST, s);
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
+// Largest instance column / row counts (LDS sizing of the on-chip solve).
+static void instance_extents(BatchHandle &h) {
+    if (h.shared) {
+        h.nmax = h.n;
+        h.mmax = h.m;
+        return;
+    }
+    h.nmax = h.mmax = 0;
+    for (int32_t b = 0; b < h.B; ++b) {
+        h.nmax = std::max(h.nmax, h.col_off_h[b + 1] - h.col_off_h[b]);
+        h.mmax = std::max(h.mmax, h.row_off_h[b + 1] - h.row_off_h[b]);
+    }
+}
+
 template <int BT>
 static void launch_solve_t(BatchHandle &h, const BOpts &o) {
     BArgs a = batch_args(h);
+    // on-chip variant when both gathered vectors fit 64 KB of LDS and every
+    // thread owns at most 8 columns and 8 rows
+    const size_t lds = ((size_t)h.nmax + (size_t)h.mmax) * sizeof(double);
+    const int32_t need = std::max(h.nmax, h.mmax);
+    if (h.onchip && lds <= 65536 && need <= 8 * BT) {
+        const size_t l = std::max<size_t>(lds, 8);
+        if (need <= BT) return launch_solve_lds_t<BT, 1>(h, o, a, l);
+        if (need <= 2 * BT) return launch_solve_lds_t<BT, 2>(h, o, a, l);
+        if (need <= 4 * BT) return launch_solve_lds_t<BT, 4>(h, o, a, l);
+        return launch_solve_lds_t<BT, 8>(h, o, a, l);
+    }
     int32_t wg = std::min(h.B, resident<BT>(reinterpret_cast<const void *>(&k_batch_solve<BT>)));
     if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
     PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
@@ -977,6 +1402,7 @@ BatchHandle *batch_create(const pdhg_batch_problem &p, const pdhg_options &o, vo
         h.row_off.alloc(1);
         h.col_off.alloc(1);
     }
+    instance_extents(h);
     // A' from the global matrix, then instance-local indices on both
     h.trp.alloc((size_t)h.n + 1);
     h.tci.alloc((size_t)h.nnz);
@@ -1009,6 +1435,13 @@ BatchHandle *batch_create(const pdhg_batch_problem &p, const pdhg_options &o, vo
     h.queue.alloc(1);
     dispatch_setup(h, nscal);
     PDHG_HIP(hipStreamSynchronize(s));
+    {
+        const int32_t nb = h.shared ? 1 : h.B;
+        std::vector<int32_t> ro = h.shared ? std::vector<int32_t>{0, h.m} : h.row_off_h;
+        std::vector<int32_t> co = h.shared ? std::vector<int32_t>{0, h.n} : h.col_off_h;
+        build_batch_sell(s, nb, ro, h.arp, h.aci, h.ava, h.nnz, h.asp, h.asci, h.asva, h.asfirst);
+        build_batch_sell(s, nb, co, h.trp, h.tci, h.tva, h.nnz, h.tsp, h.tsci, h.tsva, h.tsfirst);
+    }
     if (p.q_rank > 0) bqp_create(h, p);
     h.setup_seconds = now_seconds() - t0;
     return hp.release();

@@ -31,12 +31,18 @@ struct BatchHandle {
     const double *x_init_ = nullptr, *y_init_ = nullptr;
     double *x_out_ = nullptr, *y_out_ = nullptr;
     std::vector<int32_t> row_off_h, col_off_h;
+    // SELL-64 copies of the scaled A~ and A~' (built after scaling): slices
+    // never cross instances; slice s of instance b is sfirst[b] + local row / 64
+    DBuf<int32_t> asp, asci, asfirst, tsp, tsci, tsfirst;
+    DBuf<double> asva, tsva;
     // QP batches: Q_b = F F' + diag(d_b), F shared (scaled copy), d per instance
     int32_t q_rank = 0;
     DBuf<double> qF, qd_o, qdd, normq, xbar, ybar, qv_, qres;
     DBuf<double> ckpt, vseg, bxb, byb, bw, bqv;
     // unrolled iterations: schedule, masks and reverse-pass scratch
     int64_t unrolled_T = 0;
+    int32_t nmax = 0, mmax = 0;           // largest instance (LDS sizing)
+    int32_t onchip = 1;                   // use the on-chip solve when it fits
     DBuf<uint8_t> u_restart;
     DBuf<double> u_omega, u_ba;
     DBuf<int32_t> u_kk;

@@ -274,6 +274,11 @@ class BatchSolver:
     @classmethod
     def from_lps(cls, lps, **opts) -> "BatchSolver":
         """Ragged batch from a list of LP objects (block-diagonal concatenation)."""
+        return cls(**cls.ragged_arrays(lps), **opts)
+
+    @staticmethod
+    def ragged_arrays(lps) -> dict:
+        """Constructor arguments of the ragged batch of `lps` (host arrays)."""
         ms = np.array([lp.m for lp in lps], dtype=np.int64)
         ns = np.array([lp.n for lp in lps], dtype=np.int64)
         row_off = np.concatenate([[0], np.cumsum(ms)])
@@ -283,10 +288,9 @@ class BatchSolver:
                                 + [[nnz_off[-1]]])
         colidx = np.concatenate([lp.colidx.astype(np.int64) + col_off[b] for b, lp in enumerate(lps)])
         cat = lambda f: np.concatenate([getattr(lp, f) for lp in lps])  # noqa: E731
-        return cls(shared_a=False, batch=len(lps), m=int(row_off[-1]), n=int(col_off[-1]),
-                   rowptr=rowptr, colidx=colidx, val=cat("val"), c=cat("c"), lc=cat("lc"),
-                   uc=cat("uc"), lv=cat("lv"), uv=cat("uv"), row_off=row_off, col_off=col_off,
-                   **opts)
+        return dict(shared_a=False, batch=len(lps), m=int(row_off[-1]), n=int(col_off[-1]),
+                    rowptr=rowptr, colidx=colidx, val=cat("val"), c=cat("c"), lc=cat("lc"),
+                    uc=cat("uc"), lv=cat("lv"), uv=cat("uv"), row_off=row_off, col_off=col_off)
 
     def close(self):
         if getattr(self, "_h", None):

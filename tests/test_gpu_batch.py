@@ -64,6 +64,27 @@ def test_ragged_batch_matches_oracle(pdhg, oracle_lib):
             assert abs(kb["kkt"] - rb["kkt_rel"]) <= 1e-9 + 1e-6 * kb["kkt"]
 
 
+def test_ragged_batch_beyond_lds_matches_oracle(pdhg, oracle_lib):
+    """Instances whose gathered vectors exceed the on-chip budget (n + m >
+    8192) run the memory-resident kernel; a small instance in the same batch
+    does not change that choice."""
+    _say("case: ragged batch with m ~ 3000, n ~ 6000 instances (memory-resident kernel)")
+    lps = gen.ragged_planted_batch(batch=2, m_lo=2900, m_hi=3000, density=0.003, seed=3950)
+    lps.append(gen.ragged_planted_batch(batch=1, m_lo=60, m_hi=60, seed=3951)[0])
+    assert max(lp.m + lp.n for lp in lps) > 8192
+    with pdhg.BatchSolver.from_lps(lps) as bs:
+        x, y, res = bs.solve()
+        for b, lp in enumerate(lps):
+            _, _, ro = oracle_lib.Oracle(lp).solve()
+            cs, rs = bs.instance_slices(b)
+            rb = res[b]
+            assert rb["status_name"] == "optimal", (b, rb)
+            assert _close(rb["primal_obj"], ro["primal_obj"]), (b, rb["primal_obj"], ro["primal_obj"])
+            assert rb["iterations"] == ro["iterations"], (b, rb["iterations"], ro["iterations"])
+            kb = oracle_lib.kkt(lp, to_np(x[cs]), to_np(y[rs]))
+            assert abs(kb["kkt"] - rb["kkt_rel"]) <= 1e-9 + 1e-6 * kb["kkt"]
+
+
 def test_batch_determinism_and_launch_shapes(pdhg):
     _say("case: batch determinism across launches and thread counts")
     sb = gen.grid_mincost_batch(batch=40, rows=8, cols=8, seed=3200)
