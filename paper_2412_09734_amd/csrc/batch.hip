@@ -163,8 +163,10 @@ __device__ __forceinline__ uint64_t splitmix64_b(uint64_t x) {
 // setup: Ruiz + Pock-Chambolle scaling and the power iteration, per instance
 // (once for a shared matrix).
 
-template <int BT>
-__global__ __launch_bounds__(BT) void k_batch_setup(BArgs a, BOpts o, int32_t count) {
+// ONCHIP: the power iteration's gathered vectors v (n) and w (m) live in LDS.
+template <int BT, bool ONCHIP>
+__global__ __launch_bounds__(BT) void k_batch_setup(BArgs a, BOpts o, int32_t count, int32_t nmax) {
+    extern __shared__ double lds[];
     for (;;) {
         const int32_t b = next_instance<BT>(a.queue);
         if (b >= count) return;
@@ -208,7 +210,9 @@ __global__ __launch_bounds__(BT) void k_batch_setup(BArgs a, BOpts o, int32_t co
         double lam = 0.0;
         int32_t it = 0;
         if (g.m > 0 && nnz > 0) {
-            double *v = a.xh + g.vc, *w = a.yh + g.vr, *u = a.xe + g.vc;
+            double *v = ONCHIP ? lds : a.xh + g.vc;
+            double *w = ONCHIP ? lds + nmax : a.yh + g.vr;
+            double *u = a.xe + g.vc;
             double q[1] = {0.0};
             for (int32_t j = threadIdx.x; j < g.n; j += BT) {
                 const double val = 0.5 + (double)(splitmix64_b((uint64_t)j) >> 11) * 0x1.0p-53;
@@ -797,8 +801,12 @@ struct UArgs {
 // check cadence (no termination test) unless replayed; every iteration
 // records omega, k, the restart flag, the set of x inside its box and the
 // clamp state of every row (bit 0: at -u_c, bit 1: at -l_c).
-template <int BT>
-__global__ __launch_bounds__(BT) void k_batch_unrolled(BArgs a, BOpts o, UArgs u) {
+// ONCHIP: y and x_ext live in LDS and the products walk the SELL-64 copies
+// (instances whose n + m fits the LDS budget); otherwise everything stays in
+// memory and the products walk the CSR arrays. Same arithmetic either way.
+template <int BT, bool ONCHIP>
+__global__ __launch_bounds__(BT) void k_batch_unrolled(BArgs a, BOpts o, UArgs u, int32_t nmax) {
+    extern __shared__ double lds[];
     for (;;) {
         const int32_t b = next_instance<BT>(a.queue);
         if (b >= a.B) return;
@@ -813,7 +821,12 @@ __global__ __launch_bounds__(BT) void k_batch_unrolled(BArgs a, BOpts o, UArgs u
         double *lc = a.lc + g.vr, *uc = a.uc + g.vr;
         double *x = a.x + g.vc, *x0 = a.x0 + g.vc, *xh = a.xh + g.vc, *xe = a.xe + g.vc;
         double *aty = a.aty + g.vc;
-        double *y = a.y + g.vr, *y0 = a.y0 + g.vr, *yh = a.yh + g.vr;
+        double *y0 = a.y0 + g.vr, *yh = a.yh + g.vr;
+        // gathered vectors: y (primal product) and x_ext (dual product)
+        double *y = ONCHIP ? lds + nmax : a.y + g.vr;
+        if (ONCHIP) xe = lds;
+        const int32_t as0 = (ONCHIP && !a.shared) ? a.asfirst[b] : 0;
+        const int32_t ts0 = (ONCHIP && !a.shared) ? a.tsfirst[b] : 0;
         uint8_t *rs_ = u.restart + (size_t)b * u.T;
         double *om_ = u.omega + (size_t)b * u.T;
         int32_t *kk_ = u.kk + (size_t)b * u.T;
@@ -872,7 +885,8 @@ __global__ __launch_bounds__(BT) void k_batch_unrolled(BArgs a, BOpts o, UArgs u
                 const int32_t j = j0 + (int32_t)threadIdx.x;
                 bool inside = false;
                 if (j < g.n) {
-                    const double s = csr_dot(trp, tci, tva, j, y);
+                    const double s = ONCHIP ? sell_dot(a.tsp, a.tsci, a.tsva, ts0 + (j >> 6), j & 63, y)
+                                            : csr_dot(trp, tci, tva, j, y);
                     const double xr = x[j];
                     const double uu = xr - tau * (c[j] - s);
                     inside = uu > lv[j] && uu < uv[j];
@@ -889,7 +903,8 @@ __global__ __launch_bounds__(BT) void k_batch_unrolled(BArgs a, BOpts o, UArgs u
                 const int32_t i = i0 + (int32_t)threadIdx.x;
                 bool at_u = false, at_l = false;
                 if (i < g.m) {
-                    const double av = csr_dot(arp, aci, ava, i, xe);
+                    const double av = ONCHIP ? sell_dot(a.asp, a.asci, a.asva, as0 + (i >> 6), i & 63, xe)
+                                             : csr_dot(arp, aci, ava, i, xe);
                     const double vv = y[i] / sigma - av;
                     at_u = vv < -uc[i];
                     at_l = vv > -lc[i];
@@ -917,7 +932,9 @@ __global__ __launch_bounds__(BT) void k_batch_unrolled(BArgs a, BOpts o, UArgs u
                     v2[0] += dx * dx;
                     const double d0 = xh[j] - x0[j];
                     v2[2] += d0 * d0;
+                    if (ONCHIP) xe[j] = dx;   // x_ext is spent: it carries dx for the cross term
                 }
+                if (ONCHIP) __syncthreads();
                 for (int32_t i = threadIdx.x; i < g.m; i += BT) {
                     const double dy = yh[i] - y[i];
                     v2[8] += dy * dy;
@@ -925,8 +942,12 @@ __global__ __launch_bounds__(BT) void k_batch_unrolled(BArgs a, BOpts o, UArgs u
                     v2[9] += d0 * d0;
                     // cross term dy' A~ dx
                     double adx = 0.0;
-                    for (int32_t e = arp[i]; e < arp[i + 1]; ++e)
-                        adx = fma(ava[e], xh[aci[e]] - x[aci[e]], adx);
+                    if (ONCHIP) {
+                        adx = sell_dot(a.asp, a.asci, a.asva, as0 + (i >> 6), i & 63, xe);
+                    } else {
+                        for (int32_t e = arp[i]; e < arp[i + 1]; ++e)
+                            adx = fma(ava[e], xh[aci[e]] - x[aci[e]], adx);
+                    }
                     v2[1] += dy * adx;
                 }
                 wg_sum<BT, 10>(v2);
@@ -976,8 +997,9 @@ __global__ __launch_bounds__(BT) void k_batch_unrolled(BArgs a, BOpts o, UArgs u
 }
 
 // Reverse pass of k_batch_unrolled with its recorded schedule and masks.
-template <int BT>
-__global__ __launch_bounds__(BT) void k_batch_backward(BArgs a, BOpts o, UArgs u) {
+template <int BT, bool ONCHIP>
+__global__ __launch_bounds__(BT) void k_batch_backward(BArgs a, BOpts o, UArgs u, int32_t nmax) {
+    extern __shared__ double lds[];
     for (;;) {
         const int32_t b = next_instance<BT>(a.queue);
         if (b >= a.B) return;
@@ -996,6 +1018,13 @@ __global__ __launch_bounds__(BT) void k_batch_backward(BArgs a, BOpts o, UArgs u
         // cotangents: bx, bx0, bxh (x, x0, xh), tmp (xe); by, by0, byh (y, y0, yh), ba
         double *bx = a.x + g.vc, *bx0 = a.x0 + g.vc, *bxh = a.xh + g.vc, *tmp = a.xe + g.vc;
         double *by = a.y + g.vr, *by0 = a.y0 + g.vr, *byh = a.yh + g.vr, *ba = u.ba + g.vr;
+        // gathered vectors: ba (A~' ba) and tmp (A~ tmp)
+        if (ONCHIP) {
+            tmp = lds;
+            ba = lds + nmax;
+        }
+        const int32_t as0 = (ONCHIP && !a.shared) ? a.asfirst[b] : 0;
+        const int32_t ts0 = (ONCHIP && !a.shared) ? a.tsfirst[b] : 0;
         double *gc = u.gc + g.vc, *glc = u.glc + g.vr, *guc = u.guc + g.vr;
         for (int32_t j = threadIdx.x; j < g.n; j += BT) {
             bx[j] = 0.0;
@@ -1059,7 +1088,8 @@ __global__ __launch_bounds__(BT) void k_batch_backward(BArgs a, BOpts o, UArgs u
             // xext = 2 xhat - x, then the primal step xhat = clamp(x - tau (c - A~'y))
             const uint64_t *xmt = xm + (size_t)t * xw;
             for (int32_t j = threadIdx.x; j < g.n; j += BT) {
-                const double bxe = csr_dot(trp, tci, tva, j, ba);
+                const double bxe = ONCHIP ? sell_dot(a.tsp, a.tsci, a.tsva, ts0 + (j >> 6), j & 63, ba)
+                                          : csr_dot(trp, tci, tva, j, ba);
                 const double bh = bxh[j] + 2.0 * bxe;
                 bx[j] -= bxe;
                 const bool inside = (xmt[j >> 6] >> (j & 63)) & 1ull;
@@ -1069,7 +1099,9 @@ __global__ __launch_bounds__(BT) void k_batch_backward(BArgs a, BOpts o, UArgs u
                 tmp[j] = tau * bu;
             }
             __syncthreads();
-            for (int32_t i = threadIdx.x; i < g.m; i += BT) by[i] += csr_dot(arp, aci, ava, i, tmp);
+            for (int32_t i = threadIdx.x; i < g.m; i += BT)
+                by[i] += ONCHIP ? sell_dot(a.asp, a.asci, a.asva, as0 + (i >> 6), i & 63, tmp)
+                                : csr_dot(arp, aci, ava, i, tmp);
             __syncthreads();
         }
         // c~ = D_c c, l~_c = D_r l_c, u~_c = D_r u_c
@@ -1206,16 +1238,7 @@ static int32_t resident(const void *kernel) {
     return std::max(1, per_cu) * prop.multiProcessorCount;
 }
 
-template <int BT>
-static void launch_setup_t(BatchHandle &h, int32_t count) {
-    BArgs a = batch_args(h);
-    const BOpts o = batch_opts(h.opt);
-    int32_t wg = std::min(count, resident<BT>(reinterpret_cast<const void *>(&k_batch_setup<BT>)));
-    if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
-    PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
-    k_batch_setup<BT><<<wg, BT, 0, h.stream>>>(a, o, count);
-    PDHG_HIP(hipGetLastError());
-}
+
 
 template <int BT, int S>
 static void launch_solve_lds_t(BatchHandle &h, const BOpts &o, BArgs a, size_t lds) {
@@ -1316,8 +1339,49 @@ static void launch_solve_t(BatchHandle &h, const BOpts &o) {
     PDHG_HIP(hipGetLastError());
 }
 
+// Dynamic LDS of the on-chip setup / unrolled / reverse kernels, or 0 when the
+// largest instance does not fit (then the memory-resident variant runs).
+static size_t onchip_lds(const BatchHandle &h) {
+    const size_t lds = ((size_t)h.nmax + (size_t)h.mmax) * sizeof(double);
+    return (h.onchip && lds <= 65536) ? std::max<size_t>(lds, 8) : 0;
+}
+
+template <int BT, class K>
+static int32_t resident_lds(BatchHandle &h, K kernel, size_t lds) {
+    int dev = 0, per_cu = 0;
+    PDHG_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    PDHG_HIP(hipGetDeviceProperties(&prop, dev));
+    PDHG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel), BT, lds));
+    int32_t wg = std::min(h.B, std::max(1, per_cu) * prop.multiProcessorCount);
+    if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
+    return wg;
+}
+
+template <int BT>
+static void launch_setup_t(BatchHandle &h, int32_t count) {
+    BArgs a = batch_args(h);
+    const BOpts o = batch_opts(h.opt);
+    const size_t lds = onchip_lds(h);
+    PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
+    if (lds) {
+        const int32_t wg = std::min(count, resident_lds<BT>(h, &k_batch_setup<BT, true>, lds));
+        k_batch_setup<BT, true><<<wg, BT, lds, h.stream>>>(a, o, count, h.nmax);
+    } else {
+        const int32_t wg = std::min(count, resident_lds<BT>(h, &k_batch_setup<BT, false>, 0));
+        k_batch_setup<BT, false><<<wg, BT, 0, h.stream>>>(a, o, count, 0);
+    }
+    PDHG_HIP(hipGetLastError());
+}
+
+// The setup (scaling sweeps and power iteration, one workgroup per instance)
+// is latency-bound: it runs with about two columns per thread whatever the
+// solve's launch shape, between 256 and 1024 threads.
 static void dispatch_setup(BatchHandle &h, int32_t count) {
-    switch (h.threads) {
+    const int32_t need = std::max(h.nmax, h.mmax);
+    int32_t bt = 256;
+    while (bt < 1024 && 2 * bt < need) bt *= 2;
+    switch (bt) {
         case 64: launch_setup_t<64>(h, count); break;
         case 128: launch_setup_t<128>(h, count); break;
         case 512: launch_setup_t<512>(h, count); break;
@@ -1544,10 +1608,15 @@ template <int BT>
 static void launch_unrolled_t(BatchHandle &h, const UArgs &u) {
     BArgs a = batch_args(h);
     const BOpts o = batch_opts(h.opt);
-    int32_t wg = std::min(h.B, resident<BT>(reinterpret_cast<const void *>(&k_batch_unrolled<BT>)));
-    if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
+    const size_t lds = onchip_lds(h);
     PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
-    k_batch_unrolled<BT><<<wg, BT, 0, h.stream>>>(a, o, u);
+    if (lds) {
+        const int32_t wg = resident_lds<BT>(h, &k_batch_unrolled<BT, true>, lds);
+        k_batch_unrolled<BT, true><<<wg, BT, lds, h.stream>>>(a, o, u, h.nmax);
+    } else {
+        const int32_t wg = resident_lds<BT>(h, &k_batch_unrolled<BT, false>, 0);
+        k_batch_unrolled<BT, false><<<wg, BT, 0, h.stream>>>(a, o, u, 0);
+    }
     PDHG_HIP(hipGetLastError());
 }
 
@@ -1555,10 +1624,15 @@ template <int BT>
 static void launch_backward_t(BatchHandle &h, const UArgs &u) {
     BArgs a = batch_args(h);
     const BOpts o = batch_opts(h.opt);
-    int32_t wg = std::min(h.B, resident<BT>(reinterpret_cast<const void *>(&k_batch_backward<BT>)));
-    if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
+    const size_t lds = onchip_lds(h);
     PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
-    k_batch_backward<BT><<<wg, BT, 0, h.stream>>>(a, o, u);
+    if (lds) {
+        const int32_t wg = resident_lds<BT>(h, &k_batch_backward<BT, true>, lds);
+        k_batch_backward<BT, true><<<wg, BT, lds, h.stream>>>(a, o, u, h.nmax);
+    } else {
+        const int32_t wg = resident_lds<BT>(h, &k_batch_backward<BT, false>, 0);
+        k_batch_backward<BT, false><<<wg, BT, 0, h.stream>>>(a, o, u, 0);
+    }
     PDHG_HIP(hipGetLastError());
 }
 
