@@ -14,6 +14,7 @@ from .lp import (  # noqa: F401
     planted_sparse_lp,
     large_zipf_lp,
     dense_planted_lp,
+    dense_knapsack_lp,
     grid_incidence,
     grid_mincost_batch,
     shortest_path_learning,

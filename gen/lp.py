@@ -283,6 +283,20 @@ def dense_planted_lp(m: int = 20_000, n: int = 40_000, rho: float = 0.3,
               meta=dict(kind="dense_planted", seed=seed))
 
 
+def dense_knapsack_lp(d: int = 1_000, items: int = 100_000, seed: int = 2500) -> LP:
+    """LP relaxation of a multi-dimensional knapsack (the dense instance shape
+    of the paper's hardware comparison): weights W ~ U(0,1) [d, items]
+    row-major, item values v ~ U(0,1), capacities b = 1/4 of each row's total
+    weight, 0 <= x <= 1. Stated as min (-v)'x s.t. W x <= b (value
+    maximisation)."""
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.0, 1.0, size=(d, items))
+    v = rng.uniform(0.0, 1.0, size=items)
+    b = 0.25 * w.sum(axis=1)
+    return LP(d, items, None, None, None, -v, np.full(d, -INF), b, np.zeros(items),
+              np.ones(items), dense=w, meta=dict(kind="dense_knapsack", seed=seed))
+
+
 # ----------------------------------------------------------------------------
 # grid min-cost flow (node-arc incidence, out - in)
 

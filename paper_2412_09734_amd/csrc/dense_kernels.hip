@@ -42,53 +42,104 @@ struct DenseVecs {
     double gamma, tau_o, sigma_o;
 };
 
-// One wave per row: a = sum_c A[i][c] v[c] (lanes strided, butterfly), or |A| norms.
-template <int MODE>
+// Row pass: a = sum_c A[i][c] v[c], or |A| norms. WIDE = false: one wave per
+// two rows (lanes strided over the columns, each v[c] loaded once for both
+// rows, butterflies), eight rows per workgroup; WIDE = true: the whole
+// workgroup on one row (for few, long rows: enough loads in flight to stream
+// HBM), wave totals added in wave order.
+template <int MODE, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict__ A, int32_t m,
                                                        int32_t n, const double *__restrict__ v,
                                                        DenseVecs d) {
     if (d.st && d.st->done) return;
-    const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
-    const int32_t lane = threadIdx.x & 63;
-    double acc = 0.0;
-    if (row < m) {
-        const double *__restrict__ Ar = A + (size_t)row * n;
-        if (MODE == ROW_ABSMAX || MODE == ROW_ABSSUM) {
-            for (int32_t c = lane; c < n; c += 64) {
-                const double a = fabs(Ar[c]);
-                acc = MODE == ROW_ABSMAX ? fmax(acc, a) : acc + a;
+    constexpr int L = WIDE ? kBlock : 64;   // lanes per row
+    constexpr int R = WIDE ? 1 : 2;         // rows per wave
+    const int64_t row0 = WIDE ? (int64_t)blockIdx.x
+                              : (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * R;
+    const int32_t lane = WIDE ? (int32_t)threadIdx.x : (int32_t)(threadIdx.x & 63);
+    double acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = 0.0;
+    const double *__restrict__ Ar[R];
+    bool live[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        live[q] = row0 + q < m;
+        Ar[q] = A + (size_t)(live[q] ? row0 + q : 0) * n;
+    }
+    if (MODE == ROW_ABSMAX || MODE == ROW_ABSSUM) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (!live[q]) continue;
+            for (int32_t c = lane; c < n; c += L) {
+                const double a = fabs(Ar[q][c]);
+                acc[q] = MODE == ROW_ABSMAX ? fmax(acc[q], a) : acc[q] + a;
             }
-        } else {
-            int32_t c = lane;
-            for (; c + 192 < n; c += 256) {
-                const double a0 = __builtin_nontemporal_load(Ar + c);
-                const double a1 = __builtin_nontemporal_load(Ar + c + 64);
-                const double a2 = __builtin_nontemporal_load(Ar + c + 128);
-                const double a3 = __builtin_nontemporal_load(Ar + c + 192);
-                acc = fma(a0, v[c], acc);
-                acc = fma(a1, v[c + 64], acc);
-                acc = fma(a2, v[c + 128], acc);
-                acc = fma(a3, v[c + 192], acc);
-            }
-            for (; c < n; c += 64) acc = fma(__builtin_nontemporal_load(Ar + c), v[c], acc);
+        }
+    } else if (live[0]) {
+        // U columns x R rows of independent loads in flight per lane, each
+        // row added in column order
+        constexpr int U = WIDE ? 8 : 4;
+        int32_t c = lane;
+        for (; c + (U - 1) * L < n; c += U * L) {
+            double x[U], a[R][U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) x[k] = v[c + k * L];
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+                    a[q][k] = live[q] ? __builtin_nontemporal_load(Ar[q] + c + k * L) : 0.0;
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+#pragma unroll
+                for (int k = 0; k < U; ++k) acc[q] = fma(a[q][k], x[k], acc[q]);
+        }
+        for (; c < n; c += L) {
+            const double x = v[c];
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                if (live[q]) acc[q] = fma(__builtin_nontemporal_load(Ar[q] + c), x, acc[q]);
         }
     }
-    if (MODE == ROW_ABSMAX) {
-        for (int off = 32; off > 0; off >>= 1) acc = fmax(acc, __shfl_xor(acc, off));
-    } else {
-        acc = wave_sum(acc);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        if (MODE == ROW_ABSMAX) {
+            for (int off = 32; off > 0; off >>= 1) acc[q] = fmax(acc[q], __shfl_xor(acc[q], off));
+        } else {
+            acc[q] = wave_sum(acc[q]);
+        }
     }
-    const bool own = row < m && lane == 0;
+    double accv = acc[0];
+    int64_t row = row0;
+    if (WIDE) {
+        __shared__ double wt[kBlock / 64];
+        if ((threadIdx.x & 63) == 0) wt[threadIdx.x >> 6] = accv;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = wt[0];
+            for (int w = 1; w < kBlock / 64; ++w) t = MODE == ROW_ABSMAX ? fmax(t, wt[w]) : t + wt[w];
+            accv = t;
+        }
+    } else {
+        // lane q of the wave owns row row0 + q
+#pragma unroll
+        for (int q = 1; q < R; ++q)
+            if (lane == q) accv = acc[q];
+        row = row0 + (lane < R ? lane : 0);
+    }
+    const double acc_own = accv;
+    const bool own = row < m && (WIDE ? threadIdx.x == 0 : lane < R);
     if (MODE == ROW_CHECK_M || MODE == ROW_STORE_SQ) {
         double vals[4] = {0.0, 0.0, 0.0, 0.0};
         if (own) {
             const int64_t r = row;
             if (MODE == ROW_STORE_SQ) {
-                d.out[r] = acc;
-                vals[0] = acc * acc;
+                d.out[r] = acc_own;
+                vals[0] = acc_own * acc_own;
             } else {
                 const double dr = d.Dr[r];
-                const double ax = acc / dr;
+                const double ax = acc_own / dr;
                 const double lo = d.lc_o[r], hi = d.uc_o[r];
                 const double rpr = ax - clampd(ax, lo, hi);
                 vals[0] = rpr * rpr;
@@ -112,17 +163,17 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
     if (!own) return;
     const int64_t r = row;
     if (MODE == ROW_ABSMAX || MODE == ROW_ABSSUM) {
-        d.out[r] = acc;
+        d.out[r] = acc_own;
     } else if (MODE == ROW_DUAL) {
         const double sigma = d.st->sigma;
         const int64_t k = d.st->k_base + (d.j - 1);
         const double yr = d.y[r];
-        const double yh = dual_prox(yr, acc, sigma, d.lc[r], d.uc[r]);
+        const double yh = dual_prox(yr, acc_own, sigma, d.lc[r], d.uc[r]);
         const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
         d.yw[r] = ak * ((1.0 + d.gamma) * yh - d.gamma * yr) + bk * d.y0[r];
     } else if (MODE == ROW_DUAL_CHK) {
         const double sigma = d.sigma_o > 0.0 ? d.sigma_o : d.st->sigma;
-        d.yhat_w[r] = dual_prox(d.y[r], acc, sigma, d.lc[r], d.uc[r]);
+        d.yhat_w[r] = dual_prox(d.y[r], acc_own, sigma, d.lc[r], d.uc[r]);
     }
 }
 
@@ -296,7 +347,18 @@ static DenseVecs dvecs(Handle &h, int32_t j) {
     return d;
 }
 
-static unsigned row_blocks(int32_t m) { return dblk((int64_t)m * 64); }
+// Few rows (fewer than 4 per CU) get a workgroup each, otherwise a wave each.
+static bool wide_rows(int32_t m) { return m < 1024; }
+static unsigned row_blocks(int32_t m) { return wide_rows(m) ? (unsigned)std::max(1, m) : dblk((int64_t)(m + 1) / 2 * 64); }
+
+template <int MODE>
+static void launch_rows(hipStream_t s, const double *A, int32_t m, int32_t n, const double *v,
+                        const DenseVecs &d) {
+    if (wide_rows(m))
+        k_dense_rows<MODE, true><<<row_blocks(m), kBlock, 0, s>>>(A, m, n, v, d);
+    else
+        k_dense_rows<MODE, false><<<row_blocks(m), kBlock, 0, s>>>(A, m, n, v, d);
+}
 static unsigned col_blocks(int32_t n) { return dblk(n); }
 
 int32_t dense_row_blocks(const Handle &h) { return (int32_t)row_blocks(h.m); }
@@ -314,7 +376,7 @@ void dense_primal(Handle &h, int32_t j) {
 
 void dense_dual(Handle &h, int32_t j) {
     if (h.m == 0) return;
-    k_dense_rows<ROW_DUAL><<<row_blocks(h.m), kBlock, 0, h.stream>>>(h.Ad.p, h.m, h.n, h.xext.p, dvecs(h, j));
+    launch_rows<ROW_DUAL>(h.stream, h.Ad.p, h.m, h.n, h.xext.p, dvecs(h, j));
 }
 
 void dense_primal_check(Handle &h, double tau_override) {
@@ -328,7 +390,7 @@ void dense_dual_check(Handle &h, double sigma_override) {
     if (h.m == 0) return;
     DenseVecs d = dvecs(h, 0);
     d.sigma_o = sigma_override;
-    k_dense_rows<ROW_DUAL_CHK><<<row_blocks(h.m), kBlock, 0, h.stream>>>(h.Ad.p, h.m, h.n, h.xext.p, d);
+    launch_rows<ROW_DUAL_CHK>(h.stream, h.Ad.p, h.m, h.n, h.xext.p, d);
 }
 
 void dense_check_sums(Handle &h) {
@@ -339,7 +401,7 @@ void dense_check_sums(Handle &h) {
     if (h.m > 0) {
         DenseVecs e = dvecs(h, 0);
         e.partials = h.pm.p;
-        k_dense_rows<ROW_CHECK_M><<<row_blocks(h.m), kBlock, 0, h.stream>>>(h.Ad.p, h.m, h.n, h.xhat.p, e);
+        launch_rows<ROW_CHECK_M>(h.stream, h.Ad.p, h.m, h.n, h.xhat.p, e);
     }
 }
 
@@ -349,7 +411,7 @@ void dense_rows_sq(Handle &h, const double *v, double *out, double *partials) {
     d.st = nullptr;
     d.out = out;
     d.partials = partials;
-    k_dense_rows<ROW_STORE_SQ><<<row_blocks(h.m), kBlock, 0, h.stream>>>(h.Ad.p, h.m, h.n, v, d);
+    launch_rows<ROW_STORE_SQ>(h.stream, h.Ad.p, h.m, h.n, v, d);
 }
 
 // out = A~' w with partial sums of out^2 (columns)
@@ -404,12 +466,12 @@ void dense_scale(Handle &h) {
         d.out = rn.p;
         dim3 grid(col_blocks(n), kDenseSplits);
         if (pc) {
-            k_dense_rows<ROW_ABSSUM><<<row_blocks(m), kBlock, 0, s>>>(h.Ad.p, m, n, nullptr, d);
+            launch_rows<ROW_ABSSUM>(s, h.Ad.p, m, n, nullptr, d);
             k_dense_cols_partial<false, true><<<grid, kBlock, 0, s>>>(h.Ad.p, m, n, nullptr, h.dpart.p, nullptr);
             d.out = cn.p;
             k_dense_cols_final<COL_ABSSUM><<<col_blocks(n), kBlock, 0, s>>>(n, h.dpart.p, d);
         } else {
-            k_dense_rows<ROW_ABSMAX><<<row_blocks(m), kBlock, 0, s>>>(h.Ad.p, m, n, nullptr, d);
+            launch_rows<ROW_ABSMAX>(s, h.Ad.p, m, n, nullptr, d);
             k_dense_cols_partial<true, false><<<grid, kBlock, 0, s>>>(h.Ad.p, m, n, nullptr, h.dpart.p, nullptr);
             d.out = cn.p;
             k_dense_cols_final<COL_ABSMAX><<<col_blocks(n), kBlock, 0, s>>>(n, h.dpart.p, d);
