@@ -294,6 +294,52 @@ static void start_vector(double *v, int32_t n) {
     for (int32_t j = 0; j < n; ++j) v[j] = v[j] / nv;
 }
 
+/* Largest eigenvalue of the k x k symmetric tridiagonal matrix T = B'B of the
+ * Golub-Kahan bidiagonal B (alpha_1..alpha_k on the diagonal, beta_1..beta_{k-1}
+ * above it): T_ii = alpha_i^2 + beta_{i-1}^2, T_i,i+1 = alpha_i beta_i. Bisection
+ * on the Sturm count (number of eigenvalues below x) over [0, Gershgorin
+ * bound] until the interval cannot be halved. */
+static int sturm_below(const double *alpha, const double *beta, int32_t k, double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (int32_t i = 0; i < k; ++i) {
+        const double di = alpha[i] * alpha[i] + (i > 0 ? beta[i - 1] * beta[i - 1] : 0.0);
+        if (i == 0) {
+            q = di - x;
+        } else {
+            const double ei = alpha[i - 1] * beta[i - 1];
+            q = di - x - (ei * ei) / q;
+        }
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+static double tridiag_max(const double *alpha, const double *beta, int32_t k) {
+    double hi = 0.0;
+    for (int32_t i = 0; i < k; ++i) {
+        const double di = alpha[i] * alpha[i] + (i > 0 ? beta[i - 1] * beta[i - 1] : 0.0);
+        const double el = i > 0 ? fabs(alpha[i - 1] * beta[i - 1]) : 0.0;
+        const double er = i + 1 < k ? fabs(alpha[i] * beta[i]) : 0.0;
+        if (di + el + er > hi) hi = di + el + er;
+    }
+    double lo = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (sturm_below(alpha, beta, k, mid) == k) hi = mid;
+        else lo = mid;
+    }
+    return hi;
+}
+
+/* ||A~||_2 by Golub-Kahan-Lanczos bidiagonalisation from the start vector:
+ *   p = A~ v_k - beta_{k-1} u_{k-1},  alpha_k = |p|,  u_k = p / alpha_k
+ *   q = A~' u_k - alpha_k v_k,        beta_k = |q|,   v_{k+1} = q / beta_k
+ * lam_k = largest eigenvalue of B_k'B_k (the square of the largest Ritz value
+ * of A~); stop at the first k >= 2 with |lam_k - lam_{k-1}| <= tol lam_k, or
+ * when the Krylov space closes (alpha or beta zero). Returns sqrt(lam). */
 static double power_norm_a(const orc_ctx *s, int32_t *iters) {
     const int32_t m = s->m, n = s->n;
     const size_t nv = s->dense ? (size_t)m * n : (m > 0 ? (size_t)s->p.rowptr[m] : 0);
@@ -301,23 +347,34 @@ static double power_norm_a(const orc_ctx *s, int32_t *iters) {
         if (iters) *iters = 0;
         return 0.0;
     }
-    double *v = dalloc(n), *w = dalloc(m), *u = dalloc(n);
+    const int32_t maxit = s->o.power_max_iters;
+    double *v = dalloc(n), *u = dalloc(m), *uprev = dalloc(m), *p = dalloc(m), *q = dalloc(n);
+    double *alpha = dalloc(maxit + 1), *beta = dalloc(maxit + 1);
     start_vector(v, n);
-    double lam = 0.0, lam_prev = 0.0;
+    for (int32_t i = 0; i < m; ++i) uprev[i] = 0.0;
+    double lam = 0.0, lam_prev = 0.0, bprev = 0.0;
     int32_t it = 0;
-    for (it = 1; it <= s->o.power_max_iters; ++it) {
-        a_mul(s, v, w);
-        lam = (double)sumsq(w, m);            /* Rayleigh quotient of A~'A~ */
-        at_mul(s, w, u);
-        double nu = sqrtl(sumsq(u, n));
-        if (!(nu > 0.0)) { lam = 0.0; break; }
-        for (int32_t j = 0; j < n; ++j) v[j] = u[j] / nu;
+    for (it = 1; it <= maxit; ++it) {
+        a_mul(s, v, p);
+        for (int32_t i = 0; i < m; ++i) p[i] = p[i] - bprev * uprev[i];
+        const double a = (double)sqrtl(sumsq(p, m));
+        if (!(a > 0.0)) { if (it == 1) lam = 0.0; break; }
+        for (int32_t i = 0; i < m; ++i) { u[i] = p[i] / a; uprev[i] = u[i]; }
+        at_mul(s, u, q);
+        for (int32_t j = 0; j < n; ++j) q[j] = q[j] - a * v[j];
+        const double b = (double)sqrtl(sumsq(q, n));
+        alpha[it - 1] = a;
+        beta[it - 1] = b;
+        lam = tridiag_max(alpha, beta, it);
+        if (!(b > 0.0)) break;
         if (it > 1 && fabs(lam - lam_prev) <= s->o.power_tol * lam) break;
         lam_prev = lam;
+        for (int32_t j = 0; j < n; ++j) v[j] = q[j] / b;
+        bprev = b;
     }
-    if (it > s->o.power_max_iters) it = s->o.power_max_iters;
+    if (it > maxit) it = maxit;
     if (iters) *iters = it;
-    free(v); free(w); free(u);
+    free(v); free(u); free(uprev); free(p); free(q); free(alpha); free(beta);
     return sqrt(lam);
 }
 

@@ -46,6 +46,7 @@ struct BArgs {
     // SELL-64 copies (entry k of local row i at sp[sfirst + i/64] + 64 k + i%64)
     const int32_t *asp, *asci, *asfirst, *tsp, *tsci, *tsfirst;
     const double *asva, *tsva;
+    double *lhist;    // Lanczos alpha / beta per instance, stride 2 (power_max_iters + 1)
 };
 
 // Geometry of instance b: matrix rows start at r0 (A) / c0 (A'); vectors at
@@ -163,6 +164,42 @@ __device__ __forceinline__ uint64_t splitmix64_b(uint64_t x) {
 // setup: Ruiz + Pock-Chambolle scaling and the power iteration, per instance
 // (once for a shared matrix).
 
+// Largest eigenvalue of T = B'B for the Golub-Kahan bidiagonal B (alpha on the
+// diagonal, beta above it): Sturm-count bisection over [0, Gershgorin bound]
+// until the interval cannot be halved (one thread).
+__device__ double bidiag_lambda_max_dev(const double *alpha, const double *beta, int32_t k) {
+    double hi = 0.0;
+    for (int32_t i = 0; i < k; ++i) {
+        const double di = alpha[i] * alpha[i] + (i > 0 ? beta[i - 1] * beta[i - 1] : 0.0);
+        const double el = i > 0 ? fabs(alpha[i - 1] * beta[i - 1]) : 0.0;
+        const double er = i + 1 < k ? fabs(alpha[i] * beta[i]) : 0.0;
+        hi = fmax(hi, di + el + er);
+    }
+    double lo = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        int32_t cnt = 0;
+        double q = 1.0;
+        for (int32_t i = 0; i < k; ++i) {
+            const double di = alpha[i] * alpha[i] + (i > 0 ? beta[i - 1] * beta[i - 1] : 0.0);
+            if (i == 0) {
+                q = di - mid;
+            } else {
+                const double ei = alpha[i - 1] * beta[i - 1];
+                q = di - mid - (ei * ei) / q;
+            }
+            if (q == 0.0) q = -1e-300;
+            if (q < 0.0) ++cnt;
+        }
+        if (cnt == k)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return hi;
+}
+
 // ONCHIP: the power iteration's gathered vectors v (n) and w (m) live in LDS.
 template <int BT, bool ONCHIP>
 __global__ __launch_bounds__(BT) void k_batch_setup(BArgs a, BOpts o, int32_t count, int32_t nmax) {
@@ -205,50 +242,73 @@ __global__ __launch_bounds__(BT) void k_batch_setup(BArgs a, BOpts o, int32_t co
             }
         }
         __syncthreads();
-        // power iteration on A~'A~ from the SplitMix64 start vector
+        // ||A~||_2 by Golub-Kahan-Lanczos bidiagonalisation from the SplitMix64
+        // start vector (see estimate_steps for the recurrences)
         int64_t nnz = (int64_t)arp[g.m] - arp[0];
         double lam = 0.0;
         int32_t it = 0;
         if (g.m > 0 && nnz > 0) {
-            double *v = ONCHIP ? lds : a.xh + g.vc;
-            double *w = ONCHIP ? lds + nmax : a.yh + g.vr;
-            double *u = a.xe + g.vc;
-            double q[1] = {0.0};
+            double *v = ONCHIP ? lds : a.xh + g.vc;          // gathered by rows
+            double *u = ONCHIP ? lds + nmax : a.yh + g.vr;   // gathered by columns
+            double *pr = a.y + g.vr, *qc = a.xe + g.vc;      // owner-only scratch
+            double *al = a.lhist + (size_t)g.sidx * 2 * (o.power_max_iters + 1);
+            double *be = al + (o.power_max_iters + 1);
+            __shared__ double lam_sh;
+            __shared__ int32_t stop_sh;
+            double q0[1] = {0.0};
             for (int32_t j = threadIdx.x; j < g.n; j += BT) {
                 const double val = 0.5 + (double)(splitmix64_b((uint64_t)j) >> 11) * 0x1.0p-53;
                 v[j] = val;
-                q[0] += val * val;
+                q0[0] += val * val;
             }
-            wg_sum<BT, 1>(q);
-            const double nv = sqrt(q[0]);
+            for (int32_t i = threadIdx.x; i < g.m; i += BT) u[i] = 0.0;
+            wg_sum<BT, 1>(q0);
+            const double nv = sqrt(q0[0]);
             for (int32_t j = threadIdx.x; j < g.n; j += BT) v[j] = v[j] / nv;
             __syncthreads();
-            double lam_prev = 0.0;
+            double lam_prev = 0.0, bprev = 0.0;
             for (it = 1; it <= o.power_max_iters; ++it) {
-                double sw[1] = {0.0};
+                double sp[1] = {0.0};
                 for (int32_t i = threadIdx.x; i < g.m; i += BT) {
-                    const double s = csr_dot(arp, a.aci, a.ava, i, v);
-                    w[i] = s;
-                    sw[0] += s * s;
+                    const double pv = csr_dot(arp, a.aci, a.ava, i, v) - bprev * u[i];
+                    pr[i] = pv;
+                    sp[0] += pv * pv;
                 }
-                wg_sum<BT, 1>(sw);
-                lam = sw[0];
-                double su[1] = {0.0};
-                for (int32_t j = threadIdx.x; j < g.n; j += BT) {
-                    const double s = csr_dot(trp, a.tci, a.tva, j, w);
-                    u[j] = s;
-                    su[0] += s * s;
-                }
-                wg_sum<BT, 1>(su);
-                const double nu = sqrt(su[0]);
-                if (!(nu > 0.0)) {
-                    lam = 0.0;
+                wg_sum<BT, 1>(sp);
+                const double al_k = sqrt(sp[0]);
+                if (!(al_k > 0.0)) {
+                    if (it == 1) lam = 0.0;
                     break;
                 }
-                for (int32_t j = threadIdx.x; j < g.n; j += BT) v[j] = u[j] / nu;
+                for (int32_t i = threadIdx.x; i < g.m; i += BT) u[i] = pr[i] / al_k;
                 __syncthreads();
-                if (it > 1 && fabs(lam - lam_prev) <= o.power_tol * lam) break;
+                double sq[1] = {0.0};
+                for (int32_t j = threadIdx.x; j < g.n; j += BT) {
+                    const double qv = csr_dot(trp, a.tci, a.tva, j, u) - al_k * v[j];
+                    qc[j] = qv;
+                    sq[0] += qv * qv;
+                }
+                wg_sum<BT, 1>(sq);
+                const double be_k = sqrt(sq[0]);
+                if (threadIdx.x == 0) {
+                    al[it - 1] = al_k;
+                    be[it - 1] = be_k;
+                    const double l = bidiag_lambda_max_dev(al, be, it);
+                    int32_t st = 0;
+                    if (!(be_k > 0.0)) st = 1;
+                    else if (it > 1 && fabs(l - lam_prev) <= o.power_tol * l) st = 1;
+                    lam_sh = l;
+                    stop_sh = st;
+                }
+                __syncthreads();
+                lam = lam_sh;
+                const bool stop = stop_sh != 0;
+                __syncthreads();
+                if (stop) break;
                 lam_prev = lam;
+                for (int32_t j = threadIdx.x; j < g.n; j += BT) v[j] = qc[j] / be_k;
+                bprev = be_k;
+                __syncthreads();
             }
             if (it > o.power_max_iters) it = o.power_max_iters;
         }
@@ -1223,6 +1283,7 @@ static BArgs batch_args(BatchHandle &h) {
     a.tsci = h.tsci.p;
     a.tsva = h.tsva.p;
     a.tsfirst = h.tsfirst.p;
+    a.lhist = h.lhist.p;
     a.x_out = h.x_out_;
     a.y_out = h.y_out_;
     return a;
@@ -1497,8 +1558,10 @@ BatchHandle *batch_create(const pdhg_batch_problem &p, const pdhg_options &o, vo
     h.power_iters.alloc((size_t)nscal);
     h.res.alloc((size_t)h.B);
     h.queue.alloc(1);
+    h.lhist.alloc((size_t)nscal * 2 * ((size_t)std::max(1, o.power_max_iters) + 1));
     dispatch_setup(h, nscal);
     PDHG_HIP(hipStreamSynchronize(s));
+    h.lhist.release();
     {
         const int32_t nb = h.shared ? 1 : h.B;
         std::vector<int32_t> ro = h.shared ? std::vector<int32_t>{0, h.m} : h.row_off_h;

@@ -35,6 +35,7 @@ struct BatchHandle {
     // never cross instances; slice s of instance b is sfirst[b] + local row / 64
     DBuf<int32_t> asp, asci, asfirst, tsp, tsci, tsfirst;
     DBuf<double> asva, tsva;
+    DBuf<double> lhist;                   // Lanczos coefficients during setup
     // QP batches: Q_b = F F' + diag(d_b), F shared (scaled copy), d per instance
     int32_t q_rank = 0;
     DBuf<double> qF, qd_o, qdd, normq, xbar, ybar, qv_, qres;

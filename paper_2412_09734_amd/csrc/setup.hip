@@ -374,6 +374,33 @@ __global__ __launch_bounds__(kBlock) void k_power_normalize(const double *__rest
     if (i < n && nu > 0.0) v[i] = u[i] / nu;
 }
 
+// Golub-Kahan-Lanczos step pieces. w <- w - coef[0] prev (coef a device
+// scalar), with per-workgroup partial sums of w^2.
+__global__ __launch_bounds__(kBlock) void k_lanczos_sub(double *__restrict__ w,
+                                                        const double *__restrict__ prev,
+                                                        const double *__restrict__ coef, int32_t len,
+                                                        double *__restrict__ partials) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double q[1] = {0.0};
+    if (i < len) {
+        const double r = w[i] - coef[0] * prev[i];
+        w[i] = r;
+        q[0] = r * r;
+    }
+    block_sum_store<1>(q, partials + blockIdx.x);
+}
+
+// out = w / |w| with |w|^2 = tot[0]; records |w| in *slot.
+__global__ __launch_bounds__(kBlock) void k_lanczos_scale(const double *__restrict__ w,
+                                                          double *__restrict__ out, int32_t len,
+                                                          const double *__restrict__ tot,
+                                                          double *__restrict__ slot) {
+    const double nw = sqrt(tot[0]);
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) slot[0] = nw;
+    if (i < len && nw > 0.0) out[i] = w[i] / nw;
+}
+
 // ---------------------------------------------------------------------------
 // host side
 
@@ -762,13 +789,57 @@ void transform_vectors(Handle &h) {
         h.uv.p, h.lc.p, h.uc.p);
 }
 
+// Largest eigenvalue of T = B'B for the Golub-Kahan bidiagonal B with
+// diagonal alpha[0..k-1] and superdiagonal beta[0..k-2]: T_ii = alpha_i^2 +
+// beta_{i-1}^2, T_i,i+1 = alpha_i beta_i. Bisection on the Sturm count over
+// [0, Gershgorin bound] until the interval cannot be halved.
+static int32_t sturm_count_below(const double *alpha, const double *beta, int32_t k, double x) {
+    int32_t cnt = 0;
+    double q = 1.0;
+    for (int32_t i = 0; i < k; ++i) {
+        const double di = alpha[i] * alpha[i] + (i > 0 ? beta[i - 1] * beta[i - 1] : 0.0);
+        if (i == 0) {
+            q = di - x;
+        } else {
+            const double ei = alpha[i - 1] * beta[i - 1];
+            q = di - x - (ei * ei) / q;
+        }
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+double bidiag_lambda_max(const double *alpha, const double *beta, int32_t k) {
+    double hi = 0.0;
+    for (int32_t i = 0; i < k; ++i) {
+        const double di = alpha[i] * alpha[i] + (i > 0 ? beta[i - 1] * beta[i - 1] : 0.0);
+        const double el = i > 0 ? fabs(alpha[i - 1] * beta[i - 1]) : 0.0;
+        const double er = i + 1 < k ? fabs(alpha[i] * beta[i]) : 0.0;
+        hi = std::max(hi, di + el + er);
+    }
+    double lo = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        if (sturm_count_below(alpha, beta, k, mid) == k)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return hi;
+}
+
 void estimate_steps(Handle &h) {
     hipStream_t s = h.stream;
     const int32_t m = h.m, n = h.n;
     h.norm_a = 0.0;
     h.power_iters = 0;
     if (h.A.nnz > 0 && m > 0) {
-        // power iteration on A~'A~: lam_k = |A~ v_k|^2 with |v_k| = 1
+        // ||A~||_2 by Golub-Kahan-Lanczos bidiagonalisation from the start
+        // vector: p = A~ v_k - beta_{k-1} u_{k-1}, alpha_k = |p|, u_k = p / alpha_k;
+        // q = A~' u_k - alpha_k v_k, beta_k = |q|, v_{k+1} = q / beta_k. lam_k is
+        // the largest eigenvalue of B_k'B_k; the host checks it every 16 steps.
         const int maxit = std::max(1, h.opt.power_max_iters);
         const int32_t nbA = h.nbm, nbT = h.nbn;
         const MatView VA = view(h.A), VT = view(h.AT);
@@ -780,19 +851,25 @@ void estimate_steps(Handle &h) {
             if (h.dense) dense_cols_sq(h, win, uout, part);
             else k_spmv_sq<<<nbT, kBlock, 0, s>>>(VT, win, uout, part);
         };
-        DBuf<double> v, w, u, pw, pu, tot, hist;
+        const int32_t bm = (int32_t)blocks_for(m), bn = (int32_t)blocks_for(n);
+        DBuf<double> v, w, u, z, pw, pu, ps, tot, hist;
         v.alloc(n);
+        z.alloc(n);
         w.alloc(m);
-        u.alloc(n);
+        u.alloc(m);
         pw.alloc(std::max<int64_t>(nbA, 1));
-        pu.alloc(std::max<int64_t>({(int64_t)nbT, (int64_t)blocks_for(n), 1}));
+        pu.alloc(std::max<int64_t>({(int64_t)nbT, (int64_t)bn, 1}));
+        ps.alloc(std::max<int64_t>({(int64_t)bm, (int64_t)bn, 1}));
         tot.alloc(2);
         hist.alloc(2 * ((size_t)maxit + 2));
-        k_power_start<<<blocks_for(n), kBlock, 0, s>>>(h.perm_c.p, n, v.p, pu.p);
-        k_total<1><<<1, kBlock, 0, s>>>(pu.p, (int32_t)blocks_for(n), tot.p);
-        k_div_sqrt<<<blocks_for(n), kBlock, 0, s>>>(v.p, n, tot.p);
+        PDHG_HIP(hipMemsetAsync(hist.p, 0, 2 * sizeof(double), s));
+        PDHG_HIP(hipMemsetAsync(u.p, 0, (size_t)m * sizeof(double), s));
+        k_power_start<<<bn, kBlock, 0, s>>>(h.perm_c.p, n, v.p, pu.p);
+        k_total<1><<<1, kBlock, 0, s>>>(pu.p, bn, tot.p);
+        k_div_sqrt<<<bn, kBlock, 0, s>>>(v.p, n, tot.p);
         const int batch = 16;
-        std::vector<double> hh(2 * ((size_t)maxit + 2));
+        std::vector<double> hh(2 * ((size_t)maxit + 2), 0.0);
+        std::vector<double> al, be;
         double lam = 0.0, lam_prev = 0.0;
         int it_done = 0;
         bool stop = false;
@@ -800,22 +877,30 @@ void estimate_steps(Handle &h) {
             const int it1 = std::min(maxit, it0 + batch - 1);
             for (int it = it0; it <= it1; ++it) {
                 mul_a(v.p, w.p, pw.p);
-                k_total<1><<<1, kBlock, 0, s>>>(pw.p, nbA, tot.p);
-                mul_at(w.p, u.p, pu.p);
-                k_total<1><<<1, kBlock, 0, s>>>(pu.p, nbT, tot.p + 1);
-                k_power_normalize<<<blocks_for(n), kBlock, 0, s>>>(u.p, v.p, n, tot.p,
-                                                                   tot.p + 1, hist.p, it);
+                k_lanczos_sub<<<bm, kBlock, 0, s>>>(w.p, u.p, hist.p + 2 * (it - 1) + 1, m, ps.p);
+                k_total<1><<<1, kBlock, 0, s>>>(ps.p, bm, tot.p);
+                k_lanczos_scale<<<bm, kBlock, 0, s>>>(w.p, u.p, m, tot.p, hist.p + 2 * it);
+                mul_at(u.p, z.p, pu.p);
+                k_lanczos_sub<<<bn, kBlock, 0, s>>>(z.p, v.p, hist.p + 2 * it, n, ps.p);
+                k_total<1><<<1, kBlock, 0, s>>>(ps.p, bn, tot.p + 1);
+                k_lanczos_scale<<<bn, kBlock, 0, s>>>(z.p, v.p, n, tot.p + 1, hist.p + 2 * it + 1);
             }
             PDHG_HIP(hipMemcpyAsync(hh.data() + 2 * it0, hist.p + 2 * it0,
                                     sizeof(double) * 2 * (it1 - it0 + 1), hipMemcpyDeviceToHost,
                                     s));
             PDHG_HIP(hipStreamSynchronize(s));
             for (int it = it0; it <= it1; ++it) {
-                lam = hh[2 * it];
-                const double nu = hh[2 * it + 1];
+                const double a = hh[2 * it], b = hh[2 * it + 1];
                 it_done = it;
-                if (!(nu > 0.0)) {
-                    lam = 0.0;
+                if (!(a > 0.0)) {
+                    if (it == 1) lam = 0.0;
+                    stop = true;
+                    break;
+                }
+                al.push_back(a);
+                be.push_back(b);
+                lam = bidiag_lambda_max(al.data(), be.data(), it);
+                if (!(b > 0.0)) {
                     stop = true;
                     break;
                 }
