@@ -1183,14 +1183,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_localize(const int32_t *__rest
                                                            int32_t B, const int32_t *__restrict__ rowptr,
                                                            int32_t *__restrict__ colidx,
                                                            int32_t *__restrict__ flag) {
-    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // one workgroup per instance, its rows strided over the threads
+    const int32_t b = blockIdx.x;
     if (b >= B) return;
     const int32_t c0 = col_off[b], c1 = col_off[b + 1];
     if (row_off[b + 1] < row_off[b] || c1 <= c0) {
-        atomicOr(flag, 32);
+        if (threadIdx.x == 0) atomicOr(flag, 32);
         return;
     }
-    for (int32_t i = row_off[b]; i < row_off[b + 1]; ++i)
+    for (int32_t i = row_off[b] + (int32_t)threadIdx.x; i < row_off[b + 1]; i += kBlock)
         for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
             const int32_t j = colidx[e];
             if (j < c0 || j >= c1) atomicOr(flag, 64);
@@ -1203,10 +1204,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_localize_t(const int32_t *__re
                                                              const int32_t *__restrict__ col_off,
                                                              int32_t B, const int32_t *__restrict__ trp,
                                                              int32_t *__restrict__ tci) {
-    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int32_t b = blockIdx.x;
     if (b >= B) return;
     const int32_t r0 = row_off[b];
-    for (int32_t j = col_off[b]; j < col_off[b + 1]; ++j)
+    for (int32_t j = col_off[b] + (int32_t)threadIdx.x; j < col_off[b + 1]; j += kBlock)
         for (int32_t e = trp[j]; e < trp[j + 1]; ++e) tci[e] -= r0;
 }
 
@@ -1320,48 +1321,82 @@ template <class T>
 static void load(DBuf<T> &dst, const T *src, size_t count, int mem, hipStream_t s);
 
 // SELL-64 copy of a batch matrix (rows of every instance padded to whole
-// slices): built on the host from the scaled CSR after the setup kernel.
+// slices) from the scaled CSR after the setup kernel: slice widths on the
+// device, their prefix sum on the host (a few thousand slices), entries placed
+// by one thread per slice row.
+__global__ __launch_bounds__(kBlock) void k_sell_widths(const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ r0,
+                                                        const int32_t *__restrict__ r1, int32_t ns,
+                                                        int32_t *__restrict__ width) {
+    const int32_t sl = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (sl >= ns) return;
+    int32_t w = 0;
+    for (int32_t r = r0[sl]; r < r1[sl]; ++r) w = max(w, rp[r + 1] - rp[r]);
+    width[sl] = w;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sell_fill(const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci,
+                                                      const double *__restrict__ va,
+                                                      const int32_t *__restrict__ r0,
+                                                      const int32_t *__restrict__ r1,
+                                                      const int32_t *__restrict__ sp, int32_t ns,
+                                                      int32_t *__restrict__ sci,
+                                                      double *__restrict__ sva) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int32_t sl = (int32_t)(t >> 6), lane = (int32_t)(t & 63);
+    if (sl >= ns) return;
+    const int32_t row = r0[sl] + lane;
+    if (row >= r1[sl]) return;
+    const int32_t e0 = rp[row], e1 = rp[row + 1];
+    for (int32_t e = e0; e < e1; ++e) {
+        const int64_t o = (int64_t)sp[sl] + 64 * (int64_t)(e - e0) + lane;
+        sci[o] = ci[e];
+        sva[o] = va[e];
+    }
+}
+
 static void build_batch_sell(hipStream_t s, int32_t nb, const std::vector<int32_t> &roff,
                              const DBuf<int32_t> &rp, const DBuf<int32_t> &ci, const DBuf<double> &va,
                              int64_t nnz, DBuf<int32_t> &sp, DBuf<int32_t> &sci, DBuf<double> &sva,
                              DBuf<int32_t> &sfirst) {
-    const int32_t rows = roff[nb];
-    std::vector<int32_t> hrp((size_t)rows + 1), hci((size_t)std::max<int64_t>(nnz, 1));
-    std::vector<double> hva((size_t)std::max<int64_t>(nnz, 1));
-    PDHG_HIP(hipMemcpyAsync(hrp.data(), rp.p, hrp.size() * 4, hipMemcpyDeviceToHost, s));
-    if (nnz > 0) {
-        PDHG_HIP(hipMemcpyAsync(hci.data(), ci.p, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
-        PDHG_HIP(hipMemcpyAsync(hva.data(), va.p, (size_t)nnz * 8, hipMemcpyDeviceToHost, s));
-    }
-    PDHG_HIP(hipStreamSynchronize(s));
-    std::vector<int32_t> first((size_t)nb + 1), off(1, 0);
-    int64_t total = 0;
+    (void)nnz;
+    std::vector<int32_t> first((size_t)nb + 1), h0, h1;
     for (int32_t b = 0; b < nb; ++b) {
-        first[b] = (int32_t)off.size() - 1;
-        for (int32_t r0 = roff[b]; r0 < roff[b + 1]; r0 += 64) {
-            int32_t w = 0;
-            for (int32_t r = r0; r < std::min(r0 + 64, roff[b + 1]); ++r) w = std::max(w, hrp[r + 1] - hrp[r]);
-            total += 64 * (int64_t)w;
-            if (total >= INT32_MAX) fail(PDHG_ERR_UNSUPPORTED, "batch matrix too large for 32-bit offsets");
-            off.push_back((int32_t)total);
+        first[b] = (int32_t)h0.size();
+        for (int32_t r = roff[b]; r < roff[b + 1]; r += 64) {
+            h0.push_back(r);
+            h1.push_back(std::min(r + 64, roff[b + 1]));
         }
     }
-    first[nb] = (int32_t)off.size() - 1;
-    std::vector<int32_t> oci((size_t)std::max<int64_t>(total, 1), 0);
-    std::vector<double> ova((size_t)std::max<int64_t>(total, 1), 0.0);
-    for (int32_t b = 0; b < nb; ++b)
-        for (int32_t r = roff[b]; r < roff[b + 1]; ++r) {
-            const int32_t loc = r - roff[b], sl = first[b] + loc / 64, l = loc % 64;
-            for (int32_t e = hrp[r]; e < hrp[r + 1]; ++e) {
-                const int64_t o = off[sl] + 64 * (int64_t)(e - hrp[r]) + l;
-                oci[o] = hci[e];
-                ova[o] = hva[e];
-            }
-        }
+    const int32_t ns = (int32_t)h0.size();
+    first[nb] = ns;
+    DBuf<int32_t> d0, d1, width;
+    load(d0, h0.data(), h0.size(), PDHG_MEM_HOST, s);
+    load(d1, h1.data(), h1.size(), PDHG_MEM_HOST, s);
+    width.alloc((size_t)std::max(1, ns));
+    std::vector<int32_t> hw((size_t)ns), off((size_t)ns + 1, 0);
+    if (ns > 0) {
+        k_sell_widths<<<(unsigned)ceil_div(ns, kBlock), kBlock, 0, s>>>(rp.p, d0.p, d1.p, ns, width.p);
+        PDHG_HIP(hipMemcpyAsync(hw.data(), width.p, (size_t)ns * 4, hipMemcpyDeviceToHost, s));
+        PDHG_HIP(hipStreamSynchronize(s));
+    }
+    int64_t total = 0;
+    for (int32_t i = 0; i < ns; ++i) {
+        total += 64 * (int64_t)hw[i];
+        if (total >= INT32_MAX) fail(PDHG_ERR_UNSUPPORTED, "batch matrix too large for 32-bit offsets");
+        off[(size_t)i + 1] = (int32_t)total;
+    }
     load(sp, off.data(), off.size(), PDHG_MEM_HOST, s);
-    load(sci, oci.data(), oci.size(), PDHG_MEM_HOST, s);
-    load(sva, ova.data(), ova.size(), PDHG_MEM_HOST, s);
     load(sfirst, first.data(), first.size(), PDHG_MEM_HOST, s);
+    sci.alloc((size_t)std::max<int64_t>(total, 1));
+    sva.alloc((size_t)std::max<int64_t>(total, 1));
+    PDHG_HIP(hipMemsetAsync(sci.p, 0, (size_t)std::max<int64_t>(total, 1) * 4, s));
+    PDHG_HIP(hipMemsetAsync(sva.p, 0, (size_t)std::max<int64_t>(total, 1) * 8, s));
+    if (ns > 0)
+        k_sell_fill<<<(unsigned)ceil_div((int64_t)ns * 64, kBlock), kBlock, 0, s>>>(
+            rp.p, ci.p, va.p, d0.p, d1.p, sp.p, ns, sci.p, sva.p);
+    PDHG_HIP(hipGetLastError());
     PDHG_HIP(hipStreamSynchronize(s));
 }
 
@@ -1537,7 +1572,7 @@ BatchHandle *batch_create(const pdhg_batch_problem &p, const pdhg_options &o, vo
         DBuf<int32_t> flag;
         flag.alloc(1);
         PDHG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
-        const unsigned nb = (unsigned)std::max<int64_t>(1, ceil_div(h.B, kBlock));
+        const unsigned nb = (unsigned)h.B;
         k_batch_localize<<<nb, kBlock, 0, s>>>(h.row_off.p, h.col_off.p, h.B, h.arp.p, h.aci.p,
                                                 flag.p);
         check_flag(s, flag.p, "a ragged instance has entries outside its column range");
