@@ -129,24 +129,46 @@ __device__ __forceinline__ double csr_dot(const int32_t *__restrict__ rp, const 
 
 // Row sum of a SELL-64 slice row: lane `lane` of slice `sl`; entries walked in
 // row order (padding entries are (column 0, value 0.0)).
+__device__ __forceinline__ double sell_dot_bw(const int32_t *__restrict__ ci, const double *__restrict__ va,
+                                              int32_t base, int32_t w, int32_t lane,
+                                              const double *__restrict__ v);
+
 __device__ __forceinline__ double sell_dot(const int32_t *__restrict__ sp, const int32_t *__restrict__ ci,
                                            const double *__restrict__ va, int32_t sl, int32_t lane,
                                            const double *__restrict__ v) {
     const int32_t b = sp[sl], w = (sp[sl + 1] - b) >> 6;
-    double acc = 0.0;
-    for (int32_t k = 0; k < w; ++k) {
-        const int32_t e = b + 64 * k + lane;
-        acc = fma(va[e], v[ci[e]], acc);
-    }
-    return acc;
+    return sell_dot_bw(ci, va, b, w, lane, v);
 }
 
-// Same with the slice's first entry and width already known.
+// Same with the slice's first entry and width already known. Entries are
+// fetched four at a time before they are used (independent loads in flight),
+// and added in row order.
 __device__ __forceinline__ double sell_dot_bw(const int32_t *__restrict__ ci, const double *__restrict__ va,
                                               int32_t base, int32_t w, int32_t lane,
                                               const double *__restrict__ v) {
     double acc = 0.0;
-    for (int32_t k = 0; k < w; ++k) {
+    int32_t k = 0;
+    for (; k + 4 <= w; k += 4) {
+        int32_t c[4];
+        double a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t e = base + 64 * (k + q) + lane;
+            c[q] = ci[e];
+            a[q] = va[e];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc = fma(a[q], v[c[q]], acc);
+    }
+    if (k + 2 <= w) {
+        const int32_t e0 = base + 64 * k + lane, e1 = e0 + 64;
+        const int32_t c0 = ci[e0], c1 = ci[e1];
+        const double a0 = va[e0], a1 = va[e1];
+        acc = fma(a0, v[c0], acc);
+        acc = fma(a1, v[c1], acc);
+        k += 2;
+    }
+    if (k < w) {
         const int32_t e = base + 64 * k + lane;
         acc = fma(va[e], v[ci[e]], acc);
     }
