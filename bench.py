@@ -112,7 +112,7 @@ def main():
                          "gradient")
     ap.add_argument("--batch", type=int, default=0, help="batch size override (batched modes)")
     ap.add_argument("--threads", type=int, default=0,
-                    help="threads per instance of the learning step (default 1024)")
+                    help="threads per instance of the batch solves (default: the library's choice)")
     ap.add_argument("--loop-sample", type=int, default=16,
                     help="instances solved one at a time for the looped comparison")
     args = ap.parse_args()
@@ -430,7 +430,7 @@ def bench_learn(args):
         _, _, res = bs.solve()                       # optimal values under the true costs
     vstar = torch.tensor([r["primal_obj"] for r in res], dtype=torch.float64, device=dev)
     lr = 0.05
-    with BatchSolver.from_shared(sb, threads=args.threads or 1024) as bs:
+    with BatchSolver.from_shared(sb, threads=args.threads or None) as bs:
         def step(Wv):
             chat = heads.linear_costs(fd, Wv)
             bs.update_data(c=chat)

@@ -241,7 +241,10 @@ pdhg_err pdhg_batch_solve(pdhg_batch *b, const double *x_init, const double *y_i
 
 /* Launch shape of the persistent kernels: threads per instance (64, 128,
  * 256, 512 or 1024) and the number of resident workgroups (<= 0: as many as
- * the GPU holds). */
+ * the GPU holds). The default after create is 1024 threads when the batch
+ * has at most one instance per compute unit, else the fewest threads, from
+ * 256, that give each thread at most 8 columns and 8 rows of the largest
+ * instance. */
 pdhg_err pdhg_batch_set_launch(pdhg_batch *b, int32_t threads, int32_t workgroups);
 
 /* Time `iterations` iterations of every instance for each supported thread

@@ -1436,6 +1436,20 @@ static void instance_extents(BatchHandle &h) {
     }
 }
 
+// Default threads per instance: 1024 when the batch has at most one instance
+// per compute unit, else the fewest (from 256) that keep the largest instance
+// on chip with at most 8 columns and 8 rows per thread.
+static int32_t default_threads(const BatchHandle &h) {
+    int dev = 0, cus = 0;
+    PDHG_HIP(hipGetDevice(&dev));
+    PDHG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (h.B <= cus) return 1024;
+    const int32_t need = std::max(h.nmax, h.mmax);
+    int32_t bt = 256;
+    while (bt < 1024 && 8 * bt < need) bt *= 2;
+    return bt;
+}
+
 template <int BT>
 static void launch_solve_t(BatchHandle &h, const BOpts &o) {
     BArgs a = batch_args(h);
@@ -1585,6 +1599,7 @@ BatchHandle *batch_create(const pdhg_batch_problem &p, const pdhg_options &o, vo
         h.col_off.alloc(1);
     }
     instance_extents(h);
+    h.threads = default_threads(h);
     // A' from the global matrix, then instance-local indices on both
     h.trp.alloc((size_t)h.n + 1);
     h.tci.alloc((size_t)h.nnz);

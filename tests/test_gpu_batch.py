@@ -30,28 +30,39 @@ def _close(a, b, tol=1e-6):
 
 
 def test_shared_grid_batch_matches_oracle_and_plain(pdhg, oracle_lib):
+    """n = 528 columns: the default launch (1024 threads, one column per
+    thread), 256 and 128 threads (4 and 8 columns per thread on chip) and 64
+    threads (memory-resident kernel) all reach the oracle's optimum."""
     _say("case: shared-A batch, 12x12 grid min-cost flow, B=24")
     sb = gen.grid_mincost_batch(batch=24, rows=12, cols=12, seed=3100)
-    with pdhg.BatchSolver.from_shared(sb) as bs:
-        x, y, res = bs.solve()
+    ref = []
     for b in range(sb.batch):
         lp = sb.instance(b)
         _, _, ro = oracle_lib.Oracle(lp).solve()
         with pdhg.Solver.from_lp(lp) as s:
             _, _, rp = s.solve()
-        rb = res[b]
-        assert rb["status_name"] == "optimal" and rb["kkt_rel"] <= 1e-4, (b, rb)
-        assert _close(rb["primal_obj"], ro["primal_obj"]), (b, rb["primal_obj"], ro["primal_obj"])
-        assert _close(rb["primal_obj"], rp["primal_obj"]), (b, rb["primal_obj"], rp["primal_obj"])
-        kb = oracle_lib.kkt(lp, to_np(x[b]), to_np(y[b]))
-        assert kb["kkt"] <= 1e-4 * (1 + 1e-6)
-    _say(f"  iterations: {[r['iterations'] for r in res[:8]]}")
+        ref.append((lp, ro, rp))
+    for threads in (None, 256, 128, 64):
+        _say(f"  threads per instance: {threads or 'default'}")
+        with pdhg.BatchSolver.from_shared(sb, threads=threads) as bs:
+            x, y, res = bs.solve()
+        for b, (lp, ro, rp) in enumerate(ref):
+            rb = res[b]
+            assert rb["status_name"] == "optimal" and rb["kkt_rel"] <= 1e-4, (threads, b, rb)
+            assert _close(rb["primal_obj"], ro["primal_obj"]), (threads, b, rb["primal_obj"], ro["primal_obj"])
+            assert _close(rb["primal_obj"], rp["primal_obj"]), (threads, b, rb["primal_obj"], rp["primal_obj"])
+            kb = oracle_lib.kkt(lp, to_np(x[b]), to_np(y[b]))
+            assert kb["kkt"] <= 1e-4 * (1 + 1e-6)
+        _say(f"  iterations: {[r['iterations'] for r in res[:8]]}")
 
 
-def test_ragged_batch_matches_oracle(pdhg, oracle_lib):
-    _say("case: ragged batch of planted LPs, B=12, m in 50..150")
+@pytest.mark.parametrize("threads", [None, 256])
+def test_ragged_batch_matches_oracle(pdhg, oracle_lib, threads):
+    """n <= 294 columns per instance: one column per thread at the default
+    launch, two at 256 threads."""
+    _say(f"case: ragged batch of planted LPs, B=12, m in 50..150, threads {threads or 'default'}")
     lps = gen.ragged_planted_batch(batch=12, m_lo=50, m_hi=150, seed=3600)
-    with pdhg.BatchSolver.from_lps(lps) as bs:
+    with pdhg.BatchSolver.from_lps(lps, threads=threads) as bs:
         x, y, res = bs.solve()
         for b, lp in enumerate(lps):
             _, _, ro = oracle_lib.Oracle(lp).solve()
@@ -94,7 +105,7 @@ def test_batch_determinism_and_launch_shapes(pdhg):
         x2, y2, r2 = bs.solve()
         np.testing.assert_array_equal(x1, to_np(x2))
         objs = {}
-        for t in (64, 128, 512):
+        for t in (64, 128, 256, 512):
             bs.set_launch(t, workgroups=7)
             _, _, r = bs.solve()
             objs[t] = [q["primal_obj"] for q in r]
