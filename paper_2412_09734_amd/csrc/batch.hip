@@ -186,38 +186,110 @@ __device__ __forceinline__ uint64_t splitmix64_b(uint64_t x) {
 // setup: Ruiz + Pock-Chambolle scaling and the power iteration, per instance
 // (once for a shared matrix).
 
-// Largest eigenvalue of T = B'B for the Golub-Kahan bidiagonal B (alpha on the
-// diagonal, beta above it): Sturm-count bisection over [0, Gershgorin bound]
-// until the interval cannot be halved (one thread).
-__device__ double bidiag_lambda_max_dev(const double *alpha, const double *beta, int32_t k) {
-    double hi = 0.0;
+// Sturm count of T - x I for T = B'B, B the Golub-Kahan bidiagonal (alpha on
+// the diagonal, beta above it): the number of negative pivots of the LDL'
+// recurrence, i.e. the number of eigenvalues of T below x.
+__device__ int32_t bidiag_sturm(const double *alpha, const double *beta, int32_t k, double x) {
+    int32_t cnt = 0;
+    double q = 1.0;
     for (int32_t i = 0; i < k; ++i) {
+        const double di = alpha[i] * alpha[i] + (i > 0 ? beta[i - 1] * beta[i - 1] : 0.0);
+        if (i == 0) {
+            q = di - x;
+        } else {
+            const double ei = alpha[i - 1] * beta[i - 1];
+            q = di - x - (ei * ei) / q;
+        }
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// Largest eigenvalue of T = B'B: bisection over [0, Gershgorin bound], at most
+// 200 halvings, until the interval cannot be halved. The whole workgroup takes
+// D = log2(BT) halvings per round: thread t (1 <= t < BT) replays the midpoint
+// arithmetic along the path to node t of the binary tree of the next D
+// midpoints (bit 0: upper half dropped, bit 1: lower half dropped) and counts
+// at its own midpoint; thread 0 then walks the tree from the root. The result
+// equals the one-point-at-a-time bisection bit for bit.
+template <int BT>
+__device__ double bidiag_lambda_max_wg(const double *alpha, const double *beta, int32_t k) {
+    constexpr int NW = BT / 64;
+    constexpr int D = BT == 64 ? 6 : BT == 128 ? 7 : BT == 256 ? 8 : BT == 512 ? 9 : 10;
+    static_assert((1 << D) == BT, "BT must be a power of two from 64 to 1024");
+    __shared__ double wmax[NW];
+    __shared__ double lohi[2];
+    __shared__ int32_t done;
+    __shared__ uint8_t halvable[BT], lower[BT];
+    const int32_t t = threadIdx.x;
+    // Gershgorin bound: a maximum, the same in any order
+    double g = 0.0;
+    for (int32_t i = t; i < k; i += BT) {
         const double di = alpha[i] * alpha[i] + (i > 0 ? beta[i - 1] * beta[i - 1] : 0.0);
         const double el = i > 0 ? fabs(alpha[i - 1] * beta[i - 1]) : 0.0;
         const double er = i + 1 < k ? fabs(alpha[i] * beta[i]) : 0.0;
-        hi = fmax(hi, di + el + er);
+        g = fmax(g, di + el + er);
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) g = fmax(g, __shfl_xor(g, off));
+    if ((t & 63) == 0) wmax[t >> 6] = g;
+    __syncthreads();
+    double hi = 0.0;
+    for (int w = 0; w < NW; ++w) hi = fmax(hi, wmax[w]);
     double lo = 0.0;
-    for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (!(mid > lo && mid < hi)) break;
-        int32_t cnt = 0;
-        double q = 1.0;
-        for (int32_t i = 0; i < k; ++i) {
-            const double di = alpha[i] * alpha[i] + (i > 0 ? beta[i - 1] * beta[i - 1] : 0.0);
-            if (i == 0) {
-                q = di - mid;
-            } else {
-                const double ei = alpha[i - 1] * beta[i - 1];
-                q = di - mid - (ei * ei) / q;
+    int32_t halvings = 0;
+    for (;;) {
+        if (t > 0) {
+            const int depth = 31 - __clz(t);
+            double l = lo, h = hi;
+            bool reach = true;
+            for (int lev = depth - 1; lev >= 0; --lev) {
+                const double mid = 0.5 * (l + h);
+                if (!(mid > l && mid < h)) {
+                    reach = false;
+                    break;
+                }
+                if ((t >> lev) & 1) l = mid;
+                else h = mid;
             }
-            if (q == 0.0) q = -1e-300;
-            if (q < 0.0) ++cnt;
+            bool hv = false, lw = false;
+            if (reach) {
+                const double mid = 0.5 * (l + h);
+                hv = mid > l && mid < h;
+                if (hv) lw = bidiag_sturm(alpha, beta, k, mid) == k;
+            }
+            halvable[t] = hv;
+            lower[t] = lw;
         }
-        if (cnt == k)
-            hi = mid;
-        else
-            lo = mid;
+        __syncthreads();
+        if (t == 0) {
+            int32_t node = 1, stop = 0;
+            for (int lev = 0; lev < D; ++lev) {
+                if (halvings >= 200 || !halvable[node]) {
+                    stop = 1;
+                    break;
+                }
+                const double mid = 0.5 * (lo + hi);
+                if (lower[node]) {   // every eigenvalue lies below mid
+                    hi = mid;
+                    node = 2 * node;
+                } else {
+                    lo = mid;
+                    node = 2 * node + 1;
+                }
+                ++halvings;
+            }
+            lohi[0] = lo;
+            lohi[1] = hi;
+            done = stop || halvings >= 200;
+        }
+        __syncthreads();
+        lo = lohi[0];
+        hi = lohi[1];
+        const bool fin = done != 0;
+        __syncthreads();
+        if (fin) break;
     }
     return hi;
 }
@@ -315,7 +387,10 @@ __global__ __launch_bounds__(BT) void k_batch_setup(BArgs a, BOpts o, int32_t co
                 if (threadIdx.x == 0) {
                     al[it - 1] = al_k;
                     be[it - 1] = be_k;
-                    const double l = bidiag_lambda_max_dev(al, be, it);
+                }
+                __syncthreads();
+                const double l = bidiag_lambda_max_wg<BT>(al, be, it);
+                if (threadIdx.x == 0) {
                     int32_t st = 0;
                     if (!(be_k > 0.0)) st = 1;
                     else if (it > 1 && fabs(l - lam_prev) <= o.power_tol * l) st = 1;

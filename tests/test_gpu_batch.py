@@ -42,6 +42,7 @@ def test_shared_grid_batch_matches_oracle_and_plain(pdhg, oracle_lib):
         with pdhg.Solver.from_lp(lp) as s:
             _, _, rp = s.solve()
         ref.append((lp, ro, rp))
+    sc = oracle_lib.Oracle(ref[0][0]).scaling()   # the instances share A
     for threads in (None, 256, 128, 64):
         _say(f"  threads per instance: {threads or 'default'}")
         with pdhg.BatchSolver.from_shared(sb, threads=threads) as bs:
@@ -49,6 +50,8 @@ def test_shared_grid_batch_matches_oracle_and_plain(pdhg, oracle_lib):
         for b, (lp, ro, rp) in enumerate(ref):
             rb = res[b]
             assert rb["status_name"] == "optimal" and rb["kkt_rel"] <= 1e-4, (threads, b, rb)
+            assert rb["power_iters"] == sc["power_iters"], (rb["power_iters"], sc["power_iters"])
+            assert abs(rb["eta"] - sc["eta"]) <= 1e-10 * sc["eta"], (rb["eta"], sc["eta"])
             assert _close(rb["primal_obj"], ro["primal_obj"]), (threads, b, rb["primal_obj"], ro["primal_obj"])
             assert _close(rb["primal_obj"], rp["primal_obj"]), (threads, b, rb["primal_obj"], rp["primal_obj"])
             kb = oracle_lib.kkt(lp, to_np(x[b]), to_np(y[b]))
@@ -65,10 +68,14 @@ def test_ragged_batch_matches_oracle(pdhg, oracle_lib, threads):
     with pdhg.BatchSolver.from_lps(lps, threads=threads) as bs:
         x, y, res = bs.solve()
         for b, lp in enumerate(lps):
-            _, _, ro = oracle_lib.Oracle(lp).solve()
+            orc = oracle_lib.Oracle(lp)
+            sc = orc.scaling()
+            _, _, ro = orc.solve()
             cs, rs = bs.instance_slices(b)
             rb = res[b]
             assert rb["status_name"] == "optimal", (b, rb)
+            assert rb["power_iters"] == sc["power_iters"], (b, rb["power_iters"], sc["power_iters"])
+            assert abs(rb["eta"] - sc["eta"]) <= 1e-10 * sc["eta"], (b, rb["eta"], sc["eta"])
             assert _close(rb["primal_obj"], ro["primal_obj"]), (b, rb["primal_obj"], ro["primal_obj"])
             assert rb["iterations"] == ro["iterations"], (b, rb["iterations"], ro["iterations"])
             kb = oracle_lib.kkt(lp, to_np(x[cs]), to_np(y[rs]))
@@ -86,10 +93,14 @@ def test_ragged_batch_beyond_lds_matches_oracle(pdhg, oracle_lib):
     with pdhg.BatchSolver.from_lps(lps) as bs:
         x, y, res = bs.solve()
         for b, lp in enumerate(lps):
-            _, _, ro = oracle_lib.Oracle(lp).solve()
+            orc = oracle_lib.Oracle(lp)
+            sc = orc.scaling()
+            _, _, ro = orc.solve()
             cs, rs = bs.instance_slices(b)
             rb = res[b]
             assert rb["status_name"] == "optimal", (b, rb)
+            assert rb["power_iters"] == sc["power_iters"], (b, rb["power_iters"], sc["power_iters"])
+            assert abs(rb["eta"] - sc["eta"]) <= 1e-10 * sc["eta"], (b, rb["eta"], sc["eta"])
             assert _close(rb["primal_obj"], ro["primal_obj"]), (b, rb["primal_obj"], ro["primal_obj"])
             assert rb["iterations"] == ro["iterations"], (b, rb["iterations"], ro["iterations"])
             kb = oracle_lib.kkt(lp, to_np(x[cs]), to_np(y[rs]))
