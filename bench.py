@@ -102,14 +102,15 @@ def main():
                     help="only run a 1 GiB device-to-device copy three times (counter calibration)")
     ap.add_argument("--workload", default="sparse",
                     choices=["sparse", "dense", "dense-knapsack", "batch-grid", "batch-ragged",
-                             "learn-grid", "qp-portfolio"],
+                             "learn-grid", "spo-grid", "qp-portfolio"],
                     help="sparse (default, the headline line), dense 20k x 40k, "
                          "batched grid min-cost flows (2,048 x 32x32 grid) or the ragged batch "
                          "(1,024 planted LPs); the batched modes also time the plain solver "
                          "looped one instance at a time on a subset; learn-grid: training steps "
                          "of the shortest-path cost model through 1,000 unrolled iterations "
-                         "(256 grids); qp-portfolio: 512 portfolio QPs, solve and unrolled "
-                         "gradient")
+                         "(256 grids); spo-grid: SPO+ training steps on the same grids (batched "
+                         "solves to 1e-4, warm-started); qp-portfolio: 512 portfolio QPs, solve "
+                         "and unrolled gradient")
     ap.add_argument("--batch", type=int, default=0, help="batch size override (batched modes)")
     ap.add_argument("--threads", type=int, default=0,
                     help="threads per instance of the batch solves (default: the library's choice)")
@@ -145,6 +146,8 @@ def main():
         return bench_knapsack(args)
     if args.workload == "learn-grid":
         return bench_learn(args)
+    if args.workload == "spo-grid":
+        return bench_spo(args)
     if args.workload == "qp-portfolio":
         return bench_qp(args)
 
@@ -459,6 +462,64 @@ def bench_learn(args):
                                   f"model on 5 features, {T} unrolled r2HPDHG iterations + reverse pass",
                       "batch": B, "unrolled_iterations": T, "mean_regret_first": losses[0],
                       "mean_regret_last": losses[-1]}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_spo(args):
+    """One SPO+ training step of the shortest-path cost model: c_hat = f W,
+    inner costs 2 c_hat - c, one batched solve to 1e-4 warm-started from the
+    previous step's solutions, SPO+ loss and subgradient, weight gradient (all
+    in libpdhg kernels), then a host-side gradient step (rate 1e-4) on the 5
+    weights.
+    value = LPs solved and differentiated per second (batch / step time)."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2412_09734_amd import heads
+    from paper_2412_09734_amd.solver import BatchSolver
+
+    B = args.batch or 256
+    sb, f, _, W = gen.shortest_path_learning(batch=B, seed=gen.seed_for(4, 0))
+    dev = torch.device("cuda:0")
+    fd = torch.from_numpy(f).to(dev)
+    ct = torch.from_numpy(sb.c).to(dev)
+    with BatchSolver.from_shared(sb, eps=1e-8) as bs:
+        w_star, _, res = bs.solve()                  # optimal decisions under the true costs
+    z_star = torch.tensor([r["primal_obj"] for r in res], dtype=torch.float64, device=dev)
+    lr = 1e-4   # larger plain-gradient steps diverge: the subgradient sums over ~4,000 arcs
+    with BatchSolver.from_shared(sb, threads=args.threads or None) as bs:
+        prev = [None]
+
+        def step(Wv):
+            chat = heads.linear_costs(fd, Wv)
+            bs.update_data(c=heads.spo_plus_costs(chat, ct))
+            wt, _, r = bs.solve(x_init=prev[0])
+            prev[0] = wt
+            loss, g = heads.spo_plus(chat, ct, w_star, z_star, wt)
+            gW = heads.linear_costs_backward(fd, g)
+            return float(loss.mean()), gW.cpu().numpy() / B, r
+        for _ in range(args.warmup):
+            step(W)
+        torch.cuda.synchronize()
+        losses, iters = [], []
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            l, g, r = step(W)
+            W = W - lr * g
+            losses.append(l)
+            iters.append(float(np.mean([q["iterations"] for q in r])))
+            log(f"bench: SPO+ step {k}: mean loss {l:.4f}, mean iterations {iters[-1]:.0f}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+    out = {"metric": METRIC, "value": round(args.steps * B / el, 2), "unit": "LPs/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(el / args.steps * 1e3, 2), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"SPO+ learning step: {B} grid shortest-path LPs (32x32), linear cost "
+                                  "model on 5 features, batched solves to 1e-4 warm-started",
+                      "batch": B, "mean_iterations": iters, "mean_spo_loss_first": losses[0],
+                      "mean_spo_loss_last": losses[-1]}}
     print(json.dumps(out), flush=True)
 
 

@@ -317,6 +317,38 @@ pdhg_err pdhg_qp_value(int32_t B, int32_t n, int32_t r, const double *F, const d
                        const double *c, const double *x, double *value, double *gx,
                        void *stream);
 
+/* ---- Surrogate losses for LP (Section 3.4 names SPO+ and the perturbed
+ * Fenchel-Young loss; Section 4.4 trains with SPO+). Both are stated for
+ * min_{w in S} c'w over the LP's feasible set S; the optimal solutions they
+ * take come from pdhg_batch_solve. Layouts as above ([B n] row-major,
+ * device pointers, work enqueued on `stream`). ---- */
+
+/* Costs of the SPO+ inner problem: c_out = 2 c_hat - c_true ([B n]). */
+pdhg_err pdhg_spo_plus_costs(int32_t B, int32_t n, const double *c_hat, const double *c_true,
+                             double *c_out, void *stream);
+
+/* SPO+ loss and subgradient. w_star [B n] is optimal under c_true with
+ * value z_star [B]; w_tilde [B n] is optimal under 2 c_hat - c_true. Then
+ * loss[b] = -(2 c_hat_b - c_true_b)'w_tilde_b + 2 c_hat_b'w_star_b - z_star[b]
+ * and grad_b = 2 (w_star_b - w_tilde_b), a subgradient in c_hat_b. */
+pdhg_err pdhg_spo_plus(int32_t B, int32_t n, const double *c_hat, const double *c_true,
+                       const double *w_star, const double *z_star, const double *w_tilde, double *loss,
+                       double *grad, void *stream);
+
+/* Perturbed costs of the Fenchel-Young estimator: c_out [B M n], sample
+ * (b, m) = c_hat_b + eps Z_bm for the caller's draws Z [B M n] (standard
+ * normal); M >= 1, eps finite. */
+pdhg_err pdhg_pfy_costs(int32_t B, int32_t M, int32_t n, const double *c_hat, const double *Z, double eps,
+                        double *c_out, void *stream);
+
+/* Perturbed Fenchel-Young loss (up to the constant Omega(w_star), which does
+ * not depend on c_hat) and gradient from M samples: w_samples [B M n] optimal
+ * under the costs of pdhg_pfy_costs; loss[b] = c_hat_b'w_star_b - (1/M)
+ * sum_m (c_hat_b + eps Z_bm)'w_bm, grad_b = w_star_b - (1/M) sum_m w_bm. */
+pdhg_err pdhg_pfy(int32_t B, int32_t M, int32_t n, const double *c_hat, const double *w_star,
+                  const double *Z, double eps, const double *w_samples, double *loss, double *grad,
+                  void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -88,6 +88,10 @@ SIGNATURES = {
     "pdhg_regret": (C.c_int, [C.c_int32, C.c_int32, P, P, P, P, P]),
     "pdhg_linear_costs_backward": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, P, P]),
     "pdhg_qp_value": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P]),
+    "pdhg_spo_plus_costs": (C.c_int, [C.c_int32, C.c_int32, P, P, P, P]),
+    "pdhg_spo_plus": (C.c_int, [C.c_int32, C.c_int32, P, P, P, P, P, P, P, P]),
+    "pdhg_pfy_costs": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, C.c_double, P, P]),
+    "pdhg_pfy": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, P, C.c_double, P, P, P, P]),
     "pdhg_batch_destroy": (None, [P]),
 }
 

@@ -9,6 +9,7 @@
 // stalling the GPU.
 #include <chrono>
 #include <climits>
+#include <cmath>
 #include <deque>
 #include <new>
 
@@ -588,5 +589,49 @@ pdhg_err pdhg_qp_value(int32_t B, int32_t n, int32_t r, const double *F, const d
         if (B > 0 && (!d || !c || !x || !value || (r > 0 && !F)))
             fail(PDHG_ERR_INVALID_ARG, "NULL array");
         head_qp_value(reinterpret_cast<hipStream_t>(stream), B, n, r, F, d, c, x, value, gx);
+    });
+}
+
+pdhg_err pdhg_spo_plus_costs(int32_t B, int32_t n, const double *c_hat, const double *c_true,
+                             double *c_out, void *stream) {
+    return guarded([&] {
+        if (B < 0 || n < 0) fail(PDHG_ERR_INVALID_ARG, "need B, n >= 0");
+        if ((int64_t)B * n > 0 && (!c_hat || !c_true || !c_out)) fail(PDHG_ERR_INVALID_ARG, "NULL array");
+        head_spo_costs(reinterpret_cast<hipStream_t>(stream), B, n, c_hat, c_true, c_out);
+    });
+}
+
+pdhg_err pdhg_spo_plus(int32_t B, int32_t n, const double *c_hat, const double *c_true,
+                       const double *w_star, const double *z_star, const double *w_tilde, double *loss,
+                       double *grad, void *stream) {
+    return guarded([&] {
+        if (B < 0 || n < 0) fail(PDHG_ERR_INVALID_ARG, "need B, n >= 0");
+        if (B > 0 && (!z_star || !loss || (n > 0 && (!c_hat || !c_true || !w_star || !w_tilde || !grad))))
+            fail(PDHG_ERR_INVALID_ARG, "NULL array");
+        head_spo_plus(reinterpret_cast<hipStream_t>(stream), B, n, c_hat, c_true, w_star, z_star, w_tilde,
+                      loss, grad);
+    });
+}
+
+pdhg_err pdhg_pfy_costs(int32_t B, int32_t M, int32_t n, const double *c_hat, const double *Z, double eps,
+                        double *c_out, void *stream) {
+    return guarded([&] {
+        if (B < 0 || M < 1 || n < 0) fail(PDHG_ERR_INVALID_ARG, "need B, n >= 0, M >= 1");
+        if (!std::isfinite(eps)) fail(PDHG_ERR_INVALID_ARG, "eps must be finite");
+        if ((int64_t)B * n > 0 && (!c_hat || !Z || !c_out)) fail(PDHG_ERR_INVALID_ARG, "NULL array");
+        head_pfy_costs(reinterpret_cast<hipStream_t>(stream), B, M, n, c_hat, Z, eps, c_out);
+    });
+}
+
+pdhg_err pdhg_pfy(int32_t B, int32_t M, int32_t n, const double *c_hat, const double *w_star,
+                  const double *Z, double eps, const double *w_samples, double *loss, double *grad,
+                  void *stream) {
+    return guarded([&] {
+        if (B < 0 || M < 1 || n < 0) fail(PDHG_ERR_INVALID_ARG, "need B, n >= 0, M >= 1");
+        if (!std::isfinite(eps)) fail(PDHG_ERR_INVALID_ARG, "eps must be finite");
+        if (B > 0 && (!loss || (n > 0 && (!c_hat || !w_star || !Z || !w_samples || !grad))))
+            fail(PDHG_ERR_INVALID_ARG, "NULL array");
+        head_pfy(reinterpret_cast<hipStream_t>(stream), B, M, n, c_hat, w_star, Z, eps, w_samples, loss,
+                 grad);
     });
 }

@@ -186,6 +186,16 @@ void head_linear_costs_backward(hipStream_t s, int32_t B, int32_t n, int32_t p, 
                                 const double *gc, double *gW);
 void head_qp_value(hipStream_t s, int32_t B, int32_t n, int32_t r, const double *F,
                    const double *d, const double *c, const double *x, double *value, double *gx);
+void head_spo_costs(hipStream_t s, int32_t B, int32_t n, const double *c_hat, const double *c_true,
+                    double *out);
+void head_spo_plus(hipStream_t s, int32_t B, int32_t n, const double *c_hat, const double *c_true,
+                   const double *w_star, const double *z_star, const double *w_tilde, double *loss,
+                   double *grad);
+void head_pfy_costs(hipStream_t s, int32_t B, int32_t M, int32_t n, const double *c_hat,
+                    const double *Z, double eps, double *out);
+void head_pfy(hipStream_t s, int32_t B, int32_t M, int32_t n, const double *c_hat,
+              const double *w_star, const double *Z, double eps, const double *w_samples, double *loss,
+              double *grad);
 
 // ---- setup (setup.hip) ---------------------------------------------------
 void build_matrices(Handle &h, const pdhg_problem &p);

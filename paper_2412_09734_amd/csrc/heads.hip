@@ -89,6 +89,83 @@ __global__ __launch_bounds__(kBlock) void k_qp_value(int32_t n, int32_t r, const
     if (threadIdx.x == 0) value[b] = v[0];
 }
 
+// SPO+ (Elmachtoub-Grigas) for min_{w in S} c'w: the inner problem's costs
+// 2 c_hat - c_true, entrywise over the N = B n variables.
+__global__ __launch_bounds__(kBlock) void k_spo_costs(int64_t N, const double *__restrict__ ch,
+                                                      const double *__restrict__ ct,
+                                                      double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < N) out[i] = 2.0 * ch[i] - ct[i];
+}
+
+// One workgroup per instance: with w* optimal under c_true (value z*) and w~
+// optimal under 2 c_hat - c_true, loss = -(2 c_hat - c)'w~ + 2 c_hat'w* - z*,
+// summed as 2 c_hat'(w* - w~) + c'w~ - z* (the same value, without the
+// cancellation of two large products), and the subgradient 2 (w* - w~).
+__global__ __launch_bounds__(kBlock) void k_spo_plus(int32_t n, const double *__restrict__ ch,
+                                                     const double *__restrict__ ct,
+                                                     const double *__restrict__ ws,
+                                                     const double *__restrict__ zs,
+                                                     const double *__restrict__ wt,
+                                                     double *__restrict__ loss,
+                                                     double *__restrict__ grad) {
+    const int32_t b = blockIdx.x;
+    const size_t o = (size_t)b * n;
+    double v[1] = {0.0};
+    for (int32_t a = threadIdx.x; a < n; a += kBlock) {
+        const double dw = ws[o + a] - wt[o + a];
+        v[0] += 2.0 * ch[o + a] * dw + ct[o + a] * wt[o + a];
+        grad[o + a] = 2.0 * dw;
+    }
+    block_sum_all<1>(v);
+    if (threadIdx.x == 0) loss[b] = v[0] - zs[b];
+}
+
+// Perturbed Fenchel-Young (Berthet et al.), minimisation form: sample (b, m)
+// has costs c_hat_b + eps Z_bm; entry i of the [B][M][n] output. Rounded as
+// a product then a sum, so the costs equal the textbook expression exactly.
+__global__ __launch_bounds__(kBlock) void k_pfy_costs(int64_t N, int32_t M, int32_t n,
+                                                      const double *__restrict__ ch,
+                                                      const double *__restrict__ Z, double eps,
+                                                      double *__restrict__ out) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= N) return;
+    const int64_t a = i % n, b = i / n / M;
+    const double pz = eps * Z[i];
+    out[i] = ch[b * n + a] + pz;
+}
+
+// One workgroup per instance: with w_m optimal under c_hat + eps Z_m,
+// grad = w* - (1/M) sum_m w_m and loss = c_hat'w* - (1/M) sum_m (c_hat +
+// eps Z_m)'w_m (the loss up to the constant Omega(w*)); samples summed in m
+// order per variable.
+__global__ __launch_bounds__(kBlock) void k_pfy(int32_t M, int32_t n, const double *__restrict__ ch,
+                                                const double *__restrict__ ws,
+                                                const double *__restrict__ Z, double eps,
+                                                const double *__restrict__ wm,
+                                                double *__restrict__ loss,
+                                                double *__restrict__ grad) {
+    const int32_t b = blockIdx.x;
+    const size_t o = (size_t)b * n;
+    const double dm = (double)M;
+    double v[1] = {0.0};
+    for (int32_t a = threadIdx.x; a < n; a += kBlock) {
+        const double c = ch[o + a];
+        double wsum = 0.0, acc = 0.0;
+        for (int32_t m = 0; m < M; ++m) {
+            const size_t e = ((size_t)b * M + m) * n + a;
+            const double w = wm[e];
+            wsum += w;
+            acc += (c + eps * Z[e]) * w;
+        }
+        grad[o + a] = ws[o + a] - wsum / dm;
+        v[0] += c * ws[o + a] - acc / dm;
+    }
+    block_sum_all<1>(v);
+    if (threadIdx.x == 0) loss[b] = v[0];
+}
+
 static unsigned grid1(int64_t N) { return (unsigned)std::max<int64_t>(1, ceil_div(N, kBlock)); }
 
 void head_linear_costs(hipStream_t s, int32_t B, int32_t n, int32_t p, const double *f,
@@ -122,6 +199,38 @@ void head_qp_value(hipStream_t s, int32_t B, int32_t n, int32_t r, const double 
     if (B == 0) return;
     if (r > kHeadRmax) fail(PDHG_ERR_UNSUPPORTED, "factor rank above 32");
     k_qp_value<<<(unsigned)B, kBlock, 0, s>>>(n, r, F, d, c, x, value, gx);
+    PDHG_HIP(hipGetLastError());
+}
+
+void head_spo_costs(hipStream_t s, int32_t B, int32_t n, const double *c_hat, const double *c_true,
+                    double *out) {
+    const int64_t N = (int64_t)B * n;
+    if (N == 0) return;
+    k_spo_costs<<<grid1(N), kBlock, 0, s>>>(N, c_hat, c_true, out);
+    PDHG_HIP(hipGetLastError());
+}
+
+void head_spo_plus(hipStream_t s, int32_t B, int32_t n, const double *c_hat, const double *c_true,
+                   const double *w_star, const double *z_star, const double *w_tilde, double *loss,
+                   double *grad) {
+    if (B == 0) return;
+    k_spo_plus<<<(unsigned)B, kBlock, 0, s>>>(n, c_hat, c_true, w_star, z_star, w_tilde, loss, grad);
+    PDHG_HIP(hipGetLastError());
+}
+
+void head_pfy_costs(hipStream_t s, int32_t B, int32_t M, int32_t n, const double *c_hat,
+                    const double *Z, double eps, double *out) {
+    const int64_t N = (int64_t)B * M * n;
+    if (N == 0) return;
+    k_pfy_costs<<<grid1(N), kBlock, 0, s>>>(N, M, n, c_hat, Z, eps, out);
+    PDHG_HIP(hipGetLastError());
+}
+
+void head_pfy(hipStream_t s, int32_t B, int32_t M, int32_t n, const double *c_hat,
+              const double *w_star, const double *Z, double eps, const double *w_samples, double *loss,
+              double *grad) {
+    if (B == 0) return;
+    k_pfy<<<(unsigned)B, kBlock, 0, s>>>(M, n, c_hat, w_star, Z, eps, w_samples, loss, grad);
     PDHG_HIP(hipGetLastError());
 }
 

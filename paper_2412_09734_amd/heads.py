@@ -1,5 +1,7 @@
 """Loss heads of the end-to-end learning pipelines, bound to libpdhg's
-pdhg_linear_costs / pdhg_regret / pdhg_linear_costs_backward / pdhg_qp_value.
+pdhg_linear_costs / pdhg_regret / pdhg_linear_costs_backward / pdhg_qp_value
+and the LP surrogates pdhg_spo_plus_costs / pdhg_spo_plus / pdhg_pfy_costs /
+pdhg_pfy.
 Argument marshalling only; the arithmetic runs in the HIP kernels."""
 
 from __future__ import annotations
@@ -58,3 +60,53 @@ def qp_value(F, d, c, x, grad=True, device=None):
     capi.check(capi.lib().pdhg_qp_value(B, n, r, _ptr(Ft), _ptr(dt), _ptr(ct), _ptr(xt), _ptr(value),
                                         _ptr(gx), _stream_ptr()), "pdhg_qp_value")
     return value, gx
+
+
+def spo_plus_costs(c_hat, c_true, device=None) -> torch.Tensor:
+    """Costs of the SPO+ inner problem, 2 c_hat - c_true [B, n]."""
+    dev = _device(device)
+    ch, ct = _f64(c_hat, dev), _f64(c_true, dev)
+    B, n = ch.shape
+    out = torch.empty(B, n, dtype=torch.float64, device=dev)
+    capi.check(capi.lib().pdhg_spo_plus_costs(B, n, _ptr(ch), _ptr(ct), _ptr(out), _stream_ptr()),
+               "pdhg_spo_plus_costs")
+    return out
+
+
+def spo_plus(c_hat, c_true, w_star, z_star, w_tilde, device=None):
+    """(loss [B], subgradient [B, n]) of SPO+; w_star optimal under c_true with
+    value z_star, w_tilde optimal under 2 c_hat - c_true."""
+    dev = _device(device)
+    ch, ct, ws, wt = (_f64(a, dev) for a in (c_hat, c_true, w_star, w_tilde))
+    zs = _f64(z_star, dev).reshape(-1)
+    B, n = ch.shape
+    loss = torch.empty(B, dtype=torch.float64, device=dev)
+    grad = torch.empty(B, n, dtype=torch.float64, device=dev)
+    capi.check(capi.lib().pdhg_spo_plus(B, n, _ptr(ch), _ptr(ct), _ptr(ws), _ptr(zs), _ptr(wt), _ptr(loss),
+                                        _ptr(grad), _stream_ptr()), "pdhg_spo_plus")
+    return loss, grad
+
+
+def pfy_costs(c_hat, Z, eps, device=None) -> torch.Tensor:
+    """Perturbed costs [B, M, n]: c_hat[b] + eps Z[b, m]."""
+    dev = _device(device)
+    ch, Zt = _f64(c_hat, dev), _f64(Z, dev)
+    B, M, n = Zt.shape
+    out = torch.empty(B, M, n, dtype=torch.float64, device=dev)
+    capi.check(capi.lib().pdhg_pfy_costs(B, M, n, _ptr(ch), _ptr(Zt), float(eps), _ptr(out), _stream_ptr()),
+               "pdhg_pfy_costs")
+    return out
+
+
+def pfy(c_hat, w_star, Z, eps, w_samples, device=None):
+    """(loss up to a constant [B], gradient [B, n]) of the perturbed
+    Fenchel-Young loss from samples w_samples [B, M, n] optimal under
+    pfy_costs(c_hat, Z, eps)."""
+    dev = _device(device)
+    ch, ws, Zt, wm = (_f64(a, dev) for a in (c_hat, w_star, Z, w_samples))
+    B, M, n = Zt.shape
+    loss = torch.empty(B, dtype=torch.float64, device=dev)
+    grad = torch.empty(B, n, dtype=torch.float64, device=dev)
+    capi.check(capi.lib().pdhg_pfy(B, M, n, _ptr(ch), _ptr(ws), _ptr(Zt), float(eps), _ptr(wm), _ptr(loss),
+                                   _ptr(grad), _stream_ptr()), "pdhg_pfy")
+    return loss, grad

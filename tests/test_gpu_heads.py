@@ -89,3 +89,121 @@ def test_learning_step_matches_oracle(mods, oracle_lib):
     assert rel_inf(to_np(x), np.array(xs)) <= 1e-10
     assert rel_inf(to_np(loss), oh.regret(sb.c, np.array(xs), vstar)) <= 1e-9
     assert rel_inf(to_np(gW), oh.linear_costs_backward(f, np.array(gcs))) <= 1e-9
+
+
+def test_surrogate_heads_match_oracle(mods):
+    """SPO+ and perturbed Fenchel-Young heads on random inputs: the cost maps
+    and gradients round exactly as the oracle's; the losses sum in another
+    order (bound: a few ulps of the sum of absolute terms)."""
+    from oracle import heads as oh
+    h, _ = mods
+    _say("case: SPO+ / PFY heads vs oracle, B=5 n=301, M=3")
+    rng = np.random.default_rng(12)
+    B, n, M = 5, 301, 3
+    ch, ct = rng.standard_normal((B, n)), rng.uniform(1, 10, (B, n))
+    ws, wt = rng.uniform(0, 1, (B, n)), rng.uniform(0, 1, (B, n))
+    zs = rng.standard_normal(B)
+    np.testing.assert_array_equal(to_np(h.spo_plus_costs(ch, ct)), oh.spo_plus_costs(ch, ct))
+    loss, grad = h.spo_plus(ch, ct, ws, zs, wt)
+    lo, go = oh.spo_plus(ch, ct, ws, zs, wt)
+    np.testing.assert_array_equal(to_np(grad), go)
+    scale = np.sum(np.abs(2 * ch * ws) + np.abs((2 * ch - ct) * wt), axis=1) + np.abs(zs)
+    assert np.all(np.abs(to_np(loss) - lo) <= 1e-14 * n * scale)
+    Z = rng.standard_normal((B, M, n))
+    np.testing.assert_array_equal(to_np(h.pfy_costs(ch, Z, 0.3)), oh.pfy_costs(ch, Z, 0.3))
+    wm = rng.uniform(0, 1, (B, M, n))
+    loss, grad = h.pfy(ch, ws, Z, 0.3, wm)
+    lo, go = oh.pfy(ch, ws, Z, 0.3, wm)
+    np.testing.assert_array_equal(to_np(grad), go)
+    scale = np.sum(np.abs(ch * ws), axis=1) + np.sum(np.abs((ch[:, None] + 0.3 * Z) * wm), axis=(1, 2)) / M
+    assert np.all(np.abs(to_np(loss) - lo) <= 1e-14 * n * scale)
+
+
+def test_surrogate_heads_reject_bad_input(mods):
+    from paper_2412_09734_amd import _capi as capi
+    _say("case: surrogate-head argument errors")
+    L = capi.lib()
+    assert L.pdhg_spo_plus_costs(-1, 3, None, None, None, None) == -1
+    assert L.pdhg_spo_plus(2, 3, None, None, None, None, None, None, None, None) == -1
+    assert L.pdhg_pfy_costs(1, 0, 3, None, None, 0.1, None, None) == -1
+    assert L.pdhg_pfy_costs(1, 2, 0, None, None, float("nan"), None, None) == -1
+    assert L.pdhg_pfy(1, 0, 3, None, None, None, 0.1, None, None, None, None) == -1
+
+
+def _true_solutions(oracle_lib, sb, B):
+    ws, zs = [], []
+    for b in range(B):
+        xo, _, ro = oracle_lib.Oracle(sb.instance(b), eps=1e-10).solve()
+        ws.append(xo); zs.append(ro["primal_obj"])
+    return np.array(ws), np.array(zs)
+
+
+def test_spo_plus_step_matches_oracle(mods, oracle_lib):
+    """cost model -> SPO+ costs -> batched solve (warm-started the second time)
+    -> SPO+ loss and subgradient -> weight gradient, against the oracle's
+    solves of the same inner problems."""
+    from oracle import heads as oh
+    h, s = mods
+    _say("case: SPO+ learning step, 4 grids 6x6, inner solves to 1e-8")
+    B = 4
+    sb, f, w_true, W = gen.shortest_path_learning(batch=B, rows=6, cols=6, seed=4600)
+    ws, zs = _true_solutions(oracle_lib, sb, B)
+    chat = h.linear_costs(f, W)
+    with s.BatchSolver.from_shared(sb, eps=1e-8) as bs:
+        bs.update_data(c=h.spo_plus_costs(chat, sb.c))
+        wt, _, res = bs.solve()
+        loss, g = h.spo_plus(chat, sb.c, ws, zs, wt)
+        gW = h.linear_costs_backward(f, g)
+        wt2, _, res2 = bs.solve(x_init=wt)
+        assert all(r["status_name"] == "optimal" for r in res + res2)
+        assert sum(r["iterations"] for r in res2) < sum(r["iterations"] for r in res)
+    ch = oh.linear_costs(f, W)
+    inner = oh.spo_plus_costs(ch, sb.c)
+    wto = []
+    for b in range(B):
+        lp = sb.instance(b)
+        lp.c = inner[b]
+        xo, _, ro = oracle_lib.Oracle(lp, eps=1e-8).solve()
+        # same algorithm and check period: the counts agree up to one period
+        assert abs(ro["iterations"] - res[b]["iterations"]) <= 64, (b, ro["iterations"], res[b]["iterations"])
+        wto.append(xo)
+    lo, go = oh.spo_plus(ch, sb.c, ws, zs, np.array(wto))
+    # both sides solve to relative KKT 1e-8
+    assert rel_inf(to_np(wt), np.array(wto)) <= 1e-6
+    assert rel_inf(to_np(loss), lo) <= 1e-6
+    assert rel_inf(to_np(gW), oh.linear_costs_backward(f, go)) <= 1e-6
+
+
+def test_pfy_step_matches_oracle(mods, oracle_lib):
+    """perturbed costs for B x M samples -> one batched solve of all samples ->
+    Fenchel-Young loss and gradient, against the oracle."""
+    from types import SimpleNamespace
+    from oracle import heads as oh
+    h, s = mods
+    B, M, eps = 2, 3, 0.5
+    _say(f"case: perturbed Fenchel-Young step, {B} grids 6x6, M={M} samples, inner solves to 1e-8")
+    sb, f, w_true, W = gen.shortest_path_learning(batch=B, rows=6, cols=6, seed=4700)
+    ws, zs = _true_solutions(oracle_lib, sb, B)
+    Z = np.random.default_rng(8).standard_normal((B, M, sb.n))
+    chat = h.linear_costs(f, W)
+    pc = h.pfy_costs(chat, Z, eps)
+    rep = lambda a: np.repeat(a, M, axis=0)
+    samples = SimpleNamespace(m=sb.m, n=sb.n, rowptr=sb.rowptr, colidx=sb.colidx, val=sb.val,
+                              c=pc.reshape(B * M, sb.n), lc=rep(sb.lc), uc=rep(sb.uc), lv=rep(sb.lv),
+                              uv=rep(sb.uv))
+    with s.BatchSolver.from_shared(samples, eps=1e-8) as bs:
+        wm, _, res = bs.solve()
+        assert all(r["status_name"] == "optimal" for r in res)
+        loss, g = h.pfy(chat, ws, Z, eps, wm.reshape(B, M, sb.n))
+    ch = oh.linear_costs(f, W)
+    pco = oh.pfy_costs(ch, Z, eps)
+    wmo = np.zeros((B, M, sb.n))
+    for b in range(B):
+        for m in range(M):
+            lp = sb.instance(b)
+            lp.c = pco[b, m]
+            wmo[b, m] = oracle_lib.Oracle(lp, eps=1e-8).solve()[0]
+    lo, go = oh.pfy(ch, ws, Z, eps, wmo)
+    assert rel_inf(to_np(wm).reshape(B, M, sb.n), wmo) <= 1e-6
+    assert rel_inf(to_np(loss), lo) <= 1e-6
+    assert rel_inf(to_np(g), go) <= 1e-6
