@@ -20,6 +20,7 @@ from .lp import (  # noqa: F401
     shortest_path_learning,
     ragged_planted_batch,
     tiny_boxed_lp,
+    infeasible_lp,
     portfolio_qp_batch,
     portfolio_instance,
     zipf_pmf,

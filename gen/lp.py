@@ -385,6 +385,56 @@ def ragged_planted_batch(batch: int = 1024, m_lo: int = 50, m_hi: int = 500,
                               seed=int(seed * 7919 + i)) for i, mi in enumerate(ms)]
 
 
+def infeasible_lp(kind: str, m: int = 60, n: int = 120, seed: int = 0) -> LP:
+    """LPs without an optimum, for the infeasibility tests.
+
+    'duplicate_row': a planted sparse LP (x >= 0) plus a copy of one of its
+        equality rows with the right-hand side moved by 1: no feasible point.
+    'boxed_sum': m random dense equality rows satisfied by some x in [0, 1]^n,
+        x boxed in [0, 1]^n, plus the row sum(x) = n + 1: no feasible point.
+    'unbounded': a planted sparse LP plus a column u >= 0 with c_u = -1 whose
+        entries are positive on some '>=' rows, negative on some '<=' rows and
+        zero on the equality rows: feasible, and the objective decreases
+        without bound along e_u, which moves A x into the interior of the
+        one-sided rows."""
+    rng = np.random.default_rng(seed)
+    if kind == "boxed_sum":
+        a = np.round(rng.standard_normal((m, n)), 3)
+        x0 = rng.random(n)
+        b = a @ x0
+        a = np.vstack([a, np.ones((1, n))])
+        b = np.append(b, n + 1.0)
+        rowptr, colidx, val = csr_from_dense(a)
+        c = np.round(rng.standard_normal(n), 3)
+        return LP(m + 1, n, rowptr, colidx, val, c, b.copy(), b.copy(), np.zeros(n), np.ones(n),
+                  meta=dict(kind="infeasible_boxed_sum", seed=seed))
+    base = planted_sparse_lp(m, n, density=max(0.02, 4.0 / n), seed=seed)
+    a = dense_from_csr(base.m, base.n, base.rowptr, base.colidx, base.val)
+    if kind == "duplicate_row":
+        eq = np.where(base.lc == base.uc)[0]
+        i = int(eq[rng.integers(len(eq))])
+        a = np.vstack([a, a[i:i + 1]])
+        lc = np.append(base.lc, base.lc[i] + 1.0)
+        uc = np.append(base.uc, base.uc[i] + 1.0)
+        rowptr, colidx, val = csr_from_dense(a)
+        return LP(m + 1, n, rowptr, colidx, val, base.c.copy(), lc, uc, base.lv.copy(), base.uv.copy(),
+                  meta=dict(kind="infeasible_duplicate_row", seed=seed, row=i))
+    if kind == "unbounded":
+        ge = np.isfinite(base.lc) & ~np.isfinite(base.uc)
+        le = ~np.isfinite(base.lc) & np.isfinite(base.uc)
+        pick = rng.random(m) < 0.3
+        mag = rng.uniform(0.5, 1.5, m)
+        col = np.where(pick & ge, mag, 0.0) - np.where(pick & le, mag, 0.0)
+        if not np.any(col):
+            col[np.where(ge | le)[0][0]] = 1.0 if ge.any() else -1.0
+        a = np.hstack([a, col[:, None]])
+        rowptr, colidx, val = csr_from_dense(a)
+        c = np.append(base.c, -1.0)
+        return LP(m, n + 1, rowptr, colidx, val, c, base.lc.copy(), base.uc.copy(),
+                  np.zeros(n + 1), np.full(n + 1, INF), meta=dict(kind="unbounded", seed=seed))
+    raise ValueError(kind)
+
+
 def tiny_boxed_lp(m: int, n: int, seed: int) -> LP:
     """Tiny dense LP with finite boxes on every variable and mixed row types
     (=, <=, >=, two-sided), feasible by construction."""

@@ -16,7 +16,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 
-STATUS = {0: "unsolved", 1: "optimal", 4: "iteration_limit", 6: "numerical_error"}
+STATUS = {0: "unsolved", 1: "optimal", 2: "primal_infeasible", 3: "dual_infeasible", 4: "iteration_limit",
+          6: "numerical_error"}
 
 
 def build(force: bool = True) -> str:
@@ -48,7 +49,8 @@ class Options(C.Structure):
                 ("step_safety", C.c_double), ("restart_sufficient", C.c_double),
                 ("restart_necessary", C.c_double), ("restart_artificial", C.c_double),
                 ("power_tol", C.c_double), ("power_max_iters", C.c_int32),
-                ("verbose", C.c_int32)]
+                ("verbose", C.c_int32), ("eps_primal_infeasible", C.c_double),
+                ("eps_dual_infeasible", C.c_double)]
 
 
 class Result(C.Structure):

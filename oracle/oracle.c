@@ -81,6 +81,8 @@ void orc_default_options(orc_options *o) {
     o->power_tol = 1e-7;
     o->power_max_iters = 2000;
     o->verbose = 0;
+    o->eps_primal_infeasible = 1e-8;   /* Appendix A */
+    o->eps_dual_infeasible = 1e-8;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -684,6 +686,95 @@ static void init_point(const orc_ctx *s, const double *x_init, const double *y_i
         y[i] = proj_y(y_init ? y_init[i] / s->dr[i] : 0.0, s->lc[i], s->uc[i]);
 }
 
+/* Infeasibility certificates (Section 3 lists infeasibility detection among
+ * the solver's heuristics and Appendix A gives its tolerances; the tests are
+ * the usual Farkas-type ray tests). The candidate rays are the differences
+ * between the PDHG point and the restart anchor, in the original space:
+ * dx = D_c (xh - x0), dy = D_r (yh - y0).
+ *  - dual ray: yp = proj_Y(dy), g = -A'dy, lam = the part of g in the cone of
+ *    the variable bounds; its objective l_c'yp+ - u_c'yp- + l_v'lam+ - u_v'lam-
+ *    must be positive and the largest violation |dy - yp|, |g - lam| at most
+ *    eps_primal_infeasible times it: the LP has no feasible point;
+ *  - primal ray: c'dx < 0 and the largest violation of A dx in the recession
+ *    cone of [l_c, u_c] and of dx in that of [l_v, u_v] at most
+ *    eps_dual_infeasible |c'dx|: the objective is unbounded below.
+ * Returns 2 or 3 and writes the ray scaled to objective 1 (dual) or -1
+ * (primal) to ray_y / ray_x; 0 when neither test holds. */
+static int infeasibility(const orc_ctx *s, const double *xh, const double *yh, const double *x0,
+                         const double *y0, double *ray_x, double *ray_y) {
+    const orc_problem *p = &s->p;
+    const int32_t m = s->m, n = s->n;
+    double *dx = dalloc(n), *dy = dalloc(m), *a = dalloc(m);
+    ld *aty = lalloc(n);
+    for (int32_t j = 0; j < n; ++j) dx[j] = s->dc[j] * (xh[j] - x0[j]);
+    for (int32_t i = 0; i < m; ++i) dy[i] = s->dr[i] * (yh[i] - y0[i]);
+    for (int32_t i = 0; i < m; ++i) {
+        ld acc = 0.0L;
+        if (p->dense) {
+            for (int32_t j = 0; j < n; ++j) {
+                acc += (ld)p->dense[(size_t)i * n + j] * (ld)dx[j];
+                aty[j] += (ld)p->dense[(size_t)i * n + j] * (ld)dy[i];
+            }
+        } else {
+            for (int32_t e = p->rowptr[i]; e < p->rowptr[i + 1]; ++e) {
+                acc += (ld)p->val[e] * (ld)dx[p->colidx[e]];
+                aty[p->colidx[e]] += (ld)p->val[e] * (ld)dy[i];
+            }
+        }
+        a[i] = (double)acc;
+    }
+    int found = 0;
+    /* dual ray */
+    ld obj_d = 0.0L;
+    double viol_d = 0.0;
+    for (int32_t i = 0; i < m; ++i) {
+        const double yp = proj_y(dy[i], p->lc[i], p->uc[i]);
+        viol_d = fmax(viol_d, fabs(dy[i] - yp));
+        if (isfinite(p->lc[i])) obj_d += (ld)p->lc[i] * (ld)fmax(yp, 0.0);
+        if (isfinite(p->uc[i])) obj_d -= (ld)p->uc[i] * (ld)fmax(-yp, 0.0);
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        const double g = -(double)aty[j];
+        const int lf = isfinite(p->lv[j]), uf = isfinite(p->uv[j]);
+        double lam;
+        if (!lf && !uf) lam = 0.0;
+        else if (lf && !uf) lam = fmax(g, 0.0);
+        else if (!lf && uf) lam = fmin(g, 0.0);
+        else lam = g;
+        viol_d = fmax(viol_d, fabs(g - lam));
+        if (lf) obj_d += (ld)p->lv[j] * (ld)fmax(lam, 0.0);
+        if (uf) obj_d -= (ld)p->uv[j] * (ld)fmax(-lam, 0.0);
+    }
+    if (s->o.eps_primal_infeasible > 0.0 && obj_d > 0.0L &&
+        viol_d <= s->o.eps_primal_infeasible * (double)obj_d) {
+        for (int32_t i = 0; i < m; ++i) ray_y[i] = dy[i] / (double)obj_d;
+        found = 2;
+    }
+    /* primal ray */
+    if (!found) {
+        ld obj_p = 0.0L;
+        double viol_p = 0.0;
+        for (int32_t j = 0; j < n; ++j) {
+            obj_p += (ld)p->c[j] * (ld)dx[j];
+            const double lo = isfinite(p->lv[j]) ? 0.0 : -INFINITY;
+            const double hi = isfinite(p->uv[j]) ? 0.0 : INFINITY;
+            viol_p = fmax(viol_p, fabs(dx[j] - clampd(dx[j], lo, hi)));
+        }
+        for (int32_t i = 0; i < m; ++i) {
+            const double lo = isfinite(p->lc[i]) ? 0.0 : -INFINITY;
+            const double hi = isfinite(p->uc[i]) ? 0.0 : INFINITY;
+            viol_p = fmax(viol_p, fabs(a[i] - clampd(a[i], lo, hi)));
+        }
+        if (s->o.eps_dual_infeasible > 0.0 && obj_p < 0.0L &&
+            viol_p <= s->o.eps_dual_infeasible * (double)(-obj_p)) {
+            for (int32_t j = 0; j < n; ++j) ray_x[j] = dx[j] / (double)(-obj_p);
+            found = 3;
+        }
+    }
+    free(dx); free(dy); free(a); free(aty);
+    return found;
+}
+
 /* Restart test shared by both methods: sufficient decay, necessary decay
  * without local progress, or an artificial restart after a long cycle. */
 static int restart_due(const orc_ctx *s, double r, double r_start, double r_prev,
@@ -721,6 +812,7 @@ static int lp_loop(orc_ctx *s, const double *x_init, const double *y_init, doubl
     double *x = dalloc(n), *y = dalloc(m), *x0 = dalloc(n), *y0 = dalloc(m);
     double *xh = dalloc(n), *yh = dalloc(m), *xn = dalloc(n), *yn = dalloc(m);
     double *xo = dalloc(n), *yo = dalloc(m);
+    double *ray_x = dalloc(n), *ray_y = dalloc(m);
     init_point(s, x_init, y_init, x, y);
     memcpy(x0, x, sizeof(double) * n);
     memcpy(y0, y, sizeof(double) * m);
@@ -766,6 +858,11 @@ static int lp_loop(orc_ctx *s, const double *x_init, const double *y_init, doubl
                         res->rel_primal, res->rel_dual, res->rel_gap);
             if (isnan(res->kkt)) { status = 6; break; }
             if (res->kkt <= s->o.eps) { status = 1; break; }
+            /* rays from the anchor are tested once a restart has set it */
+            if (nr > 0) {
+                status = infeasibility(s, xh, yh, x0, y0, ray_x, ray_y);
+                if (status) break;
+            }
         }
         if (is_last) { status = 4; break; }
         int restart = 0;
@@ -805,6 +902,8 @@ static int lp_loop(orc_ctx *s, const double *x_init, const double *y_init, doubl
         ++t;
     }
     unscale(s, xh, yh, x_out, y_out);
+    if (status == 2) memcpy(y_out, ray_y, sizeof(double) * m);
+    if (status == 3) memcpy(x_out, ray_x, sizeof(double) * n);
     if (tr) orc_kkt(&s->p, x_out, y_out, res);
     res->status = status;
     res->iterations = t + 1;
@@ -815,7 +914,7 @@ static int lp_loop(orc_ctx *s, const double *x_init, const double *y_init, doubl
     res->norm_q = s->norm_q;
     res->power_iters = s->power_iters;
     free(x); free(y); free(x0); free(y0); free(xh); free(yh); free(xn); free(yn);
-    free(xo); free(yo);
+    free(xo); free(yo); free(ray_x); free(ray_y);
     return status;
 }
 

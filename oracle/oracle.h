@@ -51,10 +51,13 @@ typedef struct {
     double power_tol;
     int32_t power_max_iters;
     int32_t verbose;
+    /* certificate tolerances of the infeasibility tests (<= 0: off) */
+    double eps_primal_infeasible, eps_dual_infeasible;
 } orc_options;
 
 typedef struct {
-    int32_t status;             /* 1 optimal, 4 iteration limit, 6 numerical error */
+    int32_t status;             /* 1 optimal, 2 primal infeasible, 3 dual infeasible,
+                                   4 iteration limit, 6 numerical error */
     int64_t iterations, restarts;
     double primal_obj, dual_obj;
     double rel_primal, rel_dual, rel_gap, kkt;
