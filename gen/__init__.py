@@ -21,6 +21,7 @@ from .lp import (  # noqa: F401
     ragged_planted_batch,
     tiny_boxed_lp,
     infeasible_lp,
+    contradict_row,
     portfolio_qp_batch,
     portfolio_instance,
     zipf_pmf,

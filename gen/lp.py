@@ -435,6 +435,22 @@ def infeasible_lp(kind: str, m: int = 60, n: int = 120, seed: int = 0) -> LP:
     raise ValueError(kind)
 
 
+def contradict_row(lp: LP, seed: int = 0) -> LP:
+    """A copy of a sparse LP plus a duplicate of one of its equality rows whose
+    right-hand side is moved by 1: the same matrix shape and structure, no
+    feasible point (works at any size; CSR append)."""
+    rng = np.random.default_rng(seed)
+    eq = np.where(np.isfinite(lp.lc) & (lp.lc == lp.uc) & (np.diff(lp.rowptr) > 0))[0]
+    i = int(eq[rng.integers(len(eq))])
+    a, b = int(lp.rowptr[i]), int(lp.rowptr[i + 1])
+    rowptr = np.append(lp.rowptr, lp.rowptr[-1] + (b - a)).astype(np.int32)
+    colidx = np.concatenate([lp.colidx, lp.colidx[a:b]]).astype(np.int32)
+    val = np.concatenate([lp.val, lp.val[a:b]])
+    return LP(lp.m + 1, lp.n, rowptr, colidx, val, lp.c, np.append(lp.lc, lp.lc[i] + 1.0),
+              np.append(lp.uc, lp.uc[i] + 1.0), lp.lv, lp.uv,
+              meta=dict(lp.meta, kind="contradicted_" + str(lp.meta.get("kind", "lp")), row=i))
+
+
 def tiny_boxed_lp(m: int, n: int, seed: int) -> LP:
     """Tiny dense LP with finite boxes on every variable and mixed row types
     (=, <=, >=, two-sided), feasible by construction."""

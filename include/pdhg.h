@@ -49,8 +49,8 @@ typedef enum {
 typedef enum {
     PDHG_UNSOLVED = 0,
     PDHG_OPTIMAL = 1,            /* relative KKT error <= eps */
-    PDHG_PRIMAL_INFEASIBLE = 2,  /* reserved */
-    PDHG_DUAL_INFEASIBLE = 3,    /* reserved */
+    PDHG_PRIMAL_INFEASIBLE = 2,  /* a dual ray certifies that no x is feasible (LP) */
+    PDHG_DUAL_INFEASIBLE = 3,    /* a primal ray certifies an unbounded objective (LP) */
     PDHG_ITERATION_LIMIT = 4,
     PDHG_TIME_LIMIT = 5,
     PDHG_NUMERICAL_ERROR = 6     /* NaN in the KKT terms */
@@ -108,6 +108,11 @@ typedef struct {
     int32_t use_graph;           /* 1: replay each check period as a HIP graph */
     int32_t timing_chunk;        /* >= 0: time the iteration kernels of that
                                     check period with HIP events (result.kernel_*) */
+    /* Infeasibility certificates (Appendix A: 1e-8 each; <= 0 switches the
+     * test off). Tested at the checks of a sparse LP solve once a restart
+     * has happened: the rays are the PDHG point minus the restart anchor. */
+    double eps_primal_infeasible;
+    double eps_dual_infeasible;
 } pdhg_options;
 
 typedef struct {
@@ -150,7 +155,11 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
  * original space (NULL = zeros, Section 3 "Warm start"); it is scaled and
  * projected onto the bounds. x_out [n], y_out [m]: original-space solution
  * (the last PDHG point for LP, the weighted average for QP), written in every
- * outcome. res may be NULL. All vector pointers are device pointers. */
+ * outcome, except that on PDHG_PRIMAL_INFEASIBLE y_out holds the dual ray
+ * D_r (yhat - y0) scaled to dual objective l_c'y+ - u_c'y- + l_v'lam+ -
+ * u_v'lam- = 1 (lam the bound-cone part of -A'y), and on
+ * PDHG_DUAL_INFEASIBLE x_out holds the primal ray D_c (xhat - x0) scaled to
+ * c'x = -1. res may be NULL. All vector pointers are device pointers. */
 pdhg_err pdhg_solve(pdhg_handle *h, const double *x_init, const double *y_init,
                     double *x_out, double *y_out, pdhg_result *res);
 

@@ -37,7 +37,8 @@ class Options(C.Structure):
                 ("restart_artificial", C.c_double), ("power_tol", C.c_double),
                 ("power_max_iters", C.c_int32), ("verbose", C.c_int32),
                 ("display_frequency", C.c_int32), ("use_graph", C.c_int32),
-                ("timing_chunk", C.c_int32)]
+                ("timing_chunk", C.c_int32), ("eps_primal_infeasible", C.c_double),
+                ("eps_dual_infeasible", C.c_double)]
 
 
 class Result(C.Structure):

@@ -203,10 +203,13 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
     }
     DevState fin;
     PDHG_HIP(hipMemcpy(&fin, h.st.p, sizeof(DevState), hipMemcpyDeviceToHost));
-    if (h.q_kind)
+    if (h.q_kind) {
         launch_qp_finalize(h, x_out, y_out);
-    else
+    } else {
+        if (fin.done && (fin.status == PDHG_PRIMAL_INFEASIBLE || fin.status == PDHG_DUAL_INFEASIBLE))
+            launch_make_ray(h, fin.status);
         launch_finalize(h, x_out, y_out);
+    }
     PDHG_HIP(hipStreamSynchronize(s));
     if (h.opt.verbose) print_check(fin);
     double kp = 0.0, kd = 0.0;
@@ -278,6 +281,8 @@ void pdhg_options_default(pdhg_options *o) {
     o->display_frequency = 10;
     o->use_graph = 1;
     o->timing_chunk = -1;
+    o->eps_primal_infeasible = 1e-8;
+    o->eps_dual_infeasible = 1e-8;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
@@ -345,6 +350,14 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
         }
         h.pn.alloc((size_t)std::max(1, h.nbn) * 6);
         h.pm.alloc((size_t)std::max(1, h.nbm) * 4);
+        if (!h.dense && !h.q_kind) {   // the sparse LP checks also test infeasibility rays
+            h.prn.alloc((size_t)std::max(1, h.nbn) * 4);
+            h.prm.alloc((size_t)std::max(1, h.nbm) * 3);
+            h.q0.alloc((size_t)h.n);
+            h.qhat.alloc((size_t)h.n);
+            h.p0.alloc((size_t)std::max(1, h.m));
+            h.phat.alloc((size_t)std::max(1, h.m));
+        }
         PDHG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h.st_host),
                                sizeof(DevState) * h.st_ring, hipHostMallocDefault));
         memset(h.st_host, 0, sizeof(DevState) * h.st_ring);

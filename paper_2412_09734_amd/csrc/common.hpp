@@ -131,6 +131,9 @@ struct DevState {
     int64_t restarts;
     int64_t t_done;      // iteration index at which the solve stopped
     int32_t done, status, action, first;
+    double ray_scale;      // 1 / |objective| of the certifying ray
+    int32_t anchor_valid;  // products of the restart anchor are stored
+    int32_t pad;
 };
 
 // Constants the controller needs.
@@ -139,7 +142,8 @@ struct CtlConst {
     double beta_suff, beta_nec, beta_art;
     double norm_q;
     int32_t qp;
-    int32_t pad;
+    int32_t detect;        // 1: infeasibility tests (sparse LP)
+    double eps_pinf, eps_dinf;
 };
 
 struct Handle {
@@ -154,6 +158,8 @@ struct Handle {
     DBuf<double> c_o, lc_o, uc_o, lv_o, uv_o;  // original data, internal order
     DBuf<double> x, y, x0, y0, xhat, yhat, xext, aty;
     DBuf<double> pn, pm;                 // per-workgroup partial sums of a check
+    DBuf<double> prn, prm;               // per-workgroup ray sums / maxima of a check
+    DBuf<double> p0, q0, phat, qhat;     // A~x0, A~'y0 of the anchor; A~xhat, A~'yhat
     DBuf<double> scratch;                // reductions of setup / power iteration
     DBuf<DevState> st;
     DevState *st_host = nullptr;         // pinned ring of status copies
@@ -265,6 +271,7 @@ void launch_dual_check(Handle &h, double sigma_override = -1.0);
 void launch_check_sums(Handle &h);
 void launch_controller(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t last_status);
 void launch_apply(Handle &h);
+void launch_make_ray(Handle &h, int32_t status);
 void launch_init_point(Handle &h, const double *x_init, const double *y_init);
 void launch_finalize(Handle &h, double *x_out, double *y_out);
 void launch_reset_state(Handle &h);

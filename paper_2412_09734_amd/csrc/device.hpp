@@ -235,6 +235,53 @@ __device__ __forceinline__ void block_sum_all(double (&v)[K]) {
     __syncthreads();
 }
 
+__device__ __forceinline__ double wave_max(double s) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s = fmax(s, __shfl_xor(s, off));
+    return s;
+}
+
+// Workgroup maxima of K values per thread (order-free), written by threads
+// 0..K-1 to out.
+template <int K>
+__device__ __forceinline__ void block_max_store(const double (&v)[K], double *__restrict__ out) {
+    __shared__ double sh[K][kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double s = wave_max(v[q]);
+        if (lane == 0) sh[q][wave] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        double s = sh[threadIdx.x][0];
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) s = fmax(s, sh[threadIdx.x][w]);
+        out[threadIdx.x] = s;
+    }
+}
+
+// Same, result broadcast to every thread.
+template <int K>
+__device__ __forceinline__ void block_max_all(double (&v)[K]) {
+    __shared__ double sh[K][kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double s = wave_max(v[q]);
+        if (lane == 0) sh[q][wave] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double s = sh[q][0];
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) s = fmax(s, sh[q][w]);
+        v[q] = s;
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ double clampd(double v, double lo, double hi) {
     return fmin(fmax(v, lo), hi);
 }

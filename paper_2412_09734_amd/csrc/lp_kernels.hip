@@ -86,16 +86,22 @@ __global__ __launch_bounds__(kBlock) void k_dual_chk(
 // Column side of a check: q = A~'yhat. Sums (per workgroup):
 //  0 |xhat - x|^2   1 (q - A~'y)'(xhat - x)   2 |xhat - x0|^2
 //  3 |r_d|^2 (original space)   4 c'x (original)   5 l_v'lambda^+ - u_v'lambda^-
+// Rays from the anchor (original space; dx = D_c (xhat - x0), g = -A'dy with
+// A'dy = (q - A~'y0) / D_c), per workgroup into rays[4]: sums of the dual
+// ray's l_v'lam+ - u_v'lam- and of c'dx, maxima of |g - lam| and of the
+// distance of dx to the recession cone of [l_v, u_v]. q is kept in qhat.
 __global__ __launch_bounds__(kBlock) void k_check_n(
     MatView M, const double *__restrict__ yhat, const double *__restrict__ xhat,
     const double *__restrict__ x, const double *__restrict__ x0, const double *__restrict__ aty,
     const double *__restrict__ Dc, const double *__restrict__ c_o, const double *__restrict__ lv_o,
     const double *__restrict__ uv_o, double *__restrict__ partials,
+    const double *__restrict__ q0, double *__restrict__ qhat, double *__restrict__ rays,
     const DevState *__restrict__ st) {
     if (st->done) return;
     const RowSum rs = mat_row_dot(M, yhat);
     const double q = rs.s;
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double rsum[2] = {0.0, 0.0}, rmax[2] = {0.0, 0.0};
     if (rs.valid) {
         const int32_t r = rs.row;
         const double xh = xhat[r];
@@ -114,21 +120,37 @@ __global__ __launch_bounds__(kBlock) void k_check_n(
         v[3] = rd * rd;
         v[4] = c_o[r] * xo;
         v[5] = (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
+        qhat[r] = q;
+        const double gr = -(q - q0[r]) / d;
+        const double lr = (!lf && !uf) ? 0.0 : (lf && !uf) ? fmax(gr, 0.0) : (!lf && uf) ? fmin(gr, 0.0) : gr;
+        rsum[0] = (lf ? lo * fmax(lr, 0.0) : 0.0) - (uf ? hi * fmax(-lr, 0.0) : 0.0);
+        rmax[0] = fabs(gr - lr);
+        const double dxo = d * d0;
+        rsum[1] = c_o[r] * dxo;
+        rmax[1] = fabs(dxo - clampd(dxo, lf ? 0.0 : -INFINITY, uf ? 0.0 : INFINITY));
     }
     block_sum_store<6>(v, partials + (size_t)blockIdx.x * 6);
+    block_sum_store<2>(rsum, rays + (size_t)blockIdx.x * 4);
+    block_max_store<2>(rmax, rays + (size_t)blockIdx.x * 4 + 2);
 }
 
 // Row side of a check: p = A~ xhat. Sums:
 //  0 |r_p|^2 (original)   1 l_c'y^+ - u_c'y^-   2 |yhat - y|^2   3 |yhat - y0|^2
+// Rays from the anchor (dy = D_r (yhat - y0), A dx = (p - A~x0) / D_r), per
+// workgroup into rays[3]: the sum of l_c'yp+ - u_c'yp- for yp = proj_Y(dy),
+// maxima of |dy - yp| and of the distance of A dx to the recession cone of
+// [l_c, u_c]. p is kept in phat.
 __global__ __launch_bounds__(kBlock) void k_check_m(
     MatView M, const double *__restrict__ xhat, const double *__restrict__ yhat,
     const double *__restrict__ y, const double *__restrict__ y0, const double *__restrict__ Dr,
     const double *__restrict__ lc_o, const double *__restrict__ uc_o, double *__restrict__ partials,
+    const double *__restrict__ p0, double *__restrict__ phat, double *__restrict__ rays,
     const DevState *__restrict__ st) {
     if (st->done) return;
     const RowSum rs = mat_row_dot(M, xhat);
     const double p = rs.s;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
+    double rsum[1] = {0.0}, rmax[2] = {0.0, 0.0};
     if (rs.valid) {
         const int32_t r = rs.row;
         const double d = Dr[r];
@@ -143,8 +165,18 @@ __global__ __launch_bounds__(kBlock) void k_check_m(
         v[2] = dy * dy;
         const double d0 = yh - y0[r];
         v[3] = d0 * d0;
+        phat[r] = p;
+        const bool lf = isfinite(lo), uf = isfinite(hi);
+        const double dyo = d * d0;
+        const double yp = clampd(dyo, uf ? -INFINITY : 0.0, lf ? INFINITY : 0.0);
+        rsum[0] = (lf ? lo * fmax(yp, 0.0) : 0.0) - (uf ? hi * fmax(-yp, 0.0) : 0.0);
+        rmax[0] = fabs(dyo - yp);
+        const double ao = (p - p0[r]) / d;
+        rmax[1] = fabs(ao - clampd(ao, lf ? 0.0 : -INFINITY, uf ? 0.0 : INFINITY));
     }
     block_sum_store<4>(v, partials + (size_t)blockIdx.x * 4);
+    block_sum_store<1>(rsum, rays + (size_t)blockIdx.x * 3);
+    block_max_store<2>(rmax, rays + (size_t)blockIdx.x * 3 + 1);
 }
 
 // One workgroup: totals of the check sums in fixed order, relative KKT error,
@@ -152,8 +184,9 @@ __global__ __launch_bounds__(kBlock) void k_check_m(
 // primal-weight update.
 __global__ __launch_bounds__(kBlock) void k_controller(
     DevState *__restrict__ st, const double *__restrict__ pn, int32_t nbn,
-    const double *__restrict__ pm, int32_t nbm, CtlConst K, int32_t chunk_plain,
-    int32_t is_last, int32_t last_status) {
+    const double *__restrict__ pm, int32_t nbm, const double *__restrict__ prn,
+    const double *__restrict__ prm, CtlConst K, int32_t chunk_plain, int32_t is_last,
+    int32_t last_status) {
     if (st->done) return;
     double vn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double vm[4] = {0.0, 0.0, 0.0, 0.0};
@@ -165,6 +198,25 @@ __global__ __launch_bounds__(kBlock) void k_controller(
         for (int q = 0; q < 4; ++q) vm[q] += pm[(size_t)b * 4 + q];
     block_sum_all<6>(vn);
     block_sum_all<4>(vm);
+    // ray totals: 0 dual-ray objective (columns), 1 c'dx, 2 dual-ray objective
+    // (rows); maxima: 0 dual-ray violation, 1 primal-ray violation
+    const bool rays = K.detect && st->anchor_valid;
+    double rs[3] = {0.0, 0.0, 0.0}, rx[2] = {0.0, 0.0};
+    if (rays) {
+        for (int32_t b = threadIdx.x; b < nbn; b += kBlock) {
+            rs[0] += prn[(size_t)b * 4];
+            rs[1] += prn[(size_t)b * 4 + 1];
+            rx[0] = fmax(rx[0], prn[(size_t)b * 4 + 2]);
+            rx[1] = fmax(rx[1], prn[(size_t)b * 4 + 3]);
+        }
+        for (int32_t b = threadIdx.x; b < nbm; b += kBlock) {
+            rs[2] += prm[(size_t)b * 3];
+            rx[0] = fmax(rx[0], prm[(size_t)b * 3 + 1]);
+            rx[1] = fmax(rx[1], prm[(size_t)b * 3 + 2]);
+        }
+        block_sum_all<3>(rs);
+        block_max_all<2>(rx);
+    }
     if (threadIdx.x != 0) return;
 
     const int64_t t = st->t_next;
@@ -204,6 +256,23 @@ __global__ __launch_bounds__(kBlock) void k_controller(
         st->action = 2;
         return;
     }
+    if (rays) {
+        const double obj_d = rs[0] + rs[2], obj_p = rs[1];
+        if (K.eps_pinf > 0.0 && obj_d > 0.0 && rx[0] <= K.eps_pinf * obj_d) {
+            st->done = 1;
+            st->status = PDHG_PRIMAL_INFEASIBLE;
+            st->ray_scale = 1.0 / obj_d;
+            st->action = 2;
+            return;
+        }
+        if (K.eps_dinf > 0.0 && obj_p < 0.0 && rx[1] <= K.eps_dinf * (-obj_p)) {
+            st->done = 1;
+            st->status = PDHG_DUAL_INFEASIBLE;
+            st->ray_scale = -1.0 / obj_p;
+            st->action = 2;
+            return;
+        }
+    }
     if (is_last) {
         st->done = 1;
         st->status = last_status;
@@ -237,6 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_controller(
         st->restarts += 1;
         st->k_base = 0;
         st->action = 1;
+        st->anchor_valid = 1;   // k_apply stores the new anchor's products
     } else {
         st->k_base = k + 1;
         st->action = 0;
@@ -244,10 +314,14 @@ __global__ __launch_bounds__(kBlock) void k_controller(
 }
 
 // Restart (z <- zhat, anchor <- zhat) or Halpern step at the check iteration.
+// With q0 / p0 set, a restart also stores the anchor's products A~'y0, A~x0
+// (the check's qhat, phat) for the infeasibility rays.
 __global__ __launch_bounds__(kBlock) void k_apply(
     const DevState *__restrict__ st, int32_t n, int32_t m, double *__restrict__ x,
     double *__restrict__ x0, const double *__restrict__ xhat, double *__restrict__ y,
-    double *__restrict__ y0, const double *__restrict__ yhat, double gamma) {
+    double *__restrict__ y0, const double *__restrict__ yhat, double gamma,
+    double *__restrict__ q0, const double *__restrict__ qhat, double *__restrict__ p0,
+    const double *__restrict__ phat) {
     if (st->done) return;
     const int32_t act = st->action;
     const int64_t k = st->k_check;
@@ -258,6 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(
         if (act == 1) {
             x[i] = xh;
             x0[i] = xh;
+            if (q0) q0[i] = qhat[i];
         } else {
             x[i] = ak * ((1.0 + gamma) * xh - gamma * x[i]) + bk * x0[i];
         }
@@ -267,6 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(
         if (act == 1) {
             y[r] = yh;
             y0[r] = yh;
+            if (p0) p0[r] = phat[r];
         } else {
             y[r] = ak * ((1.0 + gamma) * yh - gamma * y[r]) + bk * y0[r];
         }
@@ -405,11 +481,12 @@ void launch_check_sums(Handle &h) {
     if (h.AT.nblocks())
         k_check_n<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
             view(h.AT), h.yhat.p, h.xhat.p, h.x.p,
-            h.x0.p, h.aty.p, h.Dc.p, h.c_o.p, h.lv_o.p, h.uv_o.p, h.pn.p, h.st.p);
+            h.x0.p, h.aty.p, h.Dc.p, h.c_o.p, h.lv_o.p, h.uv_o.p, h.pn.p, h.q0.p, h.qhat.p,
+            h.prn.p, h.st.p);
     if (h.A.nblocks())
         k_check_m<<<grid_of(h.A), kBlock, 0, h.stream>>>(
             view(h.A), h.xhat.p, h.yhat.p, h.y.p, h.y0.p,
-            h.Dr.p, h.lc_o.p, h.uc_o.p, h.pm.p, h.st.p);
+            h.Dr.p, h.lc_o.p, h.uc_o.p, h.pm.p, h.p0.p, h.phat.p, h.prm.p, h.st.p);
 }
 
 void launch_controller(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t last_status) {
@@ -422,16 +499,39 @@ void launch_controller(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t 
     K.beta_nec = h.opt.restart_necessary;
     K.beta_art = h.opt.restart_artificial;
     K.qp = 0;
-    K.pad = 0;
-    k_controller<<<1, kBlock, 0, h.stream>>>(h.st.p, h.pn.p, h.nbn, h.pm.p,
-                                              h.nbm, K, chunk_plain, is_last,
-                                              last_status);
+    // the sparse checks produce the ray terms; the dense ones do not
+    K.detect = !h.dense && (h.opt.eps_primal_infeasible > 0.0 || h.opt.eps_dual_infeasible > 0.0);
+    K.eps_pinf = h.opt.eps_primal_infeasible;
+    K.eps_dinf = h.opt.eps_dual_infeasible;
+    k_controller<<<1, kBlock, 0, h.stream>>>(h.st.p, h.pn.p, h.nbn, h.pm.p, h.nbm, h.prn.p,
+                                              h.prm.p, K, chunk_plain, is_last, last_status);
 }
 
 void launch_apply(Handle &h) {
     const int64_t tot = (int64_t)h.n + h.m;
     k_apply<<<(unsigned)ceil_div(tot, kBlock), kBlock, 0, h.stream>>>(
-        h.st.p, h.n, h.m, h.x.p, h.x0.p, h.xhat.p, h.y.p, h.y0.p, h.yhat.p, h.opt.gamma);
+        h.st.p, h.n, h.m, h.x.p, h.x0.p, h.xhat.p, h.y.p, h.y0.p, h.yhat.p, h.opt.gamma,
+        h.q0.p, h.qhat.p, h.p0.p, h.phat.p);
+}
+
+// On an infeasibility certificate the finalised output carries the ray:
+// xhat <- (xhat - x0) s (primal ray) or yhat <- (yhat - y0) s (dual ray),
+// s = st->ray_scale; the finalize then applies D_c / D_r.
+__global__ __launch_bounds__(kBlock) void k_make_ray(const DevState *__restrict__ st, int32_t len,
+                                                     double *__restrict__ v,
+                                                     const double *__restrict__ v0) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) v[i] = (v[i] - v0[i]) * st->ray_scale;
+}
+
+void launch_make_ray(Handle &h, int32_t status) {
+    if (status == PDHG_PRIMAL_INFEASIBLE && h.m > 0)
+        k_make_ray<<<(unsigned)ceil_div(h.m, kBlock), kBlock, 0, h.stream>>>(h.st.p, h.m, h.yhat.p,
+                                                                             h.y0.p);
+    if (status == PDHG_DUAL_INFEASIBLE && h.n > 0)
+        k_make_ray<<<(unsigned)ceil_div(h.n, kBlock), kBlock, 0, h.stream>>>(h.st.p, h.n, h.xhat.p,
+                                                                             h.x0.p);
+    PDHG_HIP(hipGetLastError());
 }
 
 void launch_debug_halpern(Handle &h, int64_t k, double *xnew_int, double *ynew_int) {

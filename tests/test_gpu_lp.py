@@ -247,3 +247,67 @@ def test_step_parity_large_zipf_lp(pdhg, oracle_lib):
     lp = gen.large_zipf_lp(seed=1000)
     _say(f"  generated nnz={lp.nnz}")
     _step_case(pdhg, oracle_lib, lp, seeds=(0,), ks=(7,), compare_eta=False)
+
+
+@pytest.mark.parametrize("kind,m,n,seed", [("duplicate_row", 60, 120, 0), ("boxed_sum", 30, 50, 3),
+                                           ("unbounded", 400, 800, 1), ("duplicate_row", 2000, 4000, 5),
+                                           ("unbounded", 2000, 4000, 6)])
+def test_infeasibility_certificates_match_oracle(pdhg, oracle_lib, kind, m, n, seed):
+    """Status, iteration of the certifying check and the returned ray (dual
+    ray in y for an infeasible LP, primal ray in x for an unbounded one)."""
+    _say(f"case: infeasibility detection, {kind} m={m} n={n} seed={seed}")
+    lp = gen.infeasible_lp(kind, m, n, seed=seed)
+    xo, yo, ro = oracle_lib.Oracle(lp, iteration_limit=100000).solve()
+    with pdhg.Solver.from_lp(lp, iteration_limit=100000) as s:
+        xg, yg, rg = s.solve()
+    _say(f"  status gpu={rg['status_name']} oracle={ro['status_name']} "
+         f"iterations gpu={rg['iterations']} oracle={ro['iterations']}")
+    want = "dual_infeasible" if kind == "unbounded" else "primal_infeasible"
+    assert ro["status_name"] == want and rg["status_name"] == want
+    # the same iterates cross the 1e-8 threshold at the same check
+    assert rg["iterations"] == ro["iterations"]
+    if want == "primal_infeasible":
+        assert rel_inf(to_np(yg), yo) <= 1e-8
+    else:
+        assert rel_inf(to_np(xg), xo) <= 1e-8
+
+
+def test_infeasibility_switches(pdhg):
+    _say("case: infeasibility tests switched off run to the iteration limit")
+    lp = gen.infeasible_lp("duplicate_row", 60, 120, seed=0)
+    with pdhg.Solver.from_lp(lp, iteration_limit=3000, eps_primal_infeasible=0.0) as s:
+        assert s.solve()[2]["status_name"] == "iteration_limit"
+    lp = gen.infeasible_lp("unbounded", 60, 120, seed=0)
+    with pdhg.Solver.from_lp(lp, iteration_limit=3000, eps_dual_infeasible=0.0) as s:
+        assert s.solve()[2]["status_name"] == "iteration_limit"
+
+
+@pytest.mark.timeout(900)
+def test_infeasibility_certificate_full_size(pdhg):
+    """The 1M x 2M Zipf LP with one equality row duplicated at a moved
+    right-hand side: the solve stops with a dual ray, checked here as a
+    Farkas certificate with scipy's sparse products (the oracle cannot
+    finish a solve of this size)."""
+    import scipy.sparse as sp
+    _say("case: infeasibility certificate at full size m=1e6+1 n=2e6 (generation ~30 s)")
+    lp = gen.contradict_row(gen.large_zipf_lp(seed=1000), seed=1)
+    with pdhg.Solver.from_lp(lp, iteration_limit=200000) as s:
+        _, yg, rg = s.solve()
+    _say(f"  status={rg['status_name']} iterations={rg['iterations']}")
+    assert rg["status_name"] == "primal_infeasible"
+    y = to_np(yg)
+    ge = np.isfinite(lp.lc) & ~np.isfinite(lp.uc)
+    le = ~np.isfinite(lp.lc) & np.isfinite(lp.uc)
+    assert np.min(y[ge], initial=0.0) >= -1e-8 and np.max(y[le], initial=0.0) <= 1e-8
+    pos, neg = (y > 0) & np.isfinite(lp.lc), (y < 0) & np.isfinite(lp.uc)
+    b_y = np.dot(lp.lc[pos], y[pos]) + np.dot(lp.uc[neg], y[neg])
+    A = sp.csr_matrix((lp.val, lp.colidx, lp.rowptr), shape=(lp.m, lp.n))
+    g = A.T @ y
+    # Farkas: feasible x have y'Ax >= b(y); over x >= 0 with u_v = 10 on half
+    # the columns, y'Ax = g'x is at most sum of u_v max(g, 0) over the boxed
+    # columns when g <= 0 (up to 1e-8) on the others. The ray is scaled so
+    # that the margin b(y) - that sum is 1.
+    boxed = np.isfinite(lp.uv)
+    assert np.max(g[~boxed], initial=0.0) <= 1e-8
+    margin = b_y - np.sum(lp.uv[boxed] * np.maximum(g[boxed], 0.0))
+    assert abs(margin - 1.0) <= 1e-6, margin
