@@ -101,9 +101,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (counter calibration)")
     ap.add_argument("--workload", default="sparse",
-                    choices=["sparse", "dense", "dense-knapsack", "batch-grid", "batch-ragged",
+                    choices=["sparse", "sparse-infeasible", "dense", "dense-knapsack", "batch-grid",
+                             "batch-ragged",
                              "learn-grid", "spo-grid", "qp-portfolio"],
-                    help="sparse (default, the headline line), dense 20k x 40k, "
+                    help="sparse (default, the headline line); sparse-infeasible: the same LP "
+                         "with one equality row duplicated at a moved right-hand side, solved "
+                         "until its infeasibility certificate; dense 20k x 40k, "
                          "batched grid min-cost flows (2,048 x 32x32 grid) or the ragged batch "
                          "(1,024 planted LPs); the batched modes also time the plain solver "
                          "looped one instance at a time on a subset; learn-grid: training steps "
@@ -155,6 +158,10 @@ def main():
     t = time.perf_counter()
     lp = gen.large_zipf_lp(m=args.m, n=args.n, seed=gen.seed_for(1, 0))
     log(f"bench: nnz={lp.nnz} generated in {time.perf_counter() - t:.1f} s")
+    infeasible = args.workload == "sparse-infeasible"
+    if infeasible:
+        lp = gen.contradict_row(lp, seed=1)
+        log(f"bench: duplicated equality row {lp.meta['row']} with its right-hand side moved by 1")
     dev = torch.device("cuda:0")
     data = dict(rowptr=torch.from_numpy(lp.rowptr).to(dev), colidx=torch.from_numpy(lp.colidx).to(dev),
                 val=torch.from_numpy(lp.val).to(dev), c=torch.from_numpy(lp.c).to(dev),
@@ -209,7 +216,10 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 2), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"plain r2HPDHG, sparse planted LP m={lp.m} n={lp.n} Zipf columns",
+        "config": {"workload": (f"plain r2HPDHG to an infeasibility certificate, sparse LP m={lp.m} "
+                                f"n={lp.n} Zipf columns with one contradicting row" if infeasible else
+                                f"plain r2HPDHG, sparse planted LP m={lp.m} n={lp.n} Zipf columns"),
+                   "status": last["status_name"],
                    "m": lp.m, "n": lp.n, "nnz": int(lp.nnz), "eps": 1e-4,
                    "iterations": iters, "restarts": int(last["restarts"]),
                    "power_iters": int(last["power_iters"]), "kkt_rel": last["kkt_rel"],
