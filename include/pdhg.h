@@ -109,8 +109,9 @@ typedef struct {
     int32_t timing_chunk;        /* >= 0: time the iteration kernels of that
                                     check period with HIP events (result.kernel_*) */
     /* Infeasibility certificates (Appendix A: 1e-8 each; <= 0 switches the
-     * test off). Tested at the checks of a sparse LP solve once a restart
-     * has happened: the rays are the PDHG point minus the restart anchor. */
+     * test off). Tested at the checks of an LP solve (CSR or dense A) once a
+     * restart has happened: the rays are the PDHG point minus the restart
+     * anchor. */
     double eps_primal_infeasible;
     double eps_dual_infeasible;
 } pdhg_options;

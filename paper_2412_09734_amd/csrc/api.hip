@@ -350,7 +350,7 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
         }
         h.pn.alloc((size_t)std::max(1, h.nbn) * 6);
         h.pm.alloc((size_t)std::max(1, h.nbm) * 4);
-        if (!h.dense && !h.q_kind) {   // the sparse LP checks also test infeasibility rays
+        if (!h.q_kind) {   // the LP checks also test infeasibility rays
             h.prn.alloc((size_t)std::max(1, h.nbn) * 4);
             h.prm.alloc((size_t)std::max(1, h.nbm) * 3);
             h.q0.alloc((size_t)h.n);

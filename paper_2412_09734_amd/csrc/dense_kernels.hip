@@ -37,6 +37,9 @@ struct DenseVecs {
     const double *y, *y0, *yhat, *lc, *uc, *Dr, *lc_o, *uc_o;
     double *yw, *yhat_w;
     double *out, *partials;
+    // checks: the anchor's products, this check's products, ray partials
+    const double *p0, *q0;
+    double *phat, *qhat, *rays;
     const DevState *st;
     int32_t j;
     double gamma, tau_o, sigma_o;
@@ -132,6 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
     const bool own = row < m && (WIDE ? threadIdx.x == 0 : lane < R);
     if (MODE == ROW_CHECK_M || MODE == ROW_STORE_SQ) {
         double vals[4] = {0.0, 0.0, 0.0, 0.0};
+        double rsum[1] = {0.0}, rmax[2] = {0.0, 0.0};
         if (own) {
             const int64_t r = row;
             if (MODE == ROW_STORE_SQ) {
@@ -150,6 +154,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
                 vals[2] = dy * dy;
                 const double d0 = yh - d.y0[r];
                 vals[3] = d0 * d0;
+                d.phat[r] = acc_own;
+                ray_row_terms(acc_own, d.p0[r], dr, d0, lo, hi, rsum, rmax);
             }
         }
         if (MODE == ROW_STORE_SQ) {
@@ -157,6 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
             block_sum_store<1>(q, d.partials + blockIdx.x);
         } else {
             block_sum_store<4>(vals, d.partials + (size_t)blockIdx.x * 4);
+            block_sum_store<1>(rsum, d.rays + (size_t)blockIdx.x * 3);
+            block_max_store<2>(rmax, d.rays + (size_t)blockIdx.x * 3 + 1);
         }
         return;
     }
@@ -229,6 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_final(int32_t n, const do
     }
     if (MODE == COL_CHECK_N || MODE == COL_STORE_SQ) {
         double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        double rsum[2] = {0.0, 0.0}, rmax[2] = {0.0, 0.0};
         if (r < n) {
             if (MODE == COL_STORE_SQ) {
                 d.out[r] = s;
@@ -251,6 +260,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_final(int32_t n, const do
                 v[3] = rd * rd;
                 v[4] = d.c_o[r] * xo;
                 v[5] = (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
+                d.qhat[r] = q;
+                ray_col_terms(q, d.q0[r], dd, d0, d.c_o[r], lo, hi, rsum, rmax);
             }
         }
         if (MODE == COL_STORE_SQ) {
@@ -258,6 +269,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_final(int32_t n, const do
             block_sum_store<1>(q1, d.partials + blockIdx.x);
         } else {
             block_sum_store<6>(v, d.partials + (size_t)blockIdx.x * 6);
+            block_sum_store<2>(rsum, d.rays + (size_t)blockIdx.x * 4);
+            block_max_store<2>(rmax, d.rays + (size_t)blockIdx.x * 4 + 2);
         }
         return;
     }
@@ -397,10 +410,16 @@ void dense_check_sums(Handle &h) {
     cols_partial(h, h.yhat.p, h.st.p);
     DenseVecs d = dvecs(h, 0);
     d.partials = h.pn.p;
+    d.q0 = h.q0.p;
+    d.qhat = h.qhat.p;
+    d.rays = h.prn.p;
     k_dense_cols_final<COL_CHECK_N><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, h.dpart.p, d);
     if (h.m > 0) {
         DenseVecs e = dvecs(h, 0);
         e.partials = h.pm.p;
+        e.p0 = h.p0.p;
+        e.phat = h.phat.p;
+        e.rays = h.prm.p;
         launch_rows<ROW_CHECK_M>(h.stream, h.Ad.p, h.m, h.n, h.xhat.p, e);
     }
 }

@@ -286,6 +286,38 @@ __device__ __forceinline__ double clampd(double v, double lo, double hi) {
     return fmin(fmax(v, lo), hi);
 }
 
+// Infeasibility-ray terms of one column j at a check, in the original space:
+// q = (A~'yhat)_j, q0 = (A~'y0)_j, d = D_c[j], dxs = xhat_j - x0_j, c = c_j,
+// [lo, hi] = [l_v, u_v]_j. With g = -(A'dy)_j and lam its part in the cone of
+// the bounds: s[0] = l_v lam+ - u_v lam-, s[1] = c dx; mx[0] = |g - lam|,
+// mx[1] = distance of dx to the recession cone of [l_v, u_v].
+__device__ __forceinline__ void ray_col_terms(double q, double q0, double d, double dxs, double c,
+                                              double lo, double hi, double (&s)[2], double (&mx)[2]) {
+    const bool lf = isfinite(lo), uf = isfinite(hi);
+    const double g = -(q - q0) / d;
+    const double lam = (!lf && !uf) ? 0.0 : (lf && !uf) ? fmax(g, 0.0) : (!lf && uf) ? fmin(g, 0.0) : g;
+    s[0] = (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
+    mx[0] = fabs(g - lam);
+    const double dx = d * dxs;
+    s[1] = c * dx;
+    mx[1] = fabs(dx - clampd(dx, lf ? 0.0 : -INFINITY, uf ? 0.0 : INFINITY));
+}
+
+// Same for row i: p = (A~xhat)_i, p0 = (A~x0)_i, d = D_r[i], dys = yhat_i -
+// y0_i, [lo, hi] = [l_c, u_c]_i. With yp = proj_Y(dy): s[0] = l_c yp+ - u_c yp-;
+// mx[0] = |dy - yp|, mx[1] = distance of (A dx)_i to the recession cone of
+// [l_c, u_c].
+__device__ __forceinline__ void ray_row_terms(double p, double p0, double d, double dys, double lo,
+                                              double hi, double (&s)[1], double (&mx)[2]) {
+    const bool lf = isfinite(lo), uf = isfinite(hi);
+    const double dy = d * dys;
+    const double yp = clampd(dy, uf ? -INFINITY : 0.0, lf ? INFINITY : 0.0);
+    s[0] = (lf ? lo * fmax(yp, 0.0) : 0.0) - (uf ? hi * fmax(-yp, 0.0) : 0.0);
+    mx[0] = fabs(dy - yp);
+    const double a = (p - p0) / d;
+    mx[1] = fabs(a - clampd(a, lf ? 0.0 : -INFINITY, uf ? 0.0 : INFINITY));
+}
+
 // Dual proximal step of eq. (pdhg-lp): v = y/sigma - a,
 // yhat = sigma (v - proj_[-u_c, -l_c](v)); exactly 0 inside, exactly signed outside.
 __device__ __forceinline__ double dual_prox(double y, double a, double sigma, double lc, double uc) {

@@ -121,13 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_check_n(
         v[4] = c_o[r] * xo;
         v[5] = (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
         qhat[r] = q;
-        const double gr = -(q - q0[r]) / d;
-        const double lr = (!lf && !uf) ? 0.0 : (lf && !uf) ? fmax(gr, 0.0) : (!lf && uf) ? fmin(gr, 0.0) : gr;
-        rsum[0] = (lf ? lo * fmax(lr, 0.0) : 0.0) - (uf ? hi * fmax(-lr, 0.0) : 0.0);
-        rmax[0] = fabs(gr - lr);
-        const double dxo = d * d0;
-        rsum[1] = c_o[r] * dxo;
-        rmax[1] = fabs(dxo - clampd(dxo, lf ? 0.0 : -INFINITY, uf ? 0.0 : INFINITY));
+        ray_col_terms(q, q0[r], d, d0, c_o[r], lo, hi, rsum, rmax);
     }
     block_sum_store<6>(v, partials + (size_t)blockIdx.x * 6);
     block_sum_store<2>(rsum, rays + (size_t)blockIdx.x * 4);
@@ -166,13 +160,7 @@ __global__ __launch_bounds__(kBlock) void k_check_m(
         const double d0 = yh - y0[r];
         v[3] = d0 * d0;
         phat[r] = p;
-        const bool lf = isfinite(lo), uf = isfinite(hi);
-        const double dyo = d * d0;
-        const double yp = clampd(dyo, uf ? -INFINITY : 0.0, lf ? INFINITY : 0.0);
-        rsum[0] = (lf ? lo * fmax(yp, 0.0) : 0.0) - (uf ? hi * fmax(-yp, 0.0) : 0.0);
-        rmax[0] = fabs(dyo - yp);
-        const double ao = (p - p0[r]) / d;
-        rmax[1] = fabs(ao - clampd(ao, lf ? 0.0 : -INFINITY, uf ? 0.0 : INFINITY));
+        ray_row_terms(p, p0[r], d, d0, lo, hi, rsum, rmax);
     }
     block_sum_store<4>(v, partials + (size_t)blockIdx.x * 4);
     block_sum_store<1>(rsum, rays + (size_t)blockIdx.x * 3);
@@ -499,8 +487,7 @@ void launch_controller(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t 
     K.beta_nec = h.opt.restart_necessary;
     K.beta_art = h.opt.restart_artificial;
     K.qp = 0;
-    // the sparse checks produce the ray terms; the dense ones do not
-    K.detect = !h.dense && (h.opt.eps_primal_infeasible > 0.0 || h.opt.eps_dual_infeasible > 0.0);
+    K.detect = h.opt.eps_primal_infeasible > 0.0 || h.opt.eps_dual_infeasible > 0.0;
     K.eps_pinf = h.opt.eps_primal_infeasible;
     K.eps_dinf = h.opt.eps_dual_infeasible;
     k_controller<<<1, kBlock, 0, h.stream>>>(h.st.p, h.pn.p, h.nbn, h.pm.p, h.nbm, h.prn.p,
