@@ -50,7 +50,8 @@ class Options(C.Structure):
                 ("restart_necessary", C.c_double), ("restart_artificial", C.c_double),
                 ("power_tol", C.c_double), ("power_max_iters", C.c_int32),
                 ("verbose", C.c_int32), ("eps_primal_infeasible", C.c_double),
-                ("eps_dual_infeasible", C.c_double)]
+                ("eps_dual_infeasible", C.c_double), ("feasibility_polishing", C.c_int32),
+                ("eps_feas_polish", C.c_double)]
 
 
 class Result(C.Structure):
@@ -60,7 +61,8 @@ class Result(C.Structure):
                 ("rel_gap", C.c_double), ("kkt", C.c_double),
                 ("abs_primal", C.c_double), ("abs_dual", C.c_double), ("abs_gap", C.c_double),
                 ("eta", C.c_double), ("omega", C.c_double), ("norm_a", C.c_double),
-                ("norm_q", C.c_double), ("power_iters", C.c_int32)]
+                ("norm_q", C.c_double), ("power_iters", C.c_int32),
+                ("polish_iterations", C.c_int64)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}

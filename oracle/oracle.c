@@ -36,6 +36,7 @@ struct orc_ctx {
     double *c, *lc, *uc, *lv, *uv;   /* scaled data */
     double eta, omega0, norm_a, norm_q;
     int32_t power_iters;
+    int polish;          /* 0 solve; 1 / 2 primal / dual polishing phase */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -83,6 +84,8 @@ void orc_default_options(orc_options *o) {
     o->verbose = 0;
     o->eps_primal_infeasible = 1e-8;   /* Appendix A */
     o->eps_dual_infeasible = 1e-8;
+    o->feasibility_polishing = 0;      /* Appendix A: off, tolerance 1e-6 */
+    o->eps_feas_polish = 1e-6;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -402,6 +405,33 @@ static double power_norm_q(const orc_ctx *s) {
 /* ------------------------------------------------------------------------ */
 /* setup                                                                     */
 
+/* Transformed data of the current original vectors s->p: c~ = D_c c,
+ * l~_c = D_r l_c, l~_v = l_v / D_c, and the initial primal weight
+ * ||c~|| / ||b~|| (b~_i the largest finite |bound| of row i). */
+static void set_vectors(orc_ctx *s) {
+    const orc_problem *p = &s->p;
+    const int32_t m = s->m, n = s->n;
+    for (int32_t j = 0; j < n; ++j) {
+        s->c[j] = s->dc[j] * p->c[j];
+        s->lv[j] = p->lv[j] / s->dc[j];
+        s->uv[j] = p->uv[j] / s->dc[j];
+    }
+    for (int32_t i = 0; i < m; ++i) {
+        s->lc[i] = s->dr[i] * p->lc[i];
+        s->uc[i] = s->dr[i] * p->uc[i];
+    }
+    double *bt = dalloc(m);
+    for (int32_t i = 0; i < m; ++i) {
+        double b = 0.0;
+        if (isfinite(s->lc[i])) b = fmax(b, fabs(s->lc[i]));
+        if (isfinite(s->uc[i])) b = fmax(b, fabs(s->uc[i]));
+        bt[i] = b;
+    }
+    double cn = (double)sqrtl(sumsq(s->c, n)), bn = (double)sqrtl(sumsq(bt, m));
+    s->omega0 = (cn > 1e-10 && bn > 1e-10) ? cn / bn : 1.0;
+    free(bt);
+}
+
 orc_ctx *orc_create(const orc_problem *p, const orc_options *o) {
     if (!validate(p)) return NULL;
     orc_ctx *s = (orc_ctx *)calloc(1, sizeof(orc_ctx));
@@ -419,18 +449,9 @@ orc_ctx *orc_create(const orc_problem *p, const orc_options *o) {
     for (int32_t i = 0; i < m; ++i) s->dr[i] = 1.0;
     for (int32_t j = 0; j < n; ++j) s->dc[j] = 1.0;
     scale(s);
-    /* transformed data: c~ = D_c c, l~_c = D_r l_c, l~_v = l_v / D_c */
     s->c = dalloc(n); s->lv = dalloc(n); s->uv = dalloc(n);
     s->lc = dalloc(m); s->uc = dalloc(m);
-    for (int32_t j = 0; j < n; ++j) {
-        s->c[j] = s->dc[j] * p->c[j];
-        s->lv[j] = p->lv[j] / s->dc[j];
-        s->uv[j] = p->uv[j] / s->dc[j];
-    }
-    for (int32_t i = 0; i < m; ++i) {
-        s->lc[i] = s->dr[i] * p->lc[i];
-        s->uc[i] = s->dr[i] * p->uc[i];
-    }
+    set_vectors(s);
     /* Q~ = D_c Q D_c */
     if (p->q_kind == 1) {
         size_t qn = (size_t)p->q_rowptr[n];
@@ -452,17 +473,6 @@ orc_ctx *orc_create(const orc_problem *p, const orc_options *o) {
     s->norm_a = power_norm_a(s, &s->power_iters);
     s->eta = s->norm_a > 0.0 ? s->o.step_safety / s->norm_a : 1.0;
     s->norm_q = power_norm_q(s);
-    /* initial primal weight: ||c~|| / ||b~||, b~_i = largest finite |bound| */
-    double *bt = dalloc(m);
-    for (int32_t i = 0; i < m; ++i) {
-        double b = 0.0;
-        if (isfinite(s->lc[i])) b = fmax(b, fabs(s->lc[i]));
-        if (isfinite(s->uc[i])) b = fmax(b, fabs(s->uc[i]));
-        bt[i] = b;
-    }
-    double cn = (double)sqrtl(sumsq(s->c, n)), bn = (double)sqrtl(sumsq(bt, m));
-    s->omega0 = (cn > 1e-10 && bn > 1e-10) ? cn / bn : 1.0;
-    free(bt);
     return s;
 }
 
@@ -857,9 +867,11 @@ static int lp_loop(orc_ctx *s, const double *x_init, const double *y_init, doubl
                         (long long)t, (long long)k, (long long)nr, omega, res->kkt,
                         res->rel_primal, res->rel_dual, res->rel_gap);
             if (isnan(res->kkt)) { status = 6; break; }
-            if (res->kkt <= s->o.eps) { status = 1; break; }
+            /* a polishing phase stops on its own residual alone */
+            const double tv = s->polish == 1 ? res->rel_primal : s->polish == 2 ? res->rel_dual : res->kkt;
+            if (tv <= (s->polish ? s->o.eps_feas_polish : s->o.eps)) { status = 1; break; }
             /* rays from the anchor are tested once a restart has set it */
-            if (nr > 0) {
+            if (nr > 0 && !s->polish) {
                 status = infeasibility(s, xh, yh, x0, y0, ray_x, ray_y);
                 if (status) break;
             }
@@ -990,10 +1002,66 @@ static int qp_loop(orc_ctx *s, const double *x_init, const double *y_init, doubl
     return status;
 }
 
+/* Feasibility polishing (Section 3: a post-processing step that solves the
+ * feasibility-only problem from the current point, to eps_feas_polish,
+ * Appendix A). Reading: two phases on the same scaled matrix,
+ *  - primal: the LP with c = 0 from (x, 0) until the relative primal
+ *    residual is <= eps_feas_polish;
+ *  - dual: the LP with every finite bound set to 0 (the problem whose dual
+ *    constraints are those of the LP and whose objective is 0) from (0, y)
+ *    until the relative dual residual is <= eps_feas_polish;
+ * the polished point is (x of the primal phase, y of the dual phase). Both
+ * residuals depend only on A, c and which bounds are finite, so they hold
+ * for the original LP too; its gap is reported as measured. x, y: original
+ * space, in and out; res gets the KKT terms of the polished point. */
+static void polish(orc_ctx *s, double *x, double *y, orc_result *res) {
+    const int32_t m = s->m, n = s->n;
+    const orc_problem saved = s->p;
+    double *zc = dalloc(n), *lc = dalloc(m), *uc = dalloc(m), *lv = dalloc(n), *uv = dalloc(n);
+    double *xp = dalloc(n), *yp = dalloc(m), *xd = dalloc(n), *yd = dalloc(m);
+    for (int32_t i = 0; i < m; ++i) {
+        lc[i] = isfinite(saved.lc[i]) ? 0.0 : saved.lc[i];
+        uc[i] = isfinite(saved.uc[i]) ? 0.0 : saved.uc[i];
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        lv[j] = isfinite(saved.lv[j]) ? 0.0 : saved.lv[j];
+        uv[j] = isfinite(saved.uv[j]) ? 0.0 : saved.uv[j];
+    }
+    orc_result r1, r2;
+    s->p.c = zc;
+    set_vectors(s);
+    s->polish = 1;
+    lp_loop(s, x, NULL, xp, yp, &r1, NULL);
+    s->p = saved;
+    s->p.lc = lc; s->p.uc = uc; s->p.lv = lv; s->p.uv = uv;
+    set_vectors(s);
+    s->polish = 2;
+    lp_loop(s, NULL, y, xd, yd, &r2, NULL);
+    s->p = saved;
+    set_vectors(s);
+    s->polish = 0;
+    memcpy(x, xp, sizeof(double) * n);
+    memcpy(y, yd, sizeof(double) * m);
+    const orc_result before = *res;
+    orc_kkt(&s->p, x, y, res);
+    res->status = before.status;
+    res->iterations = before.iterations + r1.iterations + r2.iterations;
+    res->restarts = before.restarts;
+    res->eta = before.eta;
+    res->omega = before.omega;
+    res->norm_a = before.norm_a;
+    res->norm_q = before.norm_q;
+    res->power_iters = before.power_iters;
+    res->polish_iterations = r1.iterations + r2.iterations;
+    free(zc); free(lc); free(uc); free(lv); free(uv); free(xp); free(yp); free(xd); free(yd);
+}
+
 int orc_solve(orc_ctx *s, const double *x_init, const double *y_init, double *x_out,
               double *y_out, orc_result *res) {
-    if (s->p.q_kind == 0) return lp_loop(s, x_init, y_init, x_out, y_out, res, NULL);
-    return qp_loop(s, x_init, y_init, x_out, y_out, res);
+    if (s->p.q_kind != 0) return qp_loop(s, x_init, y_init, x_out, y_out, res);
+    int st = lp_loop(s, x_init, y_init, x_out, y_out, res, NULL);
+    if (st == 1 && s->o.feasibility_polishing) polish(s, x_out, y_out, res);
+    return st;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -53,6 +53,9 @@ typedef struct {
     int32_t verbose;
     /* certificate tolerances of the infeasibility tests (<= 0: off) */
     double eps_primal_infeasible, eps_dual_infeasible;
+    /* 1: polish the point of an optimal LP solve to eps_feas_polish */
+    int32_t feasibility_polishing;
+    double eps_feas_polish;
 } orc_options;
 
 typedef struct {
@@ -64,6 +67,7 @@ typedef struct {
     double abs_primal, abs_dual, abs_gap;  /* ||r_p||, ||r_d||, |P - D| */
     double eta, omega, norm_a, norm_q;
     int32_t power_iters;
+    int64_t polish_iterations;  /* iterations of the two polishing phases */
 } orc_result;
 
 typedef struct orc_ctx orc_ctx;
