@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iteration-limit", type=int, default=0,
                     help="stop every solve after this many iterations (profiling runs only)")
+    ap.add_argument("--polish", action="store_true",
+                    help="sparse workloads: feasibility polishing after the optimal solve")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device-to-device copy three times (counter calibration)")
     ap.add_argument("--workload", default="sparse",
@@ -170,6 +172,8 @@ def main():
     torch.cuda.synchronize()
 
     extra = {"iteration_limit": args.iteration_limit} if args.iteration_limit > 0 else {}
+    if args.polish:
+        extra["feasibility_polishing"] = 1
 
     def step(timing_chunk=-1):
         with Solver(lp.m, lp.n, device=dev, timing_chunk=timing_chunk, **extra, **data) as s:
@@ -220,6 +224,10 @@ def main():
                                 f"n={lp.n} Zipf columns with one contradicting row" if infeasible else
                                 f"plain r2HPDHG, sparse planted LP m={lp.m} n={lp.n} Zipf columns"),
                    "status": last["status_name"],
+                   "feasibility_polishing": bool(args.polish),
+                   "polish_iterations": int(last["polish_iterations"]),
+                   "rel_primal": last["rel_primal_res"], "rel_dual": last["rel_dual_res"],
+                   "rel_gap": last["rel_gap"],
                    "m": lp.m, "n": lp.n, "nnz": int(lp.nnz), "eps": 1e-4,
                    "iterations": iters, "restarts": int(last["restarts"]),
                    "power_iters": int(last["power_iters"]), "kkt_rel": last["kkt_rel"],

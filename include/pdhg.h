@@ -114,6 +114,13 @@ typedef struct {
      * anchor. */
     double eps_primal_infeasible;
     double eps_dual_infeasible;
+    /* Feasibility polishing (Section 3; Appendix A: off, 1e-6): after an
+     * optimal LP solve, a primal phase (c = 0, from x) and a dual phase (the
+     * finite bounds set to 0, from y) run to relative primal / dual
+     * residuals <= eps_feas_polish; the solve returns x of the first and y
+     * of the second, with the KKT terms of that point. */
+    int32_t feasibility_polishing;
+    double eps_feas_polish;
 } pdhg_options;
 
 typedef struct {
@@ -130,6 +137,7 @@ typedef struct {
     int32_t kernel_samples;      /* number of timed plain iterations */
     double kernel_primal_ms;     /* average primal-step kernel duration */
     double kernel_dual_ms;       /* average dual-step kernel duration */
+    int64_t polish_iterations;   /* iterations of the polishing phases (in iterations too) */
 } pdhg_result;
 
 typedef struct pdhg_handle pdhg_handle;

@@ -38,7 +38,8 @@ class Options(C.Structure):
                 ("power_max_iters", C.c_int32), ("verbose", C.c_int32),
                 ("display_frequency", C.c_int32), ("use_graph", C.c_int32),
                 ("timing_chunk", C.c_int32), ("eps_primal_infeasible", C.c_double),
-                ("eps_dual_infeasible", C.c_double)]
+                ("eps_dual_infeasible", C.c_double), ("feasibility_polishing", C.c_int32),
+                ("eps_feas_polish", C.c_double)]
 
 
 class Result(C.Structure):
@@ -50,7 +51,7 @@ class Result(C.Structure):
                 ("eta", C.c_double), ("omega", C.c_double), ("norm_a", C.c_double),
                 ("norm_q", C.c_double), ("power_iters", C.c_int32),
                 ("kernel_samples", C.c_int32), ("kernel_primal_ms", C.c_double),
-                ("kernel_dual_ms", C.c_double)]
+                ("kernel_dual_ms", C.c_double), ("polish_iterations", C.c_int64)]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}

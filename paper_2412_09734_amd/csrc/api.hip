@@ -119,7 +119,9 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
     if (h.q_kind) launch_qp_init(h);
     const int32_t C = h.opt.check_every;
     const int64_t L = h.opt.iteration_limit;
-    if (h.opt.use_graph) build_graph(h);
+    // graphs hold the solve's controller constants: polishing phases run unrolled
+    const bool graphs = h.opt.use_graph && !h.polish;
+    if (graphs) build_graph(h);
 
     std::vector<hipEvent_t> tev;
     int64_t timing_t = -1;
@@ -147,7 +149,7 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
                 plain = std::min<int64_t>(C - 1, L - 2 - t);
                 const bool timed = h.opt.timing_chunk >= 0 && chunk == h.opt.timing_chunk &&
                                    plain == C - 1 && tev.empty() && !h.q_kind;
-                if (plain == C - 1 && h.opt.use_graph && !timed) {
+                if (plain == C - 1 && graphs && !timed) {
                     PDHG_HIP(hipGraphLaunch(h.chunk_exec, s));
                 } else {
                     enqueue_check(h, (int32_t)plain, 0, 0);
@@ -283,6 +285,8 @@ void pdhg_options_default(pdhg_options *o) {
     o->timing_chunk = -1;
     o->eps_primal_infeasible = 1e-8;
     o->eps_dual_infeasible = 1e-8;
+    o->feasibility_polishing = 0;
+    o->eps_feas_polish = 1e-6;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
@@ -369,12 +373,97 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
     return rc;
 }
 
+// Feasibility polishing of an optimal LP point (x_out, y_out; original space,
+// device): the primal phase solves the LP with c = 0 from x, the dual phase
+// the LP with its finite bounds set to 0 from y, each to its own residual
+// <= eps_feas_polish; the handle's data is restored after. res receives the
+// KKT terms of the polished point for the original LP.
+static void polish(Handle &h, double *x_out, double *y_out, pdhg_result *res) {
+    hipStream_t s = h.stream;
+    const int32_t m = h.m, n = h.n;
+    const size_t bn = sizeof(double) * n, bm = sizeof(double) * m;
+    DBuf<double> sc, slc, suc, slv, suv, xs, ys, xt, yt;
+    for (auto *b : {&sc, &slv, &suv, &xs, &xt}) b->alloc(n);
+    for (auto *b : {&slc, &suc, &ys, &yt}) b->alloc(std::max(1, m));
+    PDHG_HIP(hipMemcpyAsync(sc.p, h.c_o.p, bn, hipMemcpyDeviceToDevice, s));
+    PDHG_HIP(hipMemcpyAsync(slv.p, h.lv_o.p, bn, hipMemcpyDeviceToDevice, s));
+    PDHG_HIP(hipMemcpyAsync(suv.p, h.uv_o.p, bn, hipMemcpyDeviceToDevice, s));
+    PDHG_HIP(hipMemcpyAsync(xs.p, x_out, bn, hipMemcpyDeviceToDevice, s));
+    if (m > 0) {
+        PDHG_HIP(hipMemcpyAsync(slc.p, h.lc_o.p, bm, hipMemcpyDeviceToDevice, s));
+        PDHG_HIP(hipMemcpyAsync(suc.p, h.uc_o.p, bm, hipMemcpyDeviceToDevice, s));
+        PDHG_HIP(hipMemcpyAsync(ys.p, y_out, bm, hipMemcpyDeviceToDevice, s));
+    }
+    auto restore = [&] {
+        h.polish = 0;
+        PDHG_HIP(hipMemcpyAsync(h.c_o.p, sc.p, bn, hipMemcpyDeviceToDevice, s));
+        PDHG_HIP(hipMemcpyAsync(h.lv_o.p, slv.p, bn, hipMemcpyDeviceToDevice, s));
+        PDHG_HIP(hipMemcpyAsync(h.uv_o.p, suv.p, bn, hipMemcpyDeviceToDevice, s));
+        if (m > 0) {
+            PDHG_HIP(hipMemcpyAsync(h.lc_o.p, slc.p, bm, hipMemcpyDeviceToDevice, s));
+            PDHG_HIP(hipMemcpyAsync(h.uc_o.p, suc.p, bm, hipMemcpyDeviceToDevice, s));
+        }
+        transform_vectors(h);
+        compute_weight(h);
+    };
+    pdhg_result r1, r2;
+    try {
+        // primal phase: c = 0
+        PDHG_HIP(hipMemsetAsync(h.c_o.p, 0, bn, s));
+        transform_vectors(h);
+        compute_weight(h);
+        h.polish = 1;
+        run_solve(h, xs.p, nullptr, x_out, yt.p, &r1);
+        // dual phase: c restored, finite bounds 0
+        PDHG_HIP(hipMemcpyAsync(h.c_o.p, sc.p, bn, hipMemcpyDeviceToDevice, s));
+        launch_zero_finite(h, h.lv_o.p, n);
+        launch_zero_finite(h, h.uv_o.p, n);
+        launch_zero_finite(h, h.lc_o.p, m);
+        launch_zero_finite(h, h.uc_o.p, m);
+        transform_vectors(h);
+        compute_weight(h);
+        h.polish = 2;
+        run_solve(h, nullptr, m > 0 ? ys.p : nullptr, xt.p, y_out, &r2);
+    } catch (...) {
+        try {
+            restore();
+        } catch (...) {
+        }
+        throw;
+    }
+    // the original data back, and the KKT terms of (x_out, y_out) from one check
+    restore();
+    launch_reset_state(h);
+    launch_init_point(h, x_out, m > 0 ? y_out : nullptr);
+    PDHG_HIP(hipMemcpyAsync(h.xhat.p, h.x.p, bn, hipMemcpyDeviceToDevice, s));
+    if (m > 0) PDHG_HIP(hipMemcpyAsync(h.yhat.p, h.y.p, bm, hipMemcpyDeviceToDevice, s));
+    launch_check_sums(h);
+    launch_controller(h, 0, 1, PDHG_OPTIMAL);
+    DevState ev;
+    PDHG_HIP(hipMemcpyAsync(&ev, h.st.p, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    PDHG_HIP(hipStreamSynchronize(s));
+    res->iterations += r1.iterations + r2.iterations;
+    res->polish_iterations = r1.iterations + r2.iterations;
+    res->primal_obj = ev.pobj;
+    res->dual_obj = ev.dobj;
+    res->rel_primal_res = ev.rel_p;
+    res->rel_dual_res = ev.rel_d;
+    res->rel_gap = ev.rel_g;
+    res->kkt_rel = ev.kkt;
+    res->solve_seconds += r1.solve_seconds + r2.solve_seconds;
+}
+
 pdhg_err pdhg_solve(pdhg_handle *ph, const double *x_init, const double *y_init, double *x_out,
                     double *y_out, pdhg_result *res) {
     return guarded([&] {
         if (!ph || !x_out || (ph->h.m > 0 && !y_out))
             fail(PDHG_ERR_INVALID_ARG, "NULL handle or output pointer");
-        run_solve(ph->h, x_init, y_init, x_out, y_out, res);
+        Handle &h = ph->h;
+        pdhg_result local;
+        pdhg_result *r = res ? res : &local;
+        run_solve(h, x_init, y_init, x_out, y_out, r);
+        if (h.opt.feasibility_polishing && !h.q_kind && r->status == PDHG_OPTIMAL)
+            polish(h, x_out, y_out, r);
     });
 }
 

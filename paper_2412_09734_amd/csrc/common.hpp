@@ -142,8 +142,10 @@ struct CtlConst {
     double beta_suff, beta_nec, beta_art;
     double norm_q;
     int32_t qp;
-    int32_t detect;        // 1: infeasibility tests (sparse LP)
+    int32_t detect;        // 1: infeasibility tests (LP)
     double eps_pinf, eps_dinf;
+    int32_t term;          // stop on: 0 the KKT error, 1 the primal residual, 2 the dual residual
+    int32_t pad;
 };
 
 struct Handle {
@@ -168,6 +170,7 @@ struct Handle {
     double cnorm = 0.0, bnorm = 0.0;
     int32_t power_iters = 0;
     double setup_seconds = 0.0;
+    int32_t polish = 0;                  // 0 solve; 1 / 2 primal / dual polishing phase
     hipGraphExec_t chunk_exec = nullptr;
     hipGraph_t chunk_graph = nullptr;
     // quadratic term Q~ = D_c Q D_c (rAPDHG), internal order
@@ -272,6 +275,7 @@ void launch_check_sums(Handle &h);
 void launch_controller(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t last_status);
 void launch_apply(Handle &h);
 void launch_make_ray(Handle &h, int32_t status);
+void launch_zero_finite(Handle &h, double *v, int32_t len);
 void launch_init_point(Handle &h, const double *x_init, const double *y_init);
 void launch_finalize(Handle &h, double *x_out, double *y_out);
 void launch_reset_state(Handle &h);

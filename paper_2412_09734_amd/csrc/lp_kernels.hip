@@ -238,7 +238,9 @@ __global__ __launch_bounds__(kBlock) void k_controller(
         st->action = 2;
         return;
     }
-    if (kkt <= K.eps) {
+    // a polishing phase stops on its own residual alone
+    const double term_val = K.term == 1 ? rel_p : K.term == 2 ? rel_d : kkt;
+    if (term_val <= K.eps) {
         st->done = 1;
         st->status = PDHG_OPTIMAL;
         st->action = 2;
@@ -479,7 +481,7 @@ void launch_check_sums(Handle &h) {
 
 void launch_controller(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t last_status) {
     CtlConst K;
-    K.eps = h.opt.eps;
+    K.eps = h.polish ? h.opt.eps_feas_polish : h.opt.eps;
     K.bnorm = h.bnorm;
     K.cnorm = h.cnorm;
     K.eta = h.eta;
@@ -487,9 +489,11 @@ void launch_controller(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t 
     K.beta_nec = h.opt.restart_necessary;
     K.beta_art = h.opt.restart_artificial;
     K.qp = 0;
-    K.detect = h.opt.eps_primal_infeasible > 0.0 || h.opt.eps_dual_infeasible > 0.0;
+    K.detect = !h.polish && (h.opt.eps_primal_infeasible > 0.0 || h.opt.eps_dual_infeasible > 0.0);
     K.eps_pinf = h.opt.eps_primal_infeasible;
     K.eps_dinf = h.opt.eps_dual_infeasible;
+    K.term = h.polish;
+    K.pad = 0;
     k_controller<<<1, kBlock, 0, h.stream>>>(h.st.p, h.pn.p, h.nbn, h.pm.p, h.nbm, h.prn.p,
                                               h.prm.p, K, chunk_plain, is_last, last_status);
 }
@@ -509,6 +513,18 @@ __global__ __launch_bounds__(kBlock) void k_make_ray(const DevState *__restrict_
                                                      const double *__restrict__ v0) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < len) v[i] = (v[i] - v0[i]) * st->ray_scale;
+}
+
+// Finite entries of a bound vector set to 0 (the dual polishing problem).
+__global__ __launch_bounds__(kBlock) void k_zero_finite(int32_t len, double *__restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len && isfinite(v[i])) v[i] = 0.0;
+}
+
+void launch_zero_finite(Handle &h, double *v, int32_t len) {
+    if (len <= 0) return;
+    k_zero_finite<<<(unsigned)ceil_div(len, kBlock), kBlock, 0, h.stream>>>(len, v);
+    PDHG_HIP(hipGetLastError());
 }
 
 void launch_make_ray(Handle &h, int32_t status) {

@@ -490,6 +490,8 @@ void launch_qp_check(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t la
     K.qp = 1;
     K.detect = 0;
     K.eps_pinf = K.eps_dinf = 0.0;
+    K.term = 0;
+    K.pad = 0;
     k_qp_controller<<<1, kBlock, 0, s>>>(h.st.p, h.pn.p, h.nbn, h.pm.p, h.nbm, K,
                                          chunk_plain, is_last, last_status);
     k_qp_apply<<<nblk((int64_t)h.n + h.m), kBlock, 0, s>>>(h.st.p, h.n, h.m, h.x.p, h.x0.p,

@@ -311,3 +311,37 @@ def test_infeasibility_certificate_full_size(pdhg):
     assert np.max(g[~boxed], initial=0.0) <= 1e-8
     margin = b_y - np.sum(lp.uv[boxed] * np.maximum(g[boxed], 0.0))
     assert abs(margin - 1.0) <= 1e-6, margin
+
+
+@pytest.mark.parametrize("name", ["planted", "boxed", "grid", "dense"])
+def test_feasibility_polishing_matches_oracle(pdhg, oracle_lib, name):
+    """Polishing after an optimal solve: the same phase lengths as the oracle,
+    the same polished point, and its reported KKT terms are those of the
+    returned point."""
+    _say(f"case: feasibility polishing parity, {name}")
+    if name == "planted":
+        lp = gen.planted_sparse_lp(200, 400, seed=11)
+    elif name == "boxed":
+        lp = gen.tiny_boxed_lp(12, 20, seed=13)
+    elif name == "grid":
+        lp = gen.grid_mincost_batch(batch=1, rows=6, cols=6, seed=14).instance(0)
+    else:
+        lp = gen.dense_planted_lp(150, 300, seed=2001)
+    xo, yo, ro = oracle_lib.Oracle(lp, feasibility_polishing=1).solve()
+    with pdhg.Solver.from_lp(lp, feasibility_polishing=1) as s:
+        xg, yg, rg = s.solve()
+    _say(f"  polish iterations gpu={rg['polish_iterations']} oracle={ro['polish_iterations']} "
+         f"rel_p={rg['rel_primal_res']:.2e} rel_d={rg['rel_dual_res']:.2e} gap={rg['rel_gap']:.2e}")
+    assert rg["status_name"] == "optimal" and ro["status_name"] == "optimal"
+    assert rg["polish_iterations"] == ro["polish_iterations"] > 0
+    assert rg["iterations"] == ro["iterations"]
+    assert rg["rel_primal_res"] <= 1e-6 and rg["rel_dual_res"] <= 1e-6
+    assert rel_inf(to_np(xg), xo) <= 1e-8
+    assert rel_inf(to_np(yg), yo) <= 1e-8
+    kg = oracle_lib.kkt(lp, to_np(xg), to_np(yg))
+    for a, b in (("rel_primal_res", "rel_primal"), ("rel_dual_res", "rel_dual"), ("rel_gap", "rel_gap")):
+        assert abs(rg[a] - kg[b]) <= 1e-12 + 1e-6 * kg[b], (a, rg[a], kg[b])
+    # the handle's data is restored: a second solve without polishing is the plain one
+    with pdhg.Solver.from_lp(lp) as s:
+        _, _, r_plain = s.solve()
+    assert r_plain["iterations"] == rg["iterations"] - rg["polish_iterations"]
