@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iteration-limit", type=int, default=0,
                     help="stop every solve after this many iterations (profiling runs only)")
+    ap.add_argument("--eps", type=float, default=1e-4,
+                    help="sparse workloads: relative KKT tolerance of the solve (default 1e-4)")
     ap.add_argument("--polish", action="store_true",
                     help="sparse workloads: feasibility polishing after the optimal solve")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -174,6 +176,8 @@ def main():
     extra = {"iteration_limit": args.iteration_limit} if args.iteration_limit > 0 else {}
     if args.polish:
         extra["feasibility_polishing"] = 1
+    if args.eps != 1e-4:
+        extra["eps"] = args.eps
 
     def step(timing_chunk=-1):
         with Solver(lp.m, lp.n, device=dev, timing_chunk=timing_chunk, **extra, **data) as s:
@@ -228,7 +232,7 @@ def main():
                    "polish_iterations": int(last["polish_iterations"]),
                    "rel_primal": last["rel_primal_res"], "rel_dual": last["rel_dual_res"],
                    "rel_gap": last["rel_gap"],
-                   "m": lp.m, "n": lp.n, "nnz": int(lp.nnz), "eps": 1e-4,
+                   "m": lp.m, "n": lp.n, "nnz": int(lp.nnz), "eps": args.eps,
                    "iterations": iters, "restarts": int(last["restarts"]),
                    "power_iters": int(last["power_iters"]), "kkt_rel": last["kkt_rel"],
                    "primal_obj": last["primal_obj"], "planted_obj": lp.v_star,

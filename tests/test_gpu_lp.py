@@ -345,3 +345,33 @@ def test_feasibility_polishing_matches_oracle(pdhg, oracle_lib, name):
     with pdhg.Solver.from_lp(lp) as s:
         _, _, r_plain = s.solve()
     assert r_plain["iterations"] == rg["iterations"] - rg["polish_iterations"]
+
+
+@pytest.mark.timeout(900)
+def test_feasibility_polishing_full_size(pdhg):
+    """The 1M x 2M Zipf LP solved to 1e-3 and polished: the returned point's
+    relative primal and dual residuals, computed here with scipy from the LP's
+    data, are <= 1e-6 and equal the reported ones."""
+    import scipy.sparse as sp
+    _say("case: feasibility polishing at full size m=1e6 n=2e6, eps 1e-3")
+    lp = gen.large_zipf_lp(seed=1000)
+    with pdhg.Solver.from_lp(lp, eps=1e-3, feasibility_polishing=1) as s:
+        xg, yg, rg = s.solve()
+    _say(f"  iterations={rg['iterations']} polish={rg['polish_iterations']} rel_p={rg['rel_primal_res']:.2e} "
+         f"rel_d={rg['rel_dual_res']:.2e} gap={rg['rel_gap']:.2e}")
+    assert rg["status_name"] == "optimal"
+    x, y = to_np(xg), to_np(yg)
+    A = sp.csr_matrix((lp.val, lp.colidx, lp.rowptr), shape=(lp.m, lp.n))
+    ax = A @ x
+    rp = ax - np.clip(ax, lp.lc, lp.uc)
+    b = np.maximum(np.where(np.isfinite(lp.lc), np.abs(lp.lc), 0.0), np.where(np.isfinite(lp.uc), np.abs(lp.uc), 0.0))
+    rel_p = np.linalg.norm(rp) / (1 + np.linalg.norm(b))
+    # x = D_c xhat with xhat in [l_v, u_v] / D_c: within an ulp of the box
+    assert np.all(x >= lp.lv - 1e-12 * (1 + np.abs(lp.lv))) and np.all(x <= lp.uv + 1e-12 * (1 + np.abs(lp.uv)))
+    g = lp.c - A.T @ y
+    lo_f, up_f = np.isfinite(lp.lv), np.isfinite(lp.uv)
+    allowed = np.where(lo_f & up_f, g, np.where(lo_f, np.maximum(g, 0), np.where(up_f, np.minimum(g, 0), 0)))
+    rel_d = np.linalg.norm(g - allowed) / (1 + np.linalg.norm(lp.c))
+    assert rel_p <= 1e-6 * (1 + 1e-9) and rel_d <= 1e-6 * (1 + 1e-9), (rel_p, rel_d)
+    assert abs(rel_p - rg["rel_primal_res"]) <= 1e-9 + 1e-6 * rel_p
+    assert abs(rel_d - rg["rel_dual_res"]) <= 1e-9 + 1e-6 * rel_d
