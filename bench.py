@@ -100,6 +100,8 @@ def main():
                     help="stop every solve after this many iterations (profiling runs only)")
     ap.add_argument("--eps", type=float, default=1e-4,
                     help="sparse workloads: relative KKT tolerance of the solve (default 1e-4)")
+    ap.add_argument("--no-infeasibility-tests", action="store_true",
+                    help="batched workloads: switch the infeasibility certificate tests off")
     ap.add_argument("--polish", action="store_true",
                     help="sparse workloads: feasibility polishing after the optimal solve")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -286,6 +288,8 @@ def bench_batch(args):
         inst = lps[: min(args.loop_sample, B)]
         name = f"batched r2HPDHG, {B} planted LPs m~U{{50..500}}, n=2m, 5% density"
     torch.cuda.synchronize()
+    if args.no_infeasibility_tests:
+        kw = dict(kw, eps_primal_infeasible=0.0, eps_dual_infeasible=0.0)
     make = lambda: BatchSolver(**kw)  # noqa: E731
     with make() as bs:
         best = bs.autotune(128)

@@ -25,6 +25,8 @@ struct BOpts {
     double eps, gamma, step_safety, beta_suff, beta_nec, beta_art, power_tol;
     int64_t limit;
     int32_t check_every, ruiz_iters, pock_chambolle, power_max_iters;
+    double eps_pinf, eps_dinf;   // infeasibility certificate tolerances
+    int32_t detect, pad;         // 1: test the rays at checks
 };
 
 struct BArgs {
@@ -47,6 +49,9 @@ struct BArgs {
     const int32_t *asp, *asci, *asfirst, *tsp, *tsci, *tsfirst;
     const double *asva, *tsva;
     double *lhist;    // Lanczos alpha / beta per instance, stride 2 (power_max_iters + 1)
+    // infeasibility rays: the anchor's products A~x0 (like y), A~'y0 (like x)
+    // and this check's A~xhat, A~'yhat
+    double *p0, *q0, *ph, *qh;
 };
 
 // Geometry of instance b: matrix rows start at r0 (A) / c0 (A'); vectors at
@@ -100,6 +105,30 @@ __device__ __forceinline__ void wg_sum(double (&v)[K]) {
     if ((int)threadIdx.x < K) {
         double s = 0.0;
         for (int w = 0; w < NW; ++w) s += sh[threadIdx.x][w];
+        tot[threadIdx.x] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = tot[q];
+    __syncthreads();
+}
+
+// Workgroup maxima of K values (order-free), result in every thread.
+template <int BT, int K>
+__device__ __forceinline__ void wg_max(double (&v)[K]) {
+    constexpr int NW = BT / 64;
+    __shared__ double sh[K][NW];
+    __shared__ double tot[K];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double s = wave_max(v[q]);
+        if (lane == 0) sh[q][wave] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < K) {
+        double s = sh[threadIdx.x][0];
+        for (int w = 1; w < NW; ++w) s = fmax(s, sh[threadIdx.x][w]);
         tot[threadIdx.x] = s;
     }
     __syncthreads();
@@ -421,7 +450,53 @@ __global__ __launch_bounds__(BT) void k_batch_setup(BArgs a, BOpts o, int32_t co
 // ---------------------------------------------------------------------------
 // solve
 
+// Infeasibility rays of instance g at a check (after its products were kept
+// in qh / ph): sums rs = (dual-ray bound terms over the columns, c'dx,
+// dual-ray bound terms over the rows) and maxima rm = (dual-ray violation,
+// primal-ray violation), every thread receiving the totals. A pass of its
+// own: folded into the check loop its accumulators would stay live beside
+// the KKT sums. x0 is read from memory (on-chip kernels keep it written
+// through at restarts).
 template <int BT>
+__device__ __forceinline__ void batch_ray_pass(const BArgs &a, const BOpts &o, const Geo &g,
+                                            const double *__restrict__ xh, const double *__restrict__ yh,
+                                            const double *__restrict__ y0, double (&rs)[3], double (&rm)[2]) {
+    const double *Dr = a.Dr + g.dr, *Dc = a.Dc + g.dc;
+    const double *x0 = a.x0 + g.vc;
+    double s[3] = {0.0, 0.0, 0.0}, mx[2] = {0.0, 0.0};
+    // opaque thread index: the addresses below are formed here, not kept
+    // live across the iteration loop the pass sits in
+    int32_t t0 = (int32_t)threadIdx.x;
+    asm volatile("" : "+v"(t0));
+#pragma unroll 1
+    for (int32_t j = t0; j < g.n; j += BT) {
+        double s2[2], m2[2];
+        ray_col_terms(a.qh[g.vc + j], a.q0[g.vc + j], Dc[j], xh[j] - x0[j], a.c_o[g.vc + j],
+                      a.lv_o[g.vc + j], a.uv_o[g.vc + j], s2, m2);
+        s[0] += s2[0];
+        s[1] += s2[1];
+        mx[0] = fmax(mx[0], m2[0]);
+        mx[1] = fmax(mx[1], m2[1]);
+    }
+#pragma unroll 1
+    for (int32_t i = t0; i < g.m; i += BT) {
+        double s1[1], m2[2];
+        ray_row_terms(a.ph[g.vr + i], a.p0[g.vr + i], Dr[i], yh[i] - y0[i], a.lc_o[g.vr + i],
+                      a.uc_o[g.vr + i], s1, m2);
+        s[2] += s1[0];
+        mx[0] = fmax(mx[0], m2[0]);
+        mx[1] = fmax(mx[1], m2[1]);
+    }
+    wg_sum<BT, 3>(s);
+    wg_max<BT, 2>(mx);
+    for (int q = 0; q < 3; ++q) rs[q] = s[q];
+    rm[0] = mx[0];
+    rm[1] = mx[1];
+}
+
+// RAYS: the checks also test infeasibility rays (a separate instantiation,
+// so that solves without the test keep the leaner register budget).
+template <int BT, bool RAYS>
 __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
     for (;;) {
         const int32_t b = next_instance<BT>(a.queue);
@@ -489,6 +564,8 @@ __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
         int64_t t = 0, k = 0, restarts = 0;
         double r_start = 0.0, r_prev = 0.0;
         int32_t status = 0;
+        bool anchor_valid = false;   // the anchor's products are stored (after a restart)
+        double ray_scale = 0.0;
         double kkt = 0.0, rel_p = 0.0, rel_d = 0.0, rel_g = 0.0, P = 0.0, D = 0.0;
         for (;;) {
             const bool check = (t % o.check_every) == 0;
@@ -546,6 +623,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
                 v[3] += rd * rd;
                 v[4] += c_o[j] * (d * xhv);
                 v[5] += (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
+                if (RAYS) a.qh[g.vc + j] = q;
             }
             for (int32_t i = threadIdx.x; i < g.m; i += BT) {
                 const double p = csr_dot(arp, aci, ava, i, xh);
@@ -561,6 +639,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
                 v[8] += dy * dy;
                 const double d0 = yhv - y0[i];
                 v[9] += d0 * d0;
+                if (RAYS) a.ph[g.vr + i] = p;
             }
             wg_sum<BT, 10>(v);
             P = v[4];
@@ -578,6 +657,21 @@ __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
             if (kkt <= o.eps) {
                 status = PDHG_OPTIMAL;
                 break;
+            }
+            if (RAYS && anchor_valid) {
+                double rs[3], rm[2];
+                batch_ray_pass<BT>(a, o, g, xh, yh, y0, rs, rm);
+                const double obj_d = rs[0] + rs[2], obj_p = rs[1];
+                if (o.eps_pinf > 0.0 && obj_d > 0.0 && rm[0] <= o.eps_pinf * obj_d) {
+                    status = PDHG_PRIMAL_INFEASIBLE;
+                    ray_scale = 1.0 / obj_d;
+                    break;
+                }
+                if (o.eps_dinf > 0.0 && obj_p < 0.0 && rm[1] <= o.eps_dinf * (-obj_p)) {
+                    status = PDHG_DUAL_INFEASIBLE;
+                    ray_scale = -1.0 / obj_p;
+                    break;
+                }
             }
             if (last) {
                 status = PDHG_ITERATION_LIMIT;
@@ -597,7 +691,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
             }
             if (restart) {
                 const double dxr = sqrt(v[2]), dyr = sqrt(v[9]);
-                if (dxr > 1e-10 && dyr > 1e-10) omega = exp(0.5 * log(dyr / dxr) + 0.5 * log(omega));
+                omega = batch_new_omega(omega, dxr, dyr);
                 tau = eta / omega;
                 sigma = eta * omega;
                 for (int32_t j = threadIdx.x; j < g.n; j += BT) {
@@ -607,6 +701,13 @@ __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
                 for (int32_t i = threadIdx.x; i < g.m; i += BT) {
                     y[i] = yh[i];
                     y0[i] = yh[i];
+                }
+                if (RAYS) {   // the new anchor's products, from this check
+                    int32_t t0 = (int32_t)threadIdx.x;
+                    asm volatile("" : "+v"(t0));
+                    for (int32_t j = t0; j < g.n; j += BT) a.q0[g.vc + j] = a.qh[g.vc + j];
+                    for (int32_t i = t0; i < g.m; i += BT) a.p0[g.vr + i] = a.ph[g.vr + i];
+                    anchor_valid = true;
                 }
                 k = 0;
                 r_start = r;
@@ -622,9 +723,12 @@ __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
             ++t;
             __syncthreads();
         }
-        // original-space output of the last PDHG point
-        for (int32_t j = threadIdx.x; j < g.n; j += BT) a.x_out[g.vc + j] = Dc[j] * xh[j];
-        for (int32_t i = threadIdx.x; i < g.m; i += BT) a.y_out[g.vr + i] = Dr[i] * yh[i];
+        // original-space output of the last PDHG point, or the certifying ray
+        const bool xray = status == PDHG_DUAL_INFEASIBLE, yray = status == PDHG_PRIMAL_INFEASIBLE;
+        for (int32_t j = threadIdx.x; j < g.n; j += BT)
+            a.x_out[g.vc + j] = Dc[j] * (xray ? (xh[j] - x0[j]) * ray_scale : xh[j]);
+        for (int32_t i = threadIdx.x; i < g.m; i += BT)
+            a.y_out[g.vr + i] = Dr[i] * (yray ? (yh[i] - y0[i]) * ray_scale : yh[i]);
         if (threadIdx.x == 0) {
             BatchRes r;
             r.pobj = P;
@@ -653,7 +757,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
 // them, so an iteration costs about one round trip for the shared matrix
 // entries plus LDS instead of a chain of memory round trips. Same arithmetic
 // and summation order as k_batch_solve.
-template <int BT, int S>
+template <int BT, int S, bool RAYS>
 __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_t nmax) {
     extern __shared__ double lds[];
     double *sx = lds;          // x_ext, at checks x^
@@ -713,6 +817,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                 const double v0 = a.x_init ? a.x_init[g.vc + j] / d : 0.0;
                 xr[q] = clampd(v0, l, u);
                 x0r[q] = xr[q];
+                if (RAYS) a.x0[g.vc + j] = xr[q];   // read by the ray pass
             }
             const int32_t i = j;
             if (i < g.m) {
@@ -744,6 +849,8 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
         int64_t t = 0, k = 0, restarts = 0;
         double r_start = 0.0, r_prev = 0.0;
         int32_t status = 0;
+        bool anchor_valid = false;   // the anchor's products are stored (after a restart)
+        double ray_scale = 0.0;
         double kkt = 0.0, rel_p = 0.0, rel_d = 0.0, rel_g = 0.0, P = 0.0, D = 0.0;
         for (;;) {
             // an opaque copy of the thread index: the element addresses are
@@ -824,6 +931,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                     v[3] += rd * rd;
                     v[4] += c_o[j] * (d * xhv);
                     v[5] += (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
+                    if (RAYS) a.qh[g.vc + j] = qq;
                 }
             }
 #pragma unroll
@@ -843,6 +951,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                     v[8] += dy * dy;
                     const double d0 = yhv - y0[i];
                     v[9] += d0 * d0;
+                    if (RAYS) a.ph[g.vr + i] = p;
                 }
             }
             wg_sum<BT, 10>(v);
@@ -862,6 +971,21 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                 status = PDHG_OPTIMAL;
                 break;
             }
+            if (RAYS && anchor_valid) {
+                double rs[3], rm[2];
+                batch_ray_pass<BT>(a, o, g, xh, yh, y0, rs, rm);
+                const double obj_d = rs[0] + rs[2], obj_p = rs[1];
+                if (o.eps_pinf > 0.0 && obj_d > 0.0 && rm[0] <= o.eps_pinf * obj_d) {
+                    status = PDHG_PRIMAL_INFEASIBLE;
+                    ray_scale = 1.0 / obj_d;
+                    break;
+                }
+                if (o.eps_dinf > 0.0 && obj_p < 0.0 && rm[1] <= o.eps_dinf * (-obj_p)) {
+                    status = PDHG_DUAL_INFEASIBLE;
+                    ray_scale = -1.0 / obj_p;
+                    break;
+                }
+            }
             if (last) {
                 status = PDHG_ITERATION_LIMIT;
                 break;
@@ -880,7 +1004,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
             }
             if (restart) {
                 const double dxr = sqrt(v[2]), dyr = sqrt(v[9]);
-                if (dxr > 1e-10 && dyr > 1e-10) omega = exp(0.5 * log(dyr / dxr) + 0.5 * log(omega));
+                omega = batch_new_omega(omega, dxr, dyr);
                 tau = eta / omega;
                 sigma = eta * omega;
 #pragma unroll
@@ -889,11 +1013,19 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                     if (j < g.n) {
                         xr[q] = xh[j];
                         x0r[q] = xr[q];
+                        if (RAYS) a.x0[g.vc + j] = xr[q];
                     }
                     if (j < g.m) {
                         sy[j] = yh[j];
                         y0[j] = yh[j];
                     }
+                }
+                if (RAYS) {   // the new anchor's products, from this check
+                    int32_t t0 = (int32_t)threadIdx.x;
+                    asm volatile("" : "+v"(t0));
+                    for (int32_t j = t0; j < g.n; j += BT) a.q0[g.vc + j] = a.qh[g.vc + j];
+                    for (int32_t i = t0; i < g.m; i += BT) a.p0[g.vr + i] = a.ph[g.vr + i];
+                    anchor_valid = true;
                 }
                 k = 0;
                 r_start = r;
@@ -911,12 +1043,13 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
             ++t;
             __syncthreads();
         }
-        // original-space output of the last PDHG point
+        // original-space output of the last PDHG point, or the certifying ray
+        const bool xray = status == PDHG_DUAL_INFEASIBLE, yray = status == PDHG_PRIMAL_INFEASIBLE;
 #pragma unroll
         for (int q = 0; q < S; ++q) {
             const int32_t j = threadIdx.x + q * BT;
-            if (j < g.n) a.x_out[g.vc + j] = Dc[j] * xh[j];
-            if (j < g.m) a.y_out[g.vr + j] = Dr[j] * yh[j];
+            if (j < g.n) a.x_out[g.vc + j] = Dc[j] * (xray ? (xh[j] - x0r[q]) * ray_scale : xh[j]);
+            if (j < g.m) a.y_out[g.vr + j] = Dr[j] * (yray ? (yh[j] - y0[j]) * ray_scale : yh[j]);
         }
         if (threadIdx.x == 0) {
             BatchRes r;
@@ -1121,7 +1254,7 @@ __global__ __launch_bounds__(BT) void k_batch_unrolled(BArgs a, BOpts o, UArgs u
                 }
                 if (restart) {
                     const double dxr = sqrt(v2[2]), dyr = sqrt(v2[9]);
-                    if (dxr > 1e-10 && dyr > 1e-10) omega = exp(0.5 * log(dyr / dxr) + 0.5 * log(omega));
+                    omega = batch_new_omega(omega, dxr, dyr);
                     r_start = r;
                     r_prev = r;
                 }
@@ -1329,6 +1462,10 @@ static BOpts batch_opts(const pdhg_options &o) {
     b.ruiz_iters = o.ruiz_iters;
     b.pock_chambolle = o.pock_chambolle;
     b.power_max_iters = o.power_max_iters;
+    b.eps_pinf = o.eps_primal_infeasible;
+    b.eps_dinf = o.eps_dual_infeasible;
+    b.detect = o.eps_primal_infeasible > 0.0 || o.eps_dual_infeasible > 0.0;
+    b.pad = 0;
     return b;
 }
 
@@ -1382,6 +1519,10 @@ static BArgs batch_args(BatchHandle &h) {
     a.tsva = h.tsva.p;
     a.tsfirst = h.tsfirst.p;
     a.lhist = h.lhist.p;
+    a.p0 = h.rp0.p;
+    a.q0 = h.rq0.p;
+    a.ph = h.rph.p;
+    a.qh = h.rqh.p;
     a.x_out = h.x_out_;
     a.y_out = h.y_out_;
     return a;
@@ -1401,7 +1542,8 @@ static int32_t resident(const void *kernel) {
 
 template <int BT, int S>
 static void launch_solve_lds_t(BatchHandle &h, const BOpts &o, BArgs a, size_t lds) {
-    const void *kern = reinterpret_cast<const void *>(&k_batch_solve_lds<BT, S>);
+    const void *kern = o.detect ? reinterpret_cast<const void *>(&k_batch_solve_lds<BT, S, true>)
+                                : reinterpret_cast<const void *>(&k_batch_solve_lds<BT, S, false>);
     int dev = 0, per_cu = 0;
     PDHG_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
@@ -1410,7 +1552,10 @@ static void launch_solve_lds_t(BatchHandle &h, const BOpts &o, BArgs a, size_t l
     int32_t wg = std::min(h.B, std::max(1, per_cu) * prop.multiProcessorCount);
     if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
     PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
-    k_batch_solve_lds<BT, S><<<wg, BT, lds, h.stream>>>(a, o, h.nmax);
+    if (o.detect)
+        k_batch_solve_lds<BT, S, true><<<wg, BT, lds, h.stream>>>(a, o, h.nmax);
+    else
+        k_batch_solve_lds<BT, S, false><<<wg, BT, lds, h.stream>>>(a, o, h.nmax);
     PDHG_HIP(hipGetLastError());
 }
 
@@ -1539,10 +1684,14 @@ static void launch_solve_t(BatchHandle &h, const BOpts &o) {
         if (need <= 4 * BT) return launch_solve_lds_t<BT, 4>(h, o, a, l);
         return launch_solve_lds_t<BT, 8>(h, o, a, l);
     }
-    int32_t wg = std::min(h.B, resident<BT>(reinterpret_cast<const void *>(&k_batch_solve<BT>)));
+    int32_t wg = std::min(h.B, resident<BT>(o.detect ? reinterpret_cast<const void *>(&k_batch_solve<BT, true>)
+                                                     : reinterpret_cast<const void *>(&k_batch_solve<BT, false>)));
     if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
     PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
-    k_batch_solve<BT><<<wg, BT, 0, h.stream>>>(a, o);
+    if (o.detect)
+        k_batch_solve<BT, true><<<wg, BT, 0, h.stream>>>(a, o);
+    else
+        k_batch_solve<BT, false><<<wg, BT, 0, h.stream>>>(a, o);
     PDHG_HIP(hipGetLastError());
 }
 
@@ -1706,6 +1855,10 @@ BatchHandle *batch_create(const pdhg_batch_problem &p, const pdhg_options &o, vo
     h.res.alloc((size_t)h.B);
     h.queue.alloc(1);
     h.lhist.alloc((size_t)nscal * 2 * ((size_t)std::max(1, o.power_max_iters) + 1));
+    if (p.q_rank == 0) {   // LP batches test infeasibility rays at checks
+        for (auto *b : {&h.rq0, &h.rqh}) b->alloc((size_t)h.vec_n);
+        for (auto *b : {&h.rp0, &h.rph}) b->alloc((size_t)std::max(1, h.vec_m));
+    }
     dispatch_setup(h, nscal);
     PDHG_HIP(hipStreamSynchronize(s));
     h.lhist.release();

@@ -36,6 +36,7 @@ struct BatchHandle {
     DBuf<int32_t> asp, asci, asfirst, tsp, tsci, tsfirst;
     DBuf<double> asva, tsva;
     DBuf<double> lhist;                   // Lanczos coefficients during setup
+    DBuf<double> rp0, rq0, rph, rqh;      // LP: A~x0, A~'y0 of each anchor; this check's products
     // QP batches: Q_b = F F' + diag(d_b), F shared (scaled copy), d per instance
     int32_t q_rank = 0;
     DBuf<double> qF, qd_o, qdd, normq, xbar, ybar, qv_, qres;

@@ -440,7 +440,7 @@ __global__ __launch_bounds__(BT) void k_bqp_solve(QArgs a, QOpts o) {
                 }
                 if (restart) {
                     const double dxr = sqrt(v[0]), dyr = sqrt(v[7]);
-                    if (dxr > 1e-10 && dyr > 1e-10) omega = exp(0.5 * log(dyr / dxr) + 0.5 * log(omega));
+                    omega = batch_new_omega(omega, dxr, dyr);
                     qrestart<BT>(a, q);
                     k = 0;
                     r_start = r;
@@ -526,7 +526,7 @@ __global__ __launch_bounds__(BT) void k_bqp_unrolled(QArgs a, QOpts o) {
                 }
                 if (restart) {
                     const double dxr = sqrt(v[0]), dyr = sqrt(v[7]);
-                    if (dxr > 1e-10 && dyr > 1e-10) omega = exp(0.5 * log(dyr / dxr) + 0.5 * log(omega));
+                    omega = batch_new_omega(omega, dxr, dyr);
                     r_start = r;
                     r_prev = r;
                 }

@@ -286,6 +286,15 @@ __device__ __forceinline__ double clampd(double v, double lo, double hi) {
     return fmin(fmax(v, lo), hi);
 }
 
+// Primal-weight update after a restart: log-smoothing (weight 1/2) towards
+// |dy| / |dx|. Out of line on purpose: restarts are rare, and inlined into
+// the persistent kernels the constants of exp / log would stay in vector
+// registers across the whole iteration loop.
+static __device__ __noinline__ double batch_new_omega(double omega, double dxr, double dyr) {
+    if (dxr > 1e-10 && dyr > 1e-10) return exp(0.5 * log(dyr / dxr) + 0.5 * log(omega));
+    return omega;
+}
+
 // Infeasibility-ray terms of one column j at a check, in the original space:
 // q = (A~'yhat)_j, q0 = (A~'y0)_j, d = D_c[j], dxs = xhat_j - x0_j, c = c_j,
 // [lo, hi] = [l_v, u_v]_j. With g = -(A'dy)_j and lam its part in the cone of

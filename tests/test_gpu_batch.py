@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import gen
-from gpu_util import to_np
+from gpu_util import rel_inf, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -137,3 +137,48 @@ def test_batch_iteration_limit(pdhg, oracle_lib):
             cs, rs = bs.instance_slices(b)
             assert res[b]["iterations"] == 70 and res[b]["status"] == 4
             assert np.abs(to_np(x[cs]) - xo).max() <= 1e-10 * max(1.0, np.abs(xo).max())
+
+
+def _mixed_batch():
+    """Planted feasible LPs with infeasible and unbounded ones among them."""
+    lps = gen.ragged_planted_batch(batch=6, m_lo=40, m_hi=90, seed=3990)
+    lps.insert(1, gen.infeasible_lp("duplicate_row", 60, 120, seed=0))
+    lps.insert(3, gen.infeasible_lp("unbounded", 60, 120, seed=2))
+    lps.insert(5, gen.infeasible_lp("boxed_sum", 30, 50, seed=3))
+    lps.append(gen.infeasible_lp("unbounded", 300, 600, seed=1))   # n > 8 x 64: memory-resident at 64 threads
+    return lps
+
+
+@pytest.mark.parametrize("threads", [None, 64])
+def test_batch_infeasibility_matches_oracle(pdhg, oracle_lib, threads):
+    """Each instance of a mixed batch ends as the oracle ends it (status and
+    iteration count), and a certifying ray comes back in its output slice;
+    64 threads per instance run the memory-resident kernel for the largest."""
+    _say(f"case: mixed ragged batch with infeasible / unbounded instances, threads {threads or 'default'}")
+    lps = _mixed_batch()
+    with pdhg.BatchSolver.from_lps(lps, threads=threads, iteration_limit=100000) as bs:
+        x, y, res = bs.solve()
+        for b, lp in enumerate(lps):
+            xo, yo, ro = oracle_lib.Oracle(lp, iteration_limit=100000).solve()
+            cs, rs = bs.instance_slices(b)
+            rb = res[b]
+            assert rb["status_name"] == ro["status_name"], (b, rb["status_name"], ro["status_name"])
+            assert rb["iterations"] == ro["iterations"], (b, rb["iterations"], ro["iterations"])
+            if ro["status_name"] == "primal_infeasible":
+                assert rel_inf(to_np(y[rs]), yo) <= 1e-8
+            elif ro["status_name"] == "dual_infeasible":
+                assert rel_inf(to_np(x[cs]), xo) <= 1e-8
+            else:
+                assert ro["status_name"] == "optimal"
+                assert _close(rb["primal_obj"], ro["primal_obj"])
+
+
+def test_batch_infeasibility_switched_off(pdhg):
+    _say("case: mixed batch with the infeasibility tests off (lean kernels)")
+    lps = _mixed_batch()
+    with pdhg.BatchSolver.from_lps(lps, iteration_limit=3000, eps_primal_infeasible=0.0,
+                                   eps_dual_infeasible=0.0) as bs:
+        _, _, res = bs.solve()
+    names = [r["status_name"] for r in res]
+    assert names[1] == names[3] == names[5] == names[-1] == "iteration_limit", names
+    assert names[0] == names[2] == names[4] == "optimal", names
