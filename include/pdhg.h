@@ -109,9 +109,12 @@ typedef struct {
     int32_t timing_chunk;        /* >= 0: time the iteration kernels of that
                                     check period with HIP events (result.kernel_*) */
     /* Infeasibility certificates (Appendix A: 1e-8 each; <= 0 switches the
-     * test off). Tested at the checks of an LP solve (CSR or dense A) once a
-     * restart has happened: the rays are the PDHG point minus the restart
-     * anchor. */
+     * test off). Tested at the checks of an LP solve (CSR or dense A, single
+     * or batched; not QPs) once a restart has happened: the rays are the PDHG
+     * point minus the restart anchor. In a batch each instance stops on its
+     * own certificate and its output slice holds the ray, as for pdhg_solve;
+     * with both tolerances <= 0 the batched kernels skip the ray terms and
+     * keep a smaller register budget. */
     double eps_primal_infeasible;
     double eps_dual_infeasible;
     /* Feasibility polishing (Section 3; Appendix A: off, 1e-6): after an
