@@ -101,7 +101,7 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-4,
                     help="sparse workloads: relative KKT tolerance of the solve (default 1e-4)")
     ap.add_argument("--no-infeasibility-tests", action="store_true",
-                    help="batched workloads: switch the infeasibility certificate tests off")
+                    help="batched and SPO+ workloads: switch the infeasibility certificate tests off")
     ap.add_argument("--polish", action="store_true",
                     help="sparse workloads: feasibility polishing after the optimal solve")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -514,7 +514,11 @@ def bench_spo(args):
         w_star, _, res = bs.solve()                  # optimal decisions under the true costs
     z_star = torch.tensor([r["primal_obj"] for r in res], dtype=torch.float64, device=dev)
     lr = 1e-4   # larger plain-gradient steps diverge: the subgradient sums over ~4,000 arcs
-    with BatchSolver.from_shared(sb, threads=args.threads or None) as bs:
+    off = dict(eps_primal_infeasible=0.0, eps_dual_infeasible=0.0) if args.no_infeasibility_tests else {}
+    with BatchSolver.from_shared(sb, threads=args.threads or None, **off) as bs:
+        if not args.threads:
+            bs.update_data(c=heads.spo_plus_costs(heads.linear_costs(fd, W), ct))
+            log(f"bench: autotuned threads per instance = {bs.autotune(128)}")
         prev = [None]
 
         def step(Wv):

@@ -1746,8 +1746,11 @@ static void dispatch_setup(BatchHandle &h, int32_t count) {
     }
 }
 
+// Solves that test infeasibility rays carry a larger register budget: the
+// 1024-thread variants spill, so the default launch takes at most 512 there.
 static void dispatch_solve(BatchHandle &h, const BOpts &o) {
-    switch (h.threads) {
+    const int32_t threads = (o.detect && !h.threads_set) ? std::min(h.threads, 512) : h.threads;
+    switch (threads) {
         case 64: launch_solve_t<64>(h, o); break;
         case 128: launch_solve_t<128>(h, o); break;
         case 512: launch_solve_t<512>(h, o); break;
@@ -1919,6 +1922,7 @@ void batch_set_launch(BatchHandle &h, int32_t threads, int32_t workgroups) {
     if (threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
         fail(PDHG_ERR_INVALID_ARG, "threads must be 64, 128, 256, 512 or 1024");
     h.threads = threads;
+    h.threads_set = true;
     h.workgroups = workgroups;
 }
 
@@ -1935,6 +1939,7 @@ int32_t batch_autotune(BatchHandle &h, int32_t iterations) {
     h.y_init_ = nullptr;
     int32_t best = h.threads;
     double best_t = 1e300;
+    h.threads_set = true;   // each trial runs the thread count it names
     for (int32_t t : {64, 128, 256, 512, 1024}) {
         h.threads = t;
         dispatch_solve(h, o);   // warm-up
@@ -1949,6 +1954,7 @@ int32_t batch_autotune(BatchHandle &h, int32_t iterations) {
         }
     }
     h.threads = best;
+    h.threads_set = true;
     return best;
 }
 

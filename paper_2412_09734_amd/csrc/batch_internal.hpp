@@ -26,6 +26,7 @@ struct BatchHandle {
     DBuf<double> x, x0, xh, xe, aty, y, y0, yh;
     DBuf<BatchRes> res;
     int32_t threads = 256;
+    bool threads_set = false;            // chosen by set_launch / autotune
     int32_t workgroups = 0;
     double setup_seconds = 0.0;
     const double *x_init_ = nullptr, *y_init_ = nullptr;
