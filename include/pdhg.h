@@ -101,7 +101,7 @@ typedef struct {
     double restart_sufficient;   /* 0.2 */
     double restart_necessary;    /* 0.8 */
     double restart_artificial;   /* 0.36 */
-    double power_tol;            /* relative change stopping the power iteration */
+    double power_tol;            /* relative change stopping the norm estimates */
     int32_t power_max_iters;
     int32_t verbose;             /* 1: one line per display_frequency checks */
     int32_t display_frequency;   /* in checks */
@@ -155,8 +155,8 @@ int32_t pdhg_version(void);
 
 /* Copy A (and Q) into library-owned device memory, apply the diagonal
  * preconditioning of Section 3 (Ruiz, then Pock-Chambolle), estimate
- * ||A~||_2 (and ||Q~||_2) by power iteration and set the step size and the
- * initial primal weight. stream: hipStream_t whose prior work the call waits
+ * ||A~||_2 by Golub-Kahan-Lanczos bidiagonalisation (||Q~||_2 by power
+ * iteration) and set the step size and the initial primal weight. stream: hipStream_t whose prior work the call waits
  * for (NULL = default stream). On success *out receives a handle that
  * pdhg_destroy releases. Errors: INVALID_ARG, INVALID_INPUT, OOM, HIP. */
 pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *stream,
