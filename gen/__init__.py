@@ -21,6 +21,7 @@ from .lp import (  # noqa: F401
     ragged_planted_batch,
     tiny_boxed_lp,
     infeasible_lp,
+    infeasible_qp,
     contradict_row,
     portfolio_qp_batch,
     portfolio_instance,

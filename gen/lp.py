@@ -509,6 +509,23 @@ def portfolio_instance(p: dict, b: int) -> LP:
               meta=dict(kind="portfolio", seed=p["seed"], index=b))
 
 
+def infeasible_qp(kind: str, m: int = 40, n: int = 80, seed: int = 0) -> LP:
+    """QPs without an optimum: the infeasible_lp family of the same kind with a
+    convex Q = G G' (G ~ 0.3 N(0, 1), n x n/4, CSR) on its first n variables.
+    The column added for 'unbounded' has no Q entries, so the objective is
+    linear, and decreasing, along its ray."""
+    lp = infeasible_lp(kind, m, n, seed)
+    rng = np.random.default_rng(seed + 31)
+    g = 0.3 * rng.standard_normal((n, max(1, n // 4)))
+    q = np.zeros((lp.n, lp.n))
+    q[:n, :n] = g @ g.T
+    qr, qc, qv = csr_from_dense(q)
+    lp.q_kind = "csr"
+    lp.q_rowptr, lp.q_colidx, lp.q_val = qr, qc, qv
+    lp.meta["kind"] = "qp_" + lp.meta.get("kind", kind)
+    return lp
+
+
 def random_qp(m: int, n: int, seed: int, density: float = 0.3) -> LP:
     """Small random convex QP with boxes and mixed rows (CSR Q = G G' + eps I)."""
     lp = tiny_boxed_lp(m, n, seed)

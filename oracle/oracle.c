@@ -706,7 +706,8 @@ static void init_point(const orc_ctx *s, const double *x_init, const double *y_i
  *    must be positive and the largest violation |dy - yp|, |g - lam| at most
  *    eps_primal_infeasible times it: the LP has no feasible point;
  *  - primal ray: c'dx < 0 and the largest violation of A dx in the recession
- *    cone of [l_c, u_c] and of dx in that of [l_v, u_v] at most
+ *    cone of [l_c, u_c], of dx in that of [l_v, u_v] and, for a QP, of
+ *    Q dx = 0 (the objective is linear along dx) at most
  *    eps_dual_infeasible |c'dx|: the objective is unbounded below.
  * Returns 2 or 3 and writes the ray scaled to objective 1 (dual) or -1
  * (primal) to ray_y / ray_x; 0 when neither test holds. */
@@ -774,6 +775,12 @@ static int infeasibility(const orc_ctx *s, const double *xh, const double *yh, c
             const double lo = isfinite(p->lc[i]) ? 0.0 : -INFINITY;
             const double hi = isfinite(p->uc[i]) ? 0.0 : INFINITY;
             viol_p = fmax(viol_p, fabs(a[i] - clampd(a[i], lo, hi)));
+        }
+        if (p->q_kind != 0) {
+            double *qdx = dalloc(n);
+            q_mul_orig(p, dx, qdx);
+            for (int32_t j = 0; j < n; ++j) viol_p = fmax(viol_p, fabs(qdx[j]));
+            free(qdx);
         }
         if (s->o.eps_dual_infeasible > 0.0 && obj_p < 0.0L &&
             viol_p <= s->o.eps_dual_infeasible * (double)(-obj_p)) {
@@ -939,6 +946,7 @@ static int qp_loop(orc_ctx *s, const double *x_init, const double *y_init, doubl
     double *x0 = dalloc(n), *y0 = dalloc(m);
     double *xn = dalloc(n), *yn = dalloc(m), *xbn = dalloc(n), *ybn = dalloc(m);
     double *xo = dalloc(n), *yo = dalloc(m);
+    double *ray_x = dalloc(n), *ray_y = dalloc(m);
     init_point(s, x_init, y_init, x, y);
     memcpy(xb, x, sizeof(double) * n); memcpy(yb, y, sizeof(double) * m);
     memcpy(x0, x, sizeof(double) * n); memcpy(y0, y, sizeof(double) * m);
@@ -962,6 +970,11 @@ static int qp_loop(orc_ctx *s, const double *x_init, const double *y_init, doubl
                         (long long)t, (long long)k, (long long)nr, omega, res->kkt);
             if (isnan(res->kkt)) { status = 6; break; }
             if (res->kkt <= s->o.eps) { status = 1; break; }
+            /* rays from the anchor (averages minus restart point), as for LPs */
+            if (nr > 0) {
+                status = infeasibility(s, xb, yb, x0, y0, ray_x, ray_y);
+                if (status) break;
+            }
             r = sqrt(omega * res->abs_primal * res->abs_primal +
                      res->abs_dual * res->abs_dual / omega + res->abs_gap * res->abs_gap);
         }
@@ -989,6 +1002,8 @@ static int qp_loop(orc_ctx *s, const double *x_init, const double *y_init, doubl
         ++t;
     }
     unscale(s, xb, yb, x_out, y_out);
+    if (status == 2) memcpy(y_out, ray_y, sizeof(double) * m);
+    if (status == 3) memcpy(x_out, ray_x, sizeof(double) * n);
     res->status = status;
     res->iterations = t + 1;
     res->restarts = nr;
@@ -997,7 +1012,7 @@ static int qp_loop(orc_ctx *s, const double *x_init, const double *y_init, doubl
     res->norm_a = s->norm_a;
     res->norm_q = s->norm_q;
     res->power_iters = s->power_iters;
-    free(x); free(y); free(xb); free(yb); free(x0); free(y0);
+    free(x); free(y); free(xb); free(yb); free(x0); free(y0); free(ray_x); free(ray_y);
     free(xn); free(yn); free(xbn); free(ybn); free(xo); free(yo);
     return status;
 }

@@ -375,3 +375,19 @@ def test_feasibility_polishing_full_size(pdhg):
     assert rel_p <= 1e-6 * (1 + 1e-9) and rel_d <= 1e-6 * (1 + 1e-9), (rel_p, rel_d)
     assert abs(rel_p - rg["rel_primal_res"]) <= 1e-9 + 1e-6 * rel_p
     assert abs(rel_d - rg["rel_dual_res"]) <= 1e-9 + 1e-6 * rel_d
+
+
+def test_infeasibility_no_rows(pdhg, oracle_lib):
+    """m = 0: the primal ray alone certifies an unbounded objective."""
+    _say("case: unbounded LP without constraint rows, n=40")
+    n = 40
+    c = np.random.default_rng(0).uniform(0.5, 2.0, n)
+    c[7] = -1.0
+    lp = gen.LP(0, n, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), c, np.zeros(0), np.zeros(0),
+                np.zeros(n), np.full(n, np.inf))
+    xo, _, ro = oracle_lib.Oracle(lp, iteration_limit=100000).solve()
+    with pdhg.Solver.from_lp(lp, iteration_limit=100000) as s:
+        xg, _, rg = s.solve()
+    assert rg["status_name"] == ro["status_name"] == "dual_infeasible"
+    assert rg["iterations"] == ro["iterations"]
+    assert rel_inf(to_np(xg), xo) <= 1e-12

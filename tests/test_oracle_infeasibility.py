@@ -90,3 +90,62 @@ def test_no_certificate_on_feasible_lps_and_switches():
     lp = gen.infeasible_lp("unbounded", 60, 120, seed=0)
     r = oracle.Oracle(lp, eps_dual_infeasible=0.0, iteration_limit=3000).solve()[2]
     assert r["status_name"] == "iteration_limit"
+
+
+def test_no_rows_unbounded_and_boxed():
+    """No constraint rows: with x >= 0 and one negative cost the objective is
+    unbounded along that coordinate alone (the ray is e_7 with c'd = -1);
+    with a box on every variable the same LP has an optimum."""
+    n = 40
+    c = np.random.default_rng(0).uniform(0.5, 2.0, n)
+    c[7] = -1.0
+    lp = gen.LP(0, n, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), c, np.zeros(0), np.zeros(0),
+                np.zeros(n), np.full(n, np.inf))
+    x, y, r = oracle.Oracle(lp, iteration_limit=100000).solve()
+    assert r["status_name"] == "dual_infeasible"
+    e = np.zeros(n); e[7] = 1.0
+    np.testing.assert_allclose(x, e, atol=1e-12)
+    lp.uv = np.full(n, 5.0)
+    x, y, r = oracle.Oracle(lp, iteration_limit=100000).solve()
+    assert r["status_name"] == "optimal" and abs(x[7] - 5.0) <= 1e-9
+
+
+def _dense_q(lp):
+    return gen.dense_from_csr(lp.n, lp.n, lp.q_rowptr, lp.q_colidx, lp.q_val)
+
+
+@pytest.mark.parametrize("kind,m,n,seed", [("duplicate_row", 40, 80, 0), ("boxed_sum", 20, 30, 1)])
+def test_qp_primal_infeasible_certificate(kind, m, n, seed):
+    """A QP is infeasible exactly when its constraints are: HiGHS's status of
+    the constraint set and the Farkas ray checks of the LP tests."""
+    lp = gen.infeasible_qp(kind, m, n, seed=seed)
+    assert _highs_status(lp) == 2
+    x, y, r = oracle.Oracle(lp, iteration_limit=100000).solve()
+    assert r["status_name"] == "primal_infeasible", r
+    if kind == "boxed_sum":
+        g = _dense(lp).T @ y
+        assert np.sum(np.maximum(g, 0.0)) < np.dot(lp.lc, y) - 0.5
+    else:
+        pos, neg = (y > 0) & np.isfinite(lp.lc), (y < 0) & np.isfinite(lp.uc)
+        assert abs(np.dot(lp.lc[pos], y[pos]) + np.dot(lp.uc[neg], y[neg]) - 1.0) <= 1e-9
+        assert np.max(_dense(lp).T @ y) <= 1e-8 * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("m,n,seed", [(40, 80, 2), (60, 120, 6)])
+def test_qp_dual_infeasible_certificate(m, n, seed):
+    """Unbounded QP (the added column has no Q entries): the primal ray has
+    c'd = -1, Q d = 0, A d in the rows' recession cones and d >= 0, checked
+    with the dense Q and A. The ray's Q term converges more slowly than an
+    LP's, so this test uses eps_dual_infeasible = 1e-6."""
+    lp = gen.infeasible_qp("unbounded", m, n, seed=seed)
+    x, y, r = oracle.Oracle(lp, iteration_limit=100000, eps_dual_infeasible=1e-6).solve()
+    assert r["status_name"] == "dual_infeasible", r
+    d = x
+    assert abs(np.dot(lp.c, d) + 1.0) <= 1e-12
+    assert np.max(np.abs(_dense_q(lp) @ d)) <= 1e-6
+    ad = _dense(lp) @ d
+    eq = lp.lc == lp.uc
+    assert np.max(np.abs(ad[eq])) <= 1e-6
+    assert np.min(ad[~eq & np.isfinite(lp.lc)], initial=0.0) >= -1e-6
+    assert np.max(ad[~eq & np.isfinite(lp.uc)], initial=0.0) <= 1e-6
+    assert np.min(d) >= -1e-6 and d[-1] > 0.0
