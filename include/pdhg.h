@@ -49,8 +49,8 @@ typedef enum {
 typedef enum {
     PDHG_UNSOLVED = 0,
     PDHG_OPTIMAL = 1,            /* relative KKT error <= eps */
-    PDHG_PRIMAL_INFEASIBLE = 2,  /* a dual ray certifies that no x is feasible (LP) */
-    PDHG_DUAL_INFEASIBLE = 3,    /* a primal ray certifies an unbounded objective (LP) */
+    PDHG_PRIMAL_INFEASIBLE = 2,  /* a dual ray certifies that no x is feasible */
+    PDHG_DUAL_INFEASIBLE = 3,    /* a primal ray certifies an unbounded objective */
     PDHG_ITERATION_LIMIT = 4,
     PDHG_TIME_LIMIT = 5,
     PDHG_NUMERICAL_ERROR = 6     /* NaN in the KKT terms */
@@ -110,8 +110,9 @@ typedef struct {
                                     check period with HIP events (result.kernel_*) */
     /* Infeasibility certificates (Appendix A: 1e-8 each; <= 0 switches the
      * test off). Tested at the checks of an LP solve (CSR or dense A, single
-     * or batched; not QPs) once a restart has happened: the rays are the PDHG
-     * point minus the restart anchor. In a batch each instance stops on its
+     * or batched) or of a single QP solve once a restart has happened: the
+     * rays are the PDHG point (the averages for a QP) minus the restart
+     * anchor; a QP's primal ray must also satisfy Q dx = 0. In a batch each instance stops on its
      * own certificate and its output slice holds the ray, as for pdhg_solve;
      * with both tolerances <= 0 the batched kernels skip the ray terms and
      * keep a smaller register budget. */

@@ -205,13 +205,12 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
     }
     DevState fin;
     PDHG_HIP(hipMemcpy(&fin, h.st.p, sizeof(DevState), hipMemcpyDeviceToHost));
-    if (h.q_kind) {
+    if (fin.done && (fin.status == PDHG_PRIMAL_INFEASIBLE || fin.status == PDHG_DUAL_INFEASIBLE))
+        launch_make_ray(h, fin.status);
+    if (h.q_kind)
         launch_qp_finalize(h, x_out, y_out);
-    } else {
-        if (fin.done && (fin.status == PDHG_PRIMAL_INFEASIBLE || fin.status == PDHG_DUAL_INFEASIBLE))
-            launch_make_ray(h, fin.status);
+    else
         launch_finalize(h, x_out, y_out);
-    }
     PDHG_HIP(hipStreamSynchronize(s));
     if (h.opt.verbose) print_check(fin);
     double kp = 0.0, kd = 0.0;
@@ -354,13 +353,16 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
         }
         h.pn.alloc((size_t)std::max(1, h.nbn) * 6);
         h.pm.alloc((size_t)std::max(1, h.nbm) * 4);
-        if (!h.q_kind) {   // the LP checks also test infeasibility rays
-            h.prn.alloc((size_t)std::max(1, h.nbn) * 4);
-            h.prm.alloc((size_t)std::max(1, h.nbm) * 3);
-            h.q0.alloc((size_t)h.n);
-            h.qhat.alloc((size_t)h.n);
-            h.p0.alloc((size_t)std::max(1, h.m));
-            h.phat.alloc((size_t)std::max(1, h.m));
+        // the checks also test infeasibility rays
+        h.prn.alloc((size_t)std::max(1, h.nbn) * 4);
+        h.prm.alloc((size_t)std::max(1, h.nbm) * 3);
+        h.q0.alloc((size_t)h.n);
+        h.qhat.alloc((size_t)h.n);
+        h.p0.alloc((size_t)std::max(1, h.m));
+        h.phat.alloc((size_t)std::max(1, h.m));
+        if (h.q_kind) {
+            h.qv0.alloc((size_t)h.n);
+            h.qvhat.alloc((size_t)h.n);
         }
         PDHG_HIP(hipHostMalloc(reinterpret_cast<void **>(&h.st_host),
                                sizeof(DevState) * h.st_ring, hipHostMallocDefault));

@@ -162,6 +162,7 @@ struct Handle {
     DBuf<double> pn, pm;                 // per-workgroup partial sums of a check
     DBuf<double> prn, prm;               // per-workgroup ray sums / maxima of a check
     DBuf<double> p0, q0, phat, qhat;     // A~x0, A~'y0 of the anchor; A~xhat, A~'yhat
+    DBuf<double> qv0, qvhat;             // QP: Q~x0 of the anchor; Q~xbar of this check
     DBuf<double> scratch;                // reductions of setup / power iteration
     DBuf<DevState> st;
     DevState *st_host = nullptr;         // pinned ring of status copies

@@ -507,7 +507,8 @@ void launch_apply(Handle &h) {
 
 // On an infeasibility certificate the finalised output carries the ray:
 // xhat <- (xhat - x0) s (primal ray) or yhat <- (yhat - y0) s (dual ray),
-// s = st->ray_scale; the finalize then applies D_c / D_r.
+// s = st->ray_scale; the finalize then applies D_c / D_r. A QP's finalised
+// points are the averages xbar / ybar.
 __global__ __launch_bounds__(kBlock) void k_make_ray(const DevState *__restrict__ st, int32_t len,
                                                      double *__restrict__ v,
                                                      const double *__restrict__ v0) {
@@ -528,12 +529,11 @@ void launch_zero_finite(Handle &h, double *v, int32_t len) {
 }
 
 void launch_make_ray(Handle &h, int32_t status) {
+    double *xv = h.q_kind ? h.xbar.p : h.xhat.p, *yv = h.q_kind ? h.ybar.p : h.yhat.p;
     if (status == PDHG_PRIMAL_INFEASIBLE && h.m > 0)
-        k_make_ray<<<(unsigned)ceil_div(h.m, kBlock), kBlock, 0, h.stream>>>(h.st.p, h.m, h.yhat.p,
-                                                                             h.y0.p);
+        k_make_ray<<<(unsigned)ceil_div(h.m, kBlock), kBlock, 0, h.stream>>>(h.st.p, h.m, yv, h.y0.p);
     if (status == PDHG_DUAL_INFEASIBLE && h.n > 0)
-        k_make_ray<<<(unsigned)ceil_div(h.n, kBlock), kBlock, 0, h.stream>>>(h.st.p, h.n, h.xhat.p,
-                                                                             h.x0.p);
+        k_make_ray<<<(unsigned)ceil_div(h.n, kBlock), kBlock, 0, h.stream>>>(h.st.p, h.n, xv, h.x0.p);
     PDHG_HIP(hipGetLastError());
 }
 

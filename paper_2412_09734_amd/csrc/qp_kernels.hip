@@ -146,15 +146,20 @@ __global__ __launch_bounds__(kBlock) void k_dual_qp(
 
 // Column side of a QP check on (xbar, ybar); qv = Q~ xbar. Sums:
 //  0 |xbar - x0|^2  1 |r_d|^2  2 x'Qx  3 c'x  4 l_v'lambda^+ - u_v'lambda^- (original space)
+// and the infeasibility-ray terms as for LPs (rays[4] per workgroup), the
+// primal ray's violation also counting |(Q dx)_j| = |qv - Q~x0| / D_c; the
+// products A~'ybar, Q~xbar are kept in qhat, qvhat.
 __global__ __launch_bounds__(kBlock) void k_qp_check_n(
     MatView M, const double *__restrict__ ybar, const double *__restrict__ xbar,
     const double *__restrict__ x0, const double *__restrict__ qv, const double *__restrict__ Dc,
     const double *__restrict__ c_o, const double *__restrict__ lv_o,
     const double *__restrict__ uv_o, double *__restrict__ partials,
-    const DevState *__restrict__ st) {
+    const double *__restrict__ q0, double *__restrict__ qhat, const double *__restrict__ qv0,
+    double *__restrict__ qvhat, double *__restrict__ rays, const DevState *__restrict__ st) {
     if (st->done) return;
     const RowSum rs = mat_row_dot(M, ybar);
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double rsum[2] = {0.0, 0.0}, rmax[2] = {0.0, 0.0};
     if (rs.valid) {
         const int32_t r = rs.row;
         const double xb = xbar[r];
@@ -172,19 +177,28 @@ __global__ __launch_bounds__(kBlock) void k_qp_check_n(
         v[2] = xo * qx;
         v[3] = c_o[r] * xo;
         v[4] = (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
+        qhat[r] = rs.s;
+        qvhat[r] = qv[r];
+        ray_col_terms(rs.s, q0[r], d, d0, c_o[r], lo, hi, rsum, rmax);
+        rmax[1] = fmax(rmax[1], fabs((qv[r] - qv0[r]) / d));
     }
     block_sum_store<6>(v, partials + (size_t)blockIdx.x * 6);
+    block_sum_store<2>(rsum, rays + (size_t)blockIdx.x * 4);
+    block_max_store<2>(rmax, rays + (size_t)blockIdx.x * 4 + 2);
 }
 
 // Row side: 0 |r_p|^2  1 l_c'y^+ - u_c'y^-  2 (unused)  3 |ybar - y0|^2
+// (plus the rows' ray terms, rays[3] per workgroup; A~xbar kept in phat)
 __global__ __launch_bounds__(kBlock) void k_qp_check_m(
     MatView M, const double *__restrict__ xbar, const double *__restrict__ ybar,
     const double *__restrict__ y0, const double *__restrict__ Dr, const double *__restrict__ lc_o,
     const double *__restrict__ uc_o, double *__restrict__ partials,
+    const double *__restrict__ p0, double *__restrict__ phat, double *__restrict__ rays,
     const DevState *__restrict__ st) {
     if (st->done) return;
     const RowSum rs = mat_row_dot(M, xbar);
     double v[4] = {0.0, 0.0, 0.0, 0.0};
+    double rsum[1] = {0.0}, rmax[2] = {0.0, 0.0};
     if (rs.valid) {
         const int32_t r = rs.row;
         const double d = Dr[r];
@@ -197,13 +211,18 @@ __global__ __launch_bounds__(kBlock) void k_qp_check_m(
         v[1] = (isfinite(lo) ? lo * fmax(yo, 0.0) : 0.0) - (isfinite(hi) ? hi * fmax(-yo, 0.0) : 0.0);
         const double d0 = yb - y0[r];
         v[3] = d0 * d0;
+        phat[r] = rs.s;
+        ray_row_terms(rs.s, p0[r], d, d0, lo, hi, rsum, rmax);
     }
     block_sum_store<4>(v, partials + (size_t)blockIdx.x * 4);
+    block_sum_store<1>(rsum, rays + (size_t)blockIdx.x * 3);
+    block_max_store<2>(rmax, rays + (size_t)blockIdx.x * 3 + 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_qp_controller(
     DevState *__restrict__ st, const double *__restrict__ pn, int32_t nbn,
-    const double *__restrict__ pm, int32_t nbm, CtlConst K, int32_t chunk_plain, int32_t is_last,
+    const double *__restrict__ pm, int32_t nbm, const double *__restrict__ prn,
+    const double *__restrict__ prm, CtlConst K, int32_t chunk_plain, int32_t is_last,
     int32_t last_status) {
     if (st->done) return;
     double vn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -216,6 +235,23 @@ __global__ __launch_bounds__(kBlock) void k_qp_controller(
         for (int q = 0; q < 4; ++q) vm[q] += pm[(size_t)b * 4 + q];
     block_sum_all<6>(vn);
     block_sum_all<4>(vm);
+    const bool rays = K.detect && st->anchor_valid;
+    double rs[3] = {0.0, 0.0, 0.0}, rx[2] = {0.0, 0.0};
+    if (rays) {
+        for (int32_t b = threadIdx.x; b < nbn; b += kBlock) {
+            rs[0] += prn[(size_t)b * 4];
+            rs[1] += prn[(size_t)b * 4 + 1];
+            rx[0] = fmax(rx[0], prn[(size_t)b * 4 + 2]);
+            rx[1] = fmax(rx[1], prn[(size_t)b * 4 + 3]);
+        }
+        for (int32_t b = threadIdx.x; b < nbm; b += kBlock) {
+            rs[2] += prm[(size_t)b * 3];
+            rx[0] = fmax(rx[0], prm[(size_t)b * 3 + 1]);
+            rx[1] = fmax(rx[1], prm[(size_t)b * 3 + 2]);
+        }
+        block_sum_all<3>(rs);
+        block_max_all<2>(rx);
+    }
     if (threadIdx.x != 0) return;
     const int64_t t = st->t_next;
     const int64_t k = st->first ? 0 : st->k_base + st->plain_prev;
@@ -254,6 +290,23 @@ __global__ __launch_bounds__(kBlock) void k_qp_controller(
         st->action = 2;
         return;
     }
+    if (rays) {
+        const double obj_d = rs[0] + rs[2], obj_p = rs[1];
+        if (K.eps_pinf > 0.0 && obj_d > 0.0 && rx[0] <= K.eps_pinf * obj_d) {
+            st->done = 1;
+            st->status = PDHG_PRIMAL_INFEASIBLE;
+            st->ray_scale = 1.0 / obj_d;
+            st->action = 2;
+            return;
+        }
+        if (K.eps_dinf > 0.0 && obj_p < 0.0 && rx[1] <= K.eps_dinf * (-obj_p)) {
+            st->done = 1;
+            st->status = PDHG_DUAL_INFEASIBLE;
+            st->ray_scale = -1.0 / obj_p;
+            st->action = 2;
+            return;
+        }
+    }
     if (is_last) {
         st->done = 1;
         st->status = last_status;
@@ -286,28 +339,36 @@ __global__ __launch_bounds__(kBlock) void k_qp_controller(
         st->restarts += 1;
         st->k_base = 0;
         st->action = 1;
+        st->anchor_valid = 1;   // k_qp_apply stores the new anchor's products
     } else {
         st->k_base = k + 1;
         st->action = 0;
     }
 }
 
-// restart: x, x0 <- xbar and y, y0 <- ybar
+// restart: x, x0 <- xbar and y, y0 <- ybar; the anchor's products A~'y0,
+// Q~x0, A~x0 from this check's qhat, qvhat, phat
 __global__ __launch_bounds__(kBlock) void k_qp_apply(const DevState *__restrict__ st, int32_t n,
                                                      int32_t m, double *__restrict__ x,
                                                      double *__restrict__ x0,
                                                      const double *__restrict__ xbar,
                                                      double *__restrict__ y, double *__restrict__ y0,
-                                                     const double *__restrict__ ybar) {
+                                                     const double *__restrict__ ybar,
+                                                     double *__restrict__ q0, const double *__restrict__ qhat,
+                                                     double *__restrict__ qv0, const double *__restrict__ qvhat,
+                                                     double *__restrict__ p0, const double *__restrict__ phat) {
     if (st->done || st->action != 1) return;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) {
         x[i] = xbar[i];
         x0[i] = xbar[i];
+        q0[i] = qhat[i];
+        qv0[i] = qvhat[i];
     } else if (i - n < m) {
         const int64_t r = i - n;
         y[r] = ybar[r];
         y0[r] = ybar[r];
+        p0[r] = phat[r];
     }
 }
 
@@ -473,11 +534,13 @@ void launch_qp_check(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t la
     enqueue_qv(h, 0, 1, h.st.p);
     k_qp_check_n<<<(unsigned)h.AT.nblocks(), kBlock, 0, s>>>(view(h.AT), h.ybar.p, h.xbar.p, h.x0.p,
                                                              h.qv.p, h.Dc.p, h.c_o.p, h.lv_o.p,
-                                                             h.uv_o.p, h.pn.p, h.st.p);
+                                                             h.uv_o.p, h.pn.p, h.q0.p, h.qhat.p,
+                                                             h.qv0.p, h.qvhat.p, h.prn.p, h.st.p);
     if (h.A.nblocks())
         k_qp_check_m<<<(unsigned)h.A.nblocks(), kBlock, 0, s>>>(view(h.A), h.xbar.p, h.ybar.p,
                                                                h.y0.p, h.Dr.p, h.lc_o.p, h.uc_o.p,
-                                                               h.pm.p, h.st.p);
+                                                               h.pm.p, h.p0.p, h.phat.p, h.prm.p,
+                                                               h.st.p);
     CtlConst K;
     K.eps = h.opt.eps;
     K.bnorm = h.bnorm;
@@ -488,14 +551,17 @@ void launch_qp_check(Handle &h, int32_t chunk_plain, int32_t is_last, int32_t la
     K.beta_art = h.opt.restart_artificial;
     K.norm_q = h.norm_q;
     K.qp = 1;
-    K.detect = 0;
-    K.eps_pinf = K.eps_dinf = 0.0;
+    K.detect = h.opt.eps_primal_infeasible > 0.0 || h.opt.eps_dual_infeasible > 0.0;
+    K.eps_pinf = h.opt.eps_primal_infeasible;
+    K.eps_dinf = h.opt.eps_dual_infeasible;
     K.term = 0;
     K.pad = 0;
-    k_qp_controller<<<1, kBlock, 0, s>>>(h.st.p, h.pn.p, h.nbn, h.pm.p, h.nbm, K,
+    k_qp_controller<<<1, kBlock, 0, s>>>(h.st.p, h.pn.p, h.nbn, h.pm.p, h.nbm, h.prn.p, h.prm.p, K,
                                          chunk_plain, is_last, last_status);
     k_qp_apply<<<nblk((int64_t)h.n + h.m), kBlock, 0, s>>>(h.st.p, h.n, h.m, h.x.p, h.x0.p,
-                                                          h.xbar.p, h.y.p, h.y0.p, h.ybar.p);
+                                                          h.xbar.p, h.y.p, h.y0.p, h.ybar.p, h.q0.p,
+                                                          h.qhat.p, h.qv0.p, h.qvhat.p, h.p0.p,
+                                                          h.phat.p);
 }
 
 void launch_qp_init(Handle &h) {

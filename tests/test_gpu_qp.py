@@ -93,3 +93,23 @@ def test_qp_water_filling_on_gpu(pdhg):
     ref = np.clip((0.5 * (lo + hi) - lp.c) / lp.q_diag, 0.0, 0.1)
     assert rg["status_name"] == "optimal"
     np.testing.assert_allclose(to_np(xg), ref, atol=1e-6)
+
+
+@pytest.mark.parametrize("kind,m,n,seed,eps_d", [("duplicate_row", 40, 80, 0, 1e-8), ("boxed_sum", 20, 30, 1, 1e-8),
+                                                 ("unbounded", 40, 80, 2, 1e-6), ("unbounded", 60, 120, 6, 1e-6)])
+def test_qp_infeasibility_matches_oracle(pdhg, oracle_lib, kind, m, n, seed, eps_d):
+    """rAPDHG: rays from the averages minus the anchor; the primal ray also
+    needs Q dx = 0 (tested at 1e-6, where the test QPs certify in reach)."""
+    _say(f"case: QP infeasibility detection, {kind} m={m} n={n} seed={seed}")
+    lp = gen.infeasible_qp(kind, m, n, seed=seed)
+    xo, yo, ro = oracle_lib.Oracle(lp, iteration_limit=100000, eps_dual_infeasible=eps_d).solve()
+    with pdhg.Solver.from_lp(lp, iteration_limit=100000, eps_dual_infeasible=eps_d) as s:
+        xg, yg, rg = s.solve()
+    _say(f"  status gpu={rg['status_name']} oracle={ro['status_name']} "
+         f"iterations gpu={rg['iterations']} oracle={ro['iterations']}")
+    want = "dual_infeasible" if kind == "unbounded" else "primal_infeasible"
+    assert ro["status_name"] == want and rg["status_name"] == want
+    assert abs(rg["iterations"] - ro["iterations"]) <= 64
+    if rg["iterations"] == ro["iterations"]:
+        ray_g, ray_o = (yg, yo) if want == "primal_infeasible" else (xg, xo)
+        assert rel_inf(to_np(ray_g), ray_o) <= 1e-7
