@@ -494,7 +494,7 @@ def bench_learn(args):
 def bench_spo(args):
     """One SPO+ training step of the shortest-path cost model: c_hat = f W,
     inner costs 2 c_hat - c, one batched solve to 1e-4 warm-started from the
-    previous step's solutions, SPO+ loss and subgradient, weight gradient (all
+    previous step's primal and dual solutions, SPO+ loss and subgradient, weight gradient (all
     in libpdhg kernels), then a host-side gradient step (rate 1e-4) on the 5
     weights.
     value = LPs solved and differentiated per second (batch / step time)."""
@@ -519,18 +519,21 @@ def bench_spo(args):
         if not args.threads:
             bs.update_data(c=heads.spo_plus_costs(heads.linear_costs(fd, W), ct))
             log(f"bench: autotuned threads per instance = {bs.autotune(128)}")
-        prev = [None]
+        prev = [None, None]
 
         def step(Wv):
             chat = heads.linear_costs(fd, Wv)
             bs.update_data(c=heads.spo_plus_costs(chat, ct))
-            wt, _, r = bs.solve(x_init=prev[0])
-            prev[0] = wt
+            wt, yt, r = bs.solve(x_init=prev[0], y_init=prev[1])
+            prev[0], prev[1] = wt, yt
             loss, g = heads.spo_plus(chat, ct, w_star, z_star, wt)
             gW = heads.linear_costs_backward(fd, g)
             return float(loss.mean()), gW.cpu().numpy() / B, r
+        # warm-up steps are training steps too: the timed steps never re-solve
+        # the costs their warm start came from
         for _ in range(args.warmup):
-            step(W)
+            _, g, _ = step(W)
+            W = W - lr * g
         torch.cuda.synchronize()
         losses, iters = [], []
         t0 = time.perf_counter()
