@@ -458,7 +458,7 @@ __global__ __launch_bounds__(BT) void k_batch_setup(BArgs a, BOpts o, int32_t co
 // the KKT sums. x0 is read from memory (on-chip kernels keep it written
 // through at restarts).
 template <int BT>
-__device__ __forceinline__ void batch_ray_pass(const BArgs &a, const BOpts &o, const Geo &g,
+__device__ __forceinline__ void batch_ray_pass(const BArgs &a, const Geo &g,
                                             const double *__restrict__ xh, const double *__restrict__ yh,
                                             const double *__restrict__ y0, double (&rs)[3], double (&rm)[2]) {
     const double *Dr = a.Dr + g.dr, *Dc = a.Dc + g.dc;
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
             }
             if (RAYS && anchor_valid) {
                 double rs[3], rm[2];
-                batch_ray_pass<BT>(a, o, g, xh, yh, y0, rs, rm);
+                batch_ray_pass<BT>(a, g, xh, yh, y0, rs, rm);
                 const double obj_d = rs[0] + rs[2], obj_p = rs[1];
                 if (o.eps_pinf > 0.0 && obj_d > 0.0 && rm[0] <= o.eps_pinf * obj_d) {
                     status = PDHG_PRIMAL_INFEASIBLE;
@@ -973,7 +973,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
             }
             if (RAYS && anchor_valid) {
                 double rs[3], rm[2];
-                batch_ray_pass<BT>(a, o, g, xh, yh, y0, rs, rm);
+                batch_ray_pass<BT>(a, g, xh, yh, y0, rs, rm);
                 const double obj_d = rs[0] + rs[2], obj_p = rs[1];
                 if (o.eps_pinf > 0.0 && obj_d > 0.0 && rm[0] <= o.eps_pinf * obj_d) {
                     status = PDHG_PRIMAL_INFEASIBLE;
