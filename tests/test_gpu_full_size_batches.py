@@ -1,0 +1,122 @@
+"""Parity at the benchmark's full batch sizes and in the launch configuration
+the benchmark times: each whole batch runs on the GPU, and sampled instances
+(the slowest one among them) are checked against the oracle one by one."""
+
+import sys
+from types import SimpleNamespace
+
+import numpy as np
+import pytest
+
+import gen
+from gpu_util import rel_inf, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2412_09734_amd.heads as h
+    import paper_2412_09734_amd.solver as s
+    return h, s
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _close(a, b, tol=1e-6):
+    return abs(a - b) <= tol * (1 + abs(b))
+
+
+def _sample(iters, B, k, seed):
+    rng = np.random.default_rng(seed)
+    return sorted({int(np.argmax(iters))} | {int(v) for v in rng.choice(B, k, replace=False)})
+
+
+def test_grid_batch_2048_sampled(mods, oracle_lib):
+    _, s = mods
+    _say("case: 2,048 grid min-cost flows (32x32) at the benchmark's autotuned launch, 6 sampled instances")
+    sb = gen.grid_mincost_batch(batch=2048, seed=gen.seed_for(3, 0))
+    with s.BatchSolver.from_shared(sb) as bs:
+        _say(f"  autotuned threads per instance = {bs.autotune(128)}")
+        x, y, res = bs.solve()
+    assert all(r["status_name"] == "optimal" for r in res)
+    iters = [r["iterations"] for r in res]
+    for b in _sample(iters, 2048, 5, 0):
+        lp = sb.instance(b)
+        _, _, ro = oracle_lib.Oracle(lp).solve()
+        rb = res[b]
+        _say(f"  instance {b}: iterations gpu={rb['iterations']} oracle={ro['iterations']}")
+        assert ro["status_name"] == "optimal"
+        assert abs(rb["iterations"] - ro["iterations"]) <= 64
+        assert _close(rb["primal_obj"], ro["primal_obj"])
+        assert oracle_lib.kkt(lp, to_np(x[b]), to_np(y[b]))["kkt"] <= 1e-4 * (1 + 1e-6)
+
+
+def test_ragged_batch_1024_sampled(mods, oracle_lib):
+    _, s = mods
+    _say("case: 1,024 ragged planted LPs (m ~ U{50..500}) at the benchmark's autotuned launch, 6 sampled instances")
+    lps = gen.ragged_planted_batch(batch=1024, seed=gen.seed_for(3, 500))
+    with s.BatchSolver.from_lps(lps) as bs:
+        _say(f"  autotuned threads per instance = {bs.autotune(128)}")
+        x, y, res = bs.solve()
+        assert all(r["status_name"] == "optimal" for r in res)
+        iters = [r["iterations"] for r in res]
+        for b in _sample(iters, 1024, 5, 1):
+            lp = lps[b]
+            _, _, ro = oracle_lib.Oracle(lp).solve()
+            rb = res[b]
+            cs, rs = bs.instance_slices(b)
+            _say(f"  instance {b} (m={lp.m}): iterations gpu={rb['iterations']} oracle={ro['iterations']}")
+            assert rb["iterations"] == ro["iterations"]
+            assert _close(rb["primal_obj"], ro["primal_obj"])
+            assert oracle_lib.kkt(lp, to_np(x[cs]), to_np(y[rs]))["kkt"] <= 1e-4 * (1 + 1e-6)
+
+
+def test_learning_step_256_sampled(mods, oracle_lib):
+    from oracle import heads as oh
+    h, s = mods
+    _say("case: learning step on 256 grids, T = 1000 unrolled + reverse pass, 3 sampled instances")
+    T = 1000
+    sb, f, _, W = gen.shortest_path_learning(batch=256, seed=gen.seed_for(4, 0))
+    chat = h.linear_costs(f, W)
+    with s.BatchSolver.from_shared(sb) as bs:
+        bs.update_data(c=chat)
+        x, _ = bs.unrolled(T)
+        gc = bs.backward(sb.c)[0]
+    ch = oh.linear_costs(f, W)
+    for b in _sample([0] * 256, 256, 3, 2):
+        lp = sb.instance(b)
+        lp.c = ch[b]
+        o = oracle_lib.Oracle(lp)
+        xo, _, sr, sw = o.unrolled(T)
+        assert rel_inf(to_np(x[b]), xo) <= 1e-10, (b, rel_inf(to_np(x[b]), xo))
+        go = o.backward(T, sr, sw, sb.c[b], np.zeros(sb.m))[0]
+        assert rel_inf(to_np(gc[b]), go) <= 1e-9, (b, rel_inf(to_np(gc[b]), go))
+
+
+def test_portfolio_qp_512_sampled(mods, oracle_lib):
+    _, s = mods
+    _say("case: 512 portfolio QPs (n = 500, rank 20), 4 sampled instances")
+    p = gen.portfolio_qp_batch(batch=512, seed=gen.seed_for(4, 500))
+    B = p["c"].shape[0]
+    sbq = SimpleNamespace(m=p["m"], n=p["n"], rowptr=p["rowptr"], colidx=p["colidx"], val=p["val"], c=p["c"],
+                          lc=np.tile(p["lc"], (B, 1)), uc=np.tile(p["uc"], (B, 1)), lv=np.tile(p["lv"], (B, 1)),
+                          uv=np.tile(p["uv"], (B, 1)), q_factor=p["F"], q_diag=p["d"])
+    with s.BatchSolver.from_shared(sbq) as bs:
+        x, y, res = bs.solve()
+    assert all(r["status_name"] == "optimal" for r in res)
+    iters = [r["iterations"] for r in res]
+    for b in _sample(iters, B, 3, 3):
+        lp = gen.portfolio_instance(p, b)
+        _, _, ro = oracle_lib.Oracle(lp).solve()
+        rb = res[b]
+        _say(f"  instance {b}: iterations gpu={rb['iterations']} oracle={ro['iterations']}")
+        assert ro["status_name"] == "optimal"
+        assert abs(rb["iterations"] - ro["iterations"]) <= 64
+        assert _close(rb["primal_obj"], ro["primal_obj"], 1e-5)
+        assert oracle_lib.kkt(lp, to_np(x[b]), to_np(y[b]))["kkt"] <= 1e-4 * (1 + 1e-6)
