@@ -22,6 +22,7 @@ from .lp import (  # noqa: F401
     tiny_boxed_lp,
     infeasible_lp,
     infeasible_qp,
+    mixed_qp_batch,
     contradict_row,
     portfolio_qp_batch,
     portfolio_instance,

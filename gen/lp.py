@@ -99,19 +99,24 @@ class SharedBatch:
     uv: np.ndarray
     v_star: Optional[np.ndarray] = None
     meta: dict = field(default_factory=dict)
+    q_factor: Optional[np.ndarray] = None   # QP batches: F [n, r] shared,
+    q_diag: Optional[np.ndarray] = None     # d [B, n]: Q_b = F F' + diag(d_b)
 
     @property
     def batch(self) -> int:
         return int(self.c.shape[0])
 
     def instance(self, b: int) -> LP:
+        q = {}
+        if self.q_factor is not None:
+            q = dict(q_kind="lowrank", q_factor=self.q_factor, q_diag=self.q_diag[b].copy())
         return LP(self.m, self.n, self.rowptr, self.colidx, self.val,
                   self.c[b].copy(), self.lc[b].copy(), self.uc[b].copy(),
                   self.lv[b].copy(), self.uv[b].copy(),
                   v_star=None if self.v_star is None else float(self.v_star[b]),
                   meta={k: (v[b] if isinstance(v, np.ndarray) and v.ndim >= 1
                             and v.shape[0] == self.batch else v)
-                        for k, v in self.meta.items()})
+                        for k, v in self.meta.items()}, **q)
 
 
 # ----------------------------------------------------------------------------
@@ -524,6 +529,55 @@ def infeasible_qp(kind: str, m: int = 40, n: int = 80, seed: int = 0) -> LP:
     lp.q_rowptr, lp.q_colidx, lp.q_val = qr, qc, qv
     lp.meta["kind"] = "qp_" + lp.meta.get("kind", kind)
     return lp
+
+
+def mixed_qp_batch(kinds, m: int = 40, n: int = 80, rank: int = 4, seed: int = 0) -> SharedBatch:
+    """A shared-A batch of QPs (Q_b = F F' + diag(d_b)) in which each instance
+    is of the given kind: 'optimal', 'primal_infeasible' or 'dual_infeasible'.
+
+    A is a planted sparse LP (x >= 0) plus a copy of one of its equality rows
+    and a column u whose entries are positive on some '>=' rows, negative on
+    some '<=' rows and zero elsewhere. F ~ 0.3 N(0, 1) has a zero row for u.
+    'optimal': the copied row keeps its right-hand side, d ~ U(0.01, 0.1)
+        everywhere (Q positive definite) and c_u = 1;
+    'primal_infeasible': the same with the copy's right-hand side moved by 1;
+    'dual_infeasible': consistent rows, d_u = 0 and c_u = -1, so the objective
+        is linear and decreasing along e_u, a direction of the recession cone.
+    The other costs are the planted ones plus 0.05 N(0, 1) per instance."""
+    rng = np.random.default_rng(seed)
+    base = planted_sparse_lp(m, n, density=max(0.02, 4.0 / n), seed=seed)
+    a = dense_from_csr(base.m, base.n, base.rowptr, base.colidx, base.val)
+    eq = np.where(base.lc == base.uc)[0]
+    i = int(eq[rng.integers(len(eq))])
+    ge = np.isfinite(base.lc) & ~np.isfinite(base.uc)
+    le = ~np.isfinite(base.lc) & np.isfinite(base.uc)
+    pick = rng.random(m) < 0.3
+    mag = rng.uniform(0.5, 1.5, m)
+    col = np.where(pick & ge, mag, 0.0) - np.where(pick & le, mag, 0.0)
+    if not np.any(col):
+        col[np.where(ge | le)[0][0]] = 1.0 if ge.any() else -1.0
+    a = np.vstack([a, a[i:i + 1]])
+    a = np.hstack([a, np.append(col, 0.0)[:, None]])
+    rowptr, colidx, val = csr_from_dense(a)
+    B, M, N = len(kinds), m + 1, n + 1
+    F = np.zeros((N, rank))
+    F[:n] = 0.3 * rng.standard_normal((n, rank))
+    c = np.empty((B, N))
+    lc = np.empty((B, M))
+    uc = np.empty((B, M))
+    d = np.empty((B, N))
+    for b, kind in enumerate(kinds):
+        if kind not in ("optimal", "primal_infeasible", "dual_infeasible"):
+            raise ValueError(kind)
+        shift = 1.0 if kind == "primal_infeasible" else 0.0
+        lc[b] = np.append(base.lc, base.lc[i] + shift)
+        uc[b] = np.append(base.uc, base.uc[i] + shift)
+        c[b] = np.append(base.c + 0.05 * rng.standard_normal(n), -1.0 if kind == "dual_infeasible" else 1.0)
+        d[b] = rng.uniform(0.01, 0.1, N)
+        if kind == "dual_infeasible":
+            d[b, n] = 0.0
+    return SharedBatch(M, N, rowptr, colidx, val, c, lc, uc, np.zeros((B, N)), np.full((B, N), INF),
+                       meta=dict(kind=np.array(list(kinds)), seed=seed, row=i), q_factor=F, q_diag=d)
 
 
 def random_qp(m: int, n: int, seed: int, density: float = 0.3) -> LP:

@@ -109,10 +109,10 @@ typedef struct {
     int32_t timing_chunk;        /* >= 0: time the iteration kernels of that
                                     check period with HIP events (result.kernel_*) */
     /* Infeasibility certificates (Appendix A: 1e-8 each; <= 0 switches the
-     * test off). Tested at the checks of an LP solve (CSR or dense A, single
-     * or batched) or of a single QP solve once a restart has happened: the
-     * rays are the PDHG point (the averages for a QP) minus the restart
-     * anchor; a QP's primal ray must also satisfy Q dx = 0. In a batch each instance stops on its
+     * test off). Tested at the checks of every solve (LP with CSR or dense
+     * A, QP, single or batched) once a restart has happened: the rays are the PDHG
+     * point (the averages for a QP) minus the restart anchor; a QP's primal
+     * ray must also satisfy Q dx = 0. In a batch each instance stops on its
      * own certificate and its output slice holds the ray, as for pdhg_solve;
      * with both tolerances <= 0 the batched kernels skip the ray terms and
      * keep a smaller register budget. */

@@ -53,8 +53,10 @@ struct QArgs {
 
 struct QOpts {
     double eps, gamma, beta_suff, beta_nec, beta_art, power_tol;
+    double eps_pinf, eps_dinf;   // infeasibility certificate tolerances
     int64_t limit;
     int32_t check_every, power_max_iters;
+    int32_t detect, pad;         // 1: test the rays at checks
 };
 
 template <int BT, int K>
@@ -326,6 +328,70 @@ __device__ __forceinline__ void qcheck(const QArgs &a, const QI &q, double (&v)[
     qsum<BT, 8>(v);
 }
 
+template <int BT, int K>
+__device__ __forceinline__ void qmax(double (&v)[K]) {
+    constexpr int NW = BT / 64;
+    __shared__ double sh[K][NW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double s = wave_max(v[q]);
+        if (lane == 0) sh[q][wave] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double s = sh[q][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) s = fmax(s, sh[q][w]);
+        v[q] = s;
+    }
+    __syncthreads();
+}
+
+// Ray terms of the averages against the restart anchor (the certificates of
+// Section 3's infeasibility detection): dx = D_c (xbar - x0), dy = D_r (ybar - y0)
+// in the original space. The scaled difference xbar - x0 goes to q.v (free
+// between iterations). rs: 0 dual-ray objective (columns), 1 c'dx, 2 dual-ray
+// objective (rows); rm: 0 dual-ray violation, 1 primal-ray violation including
+// |Q dx|.
+template <int BT>
+__device__ __forceinline__ void qray(const QArgs &a, const QI &q, double (&rs)[3], double (&rm)[2]) {
+    for (int32_t j = threadIdx.x; j < a.n; j += BT) q.v[j] = q.xb[j] - q.x0[j];
+    rs[0] = rs[1] = rs[2] = 0.0;
+    rm[0] = rm[1] = 0.0;
+    {
+        // |Q dx| first: F~'(xbar - x0) is live in this loop only
+        double t[kRmax];
+        qt_of<BT>(a, q.v, t);
+        for (int32_t j = threadIdx.x; j < a.n; j += BT) rm[1] = fmax(rm[1], fabs(qv_row(a, q, j, t, q.v) / a.Dc[j]));
+    }
+    for (int32_t j = threadIdx.x; j < a.n; j += BT) {
+        const double d = a.Dc[j];
+        const double sh = qdot(a.trp, a.tci, a.tva, j, q.yb);
+        const double s0 = qdot(a.trp, a.tci, a.tva, j, q.y0);
+        double s[2], mx[2];
+        ray_col_terms(sh, s0, d, q.v[j], q.c_o[j], q.lv_o[j], q.uv_o[j], s, mx);
+        rs[0] += s[0];
+        rs[1] += s[1];
+        rm[0] = fmax(rm[0], mx[0]);
+        rm[1] = fmax(rm[1], mx[1]);
+    }
+    const bool wr = a.wave_rows != 0;
+    for (int32_t i = wr ? (int32_t)(threadIdx.x >> 6) : (int32_t)threadIdx.x; i < a.m;
+         i += wr ? BT / 64 : BT) {
+        const double p = wr ? qdot_wave(a.arp, a.aci, a.ava, i, q.v) : qdot(a.arp, a.aci, a.ava, i, q.v);
+        if (wr && (threadIdx.x & 63) != 0) continue;
+        double s[1], mx[2];
+        ray_row_terms(p, 0.0, a.Dr[i], q.yb[i] - q.y0[i], q.lc_o[i], q.uc_o[i], s, mx);
+        rs[2] += s[0];
+        rm[0] = fmax(rm[0], mx[0]);
+        rm[1] = fmax(rm[1], mx[1]);
+    }
+    qsum<BT, 3>(rs);
+    qmax<BT, 2>(rm);
+}
+
 template <int BT>
 __device__ __forceinline__ void qrestart(const QArgs &a, const QI &q) {
     for (int32_t j = threadIdx.x; j < a.n; j += BT) {
@@ -393,7 +459,7 @@ __global__ __launch_bounds__(BT) void k_bqp_norm(QArgs a, QOpts o) {
     }
 }
 
-template <int BT>
+template <int BT, bool RAYS>
 __global__ __launch_bounds__(BT) void k_bqp_solve(QArgs a, QOpts o) {
     for (;;) {
         const int32_t b = qnext<BT>(a.queue);
@@ -408,6 +474,7 @@ __global__ __launch_bounds__(BT) void k_bqp_solve(QArgs a, QOpts o) {
         int64_t t = 0, k = 0, restarts = 0;
         double r_start = 0.0, r_prev = 0.0, P = 0.0, D = 0.0, kkt = 0.0, rp = 0.0, rd = 0.0, rg = 0.0;
         int32_t status = 0;
+        double ray_scale = 0.0;
         for (;;) {
             qstep<BT>(a, q, k, omega, normq, nullptr, nullptr);
             const bool check = (t % o.check_every) == 0;
@@ -426,6 +493,22 @@ __global__ __launch_bounds__(BT) void k_bqp_solve(QArgs a, QOpts o) {
                 if (rg > kkt || isnan(rg)) kkt = rg;
                 if (isnan(kkt)) { status = PDHG_NUMERICAL_ERROR; break; }
                 if (kkt <= o.eps) { status = PDHG_OPTIMAL; break; }
+                // the anchor is a restart point once a restart has happened
+                if (RAYS && restarts > 0) {
+                    double rs[3], rm[2];
+                    qray<BT>(a, q, rs, rm);
+                    const double obj_d = rs[0] + rs[2], obj_p = rs[1];
+                    if (o.eps_pinf > 0.0 && obj_d > 0.0 && rm[0] <= o.eps_pinf * obj_d) {
+                        status = PDHG_PRIMAL_INFEASIBLE;
+                        ray_scale = 1.0 / obj_d;
+                        break;
+                    }
+                    if (o.eps_dinf > 0.0 && obj_p < 0.0 && rm[1] <= o.eps_dinf * (-obj_p)) {
+                        status = PDHG_DUAL_INFEASIBLE;
+                        ray_scale = -1.0 / obj_p;
+                        break;
+                    }
+                }
                 if (last) { status = PDHG_ITERATION_LIMIT; break; }
                 const double r = sqrt(omega * ap * ap + ad * ad / omega + ag * ag);
                 bool restart = false;
@@ -454,8 +537,13 @@ __global__ __launch_bounds__(BT) void k_bqp_solve(QArgs a, QOpts o) {
             }
             ++t;
         }
-        for (int32_t j = threadIdx.x; j < a.n; j += BT) a.x_out[(size_t)b * a.n + j] = a.Dc[j] * q.xb[j];
-        for (int32_t i = threadIdx.x; i < a.m; i += BT) a.y_out[(size_t)b * a.m + i] = a.Dr[i] * q.yb[i];
+        // a certificate replaces the average it was found from, scaled to
+        // objective 1 (dual ray) or -1 (primal ray)
+        const bool xray = status == PDHG_DUAL_INFEASIBLE, yray = status == PDHG_PRIMAL_INFEASIBLE;
+        for (int32_t j = threadIdx.x; j < a.n; j += BT)
+            a.x_out[(size_t)b * a.n + j] = a.Dc[j] * (xray ? (q.xb[j] - q.x0[j]) * ray_scale : q.xb[j]);
+        for (int32_t i = threadIdx.x; i < a.m; i += BT)
+            a.y_out[(size_t)b * a.m + i] = a.Dr[i] * (yray ? (q.yb[i] - q.y0[i]) * ray_scale : q.yb[i]);
         if (threadIdx.x == 0) {
             double *r = a.res + (size_t)b * 12;
             r[0] = P; r[1] = D; r[2] = rp; r[3] = rd; r[4] = rg; r[5] = kkt; r[6] = omega;
@@ -720,6 +808,10 @@ static QOpts qopts(const pdhg_options &o) {
     q.limit = std::min<int64_t>(o.iteration_limit, 10000000);
     q.check_every = o.check_every;
     q.power_max_iters = o.power_max_iters;
+    q.eps_pinf = o.eps_primal_infeasible;
+    q.eps_dinf = o.eps_dual_infeasible;
+    q.detect = o.eps_primal_infeasible > 0.0 || o.eps_dual_infeasible > 0.0;
+    q.pad = 0;
     return q;
 }
 
@@ -804,7 +896,11 @@ static void qlaunch_t(BatchHandle &h, QK which, const QArgs &a, const QOpts &o) 
             k_bqp_norm<BT><<<q_wgs(h, k_bqp_norm<BT>, BT), BT, 0, h.stream>>>(a, o);
             break;
         case QK::solve:
-            k_bqp_solve<BT><<<q_wgs(h, k_bqp_solve<BT>, BT), BT, 0, h.stream>>>(a, o);
+            // the ray pass costs registers: kernels without it when the tests are off
+            if (o.detect)
+                k_bqp_solve<BT, true><<<q_wgs(h, k_bqp_solve<BT, true>, BT), BT, 0, h.stream>>>(a, o);
+            else
+                k_bqp_solve<BT, false><<<q_wgs(h, k_bqp_solve<BT, false>, BT), BT, 0, h.stream>>>(a, o);
             break;
         case QK::unrolled:
             k_bqp_unrolled<BT><<<q_wgs(h, k_bqp_unrolled<BT>, BT), BT, 0, h.stream>>>(a, o);
@@ -819,7 +915,10 @@ static void qlaunch_t(BatchHandle &h, QK which, const QArgs &a, const QOpts &o) 
 
 static void qlaunch(BatchHandle &h, QK which, const QArgs &a) {
     const QOpts o = qopts(h.opt);
-    switch (h.threads) {
+    // at 1024 threads the solve kernel with the ray pass spills: 512 unless
+    // the caller chose the shape
+    const int32_t threads = (which == QK::solve && o.detect && !h.threads_set) ? std::min(h.threads, 512) : h.threads;
+    switch (threads) {
         case 64: qlaunch_t<64>(h, which, a, o); break;
         case 128: qlaunch_t<128>(h, which, a, o); break;
         case 512: qlaunch_t<512>(h, which, a, o); break;

@@ -137,3 +137,65 @@ def test_batch_qp_rejects_bad_input(pdhg):
     p["F"][5, 1] = np.nan
     with pytest.raises(Exception):
         pdhg.BatchSolver.from_shared(_batch(p))
+
+
+_KINDS = ["optimal", "primal_infeasible", "dual_infeasible", "optimal", "dual_infeasible", "primal_infeasible"]
+
+
+@pytest.mark.parametrize("m,n,r,seed,threads", [(40, 80, 4, 0, None), (60, 120, 6, 1, None), (40, 80, 4, 0, 1024)])
+def test_batch_qp_infeasibility_matches_oracle(pdhg, oracle_lib, m, n, r, seed, threads):
+    """A shared-A QP batch whose instances are optimal, infeasible or
+    unbounded ends each instance as the oracle ends it. The detection check
+    may differ from the oracle's by a period or two (the batched power
+    iteration starts from another vector, so the trajectories drift apart):
+    every returned ray is checked against its definition with the dense A and
+    Q, and against the oracle's element by element when both stop at the same
+    iteration. 1024 threads per instance is the shape the caller may choose."""
+    _say(f"case: batched QP infeasibility, m={m} n={n} rank={r} seed={seed} threads {threads or 'default'}")
+    sb = gen.mixed_qp_batch(_KINDS, m, n, r, seed)
+    a = gen.dense_from_csr(sb.m, sb.n, sb.rowptr, sb.colidx, sb.val)
+    kw = dict(threads=threads) if threads else {}
+    with pdhg.BatchSolver.from_shared(sb, iteration_limit=100000, **kw) as bs:
+        x, y, res = bs.solve()
+    for b, kind in enumerate(_KINDS):
+        lp = sb.instance(b)
+        xo, yo, ro = oracle_lib.Oracle(lp, iteration_limit=100000).solve()
+        rb = res[b]
+        _say(f"  instance {b} ({kind}): gpu {rb['status_name']} at {rb['iterations']}, "
+             f"oracle {ro['status_name']} at {ro['iterations']}")
+        assert ro["status_name"] == kind
+        assert rb["status_name"] == kind, (b, rb["status_name"], kind)
+        assert abs(rb["iterations"] - ro["iterations"]) <= 4 * 64, (b, rb["iterations"], ro["iterations"])
+        xb, yb = to_np(x[b]), to_np(y[b])
+        if kind == "primal_infeasible":
+            pos, neg = (yb > 0) & np.isfinite(lp.lc), (yb < 0) & np.isfinite(lp.uc)
+            assert abs(np.dot(lp.lc[pos], yb[pos]) + np.dot(lp.uc[neg], yb[neg]) - 1.0) <= 1e-9
+            assert np.max(a.T @ yb) <= 1e-8 * (1 + 1e-6)
+            if rb["iterations"] == ro["iterations"]:
+                assert rel_inf(yb, yo) <= 1e-6
+        elif kind == "dual_infeasible":
+            q = sb.q_factor @ sb.q_factor.T + np.diag(sb.q_diag[b])
+            assert abs(np.dot(lp.c, xb) + 1.0) <= 1e-12
+            assert np.max(np.abs(q @ xb)) <= 1e-8 * (1 + 1e-6)
+            ad = a @ xb
+            eq = lp.lc == lp.uc
+            assert np.max(np.abs(ad[eq])) <= 1e-8 * (1 + 1e-6)
+            assert np.min(ad[~eq & np.isfinite(lp.lc)], initial=0.0) >= -1e-8 * (1 + 1e-6)
+            assert np.max(ad[~eq & np.isfinite(lp.uc)], initial=0.0) <= 1e-8 * (1 + 1e-6)
+            assert np.min(xb) >= -1e-8 and xb[-1] > 0.0
+            if rb["iterations"] == ro["iterations"]:
+                assert rel_inf(xb, xo) <= 1e-6
+        else:
+            assert abs(rb["primal_obj"] - ro["primal_obj"]) <= 1e-5 * (1 + abs(ro["primal_obj"]))
+            assert oracle_lib.kkt(lp, xb, yb)["kkt"] <= 1e-4 * (1 + 1e-6)
+
+
+def test_batch_qp_infeasibility_switched_off(pdhg):
+    _say("case: batched QP with the infeasibility tests off (lean kernel)")
+    sb = gen.mixed_qp_batch(_KINDS, 40, 80, 4, 0)
+    with pdhg.BatchSolver.from_shared(sb, iteration_limit=3000, eps_primal_infeasible=0.0,
+                                      eps_dual_infeasible=0.0) as bs:
+        _, _, res = bs.solve()
+    names = [r["status_name"] for r in res]
+    assert names[1] == names[2] == names[4] == names[5] == "iteration_limit", names
+    assert names[0] == names[3] == "optimal", names

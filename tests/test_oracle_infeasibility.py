@@ -149,3 +149,43 @@ def test_qp_dual_infeasible_certificate(m, n, seed):
     assert np.min(ad[~eq & np.isfinite(lp.lc)], initial=0.0) >= -1e-6
     assert np.max(ad[~eq & np.isfinite(lp.uc)], initial=0.0) <= 1e-6
     assert np.min(d) >= -1e-6 and d[-1] > 0.0
+
+
+_KINDS = ["optimal", "primal_infeasible", "dual_infeasible", "optimal", "dual_infeasible", "primal_infeasible"]
+
+
+@pytest.mark.parametrize("m,n,r,seed", [(40, 80, 4, 0), (60, 120, 6, 1)])
+def test_lowrank_qp_batch_certificates(m, n, r, seed):
+    """The shared-A QP batch with Q_b = F F' + diag(d_b): each instance ends
+    as it was built, checked by means outside the oracle: HiGHS's status of
+    the constraint set (c = 0), the Farkas checks of the dual rays, and the
+    primal rays' definition (c'd = -1, Q d = 0, A d in the rows' recession
+    cones, d >= 0) with the dense Q and A, at the default 1e-8 tolerances."""
+    import copy
+    sb = gen.mixed_qp_batch(_KINDS, m, n, r, seed)
+    a = gen.dense_from_csr(sb.m, sb.n, sb.rowptr, sb.colidx, sb.val)
+    for b, kind in enumerate(_KINDS):
+        lp = sb.instance(b)
+        feas = copy.copy(lp)
+        feas.c = np.zeros(lp.n)
+        assert _highs_status(feas) == (2 if kind == "primal_infeasible" else 0), (b, kind)
+        x, y, res = oracle.Oracle(lp, iteration_limit=100000).solve()
+        assert res["status_name"] == kind, (b, kind, res)
+        if kind == "primal_infeasible":
+            ge = np.isfinite(lp.lc) & ~np.isfinite(lp.uc)
+            le = ~np.isfinite(lp.lc) & np.isfinite(lp.uc)
+            assert np.min(y[ge], initial=0.0) >= -1e-8 and np.max(y[le], initial=0.0) <= 1e-8
+            pos, neg = (y > 0) & np.isfinite(lp.lc), (y < 0) & np.isfinite(lp.uc)
+            assert abs(np.dot(lp.lc[pos], y[pos]) + np.dot(lp.uc[neg], y[neg]) - 1.0) <= 1e-9
+            assert np.max(a.T @ y) <= 1e-8 * (1 + 1e-9)
+        elif kind == "dual_infeasible":
+            d = x
+            q = sb.q_factor @ sb.q_factor.T + np.diag(sb.q_diag[b])
+            assert abs(np.dot(lp.c, d) + 1.0) <= 1e-12
+            assert np.max(np.abs(q @ d)) <= 1e-8 * (1 + 1e-6)
+            ad = a @ d
+            eq = lp.lc == lp.uc
+            assert np.max(np.abs(ad[eq])) <= 1e-8 * (1 + 1e-6)
+            assert np.min(ad[~eq & np.isfinite(lp.lc)], initial=0.0) >= -1e-8 * (1 + 1e-6)
+            assert np.max(ad[~eq & np.isfinite(lp.uc)], initial=0.0) <= 1e-8 * (1 + 1e-6)
+            assert np.min(d) >= -1e-8 and d[-1] > 0.0
