@@ -266,8 +266,8 @@ pdhg_err pdhg_batch_solve(pdhg_batch *b, const double *x_init, const double *y_i
  * the GPU holds). The default after create is 1024 threads when the batch
  * has at most one instance per compute unit, else the fewest threads, from
  * 256, that give each thread at most 8 columns and 8 rows of the largest
- * instance; solves that test infeasibility rays take at most 512 of them
- * unless this call or pdhg_batch_autotune chose the shape. */
+ * instance; QP batches, and LP solves that test infeasibility rays, take at
+ * most 512 of them unless this call or pdhg_batch_autotune chose the shape. */
 pdhg_err pdhg_batch_set_launch(pdhg_batch *b, int32_t threads, int32_t workgroups);
 
 /* Time `iterations` iterations of every instance for each supported thread

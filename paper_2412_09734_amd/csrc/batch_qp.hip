@@ -27,7 +27,7 @@ struct QArgs {
     const int32_t *arp, *aci, *trp, *tci;
     const double *ava, *tva, *Dr, *Dc;
     double eta;
-    const double *F;        // F~ [n][r]
+    const double *FT;       // F~' [r][n] (column p of F~ is contiguous)
     const double *d_o;      // original d [B][n]
     double *normq;          // [B]
     const double *c_o, *lc_o, *uc_o, *lv_o, *uv_o;
@@ -125,24 +125,63 @@ __device__ __forceinline__ QI qinst(const QArgs &a, int32_t b) {
     return q;
 }
 
-// qv_j for the momentum vector already in q.v (t = F~'v known to all threads)
-__device__ __forceinline__ double qv_row(const QArgs &a, const QI &q, int32_t j,
-                                         const double (&t)[kRmax], const double *vv) {
+// (Q~ v)_j = (F~ t)_j + d~_j v_j with t = F~'v from qt_of (in LDS)
+__device__ __forceinline__ double qv_row(const QArgs &a, const QI &q, int32_t j, const double *t,
+                                         const double *vv) {
+    constexpr int U = 4;   // independent loads in flight; the sum stays in order of p
+    const double *__restrict__ fj = a.FT + j;
+    const size_t n = (size_t)a.n;
     double acc = 0.0;
-    for (int32_t p = 0; p < a.r; ++p) acc = fma(a.F[(size_t)j * a.r + p], t[p], acc);
+    int32_t p = 0;
+    for (; p + U <= a.r; p += U) {
+        double f[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) f[u] = fj[(size_t)(p + u) * n];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = fma(f[u], t[p + u], acc);
+    }
+    for (; p < a.r; ++p) acc = fma(fj[(size_t)p * n], t[p], acc);
     return acc + q.dd[j] * vv[j];
 }
 
-// t = F~' w over the instance (workgroup tree); every thread gets all r values
+// t = F~' w over the instance: per p, each thread's columns in order, then the
+// wave butterfly and the waves in order (eight values of p per pass). The r values land in LDS, where every
+// thread reads them (a register array indexed by the runtime rank would live
+// in scratch memory). The next call overwrites them.
 template <int BT>
-__device__ __forceinline__ void qt_of(const QArgs &a, const double *w, double (&t)[kRmax]) {
+__device__ __forceinline__ const double *qt_of(const QArgs &a, const double *w) {
+    constexpr int NW = BT / 64;
+    __shared__ double sh[kRmax][NW];
+    __shared__ double t[kRmax];
+    constexpr int U = 8;   // factor columns per pass: independent loads and butterflies
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t n = (size_t)a.n;
+    for (int32_t p0 = 0; p0 < a.r; p0 += U) {
+        const double *__restrict__ fp = a.FT + (size_t)p0 * n;
+        double s[U];
 #pragma unroll
-    for (int p = 0; p < kRmax; ++p) t[p] = 0.0;
-    for (int32_t j = threadIdx.x; j < a.n; j += BT) {
-        const double wj = w[j];
-        for (int32_t p = 0; p < a.r; ++p) t[p] = fma(a.F[(size_t)j * a.r + p], wj, t[p]);
+        for (int u = 0; u < U; ++u) s[u] = 0.0;
+        for (int32_t j = threadIdx.x; j < a.n; j += BT) {
+            const double wj = w[j];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (p0 + u < a.r) s[u] = fma(fp[(size_t)u * n + j], wj, s[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double ws = wave_sum(s[u]);
+            if (lane == 0 && p0 + u < a.r) sh[p0 + u][wave] = ws;
+        }
     }
-    qsum<BT, kRmax>(t);
+    __syncthreads();
+    if ((int32_t)threadIdx.x < a.r) {
+        double s = 0.0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) s += sh[threadIdx.x][v];
+        t[threadIdx.x] = s;
+    }
+    __syncthreads();
+    return t;
 }
 
 // Transformed data and the norms of one instance.
@@ -209,8 +248,7 @@ __device__ __forceinline__ void qstep(const QArgs &a, const QI &q, int64_t k, do
     const double tau = 1.0 / (omega / a.eta + 2.0 * normq / (double)(k + 1));
     const double sigma = a.eta * omega;
     for (int32_t j = threadIdx.x; j < a.n; j += BT) q.v[j] = (1.0 - beta) * q.xb[j] + beta * q.x[j];
-    double t[kRmax];
-    qt_of<BT>(a, q.v, t);
+    const double *t = qt_of<BT>(a, q.v);
     for (int32_t j0 = 0; j0 < a.n; j0 += BT) {
         const int32_t j = j0 + (int32_t)threadIdx.x;
         bool inside = false;
@@ -287,8 +325,7 @@ __device__ __forceinline__ void qstep(const QArgs &a, const QI &q, int64_t k, do
 //  0 |xbar-x0|^2 1 |r_d|^2 2 x'Qx 3 c'x 4 l_v'lam+ - u_v'lam- 5 |r_p|^2 6 l_c'y+ - u_c'y- 7 |ybar-y0|^2
 template <int BT>
 __device__ __forceinline__ void qcheck(const QArgs &a, const QI &q, double (&v)[8]) {
-    double t[kRmax];
-    qt_of<BT>(a, q.xb, t);
+    const double *t = qt_of<BT>(a, q.xb);
 #pragma unroll
     for (int p = 0; p < 8; ++p) v[p] = 0.0;
     for (int32_t j = threadIdx.x; j < a.n; j += BT) {
@@ -362,8 +399,7 @@ __device__ __forceinline__ void qray(const QArgs &a, const QI &q, double (&rs)[3
     rm[0] = rm[1] = 0.0;
     {
         // |Q dx| first: F~'(xbar - x0) is live in this loop only
-        double t[kRmax];
-        qt_of<BT>(a, q.v, t);
+        const double *t = qt_of<BT>(a, q.v);
         for (int32_t j = threadIdx.x; j < a.n; j += BT) rm[1] = fmax(rm[1], fabs(qv_row(a, q, j, t, q.v) / a.Dc[j]));
     }
     for (int32_t j = threadIdx.x; j < a.n; j += BT) {
@@ -433,8 +469,7 @@ __global__ __launch_bounds__(BT) void k_bqp_norm(QArgs a, QOpts o) {
         __syncthreads();
         double lam = 0.0, lam_prev = 0.0;
         for (int32_t it = 1; it <= o.power_max_iters; ++it) {
-            double t[kRmax];
-            qt_of<BT>(a, vv, t);
+            const double *t = qt_of<BT>(a, vv);
             double s2[2] = {0.0, 0.0};
             for (int32_t j = threadIdx.x; j < a.n; j += BT) {
                 const double w = qv_row(a, q, j, t, vv);
@@ -751,8 +786,7 @@ __global__ __launch_bounds__(BT) void k_bqp_backward(QArgs a, QOpts o) {
                     for (int32_t i = threadIdx.x; i < a.m; i += BT) by[i] += qdot(a.arp, a.aci, a.ava, i, q.xe);
                 }
                 // Q~ v: bv = F~ (F~' bqv) + d~ bqv, gradient in d~
-                double t2[kRmax];
-                qt_of<BT>(a, bqv, t2);
+                const double *t2 = qt_of<BT>(a, bqv);
                 const double *vt = vseg + (size_t)(t - t0) * a.n;
                 for (int32_t j = threadIdx.x; j < a.n; j += BT) {
                     const double bv = qv_row(a, q, j, t2, bqv);
@@ -776,6 +810,7 @@ __global__ __launch_bounds__(BT) void k_bqp_backward(QArgs a, QOpts o) {
     }
 }
 
+// F~' = (D_c F)' stored [r][n] from F [n][r]; flags non-finite entries.
 __global__ __launch_bounds__(kBlock) void k_bqp_scale_factor(int32_t n, int32_t r,
                                                              const double *__restrict__ Dc,
                                                              const double *__restrict__ F,
@@ -783,9 +818,9 @@ __global__ __launch_bounds__(kBlock) void k_bqp_scale_factor(int32_t n, int32_t 
                                                              int32_t *__restrict__ flag) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= (int64_t)n * r) return;
-    const int64_t j = t / r;
+    const int64_t j = t / r, p = t % r;
     if (!isfinite(F[t])) atomicOr(flag, 1);
-    Fo[t] = Dc[j] * F[t];
+    Fo[p * n + j] = Dc[j] * F[t];
 }
 
 }  // namespace pdhg
@@ -835,7 +870,7 @@ static QArgs qargs(BatchHandle &h) {
     double eta = 1.0;
     PDHG_HIP(hipMemcpy(&eta, h.eta.p, sizeof(double), hipMemcpyDeviceToHost));
     a.eta = eta;
-    a.F = h.qF.p;
+    a.FT = h.qF.p;
     a.d_o = h.qd_o.p;
     a.normq = h.normq.p;
     a.c_o = h.c_o.p;
@@ -915,9 +950,9 @@ static void qlaunch_t(BatchHandle &h, QK which, const QArgs &a, const QOpts &o) 
 
 static void qlaunch(BatchHandle &h, QK which, const QArgs &a) {
     const QOpts o = qopts(h.opt);
-    // at 1024 threads the solve kernel with the ray pass spills: 512 unless
-    // the caller chose the shape
-    const int32_t threads = (which == QK::solve && o.detect && !h.threads_set) ? std::min(h.threads, 512) : h.threads;
+    // the QP kernels spill registers at 1024 threads: at most 512 unless the
+    // caller chose the shape
+    const int32_t threads = h.threads_set ? h.threads : std::min(h.threads, 512);
     switch (threads) {
         case 64: qlaunch_t<64>(h, which, a, o); break;
         case 128: qlaunch_t<128>(h, which, a, o); break;
