@@ -125,6 +125,39 @@ __device__ __forceinline__ QI qinst(const QArgs &a, int32_t b) {
     return q;
 }
 
+// On-chip variant: the instance's scaled data and iterates in dynamic LDS
+// (9 n-vectors c~, l~_v, u~_v, d~, x, xbar, x0, x_ext, v and 5 m-vectors
+// l~_c, u~_c, y, ybar, y0). Every one of them is written before it is read
+// (scaling, initial point, or within the step), so nothing is copied in.
+constexpr size_t kQOnchipBytes = 56 * 1024;
+
+__host__ __device__ inline size_t q_onchip_bytes(int32_t n, int32_t m) {
+    return (9 * (size_t)n + 5 * (size_t)m) * sizeof(double);
+}
+
+// The reverse pass adds its cotangent scratch (2 n- and 2 m-vectors).
+__host__ __device__ inline size_t q_onchip_bytes_bwd(int32_t n, int32_t m) {
+    return (11 * (size_t)n + 7 * (size_t)m) * sizeof(double);
+}
+
+__device__ __forceinline__ void q_onchip(const QArgs &a, QI &q, double *lds) {
+    double *p = lds;
+    q.c = p; p += a.n;
+    q.lv = p; p += a.n;
+    q.uv = p; p += a.n;
+    q.dd = p; p += a.n;
+    q.x = p; p += a.n;
+    q.xb = p; p += a.n;
+    q.x0 = p; p += a.n;
+    q.xe = p; p += a.n;
+    q.v = p; p += a.n;
+    q.lc = p; p += a.m;
+    q.uc = p; p += a.m;
+    q.y = p; p += a.m;
+    q.yb = p; p += a.m;
+    q.y0 = p;
+}
+
 // (Q~ v)_j = (F~ t)_j + d~_j v_j with t = F~'v from qt_of (in LDS)
 __device__ __forceinline__ double qv_row(const QArgs &a, const QI &q, int32_t j, const double *t,
                                          const double *vv) {
@@ -494,12 +527,14 @@ __global__ __launch_bounds__(BT) void k_bqp_norm(QArgs a, QOpts o) {
     }
 }
 
-template <int BT, bool RAYS>
+template <int BT, bool RAYS, bool ONCHIP>
 __global__ __launch_bounds__(BT) void k_bqp_solve(QArgs a, QOpts o) {
+    extern __shared__ double qlds[];
     for (;;) {
         const int32_t b = qnext<BT>(a.queue);
         if (b >= a.B) return;
-        const QI q = qinst(a, b);
+        QI q = qinst(a, b);
+        if (ONCHIP) q_onchip(a, q, qlds);
         double cn, bn, cnorm, bnorm;
         qprepare<BT>(a, q, cn, bn, cnorm, bnorm);
         qinit<BT>(a, q, a.x_init ? a.x_init + (size_t)b * a.n : nullptr,
@@ -590,15 +625,17 @@ __global__ __launch_bounds__(BT) void k_bqp_solve(QArgs a, QOpts o) {
 
 // Unrolled rAPDHG: exactly T iterations from zero; schedule recorded or
 // replayed; checkpoints of (x, y, xbar, ybar) before every kCkpt-th iteration.
-template <int BT>
+template <int BT, bool ONCHIP>
 __global__ __launch_bounds__(BT) void k_bqp_unrolled(QArgs a, QOpts o) {
+    extern __shared__ double qlds[];
     const int32_t xw = (a.n + 63) >> 6, yw = (a.m + 63) >> 6;
     const int64_t nck = (a.T + kCkpt - 1) / kCkpt;
     const size_t cks = 2 * (size_t)a.n + 2 * (size_t)a.m;
     for (;;) {
         const int32_t b = qnext<BT>(a.queue);
         if (b >= a.B) return;
-        const QI q = qinst(a, b);
+        QI q = qinst(a, b);
+        if (ONCHIP) q_onchip(a, q, qlds);
         double cn, bn, cnorm, bnorm;
         qprepare<BT>(a, q, cn, bn, cnorm, bnorm);
         qinit<BT>(a, q, nullptr, nullptr);
@@ -671,15 +708,17 @@ __global__ __launch_bounds__(BT) void k_bqp_unrolled(QArgs a, QOpts o) {
 
 // Reverse pass of k_bqp_unrolled: per segment, recompute the momentum points
 // from the checkpoint, then walk the segment backwards.
-template <int BT>
+template <int BT, bool ONCHIP>
 __global__ __launch_bounds__(BT) void k_bqp_backward(QArgs a, QOpts o) {
+    extern __shared__ double qlds[];
     const int32_t xw = (a.n + 63) >> 6, yw = (a.m + 63) >> 6;
     const int64_t nck = (a.T + kCkpt - 1) / kCkpt;
     const size_t cks = 2 * (size_t)a.n + 2 * (size_t)a.m;
     for (;;) {
         const int32_t b = qnext<BT>(a.queue);
         if (b >= a.B) return;
-        const QI q = qinst(a, b);
+        QI q = qinst(a, b);
+        if (ONCHIP) q_onchip(a, q, qlds);
         double cn, bn, cnorm, bnorm;
         qprepare<BT>(a, q, cn, bn, cnorm, bnorm);
         const double normq = a.normq[b];
@@ -691,6 +730,14 @@ __global__ __launch_bounds__(BT) void k_bqp_backward(QArgs a, QOpts o) {
         double *bx = q.x0, *by = q.y0;
         double *bxb = a.bxb + (size_t)b * a.n, *byb = a.byb + (size_t)b * a.m;
         double *bw = a.bw + (size_t)b * a.m, *bqv = a.bqv + (size_t)b * a.n;
+        if (ONCHIP) {
+            // after the 9 n- and 5 m-vectors of q_onchip
+            double *p = qlds + 9 * (size_t)a.n + 5 * (size_t)a.m;
+            bxb = p; p += a.n;
+            bqv = p; p += a.n;
+            byb = p; p += a.m;
+            bw = p;
+        }
         double *gc = a.gc + (size_t)b * a.n, *gd = a.gd + (size_t)b * a.n;
         double *glc = a.glc + (size_t)b * a.m, *guc = a.guc + (size_t)b * a.m;
         for (int32_t j = threadIdx.x; j < a.n; j += BT) {
@@ -910,12 +957,12 @@ static QArgs qargs(BatchHandle &h) {
 }
 
 template <class K>
-static int32_t q_wgs(BatchHandle &h, K kernel, int BT) {
+static int32_t q_wgs(BatchHandle &h, K kernel, int BT, size_t lds = 0) {
     int dev = 0, per_cu = 0;
     PDHG_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     PDHG_HIP(hipGetDeviceProperties(&prop, dev));
-    PDHG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel), BT, 0));
+    PDHG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel), BT, lds));
     int32_t wg = std::min(h.B, std::max(1, per_cu) * prop.multiProcessorCount);
     if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
     return wg;
@@ -932,17 +979,34 @@ static void qlaunch_t(BatchHandle &h, QK which, const QArgs &a, const QOpts &o) 
             break;
         case QK::solve:
             // the ray pass costs registers: kernels without it when the tests are off
-            if (o.detect)
-                k_bqp_solve<BT, true><<<q_wgs(h, k_bqp_solve<BT, true>, BT), BT, 0, h.stream>>>(a, o);
+            if (q_onchip_bytes(a.n, a.m) <= kQOnchipBytes) {
+                const size_t l = q_onchip_bytes(a.n, a.m);
+                if (o.detect)
+                    k_bqp_solve<BT, true, true><<<q_wgs(h, k_bqp_solve<BT, true, true>, BT, l), BT, l, h.stream>>>(a, o);
+                else
+                    k_bqp_solve<BT, false, true><<<q_wgs(h, k_bqp_solve<BT, false, true>, BT, l), BT, l, h.stream>>>(a, o);
+            } else if (o.detect) {
+                k_bqp_solve<BT, true, false><<<q_wgs(h, k_bqp_solve<BT, true, false>, BT), BT, 0, h.stream>>>(a, o);
+            } else {
+                k_bqp_solve<BT, false, false><<<q_wgs(h, k_bqp_solve<BT, false, false>, BT), BT, 0, h.stream>>>(a, o);
+            }
+            break;
+        case QK::unrolled: {
+            const size_t l = q_onchip_bytes(a.n, a.m);
+            if (l <= kQOnchipBytes)
+                k_bqp_unrolled<BT, true><<<q_wgs(h, k_bqp_unrolled<BT, true>, BT, l), BT, l, h.stream>>>(a, o);
             else
-                k_bqp_solve<BT, false><<<q_wgs(h, k_bqp_solve<BT, false>, BT), BT, 0, h.stream>>>(a, o);
+                k_bqp_unrolled<BT, false><<<q_wgs(h, k_bqp_unrolled<BT, false>, BT), BT, 0, h.stream>>>(a, o);
             break;
-        case QK::unrolled:
-            k_bqp_unrolled<BT><<<q_wgs(h, k_bqp_unrolled<BT>, BT), BT, 0, h.stream>>>(a, o);
+        }
+        case QK::backward: {
+            const size_t l = q_onchip_bytes_bwd(a.n, a.m);
+            if (l <= kQOnchipBytes)
+                k_bqp_backward<BT, true><<<q_wgs(h, k_bqp_backward<BT, true>, BT, l), BT, l, h.stream>>>(a, o);
+            else
+                k_bqp_backward<BT, false><<<q_wgs(h, k_bqp_backward<BT, false>, BT), BT, 0, h.stream>>>(a, o);
             break;
-        case QK::backward:
-            k_bqp_backward<BT><<<q_wgs(h, k_bqp_backward<BT>, BT), BT, 0, h.stream>>>(a, o);
-            break;
+        }
     }
     PDHG_HIP(hipGetLastError());
     PDHG_HIP(hipStreamSynchronize(h.stream));

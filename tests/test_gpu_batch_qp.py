@@ -86,6 +86,33 @@ def test_batch_qp_rows_paths_match_oracle(pdhg, oracle_lib, rows):
             assert abs(res[b]["primal_obj"] - ro["primal_obj"]) <= 1e-5 * (1 + abs(ro["primal_obj"]))
 
 
+def test_batch_qp_beyond_lds_matches_oracle(pdhg, oracle_lib):
+    """n = 1,000: the instance's vectors exceed the on-chip budget, so the
+    memory-resident kernels run (solve, unrolled forward and reverse pass)."""
+    _say("case: batched rAPDHG, 2 portfolio QPs n=1000 rank 5 (memory-resident kernels)")
+    p = gen.portfolio_qp_batch(batch=2, n=1000, rank=5, seed=4760)
+    p["uv"] = np.full(1000, 0.05)
+    T = 120
+    rng = np.random.default_rng(6)
+    with pdhg.BatchSolver.from_shared(_batch(p)) as bs:
+        x, y = bs.unrolled(T)
+        gx = rng.standard_normal((2, p["n"]))
+        gc, glc, guc, gd = bs.backward(gx)
+        xs, ys, res = bs.solve()
+        for b in range(2):
+            o = oracle_lib.Oracle(_instance(p, b))
+            xo, yo, sr, sw = o.unrolled_qp(T)
+            assert rel_inf(to_np(x[b]), xo) <= 1e-10
+            assert rel_inf(to_np(y[b]), yo) <= 1e-10
+            gco, glco, guco, gdo = o.backward_qp(T, sr, sw, gx[b], np.zeros(p["m"]))
+            assert rel_inf(to_np(gc[b]), gco) <= 1e-9
+            assert rel_inf(to_np(gd[b]), gdo) <= 1e-9
+            xso, yso, ro = o.solve()
+            assert res[b]["status"] == 1 and ro["status"] == 1
+            assert abs(res[b]["iterations"] - ro["iterations"]) <= 64
+            assert abs(res[b]["primal_obj"] - ro["primal_obj"]) <= 1e-5 * (1 + abs(ro["primal_obj"]))
+
+
 def test_batch_qp_solve_matches_oracle(pdhg, oracle_lib):
     _say("case: batched rAPDHG solve, 6 portfolio QPs n=90 rank 6, eps 1e-6")
     p = gen.portfolio_qp_batch(batch=6, n=90, rank=6, seed=4700)
