@@ -271,7 +271,8 @@ pdhg_err pdhg_batch_solve(pdhg_batch *b, const double *x_init, const double *y_i
 pdhg_err pdhg_batch_set_launch(pdhg_batch *b, int32_t threads, int32_t workgroups);
 
 /* Time `iterations` iterations of every instance for each supported thread
- * count and keep the fastest (written to *best_threads, may be NULL). The
+ * count and keep the fastest (written to *best_threads, may be NULL); for QP
+ * batches the trials are batched rAPDHG solves limited to `iterations`. The
  * solver state is reset afterwards. */
 pdhg_err pdhg_batch_autotune(pdhg_batch *b, int32_t iterations, int32_t *best_threads);
 

@@ -1927,7 +1927,31 @@ void batch_set_launch(BatchHandle &h, int32_t threads, int32_t workgroups) {
 }
 
 int32_t batch_autotune(BatchHandle &h, int32_t iterations) {
-    if (h.q_rank > 0) fail(PDHG_ERR_UNSUPPORTED, "autotune is for LP batches");
+    if (h.q_rank > 0) {
+        // QP batches: time the batched rAPDHG solve at each thread count
+        DBuf<double> xo, yo;
+        xo.alloc((size_t)h.vec_n);
+        yo.alloc((size_t)std::max(1, h.vec_m));
+        const int64_t limit = h.opt.iteration_limit;
+        h.opt.iteration_limit = iterations;
+        int32_t best = h.threads;
+        double best_t = 1e300;
+        h.threads_set = true;
+        for (int32_t t : {64, 128, 256, 512, 1024}) {
+            h.threads = t;
+            bqp_solve(h, nullptr, nullptr, xo.p, yo.p, nullptr);   // warm-up
+            const double t0 = now_seconds();
+            bqp_solve(h, nullptr, nullptr, xo.p, yo.p, nullptr);
+            const double el = now_seconds() - t0;
+            if (el < best_t) {
+                best_t = el;
+                best = t;
+            }
+        }
+        h.opt.iteration_limit = limit;
+        h.threads = best;
+        return best;
+    }
     BOpts o = batch_opts(h.opt);
     o.limit = iterations;
     DBuf<double> xo, yo;

@@ -113,6 +113,22 @@ def test_batch_qp_beyond_lds_matches_oracle(pdhg, oracle_lib):
             assert abs(res[b]["primal_obj"] - ro["primal_obj"]) <= 1e-5 * (1 + abs(ro["primal_obj"]))
 
 
+def test_batch_qp_autotune_then_solve(pdhg, oracle_lib):
+    _say("case: batched rAPDHG autotune (64..1024 threads), then a solve at the chosen shape")
+    p = gen.portfolio_qp_batch(batch=4, n=90, rank=6, seed=4710)
+    with pdhg.BatchSolver.from_shared(_batch(p)) as bs:
+        best = bs.autotune(64)
+        _say(f"  autotuned threads per instance = {best}")
+        assert best in (64, 128, 256, 512, 1024)
+        x, y, res = bs.solve()
+    for b in range(4):
+        lp = gen.portfolio_instance(p, b)
+        _, _, ro = oracle_lib.Oracle(lp).solve()
+        assert res[b]["status"] == 1 and ro["status"] == 1
+        assert abs(res[b]["iterations"] - ro["iterations"]) <= 64
+        assert abs(res[b]["primal_obj"] - ro["primal_obj"]) <= 1e-5 * (1 + abs(ro["primal_obj"]))
+
+
 def test_batch_qp_solve_matches_oracle(pdhg, oracle_lib):
     _say("case: batched rAPDHG solve, 6 portfolio QPs n=90 rank 6, eps 1e-6")
     p = gen.portfolio_qp_batch(batch=6, n=90, rank=6, seed=4700)
