@@ -177,8 +177,35 @@ __device__ __forceinline__ double qv_row(const QArgs &a, const QI &q, int32_t j,
     return acc + q.dd[j] * vv[j];
 }
 
+// Eight wave sums at once: the first three butterfly steps (lane bits 5, 4, 3)
+// each halve the values a lane carries, so 3 + 3 + 1 exchanges of the last
+// value finish the job instead of 8 x 6. Lane l ends with the total of
+// value 4 bit3(l) + 2 bit4(l) + bit5(l).
+__device__ __forceinline__ double wave_sum_x8(const double (&s)[8]) {
+    const int lane = (int)(threadIdx.x & 63);
+    double a[4], b[2];
+    const bool h5 = (lane >> 5) & 1, h4 = (lane >> 4) & 1, h3 = (lane >> 3) & 1;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double keep = h5 ? s[2 * i + 1] : s[2 * i];
+        const double send = h5 ? s[2 * i] : s[2 * i + 1];
+        a[i] = keep + __shfl_xor(send, 32);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double keep = h4 ? a[2 * i + 1] : a[2 * i];
+        const double send = h4 ? a[2 * i] : a[2 * i + 1];
+        b[i] = keep + __shfl_xor(send, 16);
+    }
+    double c = (h3 ? b[1] : b[0]) + __shfl_xor(h3 ? b[0] : b[1], 8);
+    c += __shfl_xor(c, 4);
+    c += __shfl_xor(c, 2);
+    c += __shfl_xor(c, 1);
+    return c;
+}
+
 // t = F~' w over the instance: per p, each thread's columns in order, then the
-// wave butterfly and the waves in order (eight values of p per pass). The r values land in LDS, where every
+// wave reduction and the waves in order (eight values of p per pass). The r values land in LDS, where every
 // thread reads them (a register array indexed by the runtime rank would live
 // in scratch memory). The next call overwrites them.
 template <int BT>
@@ -186,7 +213,7 @@ __device__ __forceinline__ const double *qt_of(const QArgs &a, const double *w) 
     constexpr int NW = BT / 64;
     __shared__ double sh[kRmax][NW];
     __shared__ double t[kRmax];
-    constexpr int U = 8;   // factor columns per pass: independent loads and butterflies
+    constexpr int U = 8;   // factor columns per pass (wave_sum_x8)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const size_t n = (size_t)a.n;
     for (int32_t p0 = 0; p0 < a.r; p0 += U) {
@@ -200,11 +227,9 @@ __device__ __forceinline__ const double *qt_of(const QArgs &a, const double *w) 
             for (int u = 0; u < U; ++u)
                 if (p0 + u < a.r) s[u] = fma(fp[(size_t)u * n + j], wj, s[u]);
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double ws = wave_sum(s[u]);
-            if (lane == 0 && p0 + u < a.r) sh[p0 + u][wave] = ws;
-        }
+        const double ws = wave_sum_x8(s);
+        const int u = 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
+        if ((lane & 7) == 0 && p0 + u < a.r) sh[p0 + u][wave] = ws;
     }
     __syncthreads();
     if ((int32_t)threadIdx.x < a.r) {
