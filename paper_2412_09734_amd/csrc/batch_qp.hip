@@ -27,7 +27,7 @@ struct QArgs {
     const int32_t *arp, *aci, *trp, *tci;
     const double *ava, *tva, *Dr, *Dc;
     double eta;
-    const double *FT;       // F~' [r][n] (column p of F~ is contiguous)
+    const double *FT;       // F~' [r_pad][n], r_pad = r rounded up to 8, zero rows past r
     const double *d_o;      // original d [B][n]
     double *normq;          // [B]
     const double *c_o, *lc_o, *uc_o, *lv_o, *uv_o;
@@ -221,11 +221,11 @@ __device__ __forceinline__ const double *qt_of(const QArgs &a, const double *w) 
         double s[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) s[u] = 0.0;
+        // F~' has zero rows up to a multiple of 8: the loads need no guard
         for (int32_t j = threadIdx.x; j < a.n; j += BT) {
             const double wj = w[j];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (p0 + u < a.r) s[u] = fma(fp[(size_t)u * n + j], wj, s[u]);
+            for (int u = 0; u < U; ++u) s[u] = fma(fp[(size_t)u * n + j], wj, s[u]);
         }
         const double ws = wave_sum_x8(s);
         const int u = 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
@@ -882,7 +882,8 @@ __global__ __launch_bounds__(BT) void k_bqp_backward(QArgs a, QOpts o) {
     }
 }
 
-// F~' = (D_c F)' stored [r][n] from F [n][r]; flags non-finite entries.
+// F~' = (D_c F)' stored [r_pad][n] (rows from r on stay zero) from F [n][r];
+// flags non-finite entries.
 __global__ __launch_bounds__(kBlock) void k_bqp_scale_factor(int32_t n, int32_t r,
                                                              const double *__restrict__ Dc,
                                                              const double *__restrict__ F,
@@ -1067,7 +1068,10 @@ void bqp_create(BatchHandle &h, const pdhg_batch_problem &p) {
     DBuf<int32_t> flag;
     flag.alloc(1);
     PDHG_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
-    h.qF.alloc(nf);
+    // F~' [r_pad][n] with zero rows r..r_pad-1 (r_pad = r rounded up to 8)
+    const size_t nfp = (size_t)h.n * (size_t)((h.q_rank + 7) & ~7);
+    h.qF.alloc(nfp);
+    PDHG_HIP(hipMemsetAsync(h.qF.p, 0, nfp * sizeof(double), s));
     k_bqp_scale_factor<<<(unsigned)std::max<int64_t>(1, ceil_div((int64_t)nf, kBlock)), kBlock, 0, s>>>(
         h.n, h.q_rank, h.Dc.p, F.p, h.qF.p, flag.p);
     check_flag(s, flag.p, "non-finite entry in the factor of Q");
