@@ -24,8 +24,11 @@
  *  - Vector arguments of solve / step / scaling calls are DEVICE pointers on
  *    the GPU the handle was created on. Problem data handed to *_create may
  *    live on the host or the device (pdhg_problem.mem).
- *  - Work is ordered after the caller's stream (passed as void*, a hipStream_t)
- *    and every call returns after its GPU work has completed.
+ *  - The library runs on a stream of its own. The caller's stream (passed to
+ *    *_create as void*, a hipStream_t; NULL = the default stream) must outlive
+ *    the handle: every call first waits for the work already queued on it, so
+ *    inputs produced there are complete, and returns after its own GPU work
+ *    has completed.
  *  - A handle must not be used from two threads at the same time.
  */
 #ifndef PDHG_H

@@ -13,6 +13,7 @@
 #include <deque>
 #include <new>
 
+#include "batch_internal.hpp"
 #include "common.hpp"
 
 namespace pdhg {
@@ -256,8 +257,11 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
 
 using namespace pdhg;
 
+// The caller's stream given at create: every call first waits for the work
+// already queued there (its inputs may have been produced by it).
 struct pdhg_handle {
     Handle h;
+    void *caller = nullptr;
 };
 
 extern "C" {
@@ -331,6 +335,7 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
         h.opt = o;
         PDHG_HIP(hipStreamCreateWithFlags(&h.stream, hipStreamNonBlocking));
         PDHG_HIP(hipEventCreateWithFlags(&h.ev_in, hipEventDisableTiming));
+        ph->caller = stream;
         order_after(h, stream);
         h.st.alloc(1);
         h.dense = p.a_format == PDHG_FMT_DENSE;
@@ -461,6 +466,7 @@ pdhg_err pdhg_solve(pdhg_handle *ph, const double *x_init, const double *y_init,
         if (!ph || !x_out || (ph->h.m > 0 && !y_out))
             fail(PDHG_ERR_INVALID_ARG, "NULL handle or output pointer");
         Handle &h = ph->h;
+        order_after(h, ph->caller);
         pdhg_result local;
         pdhg_result *r = res ? res : &local;
         run_solve(h, x_init, y_init, x_out, y_out, r);
@@ -474,6 +480,7 @@ pdhg_err pdhg_update_data(pdhg_handle *ph, const double *c, const double *lc, co
     return guarded([&] {
         if (!ph) fail(PDHG_ERR_INVALID_ARG, "NULL handle");
         Handle &h = ph->h;
+        order_after(h, ph->caller);
         hipStream_t s = h.stream;
         DBuf<double> tc, tl, tu, tlv, tuv;
         // validate the new data in original order before taking it
@@ -514,6 +521,7 @@ pdhg_err pdhg_debug_step(pdhg_handle *ph, const double *x, const double *y, cons
         if (!(tau > 0.0) || !(sigma > 0.0) || k < 0)
             fail(PDHG_ERR_INVALID_ARG, "tau, sigma must be > 0 and k >= 0");
         Handle &h = ph->h;
+        order_after(h, ph->caller);
         if (h.q_kind) fail(PDHG_ERR_UNSUPPORTED, "pdhg_debug_step is for LP handles");
         hipStream_t s = h.stream;
         launch_reset_state(h);
@@ -543,6 +551,7 @@ pdhg_err pdhg_debug_qp_step(pdhg_handle *ph, const double *x, const double *y,
             fail(PDHG_ERR_INVALID_ARG, "NULL handle or state pointer");
         if (!(omega > 0.0) || k < 0) fail(PDHG_ERR_INVALID_ARG, "omega must be > 0 and k >= 0");
         Handle &h = ph->h;
+        order_after(h, ph->caller);
         if (!h.q_kind) fail(PDHG_ERR_UNSUPPORTED, "pdhg_debug_qp_step is for QP handles");
         hipStream_t s = h.stream;
         launch_gather(s, h.perm_c.p, x, h.x.p, h.n);
@@ -563,6 +572,7 @@ pdhg_err pdhg_get_scaling(pdhg_handle *ph, double *dr, double *dc, double *scala
     return guarded([&] {
         if (!ph) fail(PDHG_ERR_INVALID_ARG, "NULL handle");
         Handle &h = ph->h;
+        order_after(h, ph->caller);
         if (dr) launch_scatter(h.stream, h.perm_r.p, h.Dr.p, dr, h.m);
         if (dc) launch_scatter(h.stream, h.perm_c.p, h.Dc.p, dc, h.n);
         PDHG_HIP(hipStreamSynchronize(h.stream));
@@ -584,7 +594,10 @@ void pdhg_destroy(pdhg_handle *ph) {
 
 struct pdhg_batch {
     BatchHandle *b;
+    void *caller;   // as for pdhg_handle
 };
+
+static void order_after_caller(pdhg_batch *pb) { order_after_stream(pb->b->stream, pb->b->ev, pb->caller); }
 
 pdhg_err pdhg_batch_create(const pdhg_batch_problem *prob, const pdhg_options *opt, void *stream,
                            pdhg_batch **out) {
@@ -598,7 +611,7 @@ pdhg_err pdhg_batch_create(const pdhg_batch_problem *prob, const pdhg_options *o
             pdhg_options_default(&o);
         check_options(o);
         BatchHandle *b = batch_create(*prob, o, stream);
-        *out = new pdhg_batch{b};
+        *out = new pdhg_batch{b, stream};
     });
 }
 
@@ -606,6 +619,7 @@ pdhg_err pdhg_batch_solve(pdhg_batch *pb, const double *x_init, const double *y_
                           double *x_out, double *y_out, pdhg_result *res) {
     return guarded([&] {
         if (!pb || !x_out || !y_out) fail(PDHG_ERR_INVALID_ARG, "NULL batch or output pointer");
+        order_after_caller(pb);
         batch_solve(*pb->b, x_init, y_init, x_out, y_out, res);
     });
 }
@@ -620,6 +634,7 @@ pdhg_err pdhg_batch_set_launch(pdhg_batch *pb, int32_t threads, int32_t workgrou
 pdhg_err pdhg_batch_autotune(pdhg_batch *pb, int32_t iterations, int32_t *best_threads) {
     return guarded([&] {
         if (!pb || iterations < 1) fail(PDHG_ERR_INVALID_ARG, "NULL batch or iterations < 1");
+        order_after_caller(pb);
         const int32_t t = batch_autotune(*pb->b, iterations);
         if (best_threads) *best_threads = t;
     });
@@ -629,6 +644,7 @@ pdhg_err pdhg_batch_update_data(pdhg_batch *pb, const double *c, const double *l
                                 const double *uc, const double *lv, const double *uv) {
     return guarded([&] {
         if (!pb) fail(PDHG_ERR_INVALID_ARG, "NULL batch");
+        order_after_caller(pb);
         batch_update_data(*pb->b, c, lc, uc, lv, uv);
     });
 }
@@ -637,6 +653,7 @@ pdhg_err pdhg_batch_unrolled_forward(pdhg_batch *pb, int64_t T, int32_t replay, 
                                      double *y_out) {
     return guarded([&] {
         if (!pb || !x_out || !y_out) fail(PDHG_ERR_INVALID_ARG, "NULL batch or output pointer");
+        order_after_caller(pb);
         batch_unrolled_forward(*pb->b, T, replay, x_out, y_out);
     });
 }
@@ -645,6 +662,7 @@ pdhg_err pdhg_batch_unrolled_backward(pdhg_batch *pb, const double *gx, const do
                                       double *gc, double *glc, double *guc, double *gd) {
     return guarded([&] {
         if (!pb || !gx || !gc) fail(PDHG_ERR_INVALID_ARG, "NULL batch, gx or gc");
+        order_after_caller(pb);
         batch_backward(*pb->b, gx, gy, gc, glc, guc, gd);
     });
 }

@@ -40,6 +40,8 @@ struct BatchHandle {
     DBuf<double> rp0, rq0, rph, rqh;      // LP: A~x0, A~'y0 of each anchor; this check's products
     // QP batches: Q_b = F F' + diag(d_b), F shared (scaled copy), d per instance
     int32_t q_rank = 0;
+    double q_eta = 1.0;                   // step size of the shared A~ (host copy)
+    int32_t q_cus = 0;                    // compute units of the device
     DBuf<double> qF, qd_o, qdd, normq, xbar, ybar, qv_, qres;
     DBuf<double> ckpt, vseg, bxb, byb, bw, bqv;
     // unrolled iterations: schedule, masks and reverse-pass scratch

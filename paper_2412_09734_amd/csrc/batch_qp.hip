@@ -940,9 +940,7 @@ static QArgs qargs(BatchHandle &h) {
     a.tva = h.tva.p;
     a.Dr = h.Dr.p;
     a.Dc = h.Dc.p;
-    double eta = 1.0;
-    PDHG_HIP(hipMemcpy(&eta, h.eta.p, sizeof(double), hipMemcpyDeviceToHost));
-    a.eta = eta;
+    a.eta = h.q_eta;
     a.FT = h.qF.p;
     a.d_o = h.qd_o.p;
     a.normq = h.normq.p;
@@ -984,12 +982,9 @@ static QArgs qargs(BatchHandle &h) {
 
 template <class K>
 static int32_t q_wgs(BatchHandle &h, K kernel, int BT, size_t lds = 0) {
-    int dev = 0, per_cu = 0;
-    PDHG_HIP(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    PDHG_HIP(hipGetDeviceProperties(&prop, dev));
+    int per_cu = 0;
     PDHG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel), BT, lds));
-    int32_t wg = std::min(h.B, std::max(1, per_cu) * prop.multiProcessorCount);
+    int32_t wg = std::min(h.B, std::max(1, per_cu) * h.q_cus);
     if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
     return wg;
 }
@@ -1058,6 +1053,14 @@ void bqp_create(BatchHandle &h, const pdhg_batch_problem &p) {
     if (p.q_rank < 1 || p.q_rank > kRmax || !p.q_factor || !p.q_diag)
         fail(PDHG_ERR_INVALID_ARG, "QP batches need 1 <= q_rank <= 32, q_factor and q_diag");
     h.q_rank = p.q_rank;
+    {
+        int dev = 0, cus = 0;
+        PDHG_HIP(hipGetDevice(&dev));
+        PDHG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        h.q_cus = std::max(1, cus);
+        // eta depends on A only: read once (the setup launch has completed)
+        PDHG_HIP(hipMemcpy(&h.q_eta, h.eta.p, sizeof(double), hipMemcpyDeviceToHost));
+    }
     const size_t nf = (size_t)h.n * h.q_rank;
     DBuf<double> F;
     F.alloc(nf);

@@ -120,3 +120,51 @@ def test_portfolio_qp_512_sampled(mods, oracle_lib):
         assert abs(rb["iterations"] - ro["iterations"]) <= 64
         assert _close(rb["primal_obj"], ro["primal_obj"], 1e-5)
         assert oracle_lib.kkt(lp, to_np(x[b]), to_np(y[b]))["kkt"] <= 1e-4 * (1 + 1e-6)
+
+
+def test_portfolio_gradient_512_sampled(mods, oracle_lib):
+    """The portfolio gradient step of the benchmark: T = 1000 unrolled
+    iterations, the value head on the caller's stream, then the reverse pass
+    with no host synchronisation in between (the library orders its calls
+    after the caller's stream). The result equals a run with the inputs
+    synchronised first, bit for bit. Sampled instances match the oracle's
+    unrolled forward to 1e-12. The reversed 1,000 iterations amplify rounding
+    (measured: 1e-14 at T = 200, 1e-11 at T = 500, up to 2e-4 at T = 1000,
+    with forwards equal to 1e-15), so two GPU reduction orders (256 and 512
+    threads per instance) disagree by as much as GPU and oracle do: the
+    gradients must match the oracle within ten times that spread (plus 1e-9)."""
+    import torch
+    h, s = mods
+    _say("case: 512 portfolio QPs, T = 1000 unrolled + value head + reverse pass, 3 sampled instances")
+    T = 1000
+    p = gen.portfolio_qp_batch(batch=512, seed=gen.seed_for(4, 500))
+    B = p["c"].shape[0]
+    sbq = SimpleNamespace(m=p["m"], n=p["n"], rowptr=p["rowptr"], colidx=p["colidx"], val=p["val"], c=p["c"],
+                          lc=np.tile(p["lc"], (B, 1)), uc=np.tile(p["uc"], (B, 1)), lv=np.tile(p["lv"], (B, 1)),
+                          uv=np.tile(p["uv"], (B, 1)), q_factor=p["F"], q_diag=p["d"])
+    dev = torch.device("cuda:0")
+    Fd, dd, cd = (torch.from_numpy(v).to(dev) for v in (p["F"], p["d"], p["c"]))
+    runs = {}
+    for threads in (None, 512):
+        with s.BatchSolver.from_shared(sbq, threads=threads) as bs:
+            xT, _ = bs.unrolled(T)
+            _, gx = h.qp_value(Fd, dd, cd, xT)
+            gc, _, _, gd = bs.backward(gx)
+            gc1, gd1 = to_np(gc).copy(), to_np(gd).copy()
+            if threads is None:
+                torch.cuda.synchronize()
+                gc2, _, _, gd2 = bs.backward(gx)
+                assert np.array_equal(gc1, to_np(gc2)) and np.array_equal(gd1, to_np(gd2))
+            runs[threads] = (to_np(xT).copy(), to_np(gx).copy(), gc1, gd1)
+    xTn, gxn, gcn, gdn = runs[None]
+    for b in _sample([0] * B, B, 3, 4):
+        o = oracle_lib.Oracle(gen.portfolio_instance(p, b))
+        xo, _, sr, sw = o.unrolled_qp(T)
+        assert rel_inf(xTn[b], xo) <= 1e-12, (b, rel_inf(xTn[b], xo))
+        gco, _, _, gdo = o.backward_qp(T, sr, sw, gxn[b], np.zeros(p["m"]))
+        sc = rel_inf(gcn[b], runs[512][2][b])
+        sd = rel_inf(gdn[b], runs[512][3][b])
+        _say(f"  instance {b}: gc rel {rel_inf(gcn[b], gco):.2e} (spread {sc:.2e}), "
+             f"gd rel {rel_inf(gdn[b], gdo):.2e} (spread {sd:.2e})")
+        assert rel_inf(gcn[b], gco) <= 10 * sc + 1e-9
+        assert rel_inf(gdn[b], gdo) <= 10 * sd + 1e-9
