@@ -8,6 +8,7 @@ the library is not built or no GPU is present, construction raises.
 from __future__ import annotations
 
 import ctypes as C
+from collections.abc import Sequence
 from typing import Optional
 
 import numpy as np
@@ -209,6 +210,33 @@ class Solver:
         capi.check(rc, "pdhg_update_data")
 
 
+class BatchResults(Sequence):
+    """Per-instance results of a batch solve: the library's result array,
+    each entry turned into a dict when it is read."""
+
+    def __init__(self, arr):
+        self._a = arr
+
+    def __len__(self) -> int:
+        return len(self._a)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self._a[k].as_dict() for k in range(*i.indices(len(self._a)))]
+        i = int(i)
+        if i < 0:
+            i += len(self._a)
+        if not 0 <= i < len(self._a):
+            raise IndexError(i)
+        return self._a[i].as_dict()
+
+    def __add__(self, other):
+        return list(self) + list(other)
+
+    def __radd__(self, other):
+        return list(other) + list(self)
+
+
 class BatchSolver:
     """Many LPs solved in one persistent launch (pdhg_batch_*).
 
@@ -321,7 +349,8 @@ class BatchSolver:
 
     def solve(self, x_init=None, y_init=None):
         """Returns (x, y, results): x [B, n] / y [B, m] for a shared A, flat
-        concatenated vectors for a ragged batch; results is a list of dicts."""
+        concatenated vectors for a ragged batch; results is a sequence of
+        dicts (BatchResults)."""
         xi = None if x_init is None else _to_dev(x_init, torch.float64, self.dev).reshape(-1)
         yi = None if y_init is None else _to_dev(y_init, torch.float64, self.dev).reshape(-1)
         x = torch.empty(self.vec_n, dtype=torch.float64, device=self.dev)
@@ -329,7 +358,7 @@ class BatchSolver:
         res = (capi.Result * self.batch)()
         rc = capi.lib().pdhg_batch_solve(self._h, _ptr(xi), _ptr(yi), _ptr(x), _ptr(y), res)
         capi.check(rc, "pdhg_batch_solve")
-        out = [r.as_dict() for r in res]
+        out = BatchResults(res)
         y = y[: self.vec_m]
         if self.shared:
             return x.reshape(self.batch, self.n), y.reshape(self.batch, self.m), out
