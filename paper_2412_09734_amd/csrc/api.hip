@@ -1,4 +1,4 @@
-// C ABI of libpdhg and the device-resident solve driver.
+// C ABI of libpdhg and the host loop that runs the device-resident solve.
 //
 // The solve runs in check periods of check_every iterations: one check
 // iteration (PDHG point kept, KKT and fixed-point residual, controller,
