@@ -1932,7 +1932,19 @@ int32_t batch_autotune(BatchHandle &h, int32_t iterations) {
         DBuf<double> xo, yo;
         xo.alloc((size_t)h.vec_n);
         yo.alloc((size_t)std::max(1, h.vec_m));
-        const int64_t limit = h.opt.iteration_limit;
+        // the trials run with the limit `iterations`; the caller's limit and
+        // launch shape come back even if a trial fails
+        struct Restore {
+            BatchHandle &h;
+            int64_t limit;
+            int32_t threads;
+            bool set;
+            ~Restore() {
+                h.opt.iteration_limit = limit;
+                h.threads = threads;
+                h.threads_set = set;
+            }
+        } restore{h, h.opt.iteration_limit, h.threads, h.threads_set};
         h.opt.iteration_limit = iterations;
         int32_t best = h.threads;
         double best_t = 1e300;
@@ -1948,8 +1960,8 @@ int32_t batch_autotune(BatchHandle &h, int32_t iterations) {
                 best = t;
             }
         }
-        h.opt.iteration_limit = limit;
-        h.threads = best;
+        restore.threads = best;
+        restore.set = true;
         return best;
     }
     BOpts o = batch_opts(h.opt);
