@@ -44,6 +44,8 @@ struct BatchHandle {
     int32_t q_cus = 0;                    // compute units of the device
     DBuf<double> qF, qd_o, qdd, normq, xbar, ybar, qv_, qres;
     DBuf<double> ckpt, vseg, bxb, byb, bw, bqv;
+    DBuf<double> vall;                    // QP: every momentum point of the unrolled forward
+    bool u_vall = false;
     // unrolled iterations: schedule, masks and reverse-pass scratch
     int64_t unrolled_T = 0;
     int32_t nmax = 0, mmax = 0;           // largest instance (LDS sizing)

@@ -46,6 +46,7 @@ struct QArgs {
     uint64_t *xmask, *ymask;   // [B][T][words]
     double *ckpt;              // [B][nck][2n + 2m]
     double *vseg;              // [B][kCkpt][n]
+    double *vall;              // [B][T][n] every momentum point, or null (recompute from checkpoints)
     const double *gx, *gy;
     double *gc, *glc, *guc, *gd;
     double *bxb, *byb, *bw, *bqv;   // reverse scratch
@@ -687,6 +688,8 @@ __global__ __launch_bounds__(BT) void k_bqp_unrolled(QArgs a, QOpts o) {
             uint64_t *xmt = a.xmask + ((size_t)b * a.T + t) * xw;
             uint64_t *ymt = a.ymask + ((size_t)b * a.T + t) * 2 * yw;
             qstep<BT>(a, q, k, omega, normq, xmt, ymt);
+            if (a.vall)
+                for (int32_t j = threadIdx.x; j < a.n; j += BT) a.vall[((size_t)b * a.T + t) * a.n + j] = q.v[j];
             if (threadIdx.x == 0) {
                 om_[t] = omega;
                 kk_[t] = (int32_t)k;
@@ -780,25 +783,28 @@ __global__ __launch_bounds__(BT) void k_bqp_backward(QArgs a, QOpts o) {
         __syncthreads();
         for (int64_t seg = nck - 1; seg >= 0; --seg) {
             const int64_t t0 = seg * kCkpt, t1 = min(a.T, t0 + kCkpt);
-            // recompute the segment's momentum points from the checkpoint
-            const double *ck = a.ckpt + ((size_t)b * nck + seg) * cks;
-            for (int32_t j = threadIdx.x; j < a.n; j += BT) {
-                q.x[j] = ck[j];
-                q.xb[j] = ck[a.n + j];
-            }
-            for (int32_t i = threadIdx.x; i < a.m; i += BT) {
-                q.y[i] = ck[2 * a.n + i];
-                q.yb[i] = ck[2 * a.n + a.m + i];
-            }
-            __syncthreads();
-            for (int64_t t = t0; t < t1; ++t) {
-                qstep<BT>(a, q, kk_[t], om_[t], normq, nullptr, nullptr);
-                for (int32_t j = threadIdx.x; j < a.n; j += BT) vseg[(size_t)(t - t0) * a.n + j] = q.v[j];
-                if (t + 1 < a.T && rs_[t]) {
-                    for (int32_t j = threadIdx.x; j < a.n; j += BT) q.x[j] = q.xb[j];
-                    for (int32_t i = threadIdx.x; i < a.m; i += BT) q.y[i] = q.yb[i];
+            // recompute the segment's momentum points from the checkpoint,
+            // unless the forward kept them all
+            if (!a.vall) {
+                const double *ck = a.ckpt + ((size_t)b * nck + seg) * cks;
+                for (int32_t j = threadIdx.x; j < a.n; j += BT) {
+                    q.x[j] = ck[j];
+                    q.xb[j] = ck[a.n + j];
+                }
+                for (int32_t i = threadIdx.x; i < a.m; i += BT) {
+                    q.y[i] = ck[2 * a.n + i];
+                    q.yb[i] = ck[2 * a.n + a.m + i];
                 }
                 __syncthreads();
+                for (int64_t t = t0; t < t1; ++t) {
+                    qstep<BT>(a, q, kk_[t], om_[t], normq, nullptr, nullptr);
+                    for (int32_t j = threadIdx.x; j < a.n; j += BT) vseg[(size_t)(t - t0) * a.n + j] = q.v[j];
+                    if (t + 1 < a.T && rs_[t]) {
+                        for (int32_t j = threadIdx.x; j < a.n; j += BT) q.x[j] = q.xb[j];
+                        for (int32_t i = threadIdx.x; i < a.m; i += BT) q.y[i] = q.yb[i];
+                    }
+                    __syncthreads();
+                }
             }
             for (int64_t t = t1 - 1; t >= t0; --t) {
                 if (t < a.T - 1 && rs_[t]) {
@@ -859,7 +865,7 @@ __global__ __launch_bounds__(BT) void k_bqp_backward(QArgs a, QOpts o) {
                 }
                 // Q~ v: bv = F~ (F~' bqv) + d~ bqv, gradient in d~
                 const double *t2 = qt_of<BT>(a, bqv);
-                const double *vt = vseg + (size_t)(t - t0) * a.n;
+                const double *vt = a.vall ? a.vall + ((size_t)b * a.T + t) * a.n : vseg + (size_t)(t - t0) * a.n;
                 for (int32_t j = threadIdx.x; j < a.n; j += BT) {
                     const double bv = qv_row(a, q, j, t2, bqv);
                     gd[j] += bqv[j] * vt[j];
@@ -973,6 +979,7 @@ static QArgs qargs(BatchHandle &h) {
     a.ymask = h.u_ymask.p;
     a.ckpt = h.ckpt.p;
     a.vseg = h.vseg.p;
+    a.vall = h.u_vall ? h.vall.p : nullptr;
     a.bxb = h.bxb.p;
     a.byb = h.byb.p;
     a.bw = h.bw.p;
@@ -1137,6 +1144,14 @@ void bqp_unrolled(BatchHandle &h, int64_t T, int32_t replay, double *x_out, doub
         h.u_kk.alloc((size_t)h.B * T);
         h.ckpt.alloc((size_t)h.B * nck * (2 * (size_t)h.n + 2 * (size_t)h.m));
         h.vseg.alloc((size_t)h.B * kCkpt * h.n);
+        // on-chip instances keep every momentum point (at most 16 GiB), so the
+        // reverse pass needs no recomputation; larger ones recompute segments
+        const size_t vbytes = (size_t)h.B * (size_t)T * (size_t)h.n * sizeof(double);
+        h.u_vall = q_onchip_bytes_bwd(h.n, h.m) <= kQOnchipBytes && vbytes <= ((size_t)16 << 30);
+        if (h.u_vall)
+            h.vall.alloc((size_t)h.B * (size_t)T * (size_t)h.n);
+        else
+            h.vall.release();
         h.bxb.alloc((size_t)h.vec_n);
         h.bqv.alloc((size_t)h.vec_n);
         h.byb.alloc((size_t)std::max(1, h.vec_m));
