@@ -11,6 +11,11 @@
  * with the same names used here: scaling, step size, primal weight, restart
  * rule, KKT composition, check cadence, rAPDHG schedule, frozen schedule).
  * Sums accumulate in long double; nothing is blocked or fused.
+ *
+ * Parity unpinned: restart_due (restart rule) and new_weight (primal-weight
+ * update). The paper defers both rules to other solvers, so no value, closed
+ * form or bound of its own pins them; only the final optima the oracle reaches
+ * through them are pinned.
  */
 #include "oracle.h"
 

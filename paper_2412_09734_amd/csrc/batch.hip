@@ -1927,70 +1927,59 @@ void batch_set_launch(BatchHandle &h, int32_t threads, int32_t workgroups) {
 }
 
 int32_t batch_autotune(BatchHandle &h, int32_t iterations) {
-    if (h.q_rank > 0) {
-        // QP batches: time the batched rAPDHG solve at each thread count
-        DBuf<double> xo, yo;
-        xo.alloc((size_t)h.vec_n);
-        yo.alloc((size_t)std::max(1, h.vec_m));
-        // the trials run with the limit `iterations`; the caller's limit and
-        // launch shape come back even if a trial fails
-        struct Restore {
-            BatchHandle &h;
-            int64_t limit;
-            int32_t threads;
-            bool set;
-            ~Restore() {
-                h.opt.iteration_limit = limit;
-                h.threads = threads;
-                h.threads_set = set;
-            }
-        } restore{h, h.opt.iteration_limit, h.threads, h.threads_set};
-        h.opt.iteration_limit = iterations;
-        int32_t best = h.threads;
-        double best_t = 1e300;
-        h.threads_set = true;
-        for (int32_t t : {64, 128, 256, 512, 1024}) {
-            h.threads = t;
-            bqp_solve(h, nullptr, nullptr, xo.p, yo.p, nullptr);   // warm-up
-            const double t0 = now_seconds();
-            bqp_solve(h, nullptr, nullptr, xo.p, yo.p, nullptr);
-            const double el = now_seconds() - t0;
-            if (el < best_t) {
-                best_t = el;
-                best = t;
-            }
+    // Every trial runs with the limit `iterations` into temporary outputs; the
+    // caller's limit, launch shape and output pointers come back even if a
+    // trial fails, and the best thread count is kept only on success.
+    struct Restore {
+        BatchHandle &h;
+        int64_t limit;
+        int32_t threads;
+        bool set;
+        const double *x_init, *y_init;
+        double *x_out, *y_out;
+        ~Restore() {
+            h.opt.iteration_limit = limit;
+            h.threads = threads;
+            h.threads_set = set;
+            h.x_init_ = x_init;
+            h.y_init_ = y_init;
+            h.x_out_ = x_out;
+            h.y_out_ = y_out;
         }
-        restore.threads = best;
-        restore.set = true;
-        return best;
-    }
-    BOpts o = batch_opts(h.opt);
-    o.limit = iterations;
+    } restore{h, h.opt.iteration_limit, h.threads, h.threads_set,
+              h.x_init_, h.y_init_, h.x_out_, h.y_out_};
     DBuf<double> xo, yo;
     xo.alloc((size_t)h.vec_n);
-    yo.alloc((size_t)h.vec_m);
+    yo.alloc((size_t)std::max(1, h.vec_m));
+    const bool qp = h.q_rank > 0;
+    BOpts o = batch_opts(h.opt);
+    o.limit = iterations;
+    h.opt.iteration_limit = iterations;
     h.x_out_ = xo.p;
     h.y_out_ = yo.p;
     h.x_init_ = nullptr;
     h.y_init_ = nullptr;
+    auto trial = [&]() {
+        if (qp) bqp_solve(h, nullptr, nullptr, xo.p, yo.p, nullptr);
+        else dispatch_solve(h, o);
+        PDHG_HIP(hipStreamSynchronize(h.stream));
+    };
     int32_t best = h.threads;
     double best_t = 1e300;
     h.threads_set = true;   // each trial runs the thread count it names
     for (int32_t t : {64, 128, 256, 512, 1024}) {
         h.threads = t;
-        dispatch_solve(h, o);   // warm-up
-        PDHG_HIP(hipStreamSynchronize(h.stream));
+        trial();   // warm-up
         const double t0 = now_seconds();
-        dispatch_solve(h, o);
-        PDHG_HIP(hipStreamSynchronize(h.stream));
+        trial();
         const double el = now_seconds() - t0;
         if (el < best_t) {
             best_t = el;
             best = t;
         }
     }
-    h.threads = best;
-    h.threads_set = true;
+    restore.threads = best;
+    restore.set = true;
     return best;
 }
 

@@ -560,3 +560,82 @@ def test_unrolled_qp_envelope(oracle_lib):
     gc, _, _, gd = o.backward_qp(T, sr, sw, qx + lp.c, np.zeros(lp.m))
     np.testing.assert_allclose(gc + x, xs, atol=2e-4)
     np.testing.assert_allclose(gd + 0.5 * x * x, 0.5 * xs * xs, atol=2e-4)
+
+
+# ---------------------------------------------------------------------------
+# ||Q~||_2 (Algorithm 2's step sizes use it; the power iteration of reading R11)
+
+
+def _splitmix64(x: int) -> int:
+    """SplitMix64 (Steele, Lea and Flood, 2014): first output of the generator
+    seeded with x."""
+    mask = (1 << 64) - 1
+    z = (x + 0x9E3779B97F4A7C15) & mask
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+    return z ^ (z >> 31)
+
+
+def _dense_q(lp):
+    if lp.q_kind == "lowrank":
+        return lp.q_factor @ lp.q_factor.T + np.diag(lp.q_diag)
+    return gen.dense_from_csr(lp.n, lp.n, lp.q_rowptr, lp.q_colidx, lp.q_val)
+
+
+def _norm_q_cases():
+    p = gen.portfolio_qp_batch(batch=1, n=80, rank=6, seed=41)
+    dense_q = gen.random_qp(6, 12, seed=5)   # G G' + 0.1 I stored with every entry
+    return [gen.portfolio_instance(p, 0), gen.random_qp(5, 9, seed=3),
+            gen.infeasible_qp("duplicate_row", seed=2), dense_q]
+
+
+def test_splitmix64_published_outputs():
+    """The generator's first outputs for seed 0 as published with it."""
+    assert _splitmix64(0) == 0xE220A8397B1DCDAF
+    assert _splitmix64(0x9E3779B97F4A7C15) == 0x6E789E6AA1B965F4
+
+
+def test_norm_q_matches_dense_eigenvalue(oracle_lib):
+    """The converged estimate is the largest eigenvalue of Q~ = D_c Q D_c (its
+    2-norm, Q~ being PSD), approached from below. With Rayleigh quotients
+    converging like rho^(2k), rho = lambda_2 / lambda_1, the stopping test
+    (relative change <= 1e-7) leaves a relative error of at most about
+    1e-7 rho^2 / (1 - rho^2); the bar adds a factor 2. A square root of the
+    eigenvalue, or a Q~ scaled by D_c once instead of on both sides, fails it."""
+    for lp in _norm_q_cases():
+        sc = _orc(lp).scaling()
+        qs = sc["dc"][:, None] * _dense_q(lp) * sc["dc"][None, :]
+        ev = np.linalg.eigvalsh(qs)
+        lam, lam2 = ev[-1], ev[-2]
+        assert abs(np.linalg.norm(qs, 2) - lam) <= 1e-12 * lam
+        rho2 = (lam2 / lam) ** 2
+        bar = 2e-7 * rho2 / (1 - rho2) + 1e-13
+        assert lam * (1 - bar) <= sc["norm_q"] <= lam * (1 + 1e-12), (sc["norm_q"], lam, bar)
+        assert abs(sc["norm_q"] - lam) > 1e-3 * lam or abs(np.sqrt(lam) - lam) > 1e-3 * lam
+
+
+def test_norm_q_rayleigh_quotients_of_the_start_vector(oracle_lib):
+    """Stopped after k power steps, the estimate is the Rayleigh quotient of
+    Q~^(k-1) v0: m_(2k-1) / m_(2k-2) with moments m_j = v0' Q~^j v0, v0 the
+    normalised start vector v0_j = 0.5 + u_j (u_j from SplitMix64 at counter
+    j, the top 53 bits). It rises monotonically towards lambda_max. Returning
+    |Q~ v| (= sqrt(m_2k / m_(2k-2))) or its square root fails it."""
+    for lp in _norm_q_cases():
+        v0 = np.array([0.5 + (_splitmix64(j) >> 11) * 2.0 ** -53 for j in range(lp.n)])
+        v0 /= np.linalg.norm(v0)
+        sc = _orc(lp).scaling()
+        qs = sc["dc"][:, None] * _dense_q(lp) * sc["dc"][None, :]
+        mom = [v0 @ v0]
+        w = v0.copy()
+        for _ in range(8):
+            w = qs @ w
+            mom.append(v0 @ w)
+        prev = -np.inf
+        for k in range(1, 5):
+            est = _orc(lp, power_max_iters=k).scaling()["norm_q"]
+            ref = mom[2 * k - 1] / mom[2 * k - 2]
+            assert abs(est - ref) <= 1e-12 * ref, (k, est, ref)
+            assert abs(np.sqrt(mom[2 * k] / mom[2 * k - 2]) - ref) > 1e-9 * ref
+            assert est >= prev * (1 - 1e-14)
+            prev = est
+        assert prev <= np.linalg.eigvalsh(qs)[-1] * (1 + 1e-12)
