@@ -123,6 +123,9 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="batch size override (batched modes)")
     ap.add_argument("--threads", type=int, default=0,
                     help="threads per instance of the batch solves (default: the library's choice)")
+    ap.add_argument("--layout", default="",
+                    help="sparse workloads: product-layout options of the solver as "
+                         "key=value,... (panel_rows, panel_min_len, panel_wgs, hot_cols)")
     ap.add_argument("--loop-sample", type=int, default=16,
                     help="instances solved one at a time for the looped comparison")
     args = ap.parse_args()
@@ -180,6 +183,11 @@ def main():
         extra["feasibility_polishing"] = 1
     if args.eps != 1e-4:
         extra["eps"] = args.eps
+    for kv in filter(None, args.layout.split(",")):
+        k, v = kv.split("=")
+        if k not in ("panel_rows", "panel_min_len", "panel_wgs", "hot_cols"):
+            raise SystemExit(f"unknown layout option {k}")
+        extra[k] = int(v)
 
     def step(timing_chunk=-1):
         with Solver(lp.m, lp.n, device=dev, timing_chunk=timing_chunk, **extra, **data) as s:

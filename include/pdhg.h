@@ -128,6 +128,20 @@ typedef struct {
      * of the second, with the KKT terms of that point. */
     int32_t feasibility_polishing;
     double eps_feas_polish;
+    /* Layouts of the plain-iteration products of a large CSR constraint matrix
+     * (the checks keep the standard layout; results differ only in the order
+     * of summation). -1 selects the automatic choice.
+     * panel_rows: entries of y staged in LDS per panel for the product A~'y
+     *   over the longest rows of A~' (auto: 16384 when m > 262144, else off;
+     *   0: off; at most 16384);
+     * panel_min_len: rows of A~' longer than this use the panels (auto: 16);
+     * panel_wgs: workgroups per panel (auto: 4);
+     * hot_cols: leading entries of x_ext staged in LDS by the product A~x_ext
+     *   (auto: 16384 when n > 262144, else off; 0: off; at most 16384). */
+    int32_t panel_rows;
+    int32_t panel_min_len;
+    int32_t panel_wgs;
+    int32_t hot_cols;
 } pdhg_options;
 
 typedef struct {
@@ -194,6 +208,18 @@ pdhg_err pdhg_debug_step(pdhg_handle *h, const double *x, const double *y,
                          const double *x0, const double *y0, int64_t k, double tau,
                          double sigma, double *xhat, double *yhat, double *xnew,
                          double *ynew);
+
+/* Exactly one plain LP iteration (eq. (pdhg-lp) then eq. (hrpdhg)), the one
+ * that pdhg_solve runs between checks, in the SCALED space, original variable
+ * order: from (x, y) with anchors (x0, y0), inner counter k and steps tau,
+ * sigma, writes the Halpern point (xnew, ynew). It runs the kernels and
+ * product layouts of the solve's plain iterations (the LDS panels and hot
+ * columns of a large sparse A), which pdhg_debug_step (check kernels) does
+ * not. Device pointers; outputs may be NULL. LP handles only (UNSUPPORTED
+ * otherwise). */
+pdhg_err pdhg_debug_plain_step(pdhg_handle *h, const double *x, const double *y,
+                               const double *x0, const double *y0, int64_t k, double tau,
+                               double sigma, double *xnew, double *ynew);
 
 /* Exactly one rAPDHG iteration (Algorithm 2) in the SCALED space, original
  * variable order, for a handle with a quadratic term: from (x, y) and the

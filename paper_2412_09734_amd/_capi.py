@@ -39,7 +39,8 @@ class Options(C.Structure):
                 ("display_frequency", C.c_int32), ("use_graph", C.c_int32),
                 ("timing_chunk", C.c_int32), ("eps_primal_infeasible", C.c_double),
                 ("eps_dual_infeasible", C.c_double), ("feasibility_polishing", C.c_int32),
-                ("eps_feas_polish", C.c_double)]
+                ("eps_feas_polish", C.c_double), ("panel_rows", C.c_int32),
+                ("panel_min_len", C.c_int32), ("panel_wgs", C.c_int32), ("hot_cols", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -76,6 +77,7 @@ SIGNATURES = {
     "pdhg_solve": (C.c_int, [P, P, P, P, P, C.POINTER(Result)]),
     "pdhg_update_data": (C.c_int, [P, P, P, P, P, P]),
     "pdhg_debug_step": (C.c_int, [P, P, P, P, P, C.c_int64, C.c_double, C.c_double, P, P, P, P]),
+    "pdhg_debug_plain_step": (C.c_int, [P, P, P, P, P, C.c_int64, C.c_double, C.c_double, P, P]),
     "pdhg_get_scaling": (C.c_int, [P, P, P, P, P]),
     "pdhg_debug_qp_step": (C.c_int, [P, P, P, P, P, C.c_int64, C.c_double, P, P, P, P]),
     "pdhg_destroy": (None, [P]),

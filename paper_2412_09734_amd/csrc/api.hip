@@ -27,6 +27,9 @@ Handle::~Handle() {
     if (chunk_graph) (void)hipGraphDestroy(chunk_graph);
     if (st_host) (void)hipHostFree(st_host);
     if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (stream2) (void)hipStreamDestroy(stream2);
     if (stream) (void)hipStreamDestroy(stream);
 }
 
@@ -66,7 +69,10 @@ static void order_after(Handle &h, void *caller) { order_after_stream(h.stream, 
 void check_options(const pdhg_options &o) {
     if (!(o.eps > 0.0) || o.iteration_limit < 1 || o.check_every < 1 || o.ruiz_iters < 0 ||
         !(o.gamma >= 0.0 && o.gamma <= 1.0) || !(o.step_safety > 0.0 && o.step_safety <= 1.0) ||
-        o.power_max_iters < 1 || !(o.power_tol >= 0.0) || o.display_frequency < 1)
+        o.power_max_iters < 1 || !(o.power_tol >= 0.0) || o.display_frequency < 1 ||
+        o.panel_rows < -1 || o.panel_rows > kPanelMax || o.panel_min_len < -1 ||
+        o.panel_wgs < -1 || o.panel_wgs == 0 || o.panel_wgs > 64 || o.hot_cols < -1 ||
+        o.hot_cols > kPanelMax)
         fail(PDHG_ERR_INVALID_ARG, "option out of range");
 }
 
@@ -290,6 +296,10 @@ void pdhg_options_default(pdhg_options *o) {
     o->eps_dual_infeasible = 1e-8;
     o->feasibility_polishing = 0;
     o->eps_feas_polish = 1e-6;
+    o->panel_rows = -1;
+    o->panel_min_len = -1;
+    o->panel_wgs = -1;
+    o->hot_cols = -1;
 }
 
 const char *pdhg_last_error(void) { return g_err.c_str(); }
@@ -355,6 +365,13 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
         if (p.q_format != PDHG_FMT_NONE) {
             qp_build(h, p);
             qp_estimate_norm(h);
+        } else if (!h.dense) {
+            build_fast_layouts(h);
+            if (h.PT.R > 0) {
+                PDHG_HIP(hipStreamCreateWithFlags(&h.stream2, hipStreamNonBlocking));
+                PDHG_HIP(hipEventCreateWithFlags(&h.ev_fork, hipEventDisableTiming));
+                PDHG_HIP(hipEventCreateWithFlags(&h.ev_join, hipEventDisableTiming));
+            }
         }
         h.pn.alloc((size_t)std::max(1, h.nbn) * 6);
         h.pm.alloc((size_t)std::max(1, h.nbm) * 4);
@@ -539,6 +556,32 @@ pdhg_err pdhg_debug_step(pdhg_handle *ph, const double *x, const double *y, cons
         if (yhat) launch_scatter(s, h.perm_r.p, h.yhat.p, yhat, h.m);
         if (xnew) launch_scatter(s, h.perm_c.p, xn.p, xnew, h.n);
         if (ynew) launch_scatter(s, h.perm_r.p, yn.p, ynew, h.m);
+        PDHG_HIP(hipStreamSynchronize(s));
+    });
+}
+
+pdhg_err pdhg_debug_plain_step(pdhg_handle *ph, const double *x, const double *y,
+                               const double *x0, const double *y0, int64_t k, double tau,
+                               double sigma, double *xnew, double *ynew) {
+    return guarded([&] {
+        if (!ph || !x || !x0 || (ph->h.m > 0 && (!y || !y0)))
+            fail(PDHG_ERR_INVALID_ARG, "NULL handle or state pointer");
+        if (!(tau > 0.0) || !(sigma > 0.0) || k < 0)
+            fail(PDHG_ERR_INVALID_ARG, "tau, sigma must be > 0 and k >= 0");
+        Handle &h = ph->h;
+        order_after(h, ph->caller);
+        if (h.q_kind) fail(PDHG_ERR_UNSUPPORTED, "pdhg_debug_plain_step is for LP handles");
+        hipStream_t s = h.stream;
+        launch_reset_state(h);
+        launch_set_step(h, tau, sigma, k);
+        launch_gather(s, h.perm_c.p, x, h.x.p, h.n);
+        launch_gather(s, h.perm_c.p, x0, h.x0.p, h.n);
+        launch_gather(s, h.perm_r.p, y, h.y.p, h.m);
+        launch_gather(s, h.perm_r.p, y0, h.y0.p, h.m);
+        launch_primal(h, 1);
+        launch_dual(h, 1);
+        if (xnew) launch_scatter(s, h.perm_c.p, h.x.p, xnew, h.n);
+        if (ynew) launch_scatter(s, h.perm_r.p, h.y.p, ynew, h.m);
         PDHG_HIP(hipStreamSynchronize(s));
     });
 }

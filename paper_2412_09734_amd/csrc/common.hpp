@@ -118,6 +118,70 @@ inline MatView view(const HMat &M) {
     return v;
 }
 
+// LDS panels for the product A~'y over rows [0, R) of A~' (the longest rows).
+// The gathered vector y is cut into panels of S consecutive entries (S doubles
+// fit in LDS). A sub-row is the part of a row whose entries fall in one panel;
+// sub-rows longer than kPanelPiece are cut into pieces. Each panel stores its
+// pieces as SELL-64 slices (pieces sorted by length, entries column-major in
+// a slice, the y index relative to the panel in 16 bits), so one lane sums one
+// piece in entry order. The first piece of sub-row (p, row) is stored to
+// part[p * R + row] (bit p of the row's mask says the sub-row exists); further
+// pieces go to part[P * R + x], listed per row in xptr / xslot.
+constexpr int kPanelMax = 16384;   // doubles per LDS panel (128 KB)
+constexpr int kPanelWaves = 16;    // waves per panel workgroup
+constexpr int kPanelThreads = 64 * kPanelWaves;
+constexpr int kPanelPiece = 128;   // longest piece one lane sums
+struct PanelMat {
+    int32_t R = 0, S = 0, P = 0, W64 = 0;   // rows, panel size, panels, mask words per row
+    int32_t vlen = 0;                       // length of the gathered vector
+    int32_t W = 0;                          // workgroups per panel
+    int32_t nslices = 0, nwg = 0, nx = 0;
+    int64_t entries = 0;                    // real entries
+    DBuf<uint16_t> idx;      // soff[nslices] entries
+    DBuf<double> val;
+    DBuf<int32_t> soff;      // nslices + 1: first entry of each slice
+    DBuf<int32_t> slot;      // nslices * 64: partial of each lane (-1: none)
+    DBuf<int32_t> pslice;    // P + 1: first slice of each panel
+    DBuf<int32_t> wg_panel;  // nwg: panel of each workgroup (-1: idle)
+    DBuf<int32_t> wg_rank;   // nwg: rank of the workgroup within its panel
+    DBuf<uint64_t> mask;     // [W64][R]
+    DBuf<int32_t> xptr;      // R + 1
+    DBuf<int32_t> xslot;     // nx
+    DBuf<double> part;       // P * R + nx
+};
+
+struct PanelView {
+    const uint16_t *idx;
+    const double *val;
+    const int32_t *soff, *slot, *pslice, *wg_panel, *wg_rank;
+    const uint64_t *mask;
+    const int32_t *xptr, *xslot;
+    double *part;
+    int32_t R, S, P, W64, vlen, W;
+};
+
+inline PanelView view(const PanelMat &M) {
+    PanelView v;
+    v.idx = M.idx.p;
+    v.val = M.val.p;
+    v.soff = M.soff.p;
+    v.slot = M.slot.p;
+    v.pslice = M.pslice.p;
+    v.wg_panel = M.wg_panel.p;
+    v.wg_rank = M.wg_rank.p;
+    v.mask = M.mask.p;
+    v.xptr = M.xptr.p;
+    v.xslot = M.xslot.p;
+    v.part = M.part.p;
+    v.R = M.R;
+    v.S = M.S;
+    v.P = M.P;
+    v.W64 = M.W64;
+    v.vlen = M.vlen;
+    v.W = M.W;
+    return v;
+}
+
 // Solver scalars kept on the device; the controller kernel owns them.
 struct DevState {
     double tau, sigma, omega, eta;
@@ -184,6 +248,18 @@ struct Handle {
     bool dense = false;
     DBuf<double> Ad, dpart;
     int32_t nbn = 0, nbm = 0;            // workgroups of the column / row check passes
+    // plain-iteration layouts of a large sparse A~ (the check kernels keep A, AT):
+    // LDS panels for the long rows of A~' (their products run beside the SELL-64
+    // rest of A~' on stream2), and the leading x_ext entries staged in LDS by
+    // the dual product
+    PanelMat PT;
+    int32_t sell_skip = 0;               // SELL-64 slices of AT that the panels cover
+    int32_t hot_cols = 0;                // 0: the dual product gathers x_ext from memory
+    int32_t dual_wgs = 0;                // persistent workgroups of the hot dual product
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::vector<int32_t> at_rowptr_host; // rows of A~' the panels may cover (kept from the build)
+    std::vector<int32_t> at_colidx_host;
     ~Handle();
 };
 
@@ -214,6 +290,7 @@ void scale_problem(Handle &h);
 void transform_vectors(Handle &h);
 void estimate_steps(Handle &h);
 void compute_weight(Handle &h);
+void build_fast_layouts(Handle &h);
 SegTable make_segments(const std::vector<int32_t> &class_count, int32_t rows);
 void validate_csr(hipStream_t s, const int32_t *rowptr, const int32_t *colidx, const double *val,
                   int32_t m, int32_t n, int64_t nnz);
@@ -280,6 +357,7 @@ void launch_zero_finite(Handle &h, double *v, int32_t len);
 void launch_init_point(Handle &h, const double *x_init, const double *y_init);
 void launch_finalize(Handle &h, double *x_out, double *y_out);
 void launch_reset_state(Handle &h);
+void launch_set_step(Handle &h, double tau, double sigma, int64_t k);
 void launch_debug_halpern(Handle &h, int64_t k, double *xnew_int, double *ynew_int);
 void launch_gather(hipStream_t s, const int32_t *perm, const double *src, double *dst, int32_t len);
 void launch_scatter(hipStream_t s, const int32_t *perm, const double *src, double *dst, int32_t len);

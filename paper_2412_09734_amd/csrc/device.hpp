@@ -6,6 +6,8 @@
 
 namespace pdhg {
 
+constexpr int kSellUnroll = 8;   // SELL-64 entries whose loads are in flight together
+
 struct RowCtx {
     int32_t row;
     int32_t lg;    // log2(lanes per row)
@@ -81,19 +83,11 @@ __device__ __forceinline__ int32_t slice_of(const MatView &M) {
     return ((int32_t)blockIdx.x - M.seg.nblocks) * (kBlock / 64) + (int32_t)(threadIdx.x >> 6);
 }
 
-// Row sum of val * x[col] for the row owned by this thread (hybrid layout).
-// Long rows: lane groups with a butterfly; short rows: one thread per row,
+// Row sum over SELL-64 slice sl (wave-uniform) for the row of this lane:
 // entries walked in order with independent, coalesced loads.
-__device__ __forceinline__ RowSum mat_row_dot(const MatView &M, const double *__restrict__ x) {
+__device__ __forceinline__ RowSum sell_row_dot(const MatView &M, const double *__restrict__ x,
+                                               int32_t sl) {
     RowSum r;
-    const int32_t sl = slice_of(M);
-    if (sl < 0) {
-        const RowCtx rc = row_ctx(M.seg);
-        r.s = row_dot(M.rowptr, M.colidx, M.val, x, rc);
-        r.row = rc.row;
-        r.valid = rc.valid && rc.lead;
-        return r;
-    }
     const int32_t lane = (int32_t)(threadIdx.x & 63);
     r.row = M.R_long + sl * 64 + lane;
     r.valid = sl < M.nslices && r.row < M.rows;
@@ -103,27 +97,45 @@ __device__ __forceinline__ RowSum mat_row_dot(const MatView &M, const double *__
         const int32_t w = (__builtin_amdgcn_readfirstlane(M.slice_ptr[sl + 1]) - b) >> 6;
         const int32_t *__restrict__ ci = M.colidx + b + lane;
         const double *__restrict__ va = M.val + b + lane;
-        int32_t k = 0;
-        for (; k + 4 <= w; k += 4) {
-            const int32_t c0 = __builtin_nontemporal_load(ci + 64 * k);
-            const int32_t c1 = __builtin_nontemporal_load(ci + 64 * (k + 1));
-            const int32_t c2 = __builtin_nontemporal_load(ci + 64 * (k + 2));
-            const int32_t c3 = __builtin_nontemporal_load(ci + 64 * (k + 3));
-            const double a0 = __builtin_nontemporal_load(va + 64 * k);
-            const double a1 = __builtin_nontemporal_load(va + 64 * (k + 1));
-            const double a2 = __builtin_nontemporal_load(va + 64 * (k + 2));
-            const double a3 = __builtin_nontemporal_load(va + 64 * (k + 3));
-            const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-            acc = fma(a0, x0, acc);
-            acc = fma(a1, x1, acc);
-            acc = fma(a2, x2, acc);
-            acc = fma(a3, x3, acc);
+        // groups of kSellUnroll entries: every load of a group is issued before
+        // the first product, also for the last, partial group (the group size
+        // is uniform over the wave); the products are added in entry order
+        for (int32_t k = 0; k < w; k += kSellUnroll) {
+            const int32_t nk = min(kSellUnroll, w - k);
+            int32_t c[kSellUnroll];
+            double a[kSellUnroll], xv[kSellUnroll];
+#pragma unroll
+            for (int u = 0; u < kSellUnroll; ++u)
+                if (u < nk) {
+                    c[u] = __builtin_nontemporal_load(ci + 64 * (k + u));
+                    a[u] = __builtin_nontemporal_load(va + 64 * (k + u));
+                }
+#pragma unroll
+            for (int u = 0; u < kSellUnroll; ++u)
+                if (u < nk) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < kSellUnroll; ++u)
+                if (u < nk) acc = fma(a[u], xv[u], acc);
         }
-        for (; k < w; ++k)
-            acc = fma(__builtin_nontemporal_load(va + 64 * k), x[__builtin_nontemporal_load(ci + 64 * k)], acc);
     }
     r.s = acc;
     return r;
+}
+
+// Row sum of val * x[col] for the row owned by this thread (hybrid layout).
+// Long rows: lane groups with a butterfly; short rows: one thread per row,
+// entries walked in order with independent, coalesced loads.
+__device__ __forceinline__ RowSum mat_row_dot(const MatView &M, const double *__restrict__ x) {
+    const int32_t sl = slice_of(M);
+    if (sl < 0) {
+        RowSum r;
+        const RowCtx rc = row_ctx(M.seg);
+        r.s = row_dot(M.rowptr, M.colidx, M.val, x, rc);
+        r.row = rc.row;
+        r.valid = rc.valid && rc.lead;
+        return r;
+    }
+    return sell_row_dot(M, x, sl);
 }
 
 // Row max (MAXNORM) or sum of |val| in the hybrid layout.

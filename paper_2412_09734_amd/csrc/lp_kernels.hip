@@ -12,6 +12,66 @@
 
 namespace pdhg {
 
+// Primal update of row r given s = (A~'y)_r: PDHG point, extrapolation and
+// the Halpern step (Algorithm 1). The row's vector entries are loaded first
+// (PrimalIn), before the product they do not depend on.
+struct PrimalIn {
+    double x, x0, c, lv, uv;
+};
+__device__ __forceinline__ PrimalIn primal_load(int32_t r, const double *__restrict__ x,
+                                                const double *__restrict__ x0,
+                                                const double *__restrict__ c,
+                                                const double *__restrict__ lv,
+                                                const double *__restrict__ uv) {
+    return PrimalIn{x[r], x0[r], c[r], lv[r], uv[r]};
+}
+__device__ __forceinline__ void primal_store(int32_t r, double s, const PrimalIn &in,
+                                             double *__restrict__ x, double *__restrict__ xext,
+                                             const DevState *st, int32_t j, double gamma) {
+    const double tau = st->tau;
+    const int64_t k = st->k_base + (j - 1);
+    const double xh = clampd(in.x - tau * (in.c - s), in.lv, in.uv);
+    const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+    xext[r] = 2.0 * xh - in.x;
+    x[r] = ak * ((1.0 + gamma) * xh - gamma * in.x) + bk * in.x0;
+}
+__device__ __forceinline__ void primal_update(int32_t r, double s, double *__restrict__ x,
+                                              const double *__restrict__ x0,
+                                              const double *__restrict__ c,
+                                              const double *__restrict__ lv,
+                                              const double *__restrict__ uv,
+                                              double *__restrict__ xext, const DevState *st,
+                                              int32_t j, double gamma) {
+    primal_store(r, s, primal_load(r, x, x0, c, lv, uv), x, xext, st, j, gamma);
+}
+
+// Dual update of row r given a = (A~ xext)_r: dual prox and the Halpern step.
+struct DualIn {
+    double y, y0, lc, uc;
+};
+__device__ __forceinline__ DualIn dual_load(int32_t r, const double *__restrict__ y,
+                                            const double *__restrict__ y0,
+                                            const double *__restrict__ lc,
+                                            const double *__restrict__ uc) {
+    return DualIn{y[r], y0[r], lc[r], uc[r]};
+}
+__device__ __forceinline__ void dual_store(int32_t r, double a, const DualIn &in,
+                                           double *__restrict__ y, const DevState *st, int32_t j,
+                                           double gamma) {
+    const double sigma = st->sigma;
+    const int64_t k = st->k_base + (j - 1);
+    const double yh = dual_prox(in.y, a, sigma, in.lc, in.uc);
+    const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+    y[r] = ak * ((1.0 + gamma) * yh - gamma * in.y) + bk * in.y0;
+}
+__device__ __forceinline__ void dual_update(int32_t r, double a, double *__restrict__ y,
+                                            const double *__restrict__ y0,
+                                            const double *__restrict__ lc,
+                                            const double *__restrict__ uc, const DevState *st,
+                                            int32_t j, double gamma) {
+    dual_store(r, a, dual_load(r, y, y0, lc, uc), y, st, j, gamma);
+}
+
 __global__ __launch_bounds__(kBlock) void k_primal(
     MatView M, const double *__restrict__ y, double *__restrict__ x,
     const double *__restrict__ x0, const double *__restrict__ c, const double *__restrict__ lv,
@@ -19,17 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_primal(
     int32_t j, double gamma) {
     if (st->done) return;
     const RowSum rs = mat_row_dot(M, y);
-    const double s = rs.s;
-    if (rs.valid) {
-        const int32_t r = rs.row;
-        const double tau = st->tau;
-        const int64_t k = st->k_base + (j - 1);
-        const double xr = x[r];
-        const double xh = clampd(xr - tau * (c[r] - s), lv[r], uv[r]);
-        const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
-        xext[r] = 2.0 * xh - xr;
-        x[r] = ak * ((1.0 + gamma) * xh - gamma * xr) + bk * x0[r];
-    }
+    if (rs.valid) primal_update(rs.row, rs.s, x, x0, c, lv, uv, xext, st, j, gamma);
 }
 
 __global__ __launch_bounds__(kBlock) void k_dual(
@@ -38,16 +88,209 @@ __global__ __launch_bounds__(kBlock) void k_dual(
     const DevState *__restrict__ st, int32_t j, double gamma) {
     if (st->done) return;
     const RowSum rs = mat_row_dot(M, xext);
-    const double a = rs.s;
-    if (rs.valid) {
-        const int32_t r = rs.row;
-        const double sigma = st->sigma;
-        const int64_t k = st->k_base + (j - 1);
-        const double yr = y[r];
-        const double yh = dual_prox(yr, a, sigma, lc[r], uc[r]);
-        const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
-        y[r] = ak * ((1.0 + gamma) * yh - gamma * yr) + bk * y0[r];
+    if (rs.valid) dual_update(rs.row, rs.s, y, y0, lc, uc, st, j, gamma);
+}
+
+// Primal step over the SELL-64 slices [skip, nslices) of A~' (the rows before
+// them go through the LDS panels).
+__global__ __launch_bounds__(kBlock) void k_primal_sell(
+    MatView M, int32_t skip, const double *__restrict__ y, double *__restrict__ x,
+    const double *__restrict__ x0, const double *__restrict__ c, const double *__restrict__ lv,
+    const double *__restrict__ uv, double *__restrict__ xext, const DevState *__restrict__ st,
+    int32_t j, double gamma) {
+    if (st->done) return;
+    const int32_t sl = skip + (int32_t)blockIdx.x * (kBlock / 64) + (int32_t)(threadIdx.x >> 6);
+    const int32_t r = M.R_long + sl * 64 + (int32_t)(threadIdx.x & 63);
+    const bool valid = sl < M.nslices && r < M.rows;
+    PrimalIn in{};
+    if (valid) in = primal_load(r, x, x0, c, lv, uv);
+    const RowSum rs = sell_row_dot(M, y, sl);
+    if (valid) primal_store(r, rs.s, in, x, xext, st, j, gamma);
+}
+
+// sh[0, len) = src[0, len) for a kPanelThreads workgroup (len <= kPanelMax):
+// every load of a thread is issued before the first LDS store, then the
+// workgroup synchronises.
+__device__ __forceinline__ void stage_lds(double *sh, const double *__restrict__ src, int32_t len) {
+    constexpr int kPer = kPanelMax / kPanelThreads;
+    double t[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int32_t i = (int32_t)threadIdx.x + u * kPanelThreads;
+        t[u] = i < len ? src[i] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int32_t i = (int32_t)threadIdx.x + u * kPanelThreads;
+        if (i < len) sh[i] = t[u];
+    }
+    __syncthreads();
+}
+
+// Piece sums of the LDS panels (PanelMat). The workgroup stages its panel of
+// v in LDS; its waves take the panel's SELL-64 slices round robin (the widest
+// first), one lane per piece, entries summed in order. With one 128 KB
+// workgroup per CU there are few waves, so each wave works on kPanelGroup
+// slices at a time: their metadata and first kPanelDepth entries are all
+// loaded before the first product; wider slices continue kPanelUnroll
+// entries per round.
+constexpr int kPanelGroup = 4;
+constexpr int kPanelDepth = 4;
+constexpr int kPanelUnroll = 8;
+__global__ __launch_bounds__(kPanelThreads) void k_panel_dot(PanelView P,
+                                                             const double *__restrict__ v,
+                                                             const DevState *__restrict__ st) {
+    if (st->done) return;
+    const int32_t p = P.wg_panel[blockIdx.x];
+    if (p < 0) return;
+    __shared__ double sh[kPanelMax];
+    const int32_t base = p * P.S;
+    stage_lds(sh, v + base, min(P.S, P.vlen - base));
+    const int32_t wave = (int32_t)(threadIdx.x >> 6), lane = (int32_t)(threadIdx.x & 63);
+    const int32_t s1 = P.pslice[p + 1];
+    const int32_t stride = P.W * kPanelWaves;
+    for (int32_t s0 = P.pslice[p] + P.wg_rank[blockIdx.x] * kPanelWaves + wave; s0 < s1;
+         s0 += kPanelGroup * stride) {
+        int32_t b[kPanelGroup], w[kPanelGroup], slot[kPanelGroup];
+#pragma unroll
+        for (int g = 0; g < kPanelGroup; ++g) {
+            const int32_t sl = s0 + g * stride;
+            b[g] = 0;
+            w[g] = 0;
+            slot[g] = -1;
+            if (sl < s1) {
+                b[g] = __builtin_amdgcn_readfirstlane(P.soff[sl]);
+                w[g] = (__builtin_amdgcn_readfirstlane(P.soff[sl + 1]) - b[g]) >> 6;
+                slot[g] = P.slot[(size_t)sl * 64 + lane];
+            }
+        }
+        uint32_t li[kPanelGroup][kPanelDepth];
+        double a[kPanelGroup][kPanelDepth];
+#pragma unroll
+        for (int g = 0; g < kPanelGroup; ++g)
+#pragma unroll
+            for (int u = 0; u < kPanelDepth; ++u)
+                if (u < w[g]) {
+                    const int32_t e = b[g] + 64 * u + lane;
+                    li[g][u] = __builtin_nontemporal_load(P.idx + e);
+                    a[g][u] = __builtin_nontemporal_load(P.val + e);
+                }
+        double acc[kPanelGroup];
+#pragma unroll
+        for (int g = 0; g < kPanelGroup; ++g) {
+            acc[g] = 0.0;
+#pragma unroll
+            for (int u = 0; u < kPanelDepth; ++u)
+                if (u < w[g]) acc[g] = fma(a[g][u], sh[li[g][u]], acc[g]);
+        }
+#pragma unroll
+        for (int g = 0; g < kPanelGroup; ++g) {
+            for (int32_t k = kPanelDepth; k < w[g]; k += kPanelUnroll) {
+                const int32_t nk = min(kPanelUnroll, w[g] - k);
+                uint32_t lj[kPanelUnroll];
+                double aj[kPanelUnroll];
+#pragma unroll
+                for (int u = 0; u < kPanelUnroll; ++u)
+                    if (u < nk) {
+                        const int32_t e = b[g] + 64 * (k + u) + lane;
+                        lj[u] = __builtin_nontemporal_load(P.idx + e);
+                        aj[u] = __builtin_nontemporal_load(P.val + e);
+                    }
+#pragma unroll
+                for (int u = 0; u < kPanelUnroll; ++u)
+                    if (u < nk) acc[g] = fma(aj[u], sh[lj[u]], acc[g]);
+            }
+            if (slot[g] >= 0) P.part[slot[g]] = acc[g];
+        }
+    }
+}
+
+// (A~'v)_r for a panel row: the first pieces of its sub-rows in panel order
+// (all lanes read panel p together), then its further pieces.
+__device__ __forceinline__ double panel_sum(const PanelView &P, int32_t r) {
+    double s = 0.0;
+    for (int32_t w = 0; w < P.W64; ++w) {
+        const uint64_t mk = P.mask[(size_t)w * P.R + r];
+        const int32_t pe = min(64, P.P - 64 * w);
+        const double *__restrict__ col = P.part + (size_t)(64 * w) * P.R + r;
+        int32_t b = 0;
+        for (; b + 16 <= pe; b += 16) {
+            double t[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) t[u] = ((mk >> (b + u)) & 1ull) ? col[(size_t)(b + u) * P.R] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if ((mk >> (b + u)) & 1ull) s += t[u];
+        }
+        for (; b < pe; ++b)
+            if ((mk >> b) & 1ull) s += col[(size_t)b * P.R];
+    }
+    for (int32_t e = P.xptr[r]; e < P.xptr[r + 1]; ++e) s += P.part[P.xslot[e]];
+    return s;
+}
+
+// Primal step of the panel rows [0, R) of A~'.
+__global__ __launch_bounds__(kBlock) void k_primal_panels(
+    PanelView P, double *__restrict__ x, const double *__restrict__ x0,
+    const double *__restrict__ c, const double *__restrict__ lv, const double *__restrict__ uv,
+    double *__restrict__ xext, const DevState *__restrict__ st, int32_t j, double gamma) {
+    if (st->done) return;
+    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (r >= P.R) return;
+    const PrimalIn in = primal_load(r, x, x0, c, lv, uv);
+    primal_store(r, panel_sum(P, r), in, x, xext, st, j, gamma);
+}
+
+// Dual step over the SELL-64 slices of A~ with x_ext[0, H) staged in LDS
+// (columns are sorted by length, so these are the most gathered entries).
+// Persistent workgroups take the slices round robin. The sums are formed in
+// the same order as sell_row_dot, so the result equals k_dual's bit for bit.
+__global__ __launch_bounds__(kPanelThreads) void k_dual_hot(
+    MatView M, int32_t H, const double *__restrict__ xext, double *__restrict__ y,
+    const double *__restrict__ y0, const double *__restrict__ lc, const double *__restrict__ uc,
+    const DevState *__restrict__ st, int32_t j, double gamma) {
+    if (st->done) return;
+    __shared__ double sh[kPanelMax];
+    stage_lds(sh, xext, H);
+    const int32_t lane = (int32_t)(threadIdx.x & 63);
+    const int32_t nw = (int32_t)gridDim.x * kPanelWaves;
+    for (int32_t sl = (int32_t)blockIdx.x * kPanelWaves + (int32_t)(threadIdx.x >> 6);
+         sl < M.nslices; sl += nw) {
+        const int32_t b = __builtin_amdgcn_readfirstlane(M.slice_ptr[sl]);
+        const int32_t w = (__builtin_amdgcn_readfirstlane(M.slice_ptr[sl + 1]) - b) >> 6;
+        const int32_t *__restrict__ ci = M.colidx + b + lane;
+        const double *__restrict__ va = M.val + b + lane;
+        const int32_t r = M.R_long + sl * 64 + lane;
+        DualIn in{};
+        if (r < M.rows) in = dual_load(r, y, y0, lc, uc);
+        double acc = 0.0;
+        for (int32_t k = 0; k < w; k += kSellUnroll) {
+            const int32_t nk = min(kSellUnroll, w - k);
+            int32_t cc[kSellUnroll];
+            double aa[kSellUnroll], xx[kSellUnroll];
+#pragma unroll
+            for (int u = 0; u < kSellUnroll; ++u)
+                if (u < nk) {
+                    cc[u] = __builtin_nontemporal_load(ci + 64 * (k + u));
+                    aa[u] = __builtin_nontemporal_load(va + 64 * (k + u));
+                }
+#pragma unroll
+            for (int u = 0; u < kSellUnroll; ++u)
+                if (u < nk) xx[u] = cc[u] < H ? sh[cc[u]] : xext[cc[u]];
+#pragma unroll
+            for (int u = 0; u < kSellUnroll; ++u)
+                if (u < nk) acc = fma(aa[u], xx[u], acc);
+        }
+        if (r < M.rows) dual_store(r, acc, in, y, st, j, gamma);
+    }
+}
+
+// Step sizes and inner counter of a debug iteration.
+__global__ void k_set_step(DevState *st, double tau, double sigma, int64_t k) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    st->tau = tau;
+    st->sigma = sigma;
+    st->k_base = k;
 }
 
 __global__ __launch_bounds__(kBlock) void k_primal_chk(
@@ -427,6 +670,23 @@ void launch_primal(Handle &h, int32_t j) {
         return;
     }
     if (h.AT.nblocks() == 0) return;
+    if (h.PT.R > 0) {
+        // panel rows on stream2 beside the SELL-64 rest on the main stream
+        PDHG_HIP(hipEventRecord(h.ev_fork, h.stream));
+        PDHG_HIP(hipStreamWaitEvent(h.stream2, h.ev_fork, 0));
+        const PanelView P = view(h.PT);
+        k_panel_dot<<<h.PT.nwg, kPanelThreads, 0, h.stream2>>>(P, h.y.p, h.st.p);
+        k_primal_panels<<<(unsigned)ceil_div(h.PT.R, kBlock), kBlock, 0, h.stream2>>>(
+            P, h.x.p, h.x0.p, h.c.p, h.lv.p, h.uv.p, h.xext.p, h.st.p, j, h.opt.gamma);
+        PDHG_HIP(hipEventRecord(h.ev_join, h.stream2));
+        const int32_t ns = h.AT.nslices - h.sell_skip;
+        if (ns > 0)
+            k_primal_sell<<<(unsigned)ceil_div(ns, kBlock / 64), kBlock, 0, h.stream>>>(
+                view(h.AT), h.sell_skip, h.y.p, h.x.p, h.x0.p, h.c.p, h.lv.p, h.uv.p, h.xext.p,
+                h.st.p, j, h.opt.gamma);
+        PDHG_HIP(hipStreamWaitEvent(h.stream, h.ev_join, 0));
+        return;
+    }
     k_primal<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
         view(h.AT), h.y.p, h.x.p, h.x0.p, h.c.p, h.lv.p,
         h.uv.p, h.xext.p, h.st.p, j, h.opt.gamma);
@@ -438,8 +698,23 @@ void launch_dual(Handle &h, int32_t j) {
         return;
     }
     if (h.A.nblocks() == 0) return;
+    if (h.hot_cols > 0) {
+        // long rows (lane groups) by the standard kernel, SELL-64 slices by the hot one
+        if (h.A.seg.nblocks > 0)
+            k_dual<<<(unsigned)h.A.seg.nblocks, kBlock, 0, h.stream>>>(
+                view(h.A), h.xext.p, h.y.p, h.y0.p, h.lc.p, h.uc.p, h.st.p, j, h.opt.gamma);
+        if (h.A.nslices > 0)
+            k_dual_hot<<<(unsigned)h.dual_wgs, kPanelThreads, 0, h.stream>>>(
+                view(h.A), h.hot_cols, h.xext.p, h.y.p, h.y0.p, h.lc.p, h.uc.p, h.st.p, j,
+                h.opt.gamma);
+        return;
+    }
     k_dual<<<grid_of(h.A), kBlock, 0, h.stream>>>(view(h.A), h.xext.p, h.y.p, h.y0.p, h.lc.p,
                                                   h.uc.p, h.st.p, j, h.opt.gamma);
+}
+
+void launch_set_step(Handle &h, double tau, double sigma, int64_t k) {
+    k_set_step<<<1, 1, 0, h.stream>>>(h.st.p, tau, sigma, k);
 }
 
 void launch_primal_check(Handle &h, double tau_override) {

@@ -3,6 +3,7 @@
 // equilibration, then one Pock-Chambolle step with alpha = 1), the power
 // iteration for ||A~||_2 that sets the step size, and the initial primal
 // weight.
+#include <algorithm>
 #include <cstring>
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
@@ -610,6 +611,40 @@ void permute_csr(hipStream_t s, int32_t rows, int32_t cols, int64_t nnz, const i
     PDHG_HIP(hipStreamSynchronize(s));
 }
 
+// Rows of y per LDS panel of the primal product (0: the panels are off).
+static int32_t panel_rows(const pdhg_options &o, int32_t m) {
+    if (o.panel_rows == 0) return 0;
+    if (o.panel_rows > 0) return o.panel_rows;
+    return m > 262144 ? kPanelMax : 0;
+}
+
+// Choose the rows of A~' that the LDS panels cover: the rows longer than
+// panel_min_len, extended to whole SELL-64 slices (rows are sorted by length,
+// the first R_long of them stored as CSR). Their structure is kept on the host
+// until the scaled values exist.
+static void keep_panel_rows(Handle &h, const PlainCsr &PT, int32_t m) {
+    const int32_t n = PT.rows;
+    const int32_t S = panel_rows(h.opt, m);
+    if (S <= 0 || m <= 0 || PT.nnz == 0) return;
+    std::vector<int32_t> rp((size_t)n + 1);
+    PDHG_HIP(hipMemcpy(rp.data(), PT.rowptr.p, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost));
+    const int32_t min_len = h.opt.panel_min_len < 0 ? 16 : h.opt.panel_min_len;
+    int32_t rt = 0;
+    while (rt < n && rp[rt + 1] - rp[rt] > min_len) ++rt;
+    const int32_t RL = h.AT.R_long;
+    int32_t R = RL;
+    if (rt > RL) R = (int32_t)std::min<int64_t>(n, RL + 64 * ceil_div(rt - RL, 64));
+    if (R == 0 || rp[R] == 0) return;
+    h.PT.R = R;
+    h.PT.S = S;
+    h.sell_skip = (int32_t)ceil_div(R - RL, 64);
+    rp.resize((size_t)R + 1);
+    h.at_colidx_host.resize((size_t)rp[R]);
+    PDHG_HIP(hipMemcpy(h.at_colidx_host.data(), PT.colidx.p, sizeof(int32_t) * (size_t)rp[R],
+                       hipMemcpyDeviceToHost));
+    h.at_rowptr_host = std::move(rp);
+}
+
 void build_matrices(Handle &h, const pdhg_problem &p) {
     hipStream_t s = h.stream;
     const int32_t m = p.m, n = p.n;
@@ -709,6 +744,7 @@ void build_matrices(Handle &h, const pdhg_problem &p) {
         PDHG_HIP(hipStreamSynchronize(s));
         to_hybrid(s, PA, n, h.A);
         to_hybrid(s, PT, m, h.AT);
+        if (p.q_format == PDHG_FMT_NONE) keep_panel_rows(h, PT, m);
     }
     PDHG_HIP(hipStreamSynchronize(s));
 }
@@ -936,4 +972,158 @@ void compute_weight(Handle &h) {
     h.bnorm = sqrt(t[3]);
 }
 
+
+// LDS panels of the primal product (rows [0, R) of A~', scaled values) and the
+// hot-column count of the dual product. The panel layout is built on the host
+// from the rows kept at the matrix build and the scaled values of AT.
+void build_fast_layouts(Handle &h) {
+    hipStream_t s = h.stream;
+    const int32_t m = h.m, n = h.n;
+    int dev = 0, cus = 0;
+    PDHG_HIP(hipGetDevice(&dev));
+    PDHG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int32_t hot = h.opt.hot_cols < 0 ? (n > 262144 ? kPanelMax : 0) : h.opt.hot_cols;
+    h.hot_cols = (m > 0 && h.A.nslices > 0) ? std::min(hot, n) : 0;
+    h.dual_wgs = 2 * std::max(1, cus);
+    PanelMat &P = h.PT;
+    if (P.R == 0) return;
+    const int32_t R = P.R, S = P.S, RL = h.AT.R_long;
+    const std::vector<int32_t> &rp = h.at_rowptr_host;
+    const std::vector<int32_t> &ci = h.at_colidx_host;
+    const int64_t nnz = rp[R];
+    // scaled values of the covered rows: the CSR part of AT, then its first
+    // sell_skip slices (entry k of row r at slice_ptr[s] + 64 k + lane)
+    std::vector<int32_t> sptr((size_t)h.sell_skip + 1, 0);
+    if (h.sell_skip > 0)
+        PDHG_HIP(hipMemcpy(sptr.data(), h.AT.slice_ptr.p, sizeof(int32_t) * sptr.size(),
+                           hipMemcpyDeviceToHost));
+    const int64_t vend = h.sell_skip > 0 ? sptr[h.sell_skip] : rp[RL];
+    std::vector<double> hv((size_t)vend);
+    PDHG_HIP(hipMemcpy(hv.data(), h.AT.val.p, sizeof(double) * (size_t)vend, hipMemcpyDeviceToHost));
+    auto value = [&](int32_t r, int64_t k) -> double {
+        if (r < RL) return hv[(size_t)(rp[r] + k)];
+        const int32_t q = r - RL;
+        return hv[(size_t)sptr[q >> 6] + 64 * (size_t)k + (q & 63)];
+    };
+    P.vlen = m;
+    P.P = (int32_t)ceil_div(m, S);
+    P.W64 = (int32_t)ceil_div(P.P, 64);
+    P.W = h.opt.panel_wgs < 0 ? 4 : h.opt.panel_wgs;
+    P.entries = nnz;
+    // pieces (row, first entry, length) per panel, in row order
+    struct Piece {
+        int32_t row;
+        int32_t len;
+        int64_t e0;
+        int32_t slot;
+    };
+    std::vector<std::vector<Piece>> pieces((size_t)P.P);
+    std::vector<uint64_t> mask((size_t)P.W64 * R, 0);
+    std::vector<int32_t> xcount((size_t)R, 0);
+    int64_t nx = 0;
+    for (int32_t r = 0; r < R; ++r) {
+        int64_t e = rp[r];
+        const int64_t e1 = rp[r + 1];
+        while (e < e1) {
+            const int32_t p = ci[(size_t)e] / S;   // entries of a row are sorted by y index
+            int64_t f = e;
+            while (f < e1 && ci[(size_t)f] / S == p) ++f;
+            mask[(size_t)(p >> 6) * R + r] |= 1ull << (p & 63);
+            for (int64_t q = e; q < f; q += kPanelPiece) {
+                const int32_t len = (int32_t)std::min<int64_t>(kPanelPiece, f - q);
+                int32_t slot = -1;
+                if (q == e) {
+                    slot = (int32_t)((int64_t)p * R + r);
+                } else {
+                    slot = -2;   // numbered below, in row order
+                    ++xcount[(size_t)r];
+                    ++nx;
+                }
+                pieces[(size_t)p].push_back(Piece{r, len, q, slot});
+            }
+            e = f;
+        }
+    }
+    if ((int64_t)P.P * R + nx >= INT32_MAX) fail(PDHG_ERR_UNSUPPORTED, "too many panel partials");
+    // extra pieces: slots P*R + x, x in row order then panel order
+    std::vector<int32_t> xptr((size_t)R + 1, 0);
+    for (int32_t r = 0; r < R; ++r) xptr[r + 1] = xptr[r] + xcount[(size_t)r];
+    std::vector<int32_t> xslot((size_t)std::max<int64_t>(1, nx));
+    std::vector<int32_t> xfill(xptr.begin(), xptr.end() - 1);
+    for (int32_t p = 0; p < P.P; ++p)
+        for (Piece &pc : pieces[(size_t)p])
+            if (pc.slot == -2) {
+                const int32_t x = xfill[(size_t)pc.row]++;
+                pc.slot = (int32_t)((int64_t)P.P * R + x);
+                xslot[(size_t)x] = pc.slot;
+            }
+    P.nx = (int32_t)nx;
+    // SELL-64 slices per panel, pieces sorted by length (stable)
+    std::vector<int32_t> pslice((size_t)P.P + 1, 0), soff(1, 0), slot;
+    std::vector<uint16_t> idx;
+    std::vector<double> val;
+    for (int32_t p = 0; p < P.P; ++p) {
+        std::vector<Piece> &v = pieces[(size_t)p];
+        std::stable_sort(v.begin(), v.end(), [](const Piece &a, const Piece &b) { return a.len > b.len; });
+        const int32_t ns = (int32_t)ceil_div((int64_t)v.size(), 64);
+        for (int32_t sl = 0; sl < ns; ++sl) {
+            const size_t first = (size_t)sl * 64;
+            const int32_t w = v[first].len;
+            const size_t base = idx.size();
+            idx.resize(base + (size_t)64 * w, 0);
+            val.resize(base + (size_t)64 * w, 0.0);
+            for (int32_t l = 0; l < 64; ++l) {
+                const size_t q = first + (size_t)l;
+                if (q >= v.size()) {
+                    slot.push_back(-1);
+                    continue;
+                }
+                const Piece &pc = v[q];
+                slot.push_back(pc.slot);
+                for (int32_t k = 0; k < pc.len; ++k) {
+                    const int64_t e = pc.e0 + k;
+                    idx[base + (size_t)64 * k + l] = (uint16_t)(ci[(size_t)e] - p * S);
+                    val[base + (size_t)64 * k + l] = value(pc.row, e - rp[pc.row]);
+                }
+            }
+            if (idx.size() >= (size_t)INT32_MAX) fail(PDHG_ERR_UNSUPPORTED, "panel layout too large");
+            soff.push_back((int32_t)idx.size());
+        }
+        pslice[p + 1] = pslice[p] + ns;
+        std::vector<Piece>().swap(v);
+    }
+    P.nslices = pslice[P.P];
+    // workgroups: W per panel, all of a panel's workgroups on one XCD (workgroup
+    // b runs on XCD b mod 8), so the panel's partial-sum lines meet in one L2
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> xcd(8);
+    for (int32_t p = 0; p < P.P; ++p)
+        for (int32_t g = 0; g < P.W; ++g) xcd[(size_t)(p % 8)].emplace_back(p, g);
+    size_t longest = 0;
+    for (const auto &l : xcd) longest = std::max(longest, l.size());
+    std::vector<int32_t> wg_panel(8 * longest, -1), wg_rank(8 * longest, 0);
+    for (int32_t x = 0; x < 8; ++x)
+        for (size_t j = 0; j < xcd[(size_t)x].size(); ++j) {
+            wg_panel[8 * j + (size_t)x] = xcd[(size_t)x][j].first;
+            wg_rank[8 * j + (size_t)x] = xcd[(size_t)x][j].second;
+        }
+    P.nwg = (int32_t)wg_panel.size();
+    auto upload = [&](auto &buf, const auto &v) {
+        buf.alloc(v.size());
+        PDHG_HIP(hipMemcpyAsync(buf.p, v.data(), sizeof(v[0]) * v.size(), hipMemcpyHostToDevice, s));
+    };
+    upload(P.idx, idx);
+    upload(P.val, val);
+    upload(P.soff, soff);
+    upload(P.slot, slot);
+    upload(P.pslice, pslice);
+    upload(P.wg_panel, wg_panel);
+    upload(P.wg_rank, wg_rank);
+    upload(P.mask, mask);
+    upload(P.xptr, xptr);
+    upload(P.xslot, xslot);
+    P.part.alloc((size_t)P.P * R + (size_t)nx);
+    PDHG_HIP(hipStreamSynchronize(s));
+    h.at_rowptr_host = {};
+    h.at_colidx_host = {};
+}
 }  // namespace pdhg

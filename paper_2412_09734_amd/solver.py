@@ -178,6 +178,19 @@ class Solver:
         capi.check(rc, "pdhg_debug_step")
         return outs[0], outs[1][: self.m], outs[2], outs[3][: self.m]
 
+    def debug_plain_step(self, x, y, x0, y0, k, tau, sigma):
+        """One plain iteration (the solve's kernels between checks) in the
+        scaled space (original order): the Halpern point (xnew, ynew)."""
+        x, x0 = self._vec(x, self.n), self._vec(x0, self.n)
+        y = self._vec(y, self.m) if self.m else torch.zeros(1, dtype=torch.float64, device=self.dev)
+        y0 = self._vec(y0, self.m) if self.m else torch.zeros(1, dtype=torch.float64, device=self.dev)
+        outs = [torch.empty(self.n, dtype=torch.float64, device=self.dev),
+                torch.empty(max(self.m, 1), dtype=torch.float64, device=self.dev)]
+        rc = capi.lib().pdhg_debug_plain_step(self._h, _ptr(x), _ptr(y), _ptr(x0), _ptr(y0), int(k),
+                                              float(tau), float(sigma), *[_ptr(o) for o in outs])
+        capi.check(rc, "pdhg_debug_plain_step")
+        return outs[0], outs[1][: self.m]
+
     def debug_qp_step(self, x, y, xbar, ybar, k, omega):
         """One rAPDHG iteration in the scaled space (original order)."""
         z = lambda: torch.zeros(1, dtype=torch.float64, device=self.dev)  # noqa: E731

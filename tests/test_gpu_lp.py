@@ -53,6 +53,11 @@ def _step_case(pdhg, oracle_lib, lp, seeds=(0, 1), ks=(0, 5, 1000), compare_eta=
                 for name, g, r in zip(("xhat", "yhat", "xnew", "ynew"), got, ref):
                     err = rel_inf(to_np(g), r)
                     assert err <= STEP_TOL, (name, seed, k, err)
+                # the plain iteration between checks (its own product layouts)
+                got = s.debug_plain_step(x, y, x0, y0, k, tau, sigma)
+                for name, g, r in zip(("xnew", "ynew"), got, ref[2:]):
+                    err = rel_inf(to_np(g), r)
+                    assert err <= STEP_TOL, ("plain " + name, seed, k, err)
 
 
 def test_step_parity_small_lp(pdhg, oracle_lib):
@@ -116,6 +121,75 @@ def test_step_parity_no_rows(pdhg, oracle_lib):
     lp = gen.LP(0, n, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0),
                 np.linspace(-1, 1, n), np.zeros(0), np.zeros(0), np.full(n, -2.0), np.full(n, 5.0))
     _step_case(pdhg, oracle_lib, lp, ks=(0, 3))
+
+
+# Product layouts of the plain iterations, forced on small LPs: LDS panels of
+# y for the long rows of A~' (many panels, sub-rows longer than a 64-entry
+# chunk, every row in the panels) and x_ext entries staged in LDS by the dual
+# product.
+PANEL_LAYOUTS = {
+    "many_panels": dict(panel_rows=64, panel_min_len=4, panel_wgs=2, hot_cols=100),
+    "all_rows_in_panels": dict(panel_rows=1000, panel_min_len=0, panel_wgs=1, hot_cols=16384),
+    "wide_panels": dict(panel_rows=16384, panel_min_len=16, panel_wgs=4, hot_cols=0),
+    "hot_columns_only": dict(panel_rows=0, hot_cols=37),
+}
+
+
+def _layout_lp(name):
+    if name == "skewed":
+        return _skewed_lp()
+    if name == "zipf":
+        return gen.large_zipf_lp(m=3000, n=6000, kmax=400, seed=83)
+    return gen.grid_mincost_batch(batch=1, seed=3001).instance(0)
+
+
+@pytest.mark.parametrize("layout", sorted(PANEL_LAYOUTS))
+@pytest.mark.parametrize("name", ["skewed", "zipf", "grid"])
+def test_plain_step_parity_panel_layouts(pdhg, oracle_lib, name, layout):
+    """One plain iteration through each product layout against the oracle;
+    with the panels off, the hot-column dual product equals the standard one
+    bit for bit (same summation order)."""
+    _say(f"case: plain step parity, {name} LP, layout {layout}")
+    lp = _layout_lp(name)
+    orc = oracle_lib.Oracle(lp)
+    sc = orc.scaling()
+    rng = np.random.default_rng(11)
+    x, y = rng.standard_normal(lp.n), rng.standard_normal(lp.m)
+    x0, y0 = rng.standard_normal(lp.n), rng.standard_normal(lp.m)
+    with pdhg.Solver.from_lp(lp, **PANEL_LAYOUTS[layout]) as s, \
+            pdhg.Solver.from_lp(lp, panel_rows=0, hot_cols=0) as plain:
+        for k in (0, 9):
+            tau, sigma = sc["eta"] / sc["omega"], sc["eta"] * sc["omega"]
+            ref = orc.lp_step(x, y, x0, y0, k, tau, sigma)
+            got = s.debug_plain_step(x, y, x0, y0, k, tau, sigma)
+            for nm, g, r in zip(("xnew", "ynew"), got, ref[2:]):
+                err = rel_inf(to_np(g), r)
+                assert err <= STEP_TOL, (nm, k, err)
+            if PANEL_LAYOUTS[layout]["panel_rows"] == 0:
+                base = plain.debug_plain_step(x, y, x0, y0, k, tau, sigma)
+                for g, b in zip(got, base):
+                    np.testing.assert_array_equal(to_np(g), to_np(b))
+
+
+@pytest.mark.parametrize("layout", ["many_panels", "all_rows_in_panels"])
+def test_solve_parity_panel_layouts(pdhg, oracle_lib, layout):
+    """Full solves whose plain iterations run through the panels and hot
+    columns: optimal at KKT <= 1e-4, objective within 1e-6 of the oracle's,
+    the reported KKT error that of the returned point, and bitwise repeatable."""
+    lp = gen.planted_sparse_lp(m=300, n=600, density=0.05, seed=7)
+    _say(f"case: full solve parity, planted m=300 n=600, layout {layout}")
+    xo, yo, ro = oracle_lib.Oracle(lp).solve()
+    with pdhg.Solver.from_lp(lp, **PANEL_LAYOUTS[layout]) as s:
+        xg, yg, rg = s.solve()
+        x2, y2, r2 = s.solve()
+    _say(f"  iterations gpu={rg['iterations']} oracle={ro['iterations']}")
+    assert rg["status_name"] == "optimal" and rg["kkt_rel"] <= 1e-4
+    assert abs(rg["primal_obj"] - ro["primal_obj"]) <= 1e-6 * (1 + abs(ro["primal_obj"]))
+    kg = oracle_lib.kkt(lp, to_np(xg), to_np(yg))
+    assert abs(kg["kkt"] - rg["kkt_rel"]) <= 1e-9 + 1e-6 * kg["kkt"]
+    np.testing.assert_array_equal(to_np(xg), to_np(x2))
+    np.testing.assert_array_equal(to_np(yg), to_np(y2))
+    assert rg["iterations"] == r2["iterations"]
 
 
 def test_solve_parity_small_lp(pdhg, oracle_lib):
