@@ -134,8 +134,8 @@ typedef struct {
      * panel_rows: entries of y staged in LDS per panel for the product A~'y
      *   over the longest rows of A~' (auto: 16384 when m > 262144, else off;
      *   0: off; at most 16384);
-     * panel_min_len: rows of A~' longer than this use the panels (auto: 16);
-     * panel_wgs: workgroups per panel (auto: 4);
+     * panel_min_len: rows of A~' longer than this use the panels (auto: 32);
+     * panel_wgs: workgroups per panel (auto: 8);
      * hot_cols: leading entries of x_ext staged in LDS by the product A~x_ext
      *   (auto: 16384 when n > 262144, else off; 0: off; at most 16384). */
     int32_t panel_rows;

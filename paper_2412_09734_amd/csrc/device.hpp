@@ -83,6 +83,53 @@ __device__ __forceinline__ int32_t slice_of(const MatView &M) {
     return ((int32_t)blockIdx.x - M.seg.nblocks) * (kBlock / 64) + (int32_t)(threadIdx.x >> 6);
 }
 
+// acc + the products of entries [k, k + U) of a SELL-64 lane whose row has w
+// entries (entry e at ci[64 e], va[64 e]; k < w, wave-uniform), in entry
+// order. The loads are unconditional at indices clamped to the last entry, so
+// the compiler issues all of them before the first product (with predicated
+// loads it waits on each in turn); products of entries past w are dropped by a
+// select, so the sum is exactly that of the entries < w.
+template <int U, class Idx, class Gather>
+__device__ __forceinline__ double sell_group(const Idx *__restrict__ ci,
+                                             const double *__restrict__ va, int32_t k,
+                                             int32_t w, double acc, Gather gather) {
+    int32_t c[U];
+    double a[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t e = 64 * min(k + u, w - 1);
+        c[u] = (int32_t)__builtin_nontemporal_load(ci + e);
+        a[u] = __builtin_nontemporal_load(va + e);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = gather(c[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const double t = fma(a[u], xv[u], acc);
+        acc = (k + u < w) ? t : acc;
+    }
+    return acc;
+}
+
+// Sum of the w entries of a SELL-64 lane in entry order: groups of
+// kSellUnroll, then one tail group of 1, 2, 4 or kSellUnroll (w is
+// wave-uniform, so the group sizes are too).
+template <class Idx, class Gather>
+__device__ __forceinline__ double sell_lane_dot(const Idx *__restrict__ ci,
+                                                const double *__restrict__ va, int32_t w,
+                                                Gather gather) {
+    double acc = 0.0;
+    int32_t k = 0;
+    for (; k + kSellUnroll <= w; k += kSellUnroll)
+        acc = sell_group<kSellUnroll>(ci, va, k, w, acc, gather);
+    const int32_t rest = w - k;
+    if (rest > 4) acc = sell_group<kSellUnroll>(ci, va, k, w, acc, gather);
+    else if (rest > 2) acc = sell_group<4>(ci, va, k, w, acc, gather);
+    else if (rest == 2) acc = sell_group<2>(ci, va, k, w, acc, gather);
+    else if (rest == 1) acc = sell_group<1>(ci, va, k, w, acc, gather);
+    return acc;
+}
+
 // Row sum over SELL-64 slice sl (wave-uniform) for the row of this lane:
 // entries walked in order with independent, coalesced loads.
 __device__ __forceinline__ RowSum sell_row_dot(const MatView &M, const double *__restrict__ x,
@@ -97,26 +144,7 @@ __device__ __forceinline__ RowSum sell_row_dot(const MatView &M, const double *_
         const int32_t w = (__builtin_amdgcn_readfirstlane(M.slice_ptr[sl + 1]) - b) >> 6;
         const int32_t *__restrict__ ci = M.colidx + b + lane;
         const double *__restrict__ va = M.val + b + lane;
-        // groups of kSellUnroll entries: every load of a group is issued before
-        // the first product, also for the last, partial group (the group size
-        // is uniform over the wave); the products are added in entry order
-        for (int32_t k = 0; k < w; k += kSellUnroll) {
-            const int32_t nk = min(kSellUnroll, w - k);
-            int32_t c[kSellUnroll];
-            double a[kSellUnroll], xv[kSellUnroll];
-#pragma unroll
-            for (int u = 0; u < kSellUnroll; ++u)
-                if (u < nk) {
-                    c[u] = __builtin_nontemporal_load(ci + 64 * (k + u));
-                    a[u] = __builtin_nontemporal_load(va + 64 * (k + u));
-                }
-#pragma unroll
-            for (int u = 0; u < kSellUnroll; ++u)
-                if (u < nk) xv[u] = x[c[u]];
-#pragma unroll
-            for (int u = 0; u < kSellUnroll; ++u)
-                if (u < nk) acc = fma(a[u], xv[u], acc);
-        }
+        acc = sell_lane_dot(ci, va, w, [&](int32_t c) { return x[c]; });
     }
     r.s = acc;
     return r;

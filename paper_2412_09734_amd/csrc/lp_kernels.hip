@@ -129,14 +129,8 @@ __device__ __forceinline__ void stage_lds(double *sh, const double *__restrict__
 
 // Piece sums of the LDS panels (PanelMat). The workgroup stages its panel of
 // v in LDS; its waves take the panel's SELL-64 slices round robin (the widest
-// first), one lane per piece, entries summed in order. With one 128 KB
-// workgroup per CU there are few waves, so each wave works on kPanelGroup
-// slices at a time: their metadata and first kPanelDepth entries are all
-// loaded before the first product; wider slices continue kPanelUnroll
-// entries per round.
-constexpr int kPanelGroup = 4;
-constexpr int kPanelDepth = 4;
-constexpr int kPanelUnroll = 8;
+// first), one lane per piece, entries summed in order by sell_lane_dot; the
+// next slice's bounds and slots are loaded while the current one is reduced.
 __global__ __launch_bounds__(kPanelThreads) void k_panel_dot(PanelView P,
                                                              const double *__restrict__ v,
                                                              const DevState *__restrict__ st) {
@@ -149,59 +143,22 @@ __global__ __launch_bounds__(kPanelThreads) void k_panel_dot(PanelView P,
     const int32_t wave = (int32_t)(threadIdx.x >> 6), lane = (int32_t)(threadIdx.x & 63);
     const int32_t s1 = P.pslice[p + 1];
     const int32_t stride = P.W * kPanelWaves;
-    for (int32_t s0 = P.pslice[p] + P.wg_rank[blockIdx.x] * kPanelWaves + wave; s0 < s1;
-         s0 += kPanelGroup * stride) {
-        int32_t b[kPanelGroup], w[kPanelGroup], slot[kPanelGroup];
-#pragma unroll
-        for (int g = 0; g < kPanelGroup; ++g) {
-            const int32_t sl = s0 + g * stride;
-            b[g] = 0;
-            w[g] = 0;
-            slot[g] = -1;
-            if (sl < s1) {
-                b[g] = __builtin_amdgcn_readfirstlane(P.soff[sl]);
-                w[g] = (__builtin_amdgcn_readfirstlane(P.soff[sl + 1]) - b[g]) >> 6;
-                slot[g] = P.slot[(size_t)sl * 64 + lane];
-            }
-        }
-        uint32_t li[kPanelGroup][kPanelDepth];
-        double a[kPanelGroup][kPanelDepth];
-#pragma unroll
-        for (int g = 0; g < kPanelGroup; ++g)
-#pragma unroll
-            for (int u = 0; u < kPanelDepth; ++u)
-                if (u < w[g]) {
-                    const int32_t e = b[g] + 64 * u + lane;
-                    li[g][u] = __builtin_nontemporal_load(P.idx + e);
-                    a[g][u] = __builtin_nontemporal_load(P.val + e);
-                }
-        double acc[kPanelGroup];
-#pragma unroll
-        for (int g = 0; g < kPanelGroup; ++g) {
-            acc[g] = 0.0;
-#pragma unroll
-            for (int u = 0; u < kPanelDepth; ++u)
-                if (u < w[g]) acc[g] = fma(a[g][u], sh[li[g][u]], acc[g]);
-        }
-#pragma unroll
-        for (int g = 0; g < kPanelGroup; ++g) {
-            for (int32_t k = kPanelDepth; k < w[g]; k += kPanelUnroll) {
-                const int32_t nk = min(kPanelUnroll, w[g] - k);
-                uint32_t lj[kPanelUnroll];
-                double aj[kPanelUnroll];
-#pragma unroll
-                for (int u = 0; u < kPanelUnroll; ++u)
-                    if (u < nk) {
-                        const int32_t e = b[g] + 64 * (k + u) + lane;
-                        lj[u] = __builtin_nontemporal_load(P.idx + e);
-                        aj[u] = __builtin_nontemporal_load(P.val + e);
-                    }
-#pragma unroll
-                for (int u = 0; u < kPanelUnroll; ++u)
-                    if (u < nk) acc[g] = fma(aj[u], sh[lj[u]], acc[g]);
-            }
-            if (slot[g] >= 0) P.part[slot[g]] = acc[g];
-        }
+    int32_t sl = P.pslice[p] + P.wg_rank[blockIdx.x] * kPanelWaves + wave;
+    if (sl >= s1) return;
+    int32_t nb = P.soff[sl], ne = P.soff[sl + 1], nslot = P.slot[(size_t)sl * 64 + lane];
+    while (sl < s1) {
+        const int32_t b = __builtin_amdgcn_readfirstlane(nb);
+        const int32_t w = (__builtin_amdgcn_readfirstlane(ne) - b) >> 6;
+        const int32_t slot = nslot;
+        const int32_t nx = min(sl + stride, s1 - 1);
+        nb = P.soff[nx];
+        ne = P.soff[nx + 1];
+        nslot = P.slot[(size_t)nx * 64 + lane];
+        const uint16_t *__restrict__ ip = P.idx + b + lane;
+        const double *__restrict__ vp = P.val + b + lane;
+        const double acc = sell_lane_dot(ip, vp, w, [&](int32_t c) { return sh[c]; });
+        if (slot >= 0) P.part[slot] = acc;
+        sl += stride;
     }
 }
 
@@ -254,34 +211,24 @@ __global__ __launch_bounds__(kPanelThreads) void k_dual_hot(
     stage_lds(sh, xext, H);
     const int32_t lane = (int32_t)(threadIdx.x & 63);
     const int32_t nw = (int32_t)gridDim.x * kPanelWaves;
-    for (int32_t sl = (int32_t)blockIdx.x * kPanelWaves + (int32_t)(threadIdx.x >> 6);
-         sl < M.nslices; sl += nw) {
-        const int32_t b = __builtin_amdgcn_readfirstlane(M.slice_ptr[sl]);
-        const int32_t w = (__builtin_amdgcn_readfirstlane(M.slice_ptr[sl + 1]) - b) >> 6;
+    int32_t sl = (int32_t)blockIdx.x * kPanelWaves + (int32_t)(threadIdx.x >> 6);
+    if (sl >= M.nslices) return;
+    // the next slice's bounds are loaded while the current one is reduced
+    int32_t nb = M.slice_ptr[sl], ne = M.slice_ptr[sl + 1];
+    while (sl < M.nslices) {
+        const int32_t b = __builtin_amdgcn_readfirstlane(nb);
+        const int32_t w = (__builtin_amdgcn_readfirstlane(ne) - b) >> 6;
+        const int32_t nx = min(sl + nw, M.nslices - 1);
+        nb = M.slice_ptr[nx];
+        ne = M.slice_ptr[nx + 1];
         const int32_t *__restrict__ ci = M.colidx + b + lane;
         const double *__restrict__ va = M.val + b + lane;
         const int32_t r = M.R_long + sl * 64 + lane;
         DualIn in{};
         if (r < M.rows) in = dual_load(r, y, y0, lc, uc);
-        double acc = 0.0;
-        for (int32_t k = 0; k < w; k += kSellUnroll) {
-            const int32_t nk = min(kSellUnroll, w - k);
-            int32_t cc[kSellUnroll];
-            double aa[kSellUnroll], xx[kSellUnroll];
-#pragma unroll
-            for (int u = 0; u < kSellUnroll; ++u)
-                if (u < nk) {
-                    cc[u] = __builtin_nontemporal_load(ci + 64 * (k + u));
-                    aa[u] = __builtin_nontemporal_load(va + 64 * (k + u));
-                }
-#pragma unroll
-            for (int u = 0; u < kSellUnroll; ++u)
-                if (u < nk) xx[u] = cc[u] < H ? sh[cc[u]] : xext[cc[u]];
-#pragma unroll
-            for (int u = 0; u < kSellUnroll; ++u)
-                if (u < nk) acc = fma(aa[u], xx[u], acc);
-        }
+        const double acc = sell_lane_dot(ci, va, w, [&](int32_t c) { return c < H ? sh[c] : xext[c]; });
         if (r < M.rows) dual_store(r, acc, in, y, st, j, gamma);
+        sl += nw;
     }
 }
 

@@ -628,7 +628,7 @@ static void keep_panel_rows(Handle &h, const PlainCsr &PT, int32_t m) {
     if (S <= 0 || m <= 0 || PT.nnz == 0) return;
     std::vector<int32_t> rp((size_t)n + 1);
     PDHG_HIP(hipMemcpy(rp.data(), PT.rowptr.p, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost));
-    const int32_t min_len = h.opt.panel_min_len < 0 ? 16 : h.opt.panel_min_len;
+    const int32_t min_len = h.opt.panel_min_len < 0 ? 32 : h.opt.panel_min_len;
     int32_t rt = 0;
     while (rt < n && rp[rt + 1] - rp[rt] > min_len) ++rt;
     const int32_t RL = h.AT.R_long;
@@ -1008,7 +1008,7 @@ void build_fast_layouts(Handle &h) {
     P.vlen = m;
     P.P = (int32_t)ceil_div(m, S);
     P.W64 = (int32_t)ceil_div(P.P, 64);
-    P.W = h.opt.panel_wgs < 0 ? 4 : h.opt.panel_wgs;
+    P.W = h.opt.panel_wgs < 0 ? 8 : h.opt.panel_wgs;
     P.entries = nnz;
     // pieces (row, first entry, length) per panel, in row order
     struct Piece {
