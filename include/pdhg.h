@@ -363,6 +363,18 @@ pdhg_err pdhg_regret(int32_t B, int32_t n, const double *c_true, const double *x
 pdhg_err pdhg_linear_costs_backward(int32_t B, int32_t n, int32_t p, const double *f,
                                     const double *gc, double *gW, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same weight
+ * gradient as pdhg_linear_costs_backward, bit for bit, with its partial sums
+ * in a static 32 KB device array (64 x 64 doubles, one per GPU, held until the
+ * process ends) instead of a buffer allocated per call. It allocates nothing
+ * and returns once the work is enqueued on `stream` (no wait). Limit: p <= 64
+ * (PDHG_ERR_INVALID_ARG beyond). Every call on one GPU uses that GPU's array,
+ * so calls that overlap on a GPU (other threads or streams) race and must be
+ * ordered by the caller. */
+pdhg_err pdhg_linear_costs_backward_noalloc(int32_t B, int32_t n, int32_t p, const double *f,
+                                            const double *gc, double *gW, void *stream);
+
 /* Objective value of B QPs with Q_b = F F' + diag(d_b) (F [n r] row-major,
  * shared, r <= 32; d, c, x [B n]): value[b] = 1/2 x_b' Q_b x_b + c_b' x_b and,
  * when gx is not NULL, its gradient gx_b = Q_b x_b + c_b. */

@@ -91,6 +91,7 @@ SIGNATURES = {
     "pdhg_linear_costs": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, P, P]),
     "pdhg_regret": (C.c_int, [C.c_int32, C.c_int32, P, P, P, P, P]),
     "pdhg_linear_costs_backward": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, P, P]),
+    "pdhg_linear_costs_backward_noalloc": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, P, P]),
     "pdhg_qp_value": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P, P]),
     "pdhg_spo_plus_costs": (C.c_int, [C.c_int32, C.c_int32, P, P, P, P]),
     "pdhg_spo_plus": (C.c_int, [C.c_int32, C.c_int32, P, P, P, P, P, P, P, P]),

@@ -747,6 +747,15 @@ pdhg_err pdhg_linear_costs_backward(int32_t B, int32_t n, int32_t p, const doubl
     });
 }
 
+pdhg_err pdhg_linear_costs_backward_noalloc(int32_t B, int32_t n, int32_t p, const double *f,
+                                            const double *gc, double *gW, void *stream) {
+    return guarded([&] {
+        if (B < 0 || n < 0 || p < 1 || p > 64) fail(PDHG_ERR_INVALID_ARG, "need B, n >= 0, 1 <= p <= 64");
+        if (!gW || ((int64_t)B * n > 0 && (!f || !gc))) fail(PDHG_ERR_INVALID_ARG, "NULL array");
+        head_linear_costs_backward_noalloc(reinterpret_cast<hipStream_t>(stream), B, n, p, f, gc, gW);
+    });
+}
+
 pdhg_err pdhg_qp_value(int32_t B, int32_t n, int32_t r, const double *F, const double *d,
                        const double *c, const double *x, double *value, double *gx, void *stream) {
     return guarded([&] {

@@ -270,6 +270,8 @@ void head_regret(hipStream_t s, int32_t B, int32_t n, const double *ct, const do
                  const double *vs, double *loss);
 void head_linear_costs_backward(hipStream_t s, int32_t B, int32_t n, int32_t p, const double *f,
                                 const double *gc, double *gW);
+void head_linear_costs_backward_noalloc(hipStream_t s, int32_t B, int32_t n, int32_t p,
+                                        const double *f, const double *gc, double *gW);
 void head_qp_value(hipStream_t s, int32_t B, int32_t n, int32_t r, const double *F,
                    const double *d, const double *c, const double *x, double *value, double *gx);
 void head_spo_costs(hipStream_t s, int32_t B, int32_t n, const double *c_hat, const double *c_true,

@@ -5,6 +5,7 @@
 // low-rank-plus-diagonal QP objective. All sums are deterministic
 // workgroup trees in a fixed order.
 #include <algorithm>
+#include <mutex>
 
 #include "device.hpp"
 
@@ -12,6 +13,15 @@ namespace pdhg {
 
 constexpr int kHeadChunks = 64;   // column chunks of the weight-gradient reduction
 constexpr int kHeadRmax = 32;     // largest factor rank of pdhg_qp_value
+constexpr int kHeadPmax = 64;     // most features of the linear cost model
+constexpr int kScratchDoubles = kHeadPmax * kHeadChunks;
+constexpr int kMaxDevices = 64;
+
+// Partial sums of the allocation-free weight gradient (32 KB on every GPU the
+// library runs on, kept until the process ends). Host code never uses this
+// name as an address: it reads the device address once per device with
+// hipGetSymbolAddress and passes that to the kernels.
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 __global__ __launch_bounds__(kBlock) void k_linear_costs(int64_t N, int32_t p,
                                                          const double *__restrict__ f,
@@ -192,6 +202,42 @@ void head_linear_costs_backward(hipStream_t s, int32_t B, int32_t n, int32_t p, 
     k_costs_grad_final<<<1, 64, 0, s>>>(p, part.p, gW);
     PDHG_HIP(hipGetLastError());
     PDHG_HIP(hipStreamSynchronize(s));
+}
+
+// Device address of `scratch` on the device that runs stream s (the current
+// device for the NULL stream), looked up once per device with that device
+// current.
+static double *scratch_address(hipStream_t s) {
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    int cur = 0, dev = 0;
+    PDHG_HIP(hipGetDevice(&cur));
+    dev = cur;
+    if (s) PDHG_HIP(hipStreamGetDevice(s, &dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(PDHG_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        if (dev != cur) PDHG_HIP(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) PDHG_HIP(hipSetDevice(cur));
+        if (e != hipSuccess || !p)
+            fail(PDHG_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        addr[dev] = static_cast<double *>(p);
+    }
+    return addr[dev];
+}
+
+// The same reduction as head_linear_costs_backward into the static scratch
+// array: no allocation and no wait; calls that overlap on one GPU race on it.
+void head_linear_costs_backward_noalloc(hipStream_t s, int32_t B, int32_t n, int32_t p,
+                                        const double *f, const double *gc, double *gW) {
+    if (p < 1 || p > kHeadPmax) fail(PDHG_ERR_INVALID_ARG, "need 1 <= p <= 64 (the scratch holds 64 x 64 partials)");
+    const int64_t N = (int64_t)B * n;
+    double *part = scratch_address(s);
+    k_costs_grad_part<<<(unsigned)(p * kHeadChunks), kBlock, 0, s>>>(N, p, f, gc, part);
+    k_costs_grad_final<<<1, 64, 0, s>>>(p, part, gW);
+    PDHG_HIP(hipGetLastError());
 }
 
 void head_qp_value(hipStream_t s, int32_t B, int32_t n, int32_t r, const double *F,

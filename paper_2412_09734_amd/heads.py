@@ -49,6 +49,18 @@ def linear_costs_backward(f, gc, device=None) -> torch.Tensor:
     return gW
 
 
+def linear_costs_backward_noalloc(f, gc, gW, device=None) -> torch.Tensor:
+    """linear_costs_backward into a caller-provided gW [p], with no device
+    allocation (static partial-sum array; p <= 64); returns gW."""
+    dev = _device(device)
+    ft, gt = _f64(f, dev), _f64(gc, dev)
+    B, n, p = ft.shape
+    capi.check(capi.lib().pdhg_linear_costs_backward_noalloc(B, n, p, _ptr(ft), _ptr(gt), _ptr(gW),
+                                                             _stream_ptr()),
+               "pdhg_linear_costs_backward_noalloc")
+    return gW
+
+
 def qp_value(F, d, c, x, grad=True, device=None):
     """(value [B], gradient [B, n] or None) of 1/2 x'(F F' + diag d)x + c'x."""
     dev = _device(device)
