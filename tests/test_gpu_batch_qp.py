@@ -82,8 +82,8 @@ def test_batch_qp_rows_paths_match_oracle(pdhg, oracle_lib, rows):
             assert rel_inf(to_np(gd[b]), gdo) <= 1e-9
             xso, yso, ro = o.solve()
             assert res[b]["status"] == 1 and ro["status"] == 1
-            assert abs(res[b]["iterations"] - ro["iterations"]) <= 64
-            assert abs(res[b]["primal_obj"] - ro["primal_obj"]) <= 1e-5 * (1 + abs(ro["primal_obj"]))
+            assert res[b]["iterations"] == ro["iterations"]
+            assert abs(res[b]["primal_obj"] - ro["primal_obj"]) <= 1e-6 * (1 + abs(ro["primal_obj"]))
 
 
 def test_batch_qp_beyond_lds_matches_oracle(pdhg, oracle_lib):
@@ -109,8 +109,8 @@ def test_batch_qp_beyond_lds_matches_oracle(pdhg, oracle_lib):
             assert rel_inf(to_np(gd[b]), gdo) <= 1e-9
             xso, yso, ro = o.solve()
             assert res[b]["status"] == 1 and ro["status"] == 1
-            assert abs(res[b]["iterations"] - ro["iterations"]) <= 64
-            assert abs(res[b]["primal_obj"] - ro["primal_obj"]) <= 1e-5 * (1 + abs(ro["primal_obj"]))
+            assert res[b]["iterations"] == ro["iterations"]
+            assert abs(res[b]["primal_obj"] - ro["primal_obj"]) <= 1e-6 * (1 + abs(ro["primal_obj"]))
 
 
 def test_batch_qp_autotune_then_solve(pdhg, oracle_lib):
@@ -125,8 +125,8 @@ def test_batch_qp_autotune_then_solve(pdhg, oracle_lib):
         lp = gen.portfolio_instance(p, b)
         _, _, ro = oracle_lib.Oracle(lp).solve()
         assert res[b]["status"] == 1 and ro["status"] == 1
-        assert abs(res[b]["iterations"] - ro["iterations"]) <= 64
-        assert abs(res[b]["primal_obj"] - ro["primal_obj"]) <= 1e-5 * (1 + abs(ro["primal_obj"]))
+        assert res[b]["iterations"] == ro["iterations"]
+        assert abs(res[b]["primal_obj"] - ro["primal_obj"]) <= 1e-6 * (1 + abs(ro["primal_obj"]))
 
 
 def test_batch_qp_solve_matches_oracle(pdhg, oracle_lib):
@@ -141,8 +141,7 @@ def test_batch_qp_solve_matches_oracle(pdhg, oracle_lib):
             assert r["status"] == 1 and ro["status"] == 1, (b, r, ro)
             assert r["kkt_rel"] <= 1e-6
             assert abs(r["primal_obj"] - ro["primal_obj"]) <= 1e-6 * (1 + abs(ro["primal_obj"]))
-            # same algorithm and check period: the counts agree up to one period
-            assert abs(r["iterations"] - ro["iterations"]) <= 64, (b, r["iterations"], ro["iterations"])
+            assert r["iterations"] == ro["iterations"], (b, r["iterations"], ro["iterations"])
             assert rel_inf(to_np(x[b]), xo) <= 1e-4
             kk = oracle_lib.kkt(lp, to_np(x[b]), to_np(y[b]))
             assert kk["kkt"] <= 2e-6
@@ -208,14 +207,13 @@ def test_batch_qp_infeasibility_matches_oracle(pdhg, oracle_lib, m, n, r, seed, 
              f"oracle {ro['status_name']} at {ro['iterations']}")
         assert ro["status_name"] == kind
         assert rb["status_name"] == kind, (b, rb["status_name"], kind)
-        assert abs(rb["iterations"] - ro["iterations"]) <= 4 * 64, (b, rb["iterations"], ro["iterations"])
+        assert rb["iterations"] == ro["iterations"], (b, rb["iterations"], ro["iterations"])
         xb, yb = to_np(x[b]), to_np(y[b])
         if kind == "primal_infeasible":
             pos, neg = (yb > 0) & np.isfinite(lp.lc), (yb < 0) & np.isfinite(lp.uc)
             assert abs(np.dot(lp.lc[pos], yb[pos]) + np.dot(lp.uc[neg], yb[neg]) - 1.0) <= 1e-9
             assert np.max(a.T @ yb) <= 1e-8 * (1 + 1e-6)
-            if rb["iterations"] == ro["iterations"]:
-                assert rel_inf(yb, yo) <= 1e-6
+            assert rel_inf(yb, yo) <= 1e-6
         elif kind == "dual_infeasible":
             q = sb.q_factor @ sb.q_factor.T + np.diag(sb.q_diag[b])
             assert abs(np.dot(lp.c, xb) + 1.0) <= 1e-12
@@ -226,10 +224,9 @@ def test_batch_qp_infeasibility_matches_oracle(pdhg, oracle_lib, m, n, r, seed, 
             assert np.min(ad[~eq & np.isfinite(lp.lc)], initial=0.0) >= -1e-8 * (1 + 1e-6)
             assert np.max(ad[~eq & np.isfinite(lp.uc)], initial=0.0) <= 1e-8 * (1 + 1e-6)
             assert np.min(xb) >= -1e-8 and xb[-1] > 0.0
-            if rb["iterations"] == ro["iterations"]:
-                assert rel_inf(xb, xo) <= 1e-6
+            assert rel_inf(xb, xo) <= 1e-6
         else:
-            assert abs(rb["primal_obj"] - ro["primal_obj"]) <= 1e-5 * (1 + abs(ro["primal_obj"]))
+            assert abs(rb["primal_obj"] - ro["primal_obj"]) <= 1e-6 * (1 + abs(ro["primal_obj"]))
             assert oracle_lib.kkt(lp, xb, yb)["kkt"] <= 1e-4 * (1 + 1e-6)
 
 

@@ -109,7 +109,6 @@ def test_qp_infeasibility_matches_oracle(pdhg, oracle_lib, kind, m, n, seed, eps
          f"iterations gpu={rg['iterations']} oracle={ro['iterations']}")
     want = "dual_infeasible" if kind == "unbounded" else "primal_infeasible"
     assert ro["status_name"] == want and rg["status_name"] == want
-    assert abs(rg["iterations"] - ro["iterations"]) <= 64
-    if rg["iterations"] == ro["iterations"]:
-        ray_g, ray_o = (yg, yo) if want == "primal_infeasible" else (xg, xo)
-        assert rel_inf(to_np(ray_g), ray_o) <= 1e-7
+    assert rg["iterations"] == ro["iterations"]
+    ray_g, ray_o = (yg, yo) if want == "primal_infeasible" else (xg, xo)
+    assert rel_inf(to_np(ray_g), ray_o) <= 1e-7
