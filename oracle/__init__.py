@@ -21,9 +21,10 @@ STATUS = {0: "unsolved", 1: "optimal", 2: "primal_infeasible", 3: "dual_infeasib
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no fast-math, no FMA contraction)."""
+    """Compile the oracle with gcc (-O2, no fast-math, no FMA contraction, OpenMP
+    for the products)."""
     if force or not os.path.exists(_SO):
-        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
                "-Wall", "-Wno-unused-function", os.path.join(_HERE, "oracle.c"),
                "-o", _SO + ".tmp", "-lm"]
         subprocess.run(cmd, check=True)
@@ -99,6 +100,9 @@ def lib():
         L.orc_unrolled_lp_backward.argtypes = [P, C.c_int64, P, P, P, P, P, P, P]
         L.orc_unrolled_lp_backward.restype = C.c_int
         L.orc_pin_steps.argtypes = [P, C.c_double, C.c_double]
+        L.orc_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads(1)   # one thread unless a caller asks for more (set_threads)
         L.orc_unrolled_qp.argtypes = [P, C.c_int64, P, P, P, P, P, P]
         L.orc_unrolled_qp.restype = C.c_int
         L.orc_unrolled_qp_backward.argtypes = [P, C.c_int64, P, P, P, P, P, P, P, P]
@@ -299,3 +303,13 @@ class Oracle:
         if rc != 0:
             raise ValueError("unrolled backward rejected")
         return gc, glc[: self.m], guc[: self.m]
+
+
+def threads() -> int:
+    """Threads the oracle's products use (OpenMP; 0 when built without it)."""
+    return int(lib().orc_threads())
+
+
+def set_threads(t: int) -> None:
+    """Run the oracle's products on t threads (results do not depend on t)."""
+    lib().orc_set_threads(int(t))

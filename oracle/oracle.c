@@ -12,6 +12,11 @@
  * rule, KKT composition, check cadence, rAPDHG schedule, frozen schedule).
  * Sums accumulate in long double; nothing is blocked or fused.
  *
+ * The products with A~ and A~' may run on several threads (OpenMP over output
+ * rows, or over columns through a column-major copy of A~): every output entry
+ * is still summed alone, in the same order as on one thread, so results do not
+ * depend on the thread count. All other loops, reductions included, are serial.
+ *
  * Parity unpinned: restart_due (restart rule) and new_weight (primal-weight
  * update). The paper defers both rules to other solvers, so no value, closed
  * form or bound of its own pins them; only the final optima the oracle reaches
@@ -23,6 +28,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef long double ld;
 
@@ -33,6 +41,9 @@ struct orc_ctx {
     /* scaled constraint matrix: same layout as the input */
     double *val;         /* CSR values (nnz) or dense (m*n) */
     int dense;
+    /* column-major copy of the scaled sparse A~ (rows ascending in a column) */
+    int32_t *cptr, *crow;
+    double *cval;
     /* scaled quadratic term */
     double *qval;        /* CSR values */
     double *qf;          /* n x r */
@@ -99,6 +110,7 @@ void orc_default_options(orc_options *o) {
 /* out = A~ v  (m-vector) */
 static void a_mul(const orc_ctx *s, const double *v, double *out) {
     const int32_t m = s->m, n = s->n;
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < m; ++i) {
         ld acc = 0.0L;
         if (s->dense) {
@@ -115,6 +127,15 @@ static void a_mul(const orc_ctx *s, const double *v, double *out) {
 /* out = A~' w  (n-vector): entries of each column summed in row order */
 static void at_mul(const orc_ctx *s, const double *w, double *out) {
     const int32_t m = s->m, n = s->n;
+    if (s->cptr) {   /* the same sums, one column at a time */
+#pragma omp parallel for schedule(static)
+        for (int32_t j = 0; j < n; ++j) {
+            ld acc = 0.0L;
+            for (int32_t e = s->cptr[j]; e < s->cptr[j + 1]; ++e) acc += (ld)s->cval[e] * (ld)w[s->crow[e]];
+            out[j] = (double)acc;
+        }
+        return;
+    }
     ld *acc = lalloc(n);
     for (int32_t i = 0; i < m; ++i) {
         if (s->dense) {
@@ -454,6 +475,23 @@ orc_ctx *orc_create(const orc_problem *p, const orc_options *o) {
     for (int32_t i = 0; i < m; ++i) s->dr[i] = 1.0;
     for (int32_t j = 0; j < n; ++j) s->dc[j] = 1.0;
     scale(s);
+    if (!s->dense && m > 0) {   /* column-major copy of A~: rows ascending within a column */
+        const int32_t nnz = p->rowptr[m];
+        s->cptr = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+        s->crow = (int32_t *)malloc(sizeof(int32_t) * (nnz > 0 ? nnz : 1));
+        s->cval = dalloc(nnz > 0 ? nnz : 1);
+        for (int32_t e = 0; e < nnz; ++e) s->cptr[p->colidx[e] + 1]++;
+        for (int32_t j = 0; j < n; ++j) s->cptr[j + 1] += s->cptr[j];
+        int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+        memcpy(fill, s->cptr, sizeof(int32_t) * ((size_t)n + 1));
+        for (int32_t i = 0; i < m; ++i)
+            for (int32_t e = p->rowptr[i]; e < p->rowptr[i + 1]; ++e) {
+                const int32_t k = fill[p->colidx[e]]++;
+                s->crow[k] = i;
+                s->cval[k] = s->val[e];
+            }
+        free(fill);
+    }
     s->c = dalloc(n); s->lv = dalloc(n); s->uv = dalloc(n);
     s->lc = dalloc(m); s->uc = dalloc(m);
     set_vectors(s);
@@ -481,9 +519,27 @@ orc_ctx *orc_create(const orc_problem *p, const orc_options *o) {
     return s;
 }
 
+/* Threads of the products (OpenMP); 0 when built without OpenMP. */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 0;
+#endif
+}
+
+void orc_set_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 void orc_destroy(orc_ctx *s) {
     if (!s) return;
     free(s->val); free(s->qval); free(s->qf); free(s->qd);
+    free(s->cptr); free(s->crow); free(s->cval);
     free(s->dr); free(s->dc); free(s->c); free(s->lc); free(s->uc);
     free(s->lv); free(s->uv);
     free(s);

@@ -76,6 +76,8 @@ void orc_default_options(orc_options *o);
 
 /* Scale the problem and estimate the step size. Returns NULL on invalid input. */
 orc_ctx *orc_create(const orc_problem *p, const orc_options *o);
+int orc_threads(void);          /* threads the products use (0 without OpenMP) */
+void orc_set_threads(int t);    /* t > 0: threads for the products */
 void orc_destroy(orc_ctx *ctx);
 
 /* Scaling vectors D_r [m], D_c [n]; step eta, initial primal weight omega,

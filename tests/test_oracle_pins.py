@@ -639,3 +639,22 @@ def test_norm_q_rayleigh_quotients_of_the_start_vector(oracle_lib):
             assert est >= prev * (1 - 1e-14)
             prev = est
         assert prev <= np.linalg.eigvalsh(qs)[-1] * (1 + 1e-12)
+
+
+def test_results_do_not_depend_on_thread_count(oracle_lib):
+    """The products may run on several threads (rows of A~, columns of A~'
+    through a column-major copy); every entry is summed in the same order, so
+    a solve and the scaling are bitwise equal on 1 and 4 threads."""
+    lp = gen.large_zipf_lp(m=3000, n=6000, kmax=300, seed=91)
+    out = []
+    for t in (1, 4):
+        oracle_lib.set_threads(t)
+        o = _orc(lp, iteration_limit=700)
+        sc = o.scaling()
+        x, y, r = o.solve()
+        out.append((sc["eta"], sc["power_iters"], x, y, r["iterations"], r["primal_obj"]))
+    oracle_lib.set_threads(1)
+    a, b = out
+    assert a[0] == b[0] and a[1] == b[1] and a[4] == b[4] and a[5] == b[5]
+    np.testing.assert_array_equal(a[2], b[2])
+    np.testing.assert_array_equal(a[3], b[3])
