@@ -42,13 +42,14 @@ def kernel_bytes(m: int, n: int, nnz: int) -> dict:
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "sparse_zipf_1Mx2M_pmc_traffic.txt")
-KERNEL_SOURCES = ["lp_kernels.hip", "device.hpp", "common.hpp"]
+KERNEL_SOURCES = ["lp_kernels.hip", "device.hpp", "common.hpp", "setup.hip"]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
-    WRITE_SIZE counter summary (calibrated against a 1 GiB copy), or None when
-    the kernel sources changed since the counters were taken."""
+def measured_traffic(step: str):
+    """HBM bytes per iteration step ('primal' or 'dual': the sum over the step's
+    kernels) from the committed FETCH_SIZE / WRITE_SIZE counter summary
+    (calibrated against a 1 GiB copy), or None when the kernel sources changed
+    since the counters were taken."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
@@ -62,30 +63,94 @@ def measured_traffic(kernel: str):
                   if line.startswith(("kernel-sources-sha256:", "traffic-bytes ")))
     if fields.get("kernel-sources-sha256", "").strip() != h.hexdigest():
         return None
-    v = fields.get(f"traffic-bytes {kernel}")
+    v = fields.get(f"traffic-bytes {step}")
     return int(v) if v else None
 
 
 def cpu_baseline(lp, gpu_iters: int, gpu_power_iters: int) -> dict:
     """The oracle on a bounded sample of the same LP: its scaling, then 40
-    iterations (checks at the first and last), timed on one host core; the
-    per-LP time is extrapolated to the GPU's power-iteration and iteration
-    counts (each power step costs about one iteration's two products)."""
+    iterations (checks at the first and last), timed on all host threads the
+    box gives the process (OMP_NUM_THREADS, else every core: the products run
+    on them) and on one; the per-LP time is extrapolated to the GPU's
+    power-iteration and iteration counts (each power step costs about one
+    iteration's two products)."""
     import oracle
     oracle.build(force=False)
     sample_iters = 40
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+
+    def run(t):
+        oracle.set_threads(t)
+        t0 = time.perf_counter()
+        orc = oracle.Oracle(lp, power_max_iters=1, iteration_limit=sample_iters)
+        t_setup = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        orc.solve()
+        t_iter = (time.perf_counter() - t1) / sample_iters
+        orc.close()
+        return t_setup, t_iter, t_setup + (gpu_power_iters + gpu_iters) * t_iter
+
+    s_all, i_all, lp_all = run(threads)
+    s_one, i_one, lp_one = run(1)
+    oracle.set_threads(1)
+    return {"value": 1.0 / lp_all, "unit": "LPs/s", "cores": threads, "kind": "oracle",
+            "single_core_value": 1.0 / lp_one,
+            "sample": (f"oracle scaling + {sample_iters} iterations on the full LP, extrapolated to "
+                       f"{gpu_power_iters} power steps + {gpu_iters} iterations per LP: on {threads} "
+                       f"threads (products parallel, the rest serial) scaling {s_all:.2f} s and "
+                       f"{i_all * 1e3:.1f} ms per iteration; on 1 thread {s_one:.2f} s and "
+                       f"{i_one * 1e3:.1f} ms")}
+
+
+def batched_vs_plain(loop_sample: int = 8, steps: int = 3) -> dict:
+    """The batched half of the metric in the default run: 2,048 grid min-cost
+    flow LPs sharing one incidence matrix, created (layout, scaling, step
+    size) and solved in one persistent launch, against the plain solver looped
+    over the first instances (create + solve each), in LPs solved per second."""
+    import numpy as np
+    import torch
+
+    import gen
+    from paper_2412_09734_amd.solver import BatchSolver, Solver
+
+    dev = torch.device("cuda:0")
+    B = 2048
+    sb = gen.grid_mincost_batch(batch=B, seed=gen.seed_for(3, 0))
+    kw = {k: (torch.from_numpy(np.ascontiguousarray(v)).to(dev, torch.int32 if v.dtype.kind in "iu"
+                                                             else torch.float64)
+              if isinstance(v, np.ndarray) else v)
+          for k, v in dict(shared_a=True, batch=B, m=sb.m, n=sb.n, rowptr=sb.rowptr, colidx=sb.colidx,
+                           val=sb.val, c=sb.c, lc=sb.lc, uc=sb.uc, lv=sb.lv, uv=sb.uv).items()}
+    with BatchSolver(**kw) as bs:
+        best = bs.autotune(128)
+        bs.set_launch(best)
+        bs.solve()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    orc = oracle.Oracle(lp, power_max_iters=1, iteration_limit=sample_iters)
-    t_setup = time.perf_counter() - t0
+    solved = 0
+    for _ in range(steps):
+        with BatchSolver(**kw) as bs:
+            bs.set_launch(best)
+            _, _, res = bs.solve()
+            solved += sum(r["status"] == 1 for r in res)
+    torch.cuda.synchronize()
+    batch_rate = solved / (time.perf_counter() - t0)
+    inst = [sb.instance(b) for b in range(loop_sample)]
+    with Solver.from_lp(inst[0]) as s:
+        s.solve()
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
-    orc.solve()
-    t_iter = (time.perf_counter() - t1) / sample_iters
-    orc.close()
-    per_lp = t_setup + (gpu_power_iters + gpu_iters) * t_iter
-    return {"value": 1.0 / per_lp, "unit": "LPs/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle scaling ({t_setup:.2f} s) + {sample_iters} iterations "
-                       f"({t_iter * 1e3:.1f} ms each) on the full LP, extrapolated to "
-                       f"{gpu_power_iters} power steps + {gpu_iters} iterations per LP")}
+    ok = 0
+    for lp in inst:
+        with Solver.from_lp(lp) as s:
+            _, _, r = s.solve()
+        ok += r["status"] == 1
+    torch.cuda.synchronize()
+    loop_rate = ok / (time.perf_counter() - t1)
+    return {"workload": f"{B} min-cost-flow LPs sharing a 32x32 grid incidence (1024 x 3968), KKT <= 1e-4",
+            "batched_lps_per_s": round(batch_rate, 2), "plain_looped_lps_per_s": round(loop_rate, 2),
+            "speedup": round(batch_rate / loop_rate, 1), "threads_per_instance": int(best),
+            "batched_steps": steps, "looped_instances": loop_sample}
 
 
 def main():
@@ -96,6 +161,8 @@ def main():
     ap.add_argument("--m", type=int, default=1_000_000)
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="sparse workload: skip the batched-vs-plain grid measurement")
     ap.add_argument("--iteration-limit", type=int, default=0,
                     help="stop every solve after this many iterations (profiling runs only)")
     ap.add_argument("--eps", type=float, default=1e-4,
@@ -215,19 +282,31 @@ def main():
     prim_ms = float(np.mean([i["kernel_primal_ms"] for i in samples])) if samples else float("nan")
     dual_ms = float(np.mean([i["kernel_dual_ms"] for i in samples])) if samples else float("nan")
     dom = "primal" if prim_ms >= dual_ms else "dual"
-    dom_ms = max(prim_ms, dual_ms)
-    achieved = kb[dom] / (dom_ms * 1e-3) / 1e9
+    other = "dual" if dom == "primal" else "primal"
+    ms = {"primal": prim_ms, "dual": dual_ms}
+    achieved = kb[dom] / (ms[dom] * 1e-3) / 1e9
     iter_bytes = kb["primal"] + kb["dual"]
     iter_ms = prim_ms + dual_ms
     solve_s = float(np.mean([i["solve_seconds"] for i in infos]))
     setup_s = float(np.mean([i["setup_seconds"] for i in infos]))
-    kname = "k_primal" if dom == "primal" else "k_dual"
-    full_size = (lp.m, lp.n) == (1_000_000, 2_000_000)
+    # the library's automatic layouts for a large sparse A (options panel_rows / hot_cols)
+    layout = dict(kv.split("=") for kv in filter(None, args.layout.split(",")))
+    panels = layout.get("panel_rows", "-1") != "0" and (lp.m > 262144 or int(layout.get("panel_rows", "-1")) > 0)
+    hot = layout.get("hot_cols", "-1") != "0" and (lp.n > 262144 or int(layout.get("hot_cols", "-1")) > 0)
+    names = {"primal": ("primal step: k_panel_dot (long rows of A~', LDS panels of y) beside k_primal_sell "
+                        "(SELL-64 rows) on a second stream, then k_primal_panels (panel sums + primal update)"
+                        if panels else "k_primal"),
+             "dual": "k_dual_hot (x_ext[0, 16384) in LDS)" if hot else "k_dual"}
+    full_size = (lp.m, lp.n) == (1_000_000, 2_000_000) and not args.layout
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(kname) if full_size else None,
-            "kernel": kname,
-            "algorithmic_bytes_per_launch": kb[dom], "avg_launch_ms": round(dom_ms, 5),
+            "traffic": measured_traffic(dom) if full_size else None,
+            "kernel": names[dom],
+            "algorithmic_bytes_per_launch": kb[dom], "avg_launch_ms": round(ms[dom], 5),
+            "other_step": {"kernel": names[other], "algorithmic_bytes": kb[other],
+                           "avg_ms": round(ms[other], 5),
+                           "achieved": round(kb[other] / (ms[other] * 1e-3) / 1e9, 1),
+                           "traffic": measured_traffic(other) if full_size else None},
             "iteration_gbps": round(iter_bytes / (iter_ms * 1e-3) / 1e9, 1)}
     out = {
         "metric": METRIC, "value": round(args.steps / elapsed, 5), "unit": "LPs/s",
@@ -253,6 +332,9 @@ def main():
                    "bytes_per_iteration": iter_bytes},
         "roofline": roof,
     }
+    if not args.no_batched and not infeasible:
+        log("bench: batched grid LPs vs the plain solver looped")
+        out["config"]["batched"] = batched_vs_plain()
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(lp, iters, int(last["power_iters"]))

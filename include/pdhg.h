@@ -156,7 +156,8 @@ typedef struct {
     int32_t power_iters;
     /* HIP-event timings of one check period (timing_chunk), milliseconds */
     int32_t kernel_samples;      /* number of timed plain iterations */
-    double kernel_primal_ms;     /* average primal-step kernel duration */
+    double kernel_primal_ms;     /* average primal step: earliest start to latest end of its
+                                    kernels (two streams when the LDS panels run) */
     double kernel_dual_ms;       /* average dual-step kernel duration */
     int64_t polish_iterations;   /* iterations of the polishing phases (in iterations too) */
 } pdhg_result;

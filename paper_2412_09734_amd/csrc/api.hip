@@ -7,6 +7,7 @@
 // period returns at once when the controller has set the done flag, so the
 // host can keep two periods in flight and poll a pinned status copy without
 // stalling the GPU.
+#include <algorithm>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -19,6 +20,7 @@
 namespace pdhg {
 
 static thread_local std::string g_err = "";
+constexpr int kTimingEvents = 7;   // per timed plain iteration
 
 void fail(pdhg_err code, const std::string &msg) { throw Error{code, msg}; }
 
@@ -161,7 +163,7 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
                 } else {
                     enqueue_check(h, (int32_t)plain, 0, 0);
                     if (timed) {
-                        tev.resize(3 * (size_t)plain);
+                        tev.resize(kTimingEvents * (size_t)plain);
                         for (auto &e : tev) PDHG_HIP(hipEventCreate(&e));
                         timing_t = t;
                     }
@@ -170,11 +172,14 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
                             enqueue_plain(h, j);
                             continue;
                         }
-                        PDHG_HIP(hipEventRecord(tev[3 * (j - 1)], s));
-                        launch_primal(h, j);
-                        PDHG_HIP(hipEventRecord(tev[3 * (j - 1) + 1], s));
+                        // events: reference, the primal step's kernels on each stream
+                        // (start / end pairs), then around the dual step
+                        hipEvent_t *e = &tev[kTimingEvents * (size_t)(j - 1)];
+                        PDHG_HIP(hipEventRecord(e[0], s));
+                        launch_primal(h, j, e + 1);
+                        PDHG_HIP(hipEventRecord(e[5], s));
                         launch_dual(h, j);
-                        PDHG_HIP(hipEventRecord(tev[3 * (j - 1) + 2], s));
+                        PDHG_HIP(hipEventRecord(e[6], s));
                     }
                 }
             }
@@ -224,12 +229,17 @@ static void run_solve(Handle &h, const double *x_init, const double *y_init, dou
     int32_t samples = 0;
     // the timed period counts only if the solve was still running after its check
     if (!tev.empty() && have_timing_state && !timing_state.done) {
-        for (size_t j = 0; j + 2 < tev.size(); j += 3) {
-            float a = 0.f, b = 0.f;
-            PDHG_HIP(hipEventElapsedTime(&a, tev[j], tev[j + 1]));
-            PDHG_HIP(hipEventElapsedTime(&b, tev[j + 1], tev[j + 2]));
-            kp += a;
-            kd += b;
+        // primal step: earliest start to latest end of its kernels on the two
+        // streams (times from the reference event); dual step: its own events
+        for (size_t j = 0; j + kTimingEvents - 1 < tev.size(); j += kTimingEvents) {
+            float t1 = 0.f, t2 = 0.f, t3 = 0.f, t4 = 0.f, d = 0.f;
+            PDHG_HIP(hipEventElapsedTime(&t1, tev[j], tev[j + 1]));
+            PDHG_HIP(hipEventElapsedTime(&t2, tev[j], tev[j + 2]));
+            PDHG_HIP(hipEventElapsedTime(&t3, tev[j], tev[j + 3]));
+            PDHG_HIP(hipEventElapsedTime(&t4, tev[j], tev[j + 4]));
+            PDHG_HIP(hipEventElapsedTime(&d, tev[j + 5], tev[j + 6]));
+            kp += std::max(t2, t4) - std::min(t1, t3);
+            kd += d;
             ++samples;
         }
     }

@@ -347,7 +347,7 @@ void batch_update_data(BatchHandle &b, const double *c, const double *lc, const 
 void batch_destroy(BatchHandle *b);
 
 // ---- iteration kernels (lp_kernels.hip) -------------------------------------
-void launch_primal(Handle &h, int32_t j);
+void launch_primal(Handle &h, int32_t j, hipEvent_t *timing = nullptr);
 void launch_dual(Handle &h, int32_t j);
 void launch_primal_check(Handle &h, double tau_override = -1.0);
 void launch_dual_check(Handle &h, double sigma_override = -1.0);

@@ -611,32 +611,43 @@ __global__ __launch_bounds__(kBlock) void k_scatter_scaled(const int32_t *__rest
 
 static inline dim3 grid_of(const HMat &M) { return dim3((unsigned)M.nblocks()); }
 
-void launch_primal(Handle &h, int32_t j) {
+void launch_primal(Handle &h, int32_t j, hipEvent_t *timing) {
     if (h.dense) {
         dense_primal(h, j);
         return;
     }
     if (h.AT.nblocks() == 0) return;
     if (h.PT.R > 0) {
-        // panel rows on stream2 beside the SELL-64 rest on the main stream
+        // panel rows on stream2 beside the SELL-64 rest on the main stream;
+        // timing (4 events): around the kernels on stream2, then on the main stream
         PDHG_HIP(hipEventRecord(h.ev_fork, h.stream));
         PDHG_HIP(hipStreamWaitEvent(h.stream2, h.ev_fork, 0));
         const PanelView P = view(h.PT);
+        if (timing) PDHG_HIP(hipEventRecord(timing[0], h.stream2));
         k_panel_dot<<<h.PT.nwg, kPanelThreads, 0, h.stream2>>>(P, h.y.p, h.st.p);
         k_primal_panels<<<(unsigned)ceil_div(h.PT.R, kBlock), kBlock, 0, h.stream2>>>(
             P, h.x.p, h.x0.p, h.c.p, h.lv.p, h.uv.p, h.xext.p, h.st.p, j, h.opt.gamma);
+        if (timing) PDHG_HIP(hipEventRecord(timing[1], h.stream2));
         PDHG_HIP(hipEventRecord(h.ev_join, h.stream2));
         const int32_t ns = h.AT.nslices - h.sell_skip;
+        if (timing) PDHG_HIP(hipEventRecord(timing[2], h.stream));
         if (ns > 0)
             k_primal_sell<<<(unsigned)ceil_div(ns, kBlock / 64), kBlock, 0, h.stream>>>(
                 view(h.AT), h.sell_skip, h.y.p, h.x.p, h.x0.p, h.c.p, h.lv.p, h.uv.p, h.xext.p,
                 h.st.p, j, h.opt.gamma);
+        if (timing) PDHG_HIP(hipEventRecord(timing[3], h.stream));
         PDHG_HIP(hipStreamWaitEvent(h.stream, h.ev_join, 0));
         return;
     }
+    if (timing) PDHG_HIP(hipEventRecord(timing[0], h.stream));
     k_primal<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
         view(h.AT), h.y.p, h.x.p, h.x0.p, h.c.p, h.lv.p,
         h.uv.p, h.xext.p, h.st.p, j, h.opt.gamma);
+    if (timing) {
+        PDHG_HIP(hipEventRecord(timing[1], h.stream));
+        PDHG_HIP(hipEventRecord(timing[2], h.stream));
+        PDHG_HIP(hipEventRecord(timing[3], h.stream));
+    }
 }
 
 void launch_dual(Handle &h, int32_t j) {
