@@ -142,7 +142,9 @@ __device__ __forceinline__ int32_t next_instance(int32_t *queue) {
     __shared__ int32_t id;
     if (threadIdx.x == 0) id = atomicAdd(queue, 1);
     __syncthreads();
-    const int32_t r = id;
+    // the same value in every lane: a scalar, so the instance's pointers and
+    // sizes live in scalar registers
+    const int32_t r = __builtin_amdgcn_readfirstlane(id);
     __syncthreads();
     return r;
 }
@@ -169,6 +171,15 @@ __device__ __forceinline__ double sell_dot(const int32_t *__restrict__ sp, const
     return sell_dot_bw(ci, va, b, w, lane, v);
 }
 
+// Sums of S SELL-64 lanes (slices starting at base[q] with w[q] entries,
+// the same in every lane of the wave), each in entry order, taken C slices at a time: the
+// first U entries of the C slices are loaded before the first product
+// (unconditional loads at indices clamped to each slice's last entry,
+// products past w dropped by a select, as in sell_group), so their round
+// trips overlap; wider slices continue U entries at a time. A slice with
+// w = 0 loads the array's first 64 entries (the array holds at least 64) and
+// sums to 0; a chunk whose slices are all empty loads nothing. Same sums, in
+// the same order, as sell_dot_bw per slice.
 // Same with the slice's first entry and width already known. Entries are
 // fetched four at a time before they are used (independent loads in flight),
 // and added in row order.
@@ -749,19 +760,43 @@ __global__ __launch_bounds__(BT) void k_batch_solve(BArgs a, BOpts o) {
     }
 }
 
+// Entries per column slice and per row slice of the register-resident matrix
+// (node-arc incidence matrices: two entries per column, node degree <= 8).
+constexpr int kResCol = 2, kResRow = 8;
+
+// A double in LDS at a byte offset from the start of the dynamic allocation.
+__device__ __forceinline__ double lds_at(const double *lds, int32_t off) {
+    return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(lds) + off);
+}
+
 // Same iteration with the gathered vectors held on chip: y (for A~'y) and
-// x_ext (for A~x_ext; at checks the PDHG points) live in LDS, and each thread
-// keeps the row pointers of its S columns and S rows in registers. The
-// per-element data (iterate, anchors, c~, bounds) are read and written by
-// their owner only; those loads do not depend on the gathers and overlap
-// them, so an iteration costs about one round trip for the shared matrix
-// entries plus LDS instead of a chain of memory round trips. Same arithmetic
-// and summation order as k_batch_solve.
-template <int BT, int S, bool RAYS>
-__global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_t nmax) {
+// x_ext (for A~x_ext; at checks the PDHG points) live in LDS, next to the
+// per-row anchor and bounds; each thread owns S columns and S rows (RES: S/4
+// rows), in SELL-64 slices, so a wave's slices are whole.
+//   RES = false: the matrix entries stream from the shared SELL-64 copies (L2)
+//     on every product; the per-column iterate, anchor, cost and bounds stay
+//     in registers.
+//   RES = true (a shared matrix whose column slices hold at most kResCol and
+//     row slices at most kResRow entries): every thread loads its slices'
+//     entries once per instance into registers, with each index turned into
+//     the byte offset of the LDS element it gathers, so an iteration reads no
+//     matrix data from memory: a product is LDS gathers and FMAs. The anchor,
+//     cost and upper bound of the columns move to LDS to make room.
+// Entries past a slice's width are zeros gathering element 0, which adds
+// +0 like the slices' own padding. Same arithmetic and summation order as
+// k_batch_solve.
+template <int BT, int S, bool RES, bool RAYS>
+__global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_t nmax, int32_t mmax) {
+    constexpr int SR = RES ? (S >= 4 ? S / 4 : 1) : S;   // row slices per thread
     extern __shared__ double lds[];
-    double *sx = lds;          // x_ext, at checks x^
-    double *sy = lds + nmax;   // y, at checks y^
+    double *sx = lds;                 // x_ext, at checks x^
+    double *sy = lds + nmax;          // y, at checks y^
+    double *slc = sy + mmax;          // scaled row bounds
+    double *suc = slc + mmax;
+    double *y0 = suc + mmax;          // dual anchor
+    double *sx0 = y0 + mmax;          // RES: primal anchor
+    double *scr = sx0 + nmax;         // RES: scaled cost
+    double *suv = scr + nmax;         // RES: scaled upper bound
     for (;;) {
         const int32_t b = next_instance<BT>(a.queue);
         if (b >= a.B) return;
@@ -771,12 +806,9 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
         const double *Dr = a.Dr + g.dr, *Dc = a.Dc + g.dc;
         const double *c_o = a.c_o + g.vc, *lv_o = a.lv_o + g.vc, *uv_o = a.uv_o + g.vc;
         const double *lc_o = a.lc_o + g.vr, *uc_o = a.uc_o + g.vr;
-        double *__restrict__ lc = a.lc + g.vr;
-        double *__restrict__ uc = a.uc + g.vr;
         double *__restrict__ xh = a.xh + g.vc;
         double *__restrict__ aty = a.aty + g.vc;
         double *__restrict__ y = a.y + g.vr;
-        double *__restrict__ y0 = a.y0 + g.vr;
         double *__restrict__ yh = a.yh + g.vr;
         const int32_t *__restrict__ tsci = a.tsci;
         const int32_t *__restrict__ asci = a.asci;
@@ -785,9 +817,12 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
         const double eta = a.eta[g.sidx];
         const double gam = o.gamma;
 
-        // slice start and width of each owned column / row (iteration invariant)
+        // streamed: slice start and width of each owned column / row
         int32_t tbase[S], tw[S], abase[S], aw[S];
-        // per-column iterate, anchor, cost and bounds stay in registers
+        // resident: the owned slices' entries (LDS byte offset, value)
+        int32_t tci[S][kResCol], rci[SR][kResRow];
+        double tva[S][kResCol], rva[SR][kResRow];
+        // per-column iterate and bounds in registers (streamed: also anchor, cost)
         double xr[S], x0r[S], cr[S], lvr[S], uvr[S];
         double nrm[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -800,7 +835,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                 tbase[q] = a.tsp[sl];
                 tw[q] = (a.tsp[sl + 1] - tbase[q]) >> 6;
             }
-            if (j < g.m) {
+            if (q < SR && j < g.m) {
                 const int32_t sl = as0 + (j >> 6);
                 abase[q] = a.asp[sl];
                 aw[q] = (a.asp[sl + 1] - abase[q]) >> 6;
@@ -809,22 +844,24 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                 const double d = Dc[j];
                 const double cj = d * c_o[j];
                 const double l = lv_o[j] / d, u = uv_o[j] / d;
-                cr[q] = cj;
+                if constexpr (RES) scr[j] = cj;
+                else cr[q] = cj;
                 lvr[q] = l;
-                uvr[q] = u;
+                if constexpr (RES) suv[j] = u;
+                else uvr[q] = u;
                 nrm[0] += cj * cj;
                 nrm[2] += c_o[j] * c_o[j];
                 const double v0 = a.x_init ? a.x_init[g.vc + j] / d : 0.0;
                 xr[q] = clampd(v0, l, u);
-                x0r[q] = xr[q];
-                if (RAYS) a.x0[g.vc + j] = xr[q];   // read by the ray pass
+                if constexpr (RES) sx0[j] = xr[q];
+                else x0r[q] = xr[q];
             }
             const int32_t i = j;
-            if (i < g.m) {
+            if (q < SR && i < g.m) {
                 const double d = Dr[i];
                 const double l = d * lc_o[i], u = d * uc_o[i];
-                lc[i] = l;
-                uc[i] = u;
+                slc[i] = l;
+                suc[i] = u;
                 double bb = 0.0, bo = 0.0;
                 if (isfinite(l)) bb = fmax(bb, fabs(l));
                 if (isfinite(u)) bb = fmax(bb, fabs(u));
@@ -840,6 +877,69 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                 y0[i] = yv;
             }
         }
+        // RES: the owned slices' entries into registers
+        auto load_matrix = [&]() {
+            if constexpr (RES) {
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+#pragma unroll
+                    for (int u = 0; u < kResCol; ++u) {
+                        const bool in = u < tw[q];
+                        const int32_t e = tbase[q] + 64 * u + lane;
+                        tci[q][u] = 8 * (nmax + (in ? tsci[e] : 0));
+                        tva[q][u] = in ? tsva[e] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < SR; ++q) {
+#pragma unroll
+                    for (int u = 0; u < kResRow; ++u) {
+                        const bool in = u < aw[q];
+                        const int32_t e = abase[q] + 64 * u + lane;
+                        rci[q][u] = 8 * (in ? asci[e] : 0);
+                        rva[q][u] = in ? asva[e] : 0.0;
+                    }
+                }
+            }
+        };
+        load_matrix();
+        // A~'y (gathering y from LDS) for owned column q; A~x_ext for owned row q
+        auto col_dot = [&](int q) -> double {
+            if constexpr (RES) {
+                double s = 0.0;
+#pragma unroll
+                for (int u = 0; u < kResCol; ++u) s = fma(tva[q][u], lds_at(lds, tci[q][u]), s);
+                return s;
+            } else {
+                return sell_dot_bw(tsci, tsva, tbase[q], tw[q], lane, sy);
+            }
+        };
+        auto row_dot = [&](int q) -> double {
+            if constexpr (RES) {
+                double s = 0.0;
+#pragma unroll
+                for (int u = 0; u < kResRow; ++u) s = fma(rva[q][u], lds_at(lds, rci[q][u]), s);
+                return s;
+            } else {
+                return sell_dot_bw(asci, asva, abase[q], aw[q], lane, sx);
+            }
+        };
+        auto x0_of = [&](int q, int32_t j) -> double {
+            if constexpr (RES) return sx0[j];
+            else return x0r[q];
+        };
+        auto set_x0 = [&](int q, int32_t j, double v) {
+            if constexpr (RES) sx0[j] = v;
+            else x0r[q] = v;
+        };
+        auto c_of = [&](int q, int32_t j) -> double {
+            if constexpr (RES) return scr[j];
+            else return cr[q];
+        };
+        auto uv_of = [&](int q, int32_t j) -> double {
+            if constexpr (RES) return suv[j];
+            else return uvr[q];
+        };
         wg_sum<BT, 4>(nrm);
         const double cn = sqrt(nrm[0]), bn = sqrt(nrm[1]);
         const double cnorm = sqrt(nrm[2]), bnorm = sqrt(nrm[3]);
@@ -847,6 +947,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
         double tau = eta / omega, sigma = eta * omega;
 
         int64_t t = 0, k = 0, restarts = 0;
+        int32_t tc = 0;   // t modulo check_every, without a 64-bit division per iteration
         double r_start = 0.0, r_prev = 0.0;
         int32_t status = 0;
         bool anchor_valid = false;   // the anchor's products are stored (after a restart)
@@ -858,7 +959,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
             // into ~40 registers per slot, which would spill
             int32_t tid = (int32_t)threadIdx.x;
             asm volatile("" : "+v"(tid));
-            const bool check = (t % o.check_every) == 0;
+            const bool check = tc == 0;
             const bool last = t + 1 >= o.limit;
             const bool keep = check || last;
             const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
@@ -866,24 +967,24 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
             for (int q = 0; q < S; ++q) {
                 const int32_t j = tid + q * BT;
                 if (j < g.n) {
-                    const double s = sell_dot_bw(tsci, tsva, tbase[q], tw[q], lane, sy);
-                    const double xhat = clampd(xr[q] - tau * (cr[q] - s), lvr[q], uvr[q]);
+                    const double s = col_dot(q);
+                    const double xhat = clampd(xr[q] - tau * (c_of(q, j) - s), lvr[q], uv_of(q, j));
                     sx[j] = 2.0 * xhat - xr[q];
                     if (keep) {
                         xh[j] = xhat;
                         aty[j] = s;
                     } else {
-                        xr[q] = ak * ((1.0 + gam) * xhat - gam * xr[q]) + bk * x0r[q];
+                        xr[q] = ak * ((1.0 + gam) * xhat - gam * xr[q]) + bk * x0_of(q, j);
                     }
                 }
             }
             __syncthreads();
 #pragma unroll
-            for (int q = 0; q < S; ++q) {
+            for (int q = 0; q < SR; ++q) {
                 const int32_t i = tid + q * BT;
                 if (i < g.m) {
-                    const double li = lc[i], ui = uc[i];
-                    const double av = sell_dot_bw(asci, asva, abase[q], aw[q], lane, sx);
+                    const double av = row_dot(q);
+                    const double li = slc[i], ui = suc[i];
                     const double yv = sy[i];
                     const double yhat = dual_prox(yv, av, sigma, li, ui);
                     if (keep) {
@@ -898,6 +999,7 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
             if (!keep) {
                 ++k;
                 ++t;
+                tc = tc + 1 == o.check_every ? 0 : tc + 1;
                 continue;
             }
             // check: the PDHG points replace x_ext and y in LDS for the products
@@ -905,22 +1007,25 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
             for (int q = 0; q < S; ++q) {
                 const int32_t j = tid + q * BT;
                 if (j < g.n) sx[j] = xh[j];
-                if (j < g.m) sy[j] = yh[j];
+                if (q < SR && j < g.m) sy[j] = yh[j];
             }
             __syncthreads();
-            double v[10];
+            // KKT sums, then (RAYS) the ray sums: v[10], v[11] over the columns
+            // (bound terms, c'dx), v[12] over the rows; rmx the ray violations
+            constexpr int NV = RAYS ? 13 : 10;
+            double v[NV], rmx[2] = {0.0, 0.0};
 #pragma unroll
-            for (int q = 0; q < 10; ++q) v[q] = 0.0;
+            for (int q = 0; q < NV; ++q) v[q] = 0.0;
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 const int32_t j = tid + q * BT;
                 if (j < g.n) {
-                    const double qq = sell_dot_bw(tsci, tsva, tbase[q], tw[q], lane, sy);
+                    const double qq = col_dot(q);
                     const double xhv = xh[j];
                     const double dx = xhv - xr[q];
                     v[0] += dx * dx;
                     v[1] += (qq - aty[j]) * dx;
-                    const double d0 = xhv - x0r[q];
+                    const double d0 = xhv - x0_of(q, j);
                     v[2] += d0 * d0;
                     const double d = Dc[j];
                     const double gr = c_o[j] - qq / d;
@@ -931,14 +1036,22 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                     v[3] += rd * rd;
                     v[4] += c_o[j] * (d * xhv);
                     v[5] += (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
-                    if (RAYS) a.qh[g.vc + j] = qq;
+                    if constexpr (RAYS) {
+                        a.qh[g.vc + j] = qq;
+                        double s2[2], m2[2];
+                        ray_col_terms(qq, a.q0[g.vc + j], d, xhv - x0_of(q, j), c_o[j], lo, hi, s2, m2);
+                        v[10] += s2[0];
+                        v[11] += s2[1];
+                        rmx[0] = fmax(rmx[0], m2[0]);
+                        rmx[1] = fmax(rmx[1], m2[1]);
+                    }
                 }
             }
 #pragma unroll
-            for (int q = 0; q < S; ++q) {
+            for (int q = 0; q < SR; ++q) {
                 const int32_t i = tid + q * BT;
                 if (i < g.m) {
-                    const double p = sell_dot_bw(asci, asva, abase[q], aw[q], lane, sx);
+                    const double p = row_dot(q);
                     const double d = Dr[i];
                     const double ax = p / d;
                     const double lo = lc_o[i], hi = uc_o[i];
@@ -951,10 +1064,17 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                     v[8] += dy * dy;
                     const double d0 = yhv - y0[i];
                     v[9] += d0 * d0;
-                    if (RAYS) a.ph[g.vr + i] = p;
+                    if constexpr (RAYS) {
+                        a.ph[g.vr + i] = p;
+                        double s1[1], m2[2];
+                        ray_row_terms(p, a.p0[g.vr + i], d, d0, lo, hi, s1, m2);
+                        v[12] += s1[0];
+                        rmx[0] = fmax(rmx[0], m2[0]);
+                        rmx[1] = fmax(rmx[1], m2[1]);
+                    }
                 }
             }
-            wg_sum<BT, 10>(v);
+            wg_sum<BT, NV>(v);
             P = v[4];
             D = v[7] + v[5];
             rel_p = sqrt(v[6]) / (1.0 + bnorm);
@@ -972,8 +1092,11 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                 break;
             }
             if (RAYS && anchor_valid) {
-                double rs[3], rm[2];
-                batch_ray_pass<BT>(a, g, xh, yh, y0, rs, rm);
+                // the rays' terms were summed in the check loops above, in
+                // the order of the separate pass of k_batch_solve
+                double rs[3] = {v[RAYS ? 10 : 0], v[RAYS ? 11 : 0], v[RAYS ? 12 : 0]};
+                double rm[2] = {rmx[0], rmx[1]};
+                wg_max<BT, 2>(rm);
                 const double obj_d = rs[0] + rs[2], obj_p = rs[1];
                 if (o.eps_pinf > 0.0 && obj_d > 0.0 && rm[0] <= o.eps_pinf * obj_d) {
                     status = PDHG_PRIMAL_INFEASIBLE;
@@ -1012,10 +1135,9 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
                     const int32_t j = tid + q * BT;
                     if (j < g.n) {
                         xr[q] = xh[j];
-                        x0r[q] = xr[q];
-                        if (RAYS) a.x0[g.vc + j] = xr[q];
+                        set_x0(q, j, xr[q]);
                     }
-                    if (j < g.m) {
+                    if (q < SR && j < g.m) {
                         sy[j] = yh[j];
                         y0[j] = yh[j];
                     }
@@ -1035,12 +1157,13 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
 #pragma unroll
                 for (int q = 0; q < S; ++q) {
                     const int32_t j = tid + q * BT;
-                    if (j < g.n) xr[q] = ak * ((1.0 + gam) * xh[j] - gam * xr[q]) + bk * x0r[q];
-                    if (j < g.m) sy[j] = ak * ((1.0 + gam) * yh[j] - gam * y[j]) + bk * y0[j];
+                    if (j < g.n) xr[q] = ak * ((1.0 + gam) * xh[j] - gam * xr[q]) + bk * x0_of(q, j);
+                    if (q < SR && j < g.m) sy[j] = ak * ((1.0 + gam) * yh[j] - gam * y[j]) + bk * y0[j];
                 }
                 ++k;
             }
             ++t;
+            tc = tc + 1 == o.check_every ? 0 : tc + 1;
             __syncthreads();
         }
         // original-space output of the last PDHG point, or the certifying ray
@@ -1048,8 +1171,8 @@ __global__ __launch_bounds__(BT) void k_batch_solve_lds(BArgs a, BOpts o, int32_
 #pragma unroll
         for (int q = 0; q < S; ++q) {
             const int32_t j = threadIdx.x + q * BT;
-            if (j < g.n) a.x_out[g.vc + j] = Dc[j] * (xray ? (xh[j] - x0r[q]) * ray_scale : xh[j]);
-            if (j < g.m) a.y_out[g.vr + j] = Dr[j] * (yray ? (yh[j] - y0[j]) * ray_scale : yh[j]);
+            if (j < g.n) a.x_out[g.vc + j] = Dc[j] * (xray ? (xh[j] - x0_of(q, j)) * ray_scale : xh[j]);
+            if (q < SR && j < g.m) a.y_out[g.vr + j] = Dr[j] * (yray ? (yh[j] - y0[j]) * ray_scale : yh[j]);
         }
         if (threadIdx.x == 0) {
             BatchRes r;
@@ -1540,10 +1663,21 @@ static int32_t resident(const void *kernel) {
 
 
 
-template <int BT, int S>
+// Dynamic LDS one workgroup may take (160 KB on gfx950), read once.
+static size_t lds_per_workgroup() {
+    static const size_t v = [] {
+        int dev = 0, bytes = 0;
+        PDHG_HIP(hipGetDevice(&dev));
+        PDHG_HIP(hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        return (size_t)bytes;
+    }();
+    return v;
+}
+
+template <int BT, int S, bool RES>
 static void launch_solve_lds_t(BatchHandle &h, const BOpts &o, BArgs a, size_t lds) {
-    const void *kern = o.detect ? reinterpret_cast<const void *>(&k_batch_solve_lds<BT, S, true>)
-                                : reinterpret_cast<const void *>(&k_batch_solve_lds<BT, S, false>);
+    const void *kern = o.detect ? reinterpret_cast<const void *>(&k_batch_solve_lds<BT, S, RES, true>)
+                                : reinterpret_cast<const void *>(&k_batch_solve_lds<BT, S, RES, false>);
     int dev = 0, per_cu = 0;
     PDHG_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
@@ -1553,9 +1687,9 @@ static void launch_solve_lds_t(BatchHandle &h, const BOpts &o, BArgs a, size_t l
     if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
     PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
     if (o.detect)
-        k_batch_solve_lds<BT, S, true><<<wg, BT, lds, h.stream>>>(a, o, h.nmax);
+        k_batch_solve_lds<BT, S, RES, true><<<wg, BT, lds, h.stream>>>(a, o, h.nmax, h.mmax);
     else
-        k_batch_solve_lds<BT, S, false><<<wg, BT, lds, h.stream>>>(a, o, h.nmax);
+        k_batch_solve_lds<BT, S, RES, false><<<wg, BT, lds, h.stream>>>(a, o, h.nmax, h.mmax);
     PDHG_HIP(hipGetLastError());
 }
 
@@ -1598,10 +1732,10 @@ __global__ __launch_bounds__(kBlock) void k_sell_fill(const int32_t *__restrict_
     }
 }
 
-static void build_batch_sell(hipStream_t s, int32_t nb, const std::vector<int32_t> &roff,
-                             const DBuf<int32_t> &rp, const DBuf<int32_t> &ci, const DBuf<double> &va,
-                             int64_t nnz, DBuf<int32_t> &sp, DBuf<int32_t> &sci, DBuf<double> &sva,
-                             DBuf<int32_t> &sfirst) {
+static int32_t build_batch_sell(hipStream_t s, int32_t nb, const std::vector<int32_t> &roff,
+                                const DBuf<int32_t> &rp, const DBuf<int32_t> &ci, const DBuf<double> &va,
+                                int64_t nnz, DBuf<int32_t> &sp, DBuf<int32_t> &sci, DBuf<double> &sva,
+                                DBuf<int32_t> &sfirst) {
     (void)nnz;
     std::vector<int32_t> first((size_t)nb + 1), h0, h1;
     for (int32_t b = 0; b < nb; ++b) {
@@ -1624,22 +1758,27 @@ static void build_batch_sell(hipStream_t s, int32_t nb, const std::vector<int32_
         PDHG_HIP(hipStreamSynchronize(s));
     }
     int64_t total = 0;
+    int32_t wmax = 0;
     for (int32_t i = 0; i < ns; ++i) {
+        wmax = std::max(wmax, hw[i]);
         total += 64 * (int64_t)hw[i];
         if (total >= INT32_MAX) fail(PDHG_ERR_UNSUPPORTED, "batch matrix too large for 32-bit offsets");
         off[(size_t)i + 1] = (int32_t)total;
     }
     load(sp, off.data(), off.size(), PDHG_MEM_HOST, s);
     load(sfirst, first.data(), first.size(), PDHG_MEM_HOST, s);
-    sci.alloc((size_t)std::max<int64_t>(total, 1));
-    sva.alloc((size_t)std::max<int64_t>(total, 1));
-    PDHG_HIP(hipMemsetAsync(sci.p, 0, (size_t)std::max<int64_t>(total, 1) * 4, s));
-    PDHG_HIP(hipMemsetAsync(sva.p, 0, (size_t)std::max<int64_t>(total, 1) * 8, s));
+    // at least one slice's worth: empty slices read the first 64 entries
+    const size_t cap = (size_t)std::max<int64_t>(total, 64);
+    sci.alloc(cap);
+    sva.alloc(cap);
+    PDHG_HIP(hipMemsetAsync(sci.p, 0, cap * 4, s));
+    PDHG_HIP(hipMemsetAsync(sva.p, 0, cap * 8, s));
     if (ns > 0)
         k_sell_fill<<<(unsigned)ceil_div((int64_t)ns * 64, kBlock), kBlock, 0, s>>>(
             rp.p, ci.p, va.p, d0.p, d1.p, sp.p, ns, sci.p, sva.p);
     PDHG_HIP(hipGetLastError());
     PDHG_HIP(hipStreamSynchronize(s));
+    return wmax;
 }
 
 // Largest instance column / row counts (LDS sizing of the on-chip solve).
@@ -1673,17 +1812,28 @@ static int32_t default_threads(const BatchHandle &h) {
 template <int BT>
 static void launch_solve_t(BatchHandle &h, const BOpts &o) {
     BArgs a = batch_args(h);
-    // on-chip variant when both gathered vectors fit 64 KB of LDS and every
-    // thread owns at most 8 columns and 8 rows
-    const size_t lds = ((size_t)h.nmax + (size_t)h.mmax) * sizeof(double);
+    // on-chip variant when x_ext, y and the three per-row vectors fit the
+    // workgroup's LDS and every thread owns at most 8 columns and 8 rows;
+    // register-resident matrix for narrow shared slices when the rows fit
+    // S/4 per thread (S >= 4) and the LDS also holds the column anchor, cost
+    // and upper bound
+    const size_t lds = ((size_t)h.nmax + 4 * (size_t)h.mmax) * sizeof(double);
+    const size_t lds_res = lds + 3 * (size_t)h.nmax * sizeof(double);
     const int32_t need = std::max(h.nmax, h.mmax);
-    if (h.onchip && lds <= 65536 && need <= 8 * BT) {
+    if (h.onchip && lds <= lds_per_workgroup() && need <= 8 * BT) {
         const size_t l = std::max<size_t>(lds, 8);
-        if (need <= BT) return launch_solve_lds_t<BT, 1>(h, o, a, l);
-        if (need <= 2 * BT) return launch_solve_lds_t<BT, 2>(h, o, a, l);
-        if (need <= 4 * BT) return launch_solve_lds_t<BT, 4>(h, o, a, l);
-        return launch_solve_lds_t<BT, 8>(h, o, a, l);
+        if (need <= BT) return launch_solve_lds_t<BT, 1, false>(h, o, a, l);
+        if (need <= 2 * BT) return launch_solve_lds_t<BT, 2, false>(h, o, a, l);
+        const bool res = h.resident && h.shared && h.ts_wmax <= kResCol && h.as_wmax <= kResRow &&
+                         lds_res <= lds_per_workgroup() && BT >= 256;
+        if (need <= 4 * BT) {
+            if (res && h.mmax <= BT) return launch_solve_lds_t<BT, 4, true>(h, o, a, lds_res);
+            return launch_solve_lds_t<BT, 4, false>(h, o, a, l);
+        }
+        if (res && h.mmax <= 2 * BT) return launch_solve_lds_t<BT, 8, true>(h, o, a, lds_res);
+        return launch_solve_lds_t<BT, 8, false>(h, o, a, l);
     }
+
     int32_t wg = std::min(h.B, resident<BT>(o.detect ? reinterpret_cast<const void *>(&k_batch_solve<BT, true>)
                                                      : reinterpret_cast<const void *>(&k_batch_solve<BT, false>)));
     if (h.workgroups > 0) wg = std::min(wg, h.workgroups);
@@ -1869,8 +2019,8 @@ BatchHandle *batch_create(const pdhg_batch_problem &p, const pdhg_options &o, vo
         const int32_t nb = h.shared ? 1 : h.B;
         std::vector<int32_t> ro = h.shared ? std::vector<int32_t>{0, h.m} : h.row_off_h;
         std::vector<int32_t> co = h.shared ? std::vector<int32_t>{0, h.n} : h.col_off_h;
-        build_batch_sell(s, nb, ro, h.arp, h.aci, h.ava, h.nnz, h.asp, h.asci, h.asva, h.asfirst);
-        build_batch_sell(s, nb, co, h.trp, h.tci, h.tva, h.nnz, h.tsp, h.tsci, h.tsva, h.tsfirst);
+        h.as_wmax = build_batch_sell(s, nb, ro, h.arp, h.aci, h.ava, h.nnz, h.asp, h.asci, h.asva, h.asfirst);
+        h.ts_wmax = build_batch_sell(s, nb, co, h.trp, h.tci, h.tva, h.nnz, h.tsp, h.tsci, h.tsva, h.tsfirst);
     }
     if (p.q_rank > 0) bqp_create(h, p);
     h.setup_seconds = now_seconds() - t0;

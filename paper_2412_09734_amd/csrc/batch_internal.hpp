@@ -50,6 +50,8 @@ struct BatchHandle {
     int64_t unrolled_T = 0;
     int32_t nmax = 0, mmax = 0;           // largest instance (LDS sizing)
     int32_t onchip = 1;                   // use the on-chip solve when it fits
+    int32_t resident = 1;                 // keep narrow shared matrices in registers
+    int32_t as_wmax = 0, ts_wmax = 0;     // widest SELL-64 slice of A~ and A~
     DBuf<uint8_t> u_restart;
     DBuf<double> u_omega, u_ba;
     DBuf<int32_t> u_kk;

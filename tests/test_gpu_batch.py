@@ -182,3 +182,68 @@ def test_batch_infeasibility_switched_off(pdhg):
     names = [r["status_name"] for r in res]
     assert names[1] == names[3] == names[5] == names[-1] == "iteration_limit", names
     assert names[0] == names[2] == names[4] == "optimal", names
+
+
+def _grid_with_certificates(rows, cols, seed):
+    """Six grid min-cost flows sharing A: instance 1 is primal infeasible
+    (supply 200 at its source, more than the <= 4 x 20 capacity leaving any
+    node) and instance 3 unbounded (both arcs between two nodes cost -1 and
+    have no capacity, so flow around that cycle lowers the cost without
+    bound)."""
+    sb = gen.grid_mincost_batch(batch=6, rows=rows, cols=cols, seed=seed)
+    src, snk = sb.meta["source"], sb.meta["sink"]
+    sb.lc[1] = 0.0
+    sb.lc[1, src[1]], sb.lc[1, snk[1]] = 200.0, -200.0
+    sb.uc[1] = sb.lc[1]
+    t, h = sb.meta["tails"], sb.meta["heads"]
+    a1 = 0
+    a2 = int(np.nonzero((t == h[a1]) & (h == t[a1]))[0][0])
+    sb.c[3, [a1, a2]] = -1.0
+    sb.uv[3, [a1, a2]] = np.inf
+    return sb
+
+
+@pytest.mark.parametrize("rows,cols,threads", [(12, 12, 256), (24, 24, 512)])
+def test_resident_matrix_batch_matches_oracle(pdhg, oracle_lib, rows, cols, threads):
+    """Launches that keep the shared incidence matrix in registers (4 columns
+    per thread for the 12x12 grid at 256 threads, 8 for the 24x24 grid at
+    512): every instance ends as the oracle ends it (status and iteration
+    count), with its objective or its certifying ray."""
+    _say(f"case: {rows}x{cols} grid batch with certificates, {threads} threads (resident matrix)")
+    sb = _grid_with_certificates(rows, cols, seed=3300 + rows)
+    with pdhg.BatchSolver.from_shared(sb, threads=threads, iteration_limit=100000) as bs:
+        x, y, res = bs.solve()
+    for b in range(sb.batch):
+        xo, yo, ro = oracle_lib.Oracle(sb.instance(b), iteration_limit=100000).solve()
+        rb = res[b]
+        _say(f"  instance {b}: {rb['status_name']} at {rb['iterations']} (oracle {ro['status_name']} at {ro['iterations']})")
+        assert rb["status_name"] == ro["status_name"], (b, rb["status_name"], ro["status_name"])
+        assert rb["iterations"] == ro["iterations"], (b, rb["iterations"], ro["iterations"])
+        if ro["status_name"] == "primal_infeasible":
+            assert b == 1 and rel_inf(to_np(y[b]), yo) <= 1e-8
+        elif ro["status_name"] == "dual_infeasible":
+            assert b == 3 and rel_inf(to_np(x[b]), xo) <= 1e-8
+        else:
+            assert ro["status_name"] == "optimal"
+            assert _close(rb["primal_obj"], ro["primal_obj"])
+
+
+@pytest.mark.parametrize("rows,cols,threads", [(12, 12, 256), (24, 24, 512)])
+def test_resident_matrix_batch_without_ray_tests(pdhg, oracle_lib, rows, cols, threads):
+    """The same launches with the infeasibility tests off (the leaner kernel):
+    the feasible instances match the oracle's iteration counts and optima,
+    the two without an optimum run to the iteration limit on both sides."""
+    _say(f"case: {rows}x{cols} grid batch, ray tests off, {threads} threads (resident matrix)")
+    sb = _grid_with_certificates(rows, cols, seed=3300 + rows)
+    off = dict(iteration_limit=4000, eps_primal_infeasible=0.0, eps_dual_infeasible=0.0)
+    with pdhg.BatchSolver.from_shared(sb, threads=threads, **off) as bs:
+        x, y, res = bs.solve()
+    for b in range(sb.batch):
+        _, _, ro = oracle_lib.Oracle(sb.instance(b), **off).solve()
+        rb = res[b]
+        assert rb["status_name"] == ro["status_name"], (b, rb["status_name"], ro["status_name"])
+        assert rb["iterations"] == ro["iterations"], (b, rb["iterations"], ro["iterations"])
+        if b in (1, 3):
+            assert rb["status_name"] == "iteration_limit"
+        else:
+            assert _close(rb["primal_obj"], ro["primal_obj"])
