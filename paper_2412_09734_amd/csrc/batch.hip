@@ -171,15 +171,6 @@ __device__ __forceinline__ double sell_dot(const int32_t *__restrict__ sp, const
     return sell_dot_bw(ci, va, b, w, lane, v);
 }
 
-// Sums of S SELL-64 lanes (slices starting at base[q] with w[q] entries,
-// the same in every lane of the wave), each in entry order, taken C slices at a time: the
-// first U entries of the C slices are loaded before the first product
-// (unconditional loads at indices clamped to each slice's last entry,
-// products past w dropped by a select, as in sell_group), so their round
-// trips overlap; wider slices continue U entries at a time. A slice with
-// w = 0 loads the array's first 64 entries (the array holds at least 64) and
-// sums to 0; a chunk whose slices are all empty loads nothing. Same sums, in
-// the same order, as sell_dot_bw per slice.
 // Same with the slice's first entry and width already known. Entries are
 // fetched four at a time before they are used (independent loads in flight),
 // and added in row order.
@@ -1409,6 +1400,439 @@ __global__ __launch_bounds__(BT) void k_batch_unrolled(BArgs a, BOpts o, UArgs u
     }
 }
 
+// Register-resident matrix for the unrolled forward and its reverse pass
+// (a shared matrix whose column slices hold at most kResCol and row slices at
+// most kResRow entries; S columns and S/4 rows per thread): the owned slices'
+// entries with every index turned into the byte offset of the LDS element it
+// gathers, y (for A~') after nmax doubles of x_ext (for A~).
+template <int BT, int S>
+struct ResSlices {
+    static constexpr int SR = S >= 4 ? S / 4 : 1;
+    int32_t tci[S][kResCol], rci[SR][kResRow];
+    double tva[S][kResCol], rva[SR][kResRow];
+
+    __device__ __forceinline__ void load(const BArgs &a, const Geo &g, int32_t nmax) {
+        const int32_t lane = (int32_t)(threadIdx.x & 63);
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int32_t j = threadIdx.x + q * BT;
+            int32_t base = 0, w = 0;
+            if (j < g.n) {
+                base = a.tsp[j >> 6];
+                w = (a.tsp[(j >> 6) + 1] - base) >> 6;
+            }
+#pragma unroll
+            for (int u = 0; u < kResCol; ++u) {
+                const bool in = u < w;
+                const int32_t e = base + 64 * u + lane;
+                tci[q][u] = 8 * (nmax + (in ? a.tsci[e] : 0));
+                tva[q][u] = in ? a.tsva[e] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SR; ++q) {
+            const int32_t i = threadIdx.x + q * BT;
+            int32_t base = 0, w = 0;
+            if (i < g.m) {
+                base = a.asp[i >> 6];
+                w = (a.asp[(i >> 6) + 1] - base) >> 6;
+            }
+#pragma unroll
+            for (int u = 0; u < kResRow; ++u) {
+                const bool in = u < w;
+                const int32_t e = base + 64 * u + lane;
+                rci[q][u] = 8 * (in ? a.asci[e] : 0);
+                rva[q][u] = in ? a.asva[e] : 0.0;
+            }
+        }
+    }
+    // (A~' y)_j of owned column q, y in LDS after nmax doubles
+    __device__ __forceinline__ double col(const double *lds, int q) const {
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < kResCol; ++u) s = fma(tva[q][u], lds_at(lds, tci[q][u]), s);
+        return s;
+    }
+    // (A~ v)_i of owned row q, v at the start of the LDS
+    __device__ __forceinline__ double row(const double *lds, int q) const {
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < kResRow; ++u) s = fma(rva[q][u], lds_at(lds, rci[q][u]), s);
+        return s;
+    }
+};
+
+// k_batch_unrolled for a register-resident shared matrix (grid batches): the
+// same iterations, records and arithmetic, with x, x^ and l~_v of the owned
+// columns and y^ of the owned rows in registers, and x_ext, y, x0, y0, c~,
+// u~_v, l~_c, u~_c in LDS.
+template <int BT, int S>
+__global__ __launch_bounds__(BT) void k_batch_unrolled_res(BArgs a, BOpts o, UArgs u, int32_t nmax,
+                                                           int32_t mmax) {
+    using RS = ResSlices<BT, S>;
+    constexpr int SR = RS::SR;
+    extern __shared__ double lds[];
+    double *sx = lds, *sy = lds + nmax;
+    double *slc = sy + mmax, *suc = slc + mmax, *sy0 = suc + mmax;
+    double *sx0 = sy0 + mmax, *scr = sx0 + nmax, *suv = scr + nmax;
+    for (;;) {
+        const int32_t b = next_instance<BT>(a.queue);
+        if (b >= a.B) return;
+        const Geo g = geometry(a, b);
+        const int32_t lane = (int32_t)(threadIdx.x & 63);
+        const double *Dr = a.Dr + g.dr, *Dc = a.Dc + g.dc;
+        const double *c_o = a.c_o + g.vc, *lv_o = a.lv_o + g.vc, *uv_o = a.uv_o + g.vc;
+        const double *lc_o = a.lc_o + g.vr, *uc_o = a.uc_o + g.vr;
+        uint8_t *rs_ = u.restart + (size_t)b * u.T;
+        double *om_ = u.omega + (size_t)b * u.T;
+        int32_t *kk_ = u.kk + (size_t)b * u.T;
+        uint64_t *xm = u.xmask + u.xm_off[b], *ym = u.ymask + u.ym_off[b];
+        const int32_t xw = (g.n + 63) >> 6, yw = (g.m + 63) >> 6;
+        const double eta = a.eta[g.sidx];
+        const double gam = o.gamma;
+        RS M;
+        M.load(a, g, nmax);
+        double xr[S], xhr[S], lvr[S], yhr[SR];
+        double nrm[2] = {0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int32_t j = threadIdx.x + q * BT;
+            xr[q] = xhr[q] = lvr[q] = 0.0;
+            if (j < g.n) {
+                const double d = Dc[j];
+                const double cj = d * c_o[j];
+                scr[j] = cj;
+                lvr[q] = lv_o[j] / d;
+                suv[j] = uv_o[j] / d;
+                nrm[0] += cj * cj;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SR; ++q) {
+            const int32_t i = threadIdx.x + q * BT;
+            yhr[q] = 0.0;
+            if (i < g.m) {
+                const double d = Dr[i];
+                const double l = d * lc_o[i], uu = d * uc_o[i];
+                slc[i] = l;
+                suc[i] = uu;
+                double bb = 0.0;
+                if (isfinite(l)) bb = fmax(bb, fabs(l));
+                if (isfinite(uu)) bb = fmax(bb, fabs(uu));
+                nrm[1] += bb * bb;
+            }
+        }
+        wg_sum<BT, 2>(nrm);
+        const double cn = sqrt(nrm[0]), bn = sqrt(nrm[1]);
+        double omega = (cn > 1e-10 && bn > 1e-10) ? cn / bn : 1.0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int32_t j = threadIdx.x + q * BT;
+            if (j < g.n) {
+                xr[q] = clampd(0.0, lvr[q], suv[j]);
+                sx0[j] = xr[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SR; ++q) {
+            const int32_t i = threadIdx.x + q * BT;
+            if (i < g.m) {
+                const double lo = isfinite(suc[i]) ? -INFINITY : 0.0;
+                const double hi = isfinite(slc[i]) ? INFINITY : 0.0;
+                const double yv = clampd(0.0, lo, hi);
+                sy[i] = yv;
+                sy0[i] = yv;
+            }
+        }
+        __syncthreads();
+        int64_t k = 0;
+        int32_t tc = 0;   // t modulo check_every
+        double r_start = 0.0, r_prev = 0.0;
+        for (int64_t t = 0; t < u.T; ++t) {
+            // opaque thread index: element addresses are formed per iteration
+            int32_t tid = (int32_t)threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            if (u.replay) omega = om_[t];
+            const double tau = eta / omega, sigma = eta * omega;
+            const bool last = t + 1 >= u.T;
+            const bool check = !u.replay && tc == 0 && !last;
+            const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+            uint64_t *xmt = xm + (size_t)t * xw;
+            uint64_t *ymt = ym + (size_t)t * 2 * yw;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int32_t j = tid + q * BT;
+                bool inside = false;
+                if (j < g.n) {
+                    const double s = M.col(lds, q);
+                    const double uu = xr[q] - tau * (scr[j] - s);
+                    const double hi = suv[j];
+                    inside = uu > lvr[q] && uu < hi;
+                    const double xhat = clampd(uu, lvr[q], hi);
+                    sx[j] = 2.0 * xhat - xr[q];
+                    xhr[q] = xhat;
+                }
+                const uint64_t bits = __ballot(inside);
+                if (lane == 0 && j < g.n) xmt[j >> 6] = bits;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < SR; ++q) {
+                const int32_t i = tid + q * BT;
+                bool at_u = false, at_l = false;
+                if (i < g.m) {
+                    const double av = M.row(lds, q);
+                    const double vv = sy[i] / sigma - av;
+                    const double lo = -suc[i], hi = -slc[i];
+                    at_u = vv < lo;
+                    at_l = vv > hi;
+                    yhr[q] = sigma * (vv - clampd(vv, lo, hi));
+                }
+                const uint64_t bu = __ballot(at_u), bl = __ballot(at_l);
+                if (lane == 0 && i < g.m) {
+                    ymt[2 * (i >> 6)] = bu;
+                    ymt[2 * (i >> 6) + 1] = bl;
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                om_[t] = omega;
+                kk_[t] = (int32_t)k;
+            }
+            if (last) break;
+            bool restart = u.replay ? rs_[t] != 0 : false;
+            if (check) {
+                double v2[10];
+#pragma unroll
+                for (int q = 0; q < 10; ++q) v2[q] = 0.0;
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const int32_t j = tid + q * BT;
+                    if (j < g.n) {
+                        const double dx = xhr[q] - xr[q];
+                        v2[0] += dx * dx;
+                        const double d0 = xhr[q] - sx0[j];
+                        v2[2] += d0 * d0;
+                        sx[j] = dx;   // x_ext is spent: it carries dx for the cross term
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < SR; ++q) {
+                    const int32_t i = tid + q * BT;
+                    if (i < g.m) {
+                        const double dy = yhr[q] - sy[i];
+                        v2[8] += dy * dy;
+                        const double d0 = yhr[q] - sy0[i];
+                        v2[9] += d0 * d0;
+                        v2[1] += dy * M.row(lds, q);   // cross term dy' A~ dx
+                    }
+                }
+                wg_sum<BT, 10>(v2);
+                const double r2 = v2[0] / tau + v2[8] / sigma + 2.0 * v2[1];
+                const double r = r2 > 0.0 ? sqrt(r2) : 0.0;
+                if (t == 0) {
+                    r_start = r;
+                    r_prev = r;
+                } else if (r <= o.beta_suff * r_start || (r <= o.beta_nec * r_start && r > r_prev) ||
+                           (double)k >= o.beta_art * (double)t) {
+                    restart = true;
+                } else {
+                    r_prev = r;
+                }
+                if (restart) {
+                    const double dxr = sqrt(v2[2]), dyr = sqrt(v2[9]);
+                    omega = batch_new_omega(omega, dxr, dyr);
+                    r_start = r;
+                    r_prev = r;
+                }
+            }
+            if (threadIdx.x == 0 && !u.replay) rs_[t] = restart ? 1 : 0;
+            if (restart) {
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const int32_t j = tid + q * BT;
+                    if (j < g.n) {
+                        xr[q] = xhr[q];
+                        sx0[j] = xhr[q];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < SR; ++q) {
+                    const int32_t i = tid + q * BT;
+                    if (i < g.m) {
+                        sy[i] = yhr[q];
+                        sy0[i] = yhr[q];
+                    }
+                }
+                k = 0;
+            } else {
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const int32_t j = tid + q * BT;
+                    if (j < g.n) xr[q] = ak * ((1.0 + gam) * xhr[q] - gam * xr[q]) + bk * sx0[j];
+                }
+#pragma unroll
+                for (int q = 0; q < SR; ++q) {
+                    const int32_t i = tid + q * BT;
+                    if (i < g.m) sy[i] = ak * ((1.0 + gam) * yhr[q] - gam * sy[i]) + bk * sy0[i];
+                }
+                ++k;
+            }
+            tc = tc + 1 == o.check_every ? 0 : tc + 1;
+            __syncthreads();
+        }
+        if (u.replay == 0 && threadIdx.x == 0) rs_[u.T - 1] = 0;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int32_t j = threadIdx.x + q * BT;
+            if (j < g.n) a.x_out[g.vc + j] = Dc[j] * xhr[q];
+        }
+#pragma unroll
+        for (int q = 0; q < SR; ++q) {
+            const int32_t i = threadIdx.x + q * BT;
+            if (i < g.m) a.y_out[g.vr + i] = Dr[i] * yhr[q];
+        }
+        __syncthreads();
+    }
+}
+
+// k_batch_backward for a register-resident shared matrix: the cotangents of
+// the owned columns and rows and the gradient sums in registers; the products
+// gather ba (after nmax doubles) and tmp (at the start) from LDS.
+template <int BT, int S>
+__global__ __launch_bounds__(BT) void k_batch_backward_res(BArgs a, BOpts o, UArgs u, int32_t nmax) {
+    using RS = ResSlices<BT, S>;
+    constexpr int SR = RS::SR;
+    extern __shared__ double lds[];
+    double *tmp = lds, *ba = lds + nmax;
+    for (;;) {
+        const int32_t b = next_instance<BT>(a.queue);
+        if (b >= a.B) return;
+        const Geo g = geometry(a, b);
+        const int32_t lane = (int32_t)(threadIdx.x & 63);
+        const double *Dr = a.Dr + g.dr, *Dc = a.Dc + g.dc;
+        const uint8_t *rs_ = u.restart + (size_t)b * u.T;
+        const double *om_ = u.omega + (size_t)b * u.T;
+        const int32_t *kk_ = u.kk + (size_t)b * u.T;
+        const uint64_t *xm = u.xmask + u.xm_off[b], *ym = u.ymask + u.ym_off[b];
+        const int32_t xw = (g.n + 63) >> 6, yw = (g.m + 63) >> 6;
+        const double eta = a.eta[g.sidx];
+        const double gam = o.gamma;
+        RS M;
+        M.load(a, g, nmax);
+        double bx[S], bx0[S], bxh[S], gcr[S];
+        double by[SR], by0[SR], byh[SR], glr[SR], gur[SR];
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int32_t j = threadIdx.x + q * BT;
+            bx[q] = bx0[q] = gcr[q] = 0.0;
+            bxh[q] = j < g.n ? Dc[j] * u.gx[g.vc + j] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < SR; ++q) {
+            const int32_t i = threadIdx.x + q * BT;
+            by[q] = by0[q] = glr[q] = gur[q] = 0.0;
+            byh[q] = i < g.m ? Dr[i] * u.gy[g.vr + i] : 0.0;
+        }
+        for (int64_t t = u.T - 1; t >= 0; --t) {
+            int32_t tid = (int32_t)threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            const double omega = om_[t];
+            const double tau = eta / omega, sigma = eta * omega;
+            if (t < u.T - 1) {
+                if (rs_[t]) {
+#pragma unroll
+                    for (int q = 0; q < S; ++q) {
+                        bxh[q] = bx[q] + bx0[q];
+                        bx[q] = 0.0;
+                        bx0[q] = 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < SR; ++q) {
+                        byh[q] = by[q] + by0[q];
+                        by[q] = 0.0;
+                        by0[q] = 0.0;
+                    }
+                } else {
+                    const int64_t k = kk_[t];
+                    const double ak = (double)(k + 1) / (double)(k + 2), bk = 1.0 / (double)(k + 2);
+#pragma unroll
+                    for (int q = 0; q < S; ++q) {
+                        const double v = bx[q];
+                        bxh[q] = ak * (1.0 + gam) * v;
+                        bx0[q] += bk * v;
+                        bx[q] = -ak * gam * v;
+                    }
+#pragma unroll
+                    for (int q = 0; q < SR; ++q) {
+                        const double v = by[q];
+                        byh[q] = ak * (1.0 + gam) * v;
+                        by0[q] += bk * v;
+                        by[q] = -ak * gam * v;
+                    }
+                }
+            }
+            // dual step: yhat = sigma (v - clamp(v, -u_c, -l_c)), v = y/sigma - A~ xext
+            const uint64_t *ymt = ym + (size_t)t * 2 * yw;
+#pragma unroll
+            for (int q = 0; q < SR; ++q) {
+                const int32_t i = tid + q * BT;
+                if (i < g.m) {
+                    const uint64_t bit = 1ull << (i & 63);
+                    const bool at_u = (ymt[2 * (i >> 6)] & bit) != 0;
+                    const bool at_l = (ymt[2 * (i >> 6) + 1] & bit) != 0;
+                    const double bv = (at_u || at_l) ? sigma * byh[q] : 0.0;
+                    if (at_u) gur[q] += sigma * byh[q];
+                    if (at_l) glr[q] += sigma * byh[q];
+                    by[q] += bv / sigma;
+                    ba[i] = -bv;
+                }
+            }
+            __syncthreads();
+            // xext = 2 xhat - x, then the primal step xhat = clamp(x - tau (c - A~'y))
+            const uint64_t *xmt = xm + (size_t)t * xw;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const int32_t j = tid + q * BT;
+                if (j < g.n) {
+                    const double bxe = M.col(lds, q);
+                    const double bh = bxh[q] + 2.0 * bxe;
+                    bx[q] -= bxe;
+                    const bool inside = (xmt[j >> 6] >> (j & 63)) & 1ull;
+                    const double bu = inside ? bh : 0.0;
+                    bx[q] += bu;
+                    gcr[q] += -tau * bu;
+                    tmp[j] = tau * bu;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < SR; ++q) {
+                const int32_t i = tid + q * BT;
+                if (i < g.m) by[q] += M.row(lds, q);
+            }
+            __syncthreads();
+        }
+        // c~ = D_c c, l~_c = D_r l_c, u~_c = D_r u_c
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const int32_t j = threadIdx.x + q * BT;
+            if (j < g.n) u.gc[g.vc + j] = Dc[j] * gcr[q];
+        }
+#pragma unroll
+        for (int q = 0; q < SR; ++q) {
+            const int32_t i = threadIdx.x + q * BT;
+            if (i < g.m) {
+                u.glc[g.vr + i] = isfinite(a.lc_o[g.vr + i]) ? Dr[i] * glr[q] : 0.0;
+                u.guc[g.vr + i] = isfinite(a.uc_o[g.vr + i]) ? Dr[i] * gur[q] : 0.0;
+            }
+        }
+        (void)lane;
+        __syncthreads();
+    }
+}
+
 // Reverse pass of k_batch_unrolled with its recorded schedule and masks.
 template <int BT, bool ONCHIP>
 __global__ __launch_bounds__(BT) void k_batch_backward(BArgs a, BOpts o, UArgs u, int32_t nmax) {
@@ -1672,6 +2096,21 @@ static size_t lds_per_workgroup() {
         return (size_t)bytes;
     }();
     return v;
+}
+
+// Columns per thread of the register-resident kernels at BT threads (4 with
+// one row slice, 8 with two), or 0 when the batch does not qualify: a shared
+// matrix with narrow slices, BT >= 256, and x_ext, y, the row data and the
+// column anchor, cost and upper bound in one workgroup's LDS.
+template <int BT>
+static int res_columns(const BatchHandle &h) {
+    if (!(h.onchip && h.resident && h.shared && h.ts_wmax >= 1 && h.ts_wmax <= kResCol &&
+          h.as_wmax <= kResRow && BT >= 256))
+        return 0;
+    if ((4 * (size_t)h.nmax + 4 * (size_t)h.mmax) * sizeof(double) > lds_per_workgroup()) return 0;
+    if (h.nmax <= 4 * BT && h.mmax <= BT) return 4;
+    if (h.nmax <= 8 * BT && h.mmax <= 2 * BT) return 8;
+    return 0;
 }
 
 template <int BT, int S, bool RES>
@@ -2022,6 +2461,10 @@ BatchHandle *batch_create(const pdhg_batch_problem &p, const pdhg_options &o, vo
         h.as_wmax = build_batch_sell(s, nb, ro, h.arp, h.aci, h.ava, h.nnz, h.asp, h.asci, h.asva, h.asfirst);
         h.ts_wmax = build_batch_sell(s, nb, co, h.trp, h.tci, h.tva, h.nnz, h.tsp, h.tsci, h.tsva, h.tsfirst);
     }
+    // one instance per CU would take 1024 threads; a matrix that the
+    // register-resident kernels can hold runs faster at 512 (their 1024-thread
+    // variants spill)
+    if (p.q_rank == 0 && h.threads == 1024 && res_columns<512>(h)) h.threads = 512;
     if (p.q_rank > 0) bqp_create(h, p);
     h.setup_seconds = now_seconds() - t0;
     return hp.release();
@@ -2154,6 +2597,21 @@ static void launch_unrolled_t(BatchHandle &h, const UArgs &u) {
     const BOpts o = batch_opts(h.opt);
     const size_t lds = onchip_lds(h);
     PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
+    if constexpr (BT == 256 || BT == 512) {
+        const int rc = res_columns<BT>(h);
+        if (rc) {
+            const size_t l = (4 * (size_t)h.nmax + 4 * (size_t)h.mmax) * sizeof(double);
+            if (rc == 4) {
+                const int32_t wg = resident_lds<BT>(h, &k_batch_unrolled_res<BT, 4>, l);
+                k_batch_unrolled_res<BT, 4><<<wg, BT, l, h.stream>>>(a, o, u, h.nmax, h.mmax);
+            } else {
+                const int32_t wg = resident_lds<BT>(h, &k_batch_unrolled_res<BT, 8>, l);
+                k_batch_unrolled_res<BT, 8><<<wg, BT, l, h.stream>>>(a, o, u, h.nmax, h.mmax);
+            }
+            PDHG_HIP(hipGetLastError());
+            return;
+        }
+    }
     if (lds) {
         const int32_t wg = resident_lds<BT>(h, &k_batch_unrolled<BT, true>, lds);
         k_batch_unrolled<BT, true><<<wg, BT, lds, h.stream>>>(a, o, u, h.nmax);
@@ -2170,6 +2628,21 @@ static void launch_backward_t(BatchHandle &h, const UArgs &u) {
     const BOpts o = batch_opts(h.opt);
     const size_t lds = onchip_lds(h);
     PDHG_HIP(hipMemsetAsync(h.queue.p, 0, sizeof(int32_t), h.stream));
+    if constexpr (BT == 256 || BT == 512) {
+        const int rc = res_columns<BT>(h);
+        if (rc) {
+            const size_t l = ((size_t)h.nmax + (size_t)h.mmax) * sizeof(double);
+            if (rc == 4) {
+                const int32_t wg = resident_lds<BT>(h, &k_batch_backward_res<BT, 4>, l);
+                k_batch_backward_res<BT, 4><<<wg, BT, l, h.stream>>>(a, o, u, h.nmax);
+            } else {
+                const int32_t wg = resident_lds<BT>(h, &k_batch_backward_res<BT, 8>, l);
+                k_batch_backward_res<BT, 8><<<wg, BT, l, h.stream>>>(a, o, u, h.nmax);
+            }
+            PDHG_HIP(hipGetLastError());
+            return;
+        }
+    }
     if (lds) {
         const int32_t wg = resident_lds<BT>(h, &k_batch_backward<BT, true>, lds);
         k_batch_backward<BT, true><<<wg, BT, lds, h.stream>>>(a, o, u, h.nmax);
