@@ -67,6 +67,33 @@ def measured_traffic(step: str):
     return int(v) if v else None
 
 
+def stream_peak() -> dict:
+    """Achievable HBM bandwidth on this GPU: the best of 5 timed 1 GiB
+    device-to-device copies (2 GiB moved each) and of 5 triads a = b + 2c on
+    1 GiB vectors (3 GiB moved each), in GB/s."""
+    import torch
+    n = 1 << 27
+    b = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    c = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    a = torch.empty_like(b)
+    out = {}
+    for name, op, moved in (("copy", lambda: a.copy_(b), 2 * 8 * n),
+                            ("triad", lambda: torch.add(b, c, alpha=2.0, out=a), 3 * 8 * n)):
+        op()
+        best = float("inf")
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            op()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e-3)
+        out[name] = round(moved / best / 1e9, 1)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(lp, gpu_iters: int, gpu_power_iters: int) -> dict:
     """The oracle on a bounded sample of the same LP: its scaling, then 40
     iterations (checks at the first and last), timed on all host threads the
@@ -332,6 +359,9 @@ def main():
                    "bytes_per_iteration": iter_bytes},
         "roofline": roof,
     }
+    sp = stream_peak()
+    roof["stream_gbs"] = sp
+    roof["frac_of_stream"] = round(achieved / max(sp.values()), 4)
     if not args.no_batched and not infeasible:
         log("bench: batched grid LPs vs the plain solver looped")
         out["config"]["batched"] = batched_vs_plain()
@@ -469,6 +499,9 @@ def bench_dense(args):
             "traffic": None, "kernel": "k_dense_rows<ROW_DUAL>", "algorithmic_bytes_per_launch": kb_rows,
             "avg_launch_ms": round(dual, 4),
             "column_pass_gbps": round(kb_cols / (prim * 1e-3) / 1e9, 1)}
+    sp = stream_peak()
+    roof["stream_gbs"] = sp
+    roof["frac_of_stream"] = round(kb_rows / (dual * 1e-3) / 1e9 / max(sp.values()), 4)
     out = {"metric": METRIC, "value": round(args.steps / el, 5), "unit": "LPs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 1),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
