@@ -13,6 +13,9 @@
 #include <cmath>
 #include <deque>
 #include <new>
+#include <unordered_map>
+#include <mutex>
+#include <map>
 
 #include "batch_internal.hpp"
 #include "common.hpp"
@@ -23,6 +26,89 @@ static thread_local std::string g_err = "";
 constexpr int kTimingEvents = 7;   // per timed plain iteration
 
 void fail(pdhg_err code, const std::string &msg) { throw Error{code, msg}; }
+
+namespace {
+constexpr size_t kKeepMinBytes = size_t(1) << 20;
+constexpr size_t kKeepMaxBytes = size_t(8) << 30;
+struct BlockCache {
+    std::mutex mu;
+    std::multimap<std::pair<int, size_t>, void *> free;   // (device, bytes) -> block
+    std::unordered_map<void *, int> device;                // device of every large block
+    size_t kept = 0;
+};
+// never destroyed: blocks still kept at exit go back with the process
+BlockCache &block_cache() {
+    static BlockCache *c = new BlockCache;
+    return *c;
+}
+// hipFree every kept block of device `dev` (the current device)
+void release_kept(BlockCache &c, int dev) {
+    for (auto it = c.free.begin(); it != c.free.end();) {
+        if (it->first.first == dev) {
+            (void)hipFree(it->second);
+            c.device.erase(it->second);
+            c.kept -= it->first.second;
+            it = c.free.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+}  // namespace
+
+void *device_alloc(size_t bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    BlockCache &c = block_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    if (bytes >= kKeepMinBytes) {
+        auto it = c.free.find({dev, bytes});
+        if (it != c.free.end()) {
+            void *p = it->second;
+            c.free.erase(it);
+            c.kept -= bytes;
+            return p;
+        }
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        release_kept(c, dev);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    if (bytes >= kKeepMinBytes) c.device[p] = dev;
+    return p;
+}
+
+void device_free(void *p, size_t bytes) {
+    if (!p) return;
+    BlockCache &c = block_cache();
+    if (bytes >= kKeepMinBytes) {
+        int dev = -1, cur = 0;
+        {
+            std::lock_guard<std::mutex> lock(c.mu);
+            auto d = c.device.find(p);
+            if (d != c.device.end()) dev = d->second;
+        }
+        if (dev >= 0 && hipGetDevice(&cur) == hipSuccess) {
+            // work in flight may still use the block: wait for its device
+            if (cur != dev) (void)hipSetDevice(dev);
+            const bool idle = hipDeviceSynchronize() == hipSuccess;
+            if (cur != dev) (void)hipSetDevice(cur);
+            std::lock_guard<std::mutex> lock(c.mu);
+            if (idle && c.kept + bytes <= kKeepMaxBytes) {
+                c.free.insert({{dev, bytes}, p});
+                c.kept += bytes;
+                return;
+            }
+            c.device.erase(p);
+        }
+    }
+    (void)hipFree(p);
+}
 
 Handle::~Handle() {
     if (chunk_exec) (void)hipGraphExecDestroy(chunk_exec);

@@ -149,13 +149,70 @@ __device__ __forceinline__ int32_t next_instance(int32_t *queue) {
     return r;
 }
 
+// CSR row dot product, entries added in row order; four entries' loads (and
+// then their gathers) are issued before their products, so a thread's walk
+// over the row waits on a quarter as many round trips.
 __device__ __forceinline__ double csr_dot(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                           const double *__restrict__ va, int32_t row,
                                           const double *__restrict__ v) {
     double acc = 0.0;
+    int32_t e = rp[row];
     const int32_t e1 = rp[row + 1];
-    for (int32_t e = rp[row]; e < e1; ++e) acc = fma(va[e], v[ci[e]], acc);
+    for (; e + 4 <= e1; e += 4) {
+        int32_t c[4];
+        double a[4], x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = ci[e + q];
+            a[q] = va[e + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = v[c[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc = fma(a[q], x[q], acc);
+    }
+    for (; e < e1; ++e) acc = fma(va[e], v[ci[e]], acc);
     return acc;
+}
+
+// Ruiz / Pock-Chambolle factor of one CSR row: max |a| (pc = false) or the sum
+// of |a| (pc = true) over the row in entry order, loads four at a time.
+__device__ __forceinline__ double csr_absnorm(const int32_t *__restrict__ rp, const double *__restrict__ va,
+                                              int32_t row, bool pc) {
+    double acc = 0.0;
+    int32_t e = rp[row];
+    const int32_t e1 = rp[row + 1];
+    for (; e + 4 <= e1; e += 4) {
+        double a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = fabs(va[e + q]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc = pc ? acc + a[q] : fmax(acc, a[q]);
+    }
+    for (; e < e1; ++e) acc = pc ? acc + fabs(va[e]) : fmax(acc, fabs(va[e]));
+    return acc;
+}
+
+// va[e] /= (r * f[ci[e]]) over CSR row `row`, four entries at a time.
+__device__ __forceinline__ void csr_rescale(const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                            double *__restrict__ va, int32_t row, double r,
+                                            const double *__restrict__ f) {
+    int32_t e = rp[row];
+    const int32_t e1 = rp[row + 1];
+    for (; e + 4 <= e1; e += 4) {
+        int32_t c[4];
+        double a[4], x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            c[q] = ci[e + q];
+            a[q] = va[e + q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = f[c[q]];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) va[e + q] = a[q] / (r * x[q]);
+    }
+    for (; e < e1; ++e) va[e] = va[e] / (r * f[ci[e]]);
 }
 
 // Row sum of a SELL-64 slice row: lane `lane` of slice `sl`; entries walked in
@@ -343,27 +400,21 @@ __global__ __launch_bounds__(BT) void k_batch_setup(BArgs a, BOpts o, int32_t co
             const bool pc = pass >= o.ruiz_iters;
             __syncthreads();
             for (int32_t i = threadIdx.x; i < g.m; i += BT) {
-                double acc = 0.0;
-                for (int32_t e = arp[i]; e < arp[i + 1]; ++e)
-                    acc = pc ? acc + fabs(a.ava[e]) : fmax(acc, fabs(a.ava[e]));
+                const double acc = csr_absnorm(arp, a.ava, i, pc);
                 rs[i] = acc > 0.0 ? sqrt(acc) : 1.0;
             }
             for (int32_t j = threadIdx.x; j < g.n; j += BT) {
-                double acc = 0.0;
-                for (int32_t e = trp[j]; e < trp[j + 1]; ++e)
-                    acc = pc ? acc + fabs(a.tva[e]) : fmax(acc, fabs(a.tva[e]));
+                const double acc = csr_absnorm(trp, a.tva, j, pc);
                 cs[j] = acc > 0.0 ? sqrt(acc) : 1.0;
             }
             __syncthreads();
             for (int32_t i = threadIdx.x; i < g.m; i += BT) {
                 Dr[i] = Dr[i] / rs[i];
-                for (int32_t e = arp[i]; e < arp[i + 1]; ++e)
-                    a.ava[e] = a.ava[e] / (rs[i] * cs[a.aci[e]]);
+                csr_rescale(arp, a.aci, a.ava, i, rs[i], cs);
             }
             for (int32_t j = threadIdx.x; j < g.n; j += BT) {
                 Dc[j] = Dc[j] / cs[j];
-                for (int32_t e = trp[j]; e < trp[j + 1]; ++e)
-                    a.tva[e] = a.tva[e] / (rs[a.tci[e]] * cs[j]);
+                csr_rescale(trp, a.tci, a.tva, j, cs[j], rs);
             }
         }
         __syncthreads();

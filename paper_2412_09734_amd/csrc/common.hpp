@@ -30,6 +30,17 @@ struct Error {
 
 [[noreturn]] void fail(pdhg_err code, const std::string &msg);
 
+// Device memory of the library's buffers. Blocks of 1 MiB and more are kept
+// after release (up to 8 GiB per process, by device and exact size) and
+// handed out again to an allocation of the same size: handles that are created
+// and destroyed over and over (a batch per training step) then skip the
+// driver's allocation and unmapping. device_free waits for the device first,
+// as hipFree does, so no work in flight still uses a block that is reused.
+// device_alloc returns nullptr when the device is out of memory (after giving
+// the kept blocks back).
+void *device_alloc(size_t bytes);
+void device_free(void *p, size_t bytes);
+
 #define PDHG_HIP(expr)                                                                  \
     do {                                                                                \
         hipError_t e_ = (expr);                                                         \
@@ -48,16 +59,13 @@ struct DBuf {
     ~DBuf() { release(); }
     void alloc(size_t count) {
         release();
-        size_t bytes = (count ? count : 1) * sizeof(T);
-        if (hipMalloc(reinterpret_cast<void **>(&p), bytes) != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            fail(PDHG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
-        }
+        const size_t bytes = (count ? count : 1) * sizeof(T);
+        p = static_cast<T *>(device_alloc(bytes));
+        if (!p) fail(PDHG_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
         n = count;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) device_free(p, (n ? n : 1) * sizeof(T));
         p = nullptr;
         n = 0;
     }
