@@ -94,6 +94,18 @@ __global__ __launch_bounds__(kBlock) void k_inverse(const int32_t *__restrict__ 
     if (i < len) inv[perm[i]] = (int32_t)i;
 }
 
+// first[j] = smallest internal row index among the entries of original column
+// j (one thread per original row; first[] starts at INT32_MAX).
+__global__ __launch_bounds__(kBlock) void k_first_row(const int32_t *__restrict__ rowptr,
+                                                      const int32_t *__restrict__ colidx,
+                                                      const int32_t *__restrict__ inv_r, int32_t m,
+                                                      int32_t *__restrict__ first) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    const int32_t ir = inv_r[i];
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) atomicMin(&first[colidx[e]], ir);
+}
+
 // len_int[i'] = length of original row perm[i'] (rowptr form or count form);
 // len_int[len] = 0 so that an exclusive scan gives the full rowptr.
 __global__ __launch_bounds__(kBlock) void k_perm_lengths(const int32_t *__restrict__ perm,
@@ -618,6 +630,63 @@ static int32_t panel_rows(const pdhg_options &o, int32_t m) {
     return m > 262144 ? kPanelMax : 0;
 }
 
+// With the LDS panels in use, the columns of A that k_primal_sell runs (the
+// SELL-64 rows of A~' from R on, R as keep_panel_rows sets it) are reordered
+// within each length: k_primal_sell's workgroup w takes 256 consecutive of
+// them and runs on XCD w mod 8, so the columns whose first entry (smallest
+// internal row) falls in eighth e of y go where (w mod 8) = e, as far as each
+// length has such columns. One of the entries a workgroup gathers per column
+// then lies in the eighth of y that its XCD keeps reading (an L2-sized
+// window). Any column order is valid: this only changes which L2 serves a
+// gather.
+static void interleave_short_columns(Handle &h, hipStream_t s, const int32_t *rowptr, const int32_t *colidx,
+                                     const int32_t *cnt, int32_t m, int32_t n) {
+    if (m < 8 || n < 1) return;
+    DBuf<int32_t> inv_r, first;
+    inv_r.alloc(m);
+    first.alloc(n);
+    k_inverse<<<blocks_for(m), kBlock, 0, s>>>(h.perm_r.p, m, inv_r.p);
+    std::vector<int32_t> init((size_t)n, INT32_MAX);
+    PDHG_HIP(hipMemcpyAsync(first.p, init.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    k_first_row<<<blocks_for(m), kBlock, 0, s>>>(rowptr, colidx, inv_r.p, m, first.p);
+    std::vector<int32_t> perm((size_t)n), len((size_t)n), fr((size_t)n);
+    PDHG_HIP(hipMemcpyAsync(perm.data(), h.perm_c.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+    PDHG_HIP(hipMemcpyAsync(len.data(), cnt, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+    PDHG_HIP(hipMemcpyAsync(fr.data(), first.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+    PDHG_HIP(hipStreamSynchronize(s));
+    // R: the first row of A~' that k_primal_sell runs (the hybrid layout's
+    // R_long, then the panel rows up to a whole slice)
+    auto L = [&](int32_t q) { return len[(size_t)perm[(size_t)q]]; };
+    const int32_t min_len = h.opt.panel_min_len < 0 ? 32 : h.opt.panel_min_len;
+    int32_t rl = 0, rt = 0;
+    while (rl < n && L(rl) > kShortMax) ++rl;
+    while (rt < n && L(rt) > min_len) ++rt;
+    int32_t R = rl;
+    if (rt > rl) R = (int32_t)std::min<int64_t>(n, rl + 64 * ceil_div(rt - rl, 64));
+    const int32_t win = (m + 7) / 8;
+    constexpr int32_t kCols = kBlock;   // columns per workgroup of k_primal_sell
+    std::vector<int32_t> q[8];
+    for (int32_t a = R; a < n;) {
+        int32_t b = a;
+        while (b < n && L(b) == L(a)) ++b;
+        for (auto &v : q) v.clear();
+        for (int32_t t = a; t < b; ++t) {
+            const int32_t j = perm[(size_t)t];
+            const int32_t f = fr[(size_t)j];
+            q[f == INT32_MAX ? 7 : std::min(7, f / win)].push_back(j);
+        }
+        size_t head[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int32_t t = a; t < b; ++t) {
+            int32_t e = ((t - R) / kCols) % 8;
+            for (int k = 0; k < 8 && head[e] == q[e].size(); ++k) e = (e + 1) % 8;
+            perm[(size_t)t] = q[e][head[e]++];
+        }
+        a = b;
+    }
+    PDHG_HIP(hipMemcpyAsync(h.perm_c.p, perm.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, s));
+    PDHG_HIP(hipStreamSynchronize(s));
+}
+
 // Choose the rows of A~' that the LDS panels cover: the rows longer than
 // panel_min_len, extended to whole SELL-64 slices (rows are sorted by length,
 // the first R_long of them stored as CSR). Their structure is kept on the host
@@ -695,6 +764,8 @@ void build_matrices(Handle &h, const pdhg_problem &p) {
         sort_pairs(s, key.p, key_sorted.p, iota.p, h.perm_c.p, n, kbits);
         key.release();
         key_sorted.release();
+        if (panel_rows(h.opt, m) > 0 && p.q_format == PDHG_FMT_NONE && nnz > 0)
+            interleave_short_columns(h, s, rowptr, colidx, cnt.p, m, n);
 
         DBuf<int32_t> inv_c, lens, row_of;
         inv_c.alloc(n);
