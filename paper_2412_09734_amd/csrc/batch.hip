@@ -506,10 +506,10 @@ __global__ __launch_bounds__(BT) void k_batch_setup(BArgs a, BOpts o, int32_t co
 // Infeasibility rays of instance g at a check (after its products were kept
 // in qh / ph): sums rs = (dual-ray bound terms over the columns, c'dx,
 // dual-ray bound terms over the rows) and maxima rm = (dual-ray violation,
-// primal-ray violation), every thread receiving the totals. A pass of its
-// own: folded into the check loop its accumulators would stay live beside
-// the KKT sums. x0 is read from memory (on-chip kernels keep it written
-// through at restarts).
+// primal-ray violation), every thread receiving the totals, for the
+// memory-resident k_batch_solve (a pass of its own there; x0 is read from
+// memory). k_batch_solve_lds sums the same terms in the same order inside its
+// check loops.
 template <int BT>
 __device__ __forceinline__ void batch_ray_pass(const BArgs &a, const Geo &g,
                                             const double *__restrict__ xh, const double *__restrict__ yh,
