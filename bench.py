@@ -323,7 +323,7 @@ def main():
     names = {"primal": ("primal step: k_panel_dot (long rows of A~', LDS panels of y) beside k_primal_sell "
                         "(SELL-64 rows) on a second stream, then k_primal_panels (panel sums + primal update)"
                         if panels else "k_primal"),
-             "dual": "k_dual_hot (x_ext[0, 16384) in LDS)" if hot else "k_dual"}
+             "dual": "k_dual_hot (x_ext[0, 20480) in LDS)" if hot else "k_dual"}
     full_size = (lp.m, lp.n) == (1_000_000, 2_000_000) and not args.layout
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),

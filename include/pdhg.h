@@ -137,7 +137,7 @@ typedef struct {
      * panel_min_len: rows of A~' longer than this use the panels (auto: 32);
      * panel_wgs: workgroups per panel (auto: 8);
      * hot_cols: leading entries of x_ext staged in LDS by the product A~x_ext
-     *   (auto: 16384 when n > 262144, else off; 0: off; at most 16384). */
+     *   (auto: 20480 when n > 262144, else off; 0: off; at most 20480). */
     int32_t panel_rows;
     int32_t panel_min_len;
     int32_t panel_wgs;

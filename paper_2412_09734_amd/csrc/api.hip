@@ -160,7 +160,7 @@ void check_options(const pdhg_options &o) {
         o.power_max_iters < 1 || !(o.power_tol >= 0.0) || o.display_frequency < 1 ||
         o.panel_rows < -1 || o.panel_rows > kPanelMax || o.panel_min_len < -1 ||
         o.panel_wgs < -1 || o.panel_wgs == 0 || o.panel_wgs > 64 || o.hot_cols < -1 ||
-        o.hot_cols > kPanelMax)
+        o.hot_cols > kHotMax)
         fail(PDHG_ERR_INVALID_ARG, "option out of range");
 }
 

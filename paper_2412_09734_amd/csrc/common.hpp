@@ -136,6 +136,7 @@ inline MatView view(const HMat &M) {
 // part[p * R + row] (bit p of the row's mask says the sub-row exists); further
 // pieces go to part[P * R + x], listed per row in xptr / xslot.
 constexpr int kPanelMax = 16384;   // doubles per LDS panel (128 KB)
+constexpr int kHotMax = 20480;     // doubles of x_ext staged by the hot-column dual (160 KB)
 constexpr int kPanelWaves = 16;    // waves per panel workgroup
 constexpr int kPanelThreads = 64 * kPanelWaves;
 constexpr int kPanelPiece = 128;   // longest piece one lane sums

@@ -108,11 +108,12 @@ __global__ __launch_bounds__(kBlock) void k_primal_sell(
     if (valid) primal_store(r, rs.s, in, x, xext, st, j, gamma);
 }
 
-// sh[0, len) = src[0, len) for a kPanelThreads workgroup (len <= kPanelMax):
+// sh[0, len) = src[0, len) for a kPanelThreads workgroup (len <= N):
 // every load of a thread is issued before the first LDS store, then the
 // workgroup synchronises.
+template <int N = kPanelMax>
 __device__ __forceinline__ void stage_lds(double *sh, const double *__restrict__ src, int32_t len) {
-    constexpr int kPer = kPanelMax / kPanelThreads;
+    constexpr int kPer = N / kPanelThreads;
     double t[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -207,8 +208,8 @@ __global__ __launch_bounds__(kPanelThreads) void k_dual_hot(
     const double *__restrict__ y0, const double *__restrict__ lc, const double *__restrict__ uc,
     const DevState *__restrict__ st, int32_t j, double gamma) {
     if (st->done) return;
-    __shared__ double sh[kPanelMax];
-    stage_lds(sh, xext, H);
+    __shared__ double sh[kHotMax];
+    stage_lds<kHotMax>(sh, xext, H);
     const int32_t lane = (int32_t)(threadIdx.x & 63);
     const int32_t nw = (int32_t)gridDim.x * kPanelWaves;
     int32_t sl = (int32_t)blockIdx.x * kPanelWaves + (int32_t)(threadIdx.x >> 6);

@@ -1053,7 +1053,7 @@ void build_fast_layouts(Handle &h) {
     int dev = 0, cus = 0;
     PDHG_HIP(hipGetDevice(&dev));
     PDHG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int32_t hot = h.opt.hot_cols < 0 ? (n > 262144 ? kPanelMax : 0) : h.opt.hot_cols;
+    const int32_t hot = h.opt.hot_cols < 0 ? (n > 262144 ? kHotMax : 0) : h.opt.hot_cols;
     h.hot_cols = (m > 0 && h.A.nslices > 0) ? std::min(hot, n) : 0;
     h.dual_wgs = 2 * std::max(1, cus);
     PanelMat &P = h.PT;
