@@ -69,8 +69,9 @@ def measured_traffic(step: str):
 
 def stream_peak() -> dict:
     """Achievable HBM bandwidth on this GPU: the best of 5 timed 1 GiB
-    device-to-device copies (2 GiB moved each) and of 5 triads a = b + 2c on
-    1 GiB vectors (3 GiB moved each), in GB/s."""
+    device-to-device copies (2 GiB moved each), of 5 triads a = b + 2c on
+    1 GiB vectors (3 GiB moved each) and of 5 sums of a 1 GiB vector (a read
+    stream, as the solver's passes mostly are), in GB/s."""
     import torch
     n = 1 << 27
     b = torch.ones(n, dtype=torch.float64, device="cuda:0")
@@ -78,7 +79,8 @@ def stream_peak() -> dict:
     a = torch.empty_like(b)
     out = {}
     for name, op, moved in (("copy", lambda: a.copy_(b), 2 * 8 * n),
-                            ("triad", lambda: torch.add(b, c, alpha=2.0, out=a), 3 * 8 * n)):
+                            ("triad", lambda: torch.add(b, c, alpha=2.0, out=a), 3 * 8 * n),
+                            ("read", lambda: torch.sum(b), 8 * n)):
         op()
         best = float("inf")
         for _ in range(5):
