@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
     } else if (live[0]) {
         // U columns x R rows of independent loads in flight per lane, each
         // row added in column order
-        constexpr int U = WIDE ? 8 : 4;
+        constexpr int U = WIDE ? 16 : 4;
         int32_t c = lane;
         for (; c + (U - 1) * L < n; c += U * L) {
             double x[U], a[R][U];
@@ -207,15 +207,13 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_partial(const double *__r
             acc = ABSMAX ? fmax(acc, a) : acc + a;
         }
     } else {
-        for (; i + 3 < r1; i += 4) {
-            const double a0 = __builtin_nontemporal_load(Ac + (size_t)i * n);
-            const double a1 = __builtin_nontemporal_load(Ac + (size_t)(i + 1) * n);
-            const double a2 = __builtin_nontemporal_load(Ac + (size_t)(i + 2) * n);
-            const double a3 = __builtin_nontemporal_load(Ac + (size_t)(i + 3) * n);
-            acc = fma(a0, w[i], acc);
-            acc = fma(a1, w[i + 1], acc);
-            acc = fma(a2, w[i + 2], acc);
-            acc = fma(a3, w[i + 3], acc);
+        // eight rows' loads in flight per thread, added in row order
+        for (; i + 7 < r1; i += 8) {
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = __builtin_nontemporal_load(Ac + (size_t)(i + u) * n);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = fma(a[u], w[i + u], acc);
         }
         for (; i < r1; ++i) acc = fma(__builtin_nontemporal_load(Ac + (size_t)i * n), w[i], acc);
     }

@@ -613,11 +613,24 @@ __global__ __launch_bounds__(kBlock) void k_scatter_scaled(const int32_t *__rest
 static inline dim3 grid_of(const HMat &M) { return dim3((unsigned)M.nblocks()); }
 
 void launch_primal(Handle &h, int32_t j, hipEvent_t *timing) {
-    if (h.dense) {
-        dense_primal(h, j);
+    // timing: four events; [0, 1] and [2, 3] bracket the step's kernels on the
+    // stream(s) they run on (one stream: [0] before, [1..3] after)
+    auto one_stream = [&](bool before) {
+        if (!timing) return;
+        if (before) {
+            PDHG_HIP(hipEventRecord(timing[0], h.stream));
+        } else {
+            PDHG_HIP(hipEventRecord(timing[1], h.stream));
+            PDHG_HIP(hipEventRecord(timing[2], h.stream));
+            PDHG_HIP(hipEventRecord(timing[3], h.stream));
+        }
+    };
+    if (h.dense || h.AT.nblocks() == 0) {
+        one_stream(true);
+        if (h.dense) dense_primal(h, j);
+        one_stream(false);
         return;
     }
-    if (h.AT.nblocks() == 0) return;
     if (h.PT.R > 0) {
         // panel rows on stream2 beside the SELL-64 rest on the main stream;
         // timing (4 events): around the kernels on stream2, then on the main stream
@@ -640,15 +653,11 @@ void launch_primal(Handle &h, int32_t j, hipEvent_t *timing) {
         PDHG_HIP(hipStreamWaitEvent(h.stream, h.ev_join, 0));
         return;
     }
-    if (timing) PDHG_HIP(hipEventRecord(timing[0], h.stream));
+    one_stream(true);
     k_primal<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
         view(h.AT), h.y.p, h.x.p, h.x0.p, h.c.p, h.lv.p,
         h.uv.p, h.xext.p, h.st.p, j, h.opt.gamma);
-    if (timing) {
-        PDHG_HIP(hipEventRecord(timing[1], h.stream));
-        PDHG_HIP(hipEventRecord(timing[2], h.stream));
-        PDHG_HIP(hipEventRecord(timing[3], h.stream));
-    }
+    one_stream(false);
 }
 
 void launch_dual(Handle &h, int32_t j) {
