@@ -227,7 +227,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the batched and sharded paths run on a single MI355X in this build)",
+              "(every workload here, batched ones included, runs on a single MI355X)",
               file=sys.stderr)
         sys.exit(2)
 

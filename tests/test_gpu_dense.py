@@ -104,3 +104,13 @@ def test_dense_infeasibility_certificates_match_oracle(pdhg, oracle_lib, kind, m
         assert rel_inf(to_np(yg), yo) <= 1e-8
     else:
         assert rel_inf(to_np(xg), xo) <= 1e-8
+
+
+def test_dense_kernel_timing(pdhg):
+    _say("case: dense planted LP 150 x 300, HIP-event timing of one check period")
+    lp = gen.dense_planted_lp(150, 300, seed=2001)
+    with pdhg.Solver.from_lp(lp, timing_chunk=1) as s:
+        _, _, r = s.solve()
+    assert r["status_name"] == "optimal"
+    assert r["kernel_samples"] > 0
+    assert r["kernel_primal_ms"] > 0 and r["kernel_dual_ms"] > 0
