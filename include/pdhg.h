@@ -132,10 +132,10 @@ typedef struct {
      * (the checks keep the standard layout; results differ only in the order
      * of summation). -1 selects the automatic choice.
      * panel_rows: entries of y staged in LDS per panel for the product A~'y
-     *   over the longest rows of A~' (auto: 16384 when m > 262144, else off;
-     *   0: off; at most 16384);
+     *   over the longest rows of A~' (auto: 20480 when m > 262144, else off;
+     *   0: off; at most 20480);
      * panel_min_len: rows of A~' longer than this use the panels (auto: 32);
-     * panel_wgs: workgroups per panel (auto: 8);
+     * panel_wgs: workgroups per panel (auto: 12);
      * hot_cols: leading entries of x_ext staged in LDS by the product A~x_ext
      *   (auto: 20480 when n > 262144, else off; 0: off; at most 20480). */
     int32_t panel_rows;

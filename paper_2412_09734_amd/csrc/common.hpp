@@ -135,7 +135,8 @@ inline MatView view(const HMat &M) {
 // piece in entry order. The first piece of sub-row (p, row) is stored to
 // part[p * R + row] (bit p of the row's mask says the sub-row exists); further
 // pieces go to part[P * R + x], listed per row in xptr / xslot.
-constexpr int kPanelMax = 16384;   // doubles per LDS panel (128 KB)
+constexpr int kPanelMax = 20480;   // doubles per LDS panel (160 KB, the most a workgroup may take)
+constexpr int kPanelWgsAuto = 12;  // workgroups per panel of the automatic layout
 constexpr int kHotMax = 20480;     // doubles of x_ext staged by the hot-column dual (160 KB)
 constexpr int kPanelWaves = 16;    // waves per panel workgroup
 constexpr int kPanelThreads = 64 * kPanelWaves;

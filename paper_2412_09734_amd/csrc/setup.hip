@@ -1079,7 +1079,7 @@ void build_fast_layouts(Handle &h) {
     P.vlen = m;
     P.P = (int32_t)ceil_div(m, S);
     P.W64 = (int32_t)ceil_div(P.P, 64);
-    P.W = h.opt.panel_wgs < 0 ? 8 : h.opt.panel_wgs;
+    P.W = h.opt.panel_wgs < 0 ? kPanelWgsAuto : h.opt.panel_wgs;
     P.entries = nnz;
     // pieces (row, first entry, length) per panel, in row order
     struct Piece {

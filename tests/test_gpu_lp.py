@@ -131,6 +131,7 @@ PANEL_LAYOUTS = {
     "many_panels": dict(panel_rows=64, panel_min_len=4, panel_wgs=2, hot_cols=100),
     "all_rows_in_panels": dict(panel_rows=1000, panel_min_len=0, panel_wgs=1, hot_cols=16384),
     "wide_panels": dict(panel_rows=16384, panel_min_len=16, panel_wgs=4, hot_cols=0),
+    "widest_panels": dict(panel_rows=20480, panel_min_len=8, panel_wgs=3, hot_cols=20480),
     "hot_columns_only": dict(panel_rows=0, hot_cols=37),
 }
 
