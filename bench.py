@@ -190,6 +190,8 @@ def main():
     ap.add_argument("--m", type=int, default=1_000_000)
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other", action="store_true",
+                    help="sparse workload: skip the portfolio-QP and dense-knapsack figures of the default run")
     ap.add_argument("--no-batched", action="store_true",
                     help="sparse workload: skip the batched-vs-plain grid measurement")
     ap.add_argument("--iteration-limit", type=int, default=0,
@@ -367,6 +369,11 @@ def main():
     if not args.no_batched and not infeasible:
         log("bench: batched grid LPs vs the plain solver looped")
         out["config"]["batched"] = batched_vs_plain()
+    if not args.no_other and not infeasible and not args.layout:
+        log("bench: 512 portfolio QPs (batched solve and unrolled gradient)")
+        out["config"]["qp_portfolio"] = qp_portfolio_run(512, steps=3, warmup=1, envelope=False)
+        log("bench: dense knapsack shape, first 10,000 iterations")
+        out["config"]["dense_knapsack"] = knapsack_run(steps=1, warmup=1)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(lp, iters, int(last["power_iters"]))
@@ -516,9 +523,9 @@ def bench_dense(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_knapsack(args):
+def knapsack_run(steps: int, warmup: int, limit: int = 10_000) -> dict:
     """The paper's hardware-comparison protocol on the dense knapsack shape
-    (1,000 x 100,000, FP64): the time of the first 10,000 iterations (the
+    (1,000 x 100,000, FP64): the time of the first `limit` iterations (the
     tolerance is set unreachably small so every run hits the limit)."""
     import numpy as np
     import torch
@@ -531,33 +538,39 @@ def bench_knapsack(args):
     a = torch.from_numpy(lp.dense).to(dev)
     vec = {k: torch.from_numpy(getattr(lp, k)).to(dev) for k in ("c", "lc", "uc", "lv", "uv")}
     torch.cuda.synchronize()
-    limit = args.iteration_limit or 10_000
 
     def step(timing_chunk=-1):
         with Solver(lp.m, lp.n, None, None, None, a_dense=a, device=dev, timing_chunk=timing_chunk,
                     iteration_limit=limit, eps=1e-14, **vec) as s:
             return s.solve()[2]
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    infos = [step(timing_chunk=2) for _ in range(args.steps)]
+    infos = [step(timing_chunk=2) for _ in range(steps)]
+    del a
     solve = float(np.mean([i["solve_seconds"] for i in infos]))
     setup = float(np.mean([i["setup_seconds"] for i in infos]))
     last = infos[-1]
     prim = float(np.mean([i["kernel_primal_ms"] for i in infos if i["kernel_samples"]] or [np.nan]))
     dual = float(np.mean([i["kernel_dual_ms"] for i in infos if i["kernel_samples"]] or [np.nan]))
     pass_bytes = 8 * lp.m * lp.n
+    return {"workload": f"plain r2HPDHG, dense knapsack LP {lp.m} x {lp.n}, {last['iterations']} iterations",
+            "solve_s": round(solve, 4), "setup_s": round(setup, 4),
+            "iter_us": round(solve / max(1, last["iterations"]) * 1e6, 2),
+            "row_pass_gbps": round(pass_bytes / (dual * 1e-3) / 1e9, 1),
+            "column_pass_gbps": round(pass_bytes / (prim * 1e-3) / 1e9, 1),
+            "paper_context_h200_fp64_s": 4.15}
+
+
+def bench_knapsack(args):
+    r = knapsack_run(args.steps, args.warmup, args.iteration_limit or 10_000)
+    solve = r.pop("solve_s")
     out = {"metric": "seconds for the first 10,000 iterations (dense knapsack shape)",
-           "value": round(solve, 4), "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "value": solve, "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(solve * 1e3, 2), "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"plain r2HPDHG, dense knapsack LP {lp.m} x {lp.n}, "
-                                  f"{last['iterations']} iterations", "setup_s": round(setup, 4),
-                      "iter_us": round(solve / max(1, last["iterations"]) * 1e6, 2),
-                      "row_pass_gbps": round(pass_bytes / (dual * 1e-3) / 1e9, 1),
-                      "column_pass_gbps": round(pass_bytes / (prim * 1e-3) / 1e9, 1),
-                      "paper_context_h200_fp64_s": 4.15}}
+           "config": r}
     print(json.dumps(out), flush=True)
 
 
@@ -681,8 +694,8 @@ def bench_spo(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_qp(args):
-    """512 portfolio QPs (n=500, Q = F F' + diag d, F shared, rank 20):
+def qp_portfolio_run(B: int, steps: int, warmup: int, envelope: bool = True) -> dict:
+    """B portfolio QPs (n=500, Q = F F' + diag d, F shared, rank 20):
     batched rAPDHG solve to 1e-4 (QPs/s), then 1,000 unrolled iterations with
     the reverse pass for the gradient of the value in (c, d)."""
     import numpy as np
@@ -693,7 +706,6 @@ def bench_qp(args):
     from paper_2412_09734_amd.solver import BatchSolver
     from types import SimpleNamespace
 
-    B = args.batch or 512
     T = 1000
     p = gen.portfolio_qp_batch(batch=B, seed=gen.seed_for(4, 500))
     sb = SimpleNamespace(m=p["m"], n=p["n"], rowptr=p["rowptr"], colidx=p["colidx"], val=p["val"],
@@ -701,49 +713,61 @@ def bench_qp(args):
                          lv=np.tile(p["lv"], (B, 1)), uv=np.tile(p["uv"], (B, 1)),
                          q_factor=p["F"], q_diag=p["d"])
     dev = torch.device("cuda:0")
+    out = {"workload": f"batched rAPDHG, {B} portfolio QPs n=500, Q = F F' + diag(d), F rank 20 shared",
+           "batch": B}
     with BatchSolver.from_shared(sb) as bs:
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             bs.solve()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             x, y, res = bs.solve()
         torch.cuda.synchronize()
-        t_solve = (time.perf_counter() - t0) / args.steps
+        t_solve = (time.perf_counter() - t0) / steps
         solved = sum(r["status"] == 1 for r in res)
         iters = [r["iterations"] for r in res]
         Fd = torch.from_numpy(p["F"]).to(dev)
         dd = torch.from_numpy(p["d"]).to(dev)
         cd = torch.from_numpy(p["c"]).to(dev)
+        for _ in range(warmup):
+            xT, _ = bs.unrolled(T)
+            val, gx = heads.qp_value(Fd, dd, cd, xT)
+            bs.backward(gx)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             xT, _ = bs.unrolled(T)
             val, gx = heads.qp_value(Fd, dd, cd, xT)
             gc, _, _, gd = bs.backward(gx)
         torch.cuda.synchronize()
-        t_grad = (time.perf_counter() - t1) / args.steps
-        # envelope check (untimed): dV/dc = x* with x* from a batched solve to
-        # relative KKT 1e-10, over the instances that solve converges within T
-        # iterations (the unrolled point has converged there too)
-        with BatchSolver.from_shared(sb, eps=1e-10, iteration_limit=100000) as tight:
-            xs_t, _, res_t = tight.solve()
-        conv = np.array([r["status"] == 1 and r["iterations"] < T for r in res_t])
-        gc_tot = (gc + xT).cpu().numpy()
-        err = np.abs(gc_tot - xs_t.cpu().numpy()).max(axis=1)
-        env_c = float(err[conv].max()) if conv.any() else None
-    out = {"metric": METRIC, "value": round(solved / t_solve, 2), "unit": "QPs/s",
+        t_grad = (time.perf_counter() - t1) / steps
+        out.update({"solve_ms": round(t_solve * 1e3, 3), "qps_per_s": round(solved / t_solve, 2),
+                    "solved": int(solved), "iterations_mean": float(np.mean(iters)),
+                    "iterations_max": int(np.max(iters)), "unrolled_iterations": T,
+                    "grad_ms": round(t_grad * 1e3, 2), "qps_per_s_with_gradient": round(B / t_grad, 2)})
+        if envelope:
+            # envelope check (untimed): dV/dc = x* with x* from a batched solve
+            # to relative KKT 1e-10, over the instances that solve converges
+            # within T iterations (the unrolled point has converged there too)
+            with BatchSolver.from_shared(sb, eps=1e-10, iteration_limit=100000) as tight:
+                xs_t, _, res_t = tight.solve()
+            conv = np.array([r["status"] == 1 and r["iterations"] < T for r in res_t])
+            gc_tot = (gc + xT).cpu().numpy()
+            err = np.abs(gc_tot - xs_t.cpu().numpy()).max(axis=1)
+            out.update({"envelope_c_max_abs_err": float(err[conv].max()) if conv.any() else None,
+                        "envelope_instances": int(conv.sum()),
+                        "envelope_reference": "batched solve to relative KKT 1e-10"})
+    return out
+
+
+def bench_qp(args):
+    r = qp_portfolio_run(args.batch or 512, args.steps, args.warmup)
+    t_solve = r["solve_ms"] * 1e-3
+    out = {"metric": METRIC, "value": r.pop("qps_per_s"), "unit": "QPs/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(t_solve * 1e3, 2), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": f"batched rAPDHG, {B} portfolio QPs n=500, Q = F F' + diag(d), "
-                                  f"F rank 20 shared", "batch": B, "solved": int(solved),
-                      "iterations_mean": float(np.mean(iters)), "iterations_max": int(np.max(iters)),
-                      "unrolled_iterations": T, "grad_ms": round(t_grad * 1e3, 2),
-                      "qps_per_s_with_gradient": round(B / t_grad, 2),
-                      "envelope_c_max_abs_err": env_c,
-                      "envelope_instances": int(conv.sum()),
-                      "envelope_reference": "batched solve to relative KKT 1e-10"}}
+           "config": r}
     print(json.dumps(out), flush=True)
 
 
