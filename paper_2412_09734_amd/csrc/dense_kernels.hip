@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
     } else if (live[0]) {
         // U columns x R rows of independent loads in flight per lane, each
         // row added in column order
-        constexpr int U = WIDE ? 16 : 4;
+        constexpr int U = 16;
         int32_t c = lane;
         for (; c + (U - 1) * L < n; c += U * L) {
             double x[U], a[R][U];
