@@ -46,8 +46,8 @@ struct DenseVecs {
 };
 
 // Row pass: a = sum_c A[i][c] v[c], or |A| norms. WIDE = false: one wave per
-// two rows (lanes strided over the columns, each v[c] loaded once for both
-// rows, butterflies), eight rows per workgroup; WIDE = true: the whole
+// four rows (lanes strided over the columns, each v[c] loaded once for the
+// four rows, butterflies), sixteen rows per workgroup; WIDE = true: the whole
 // workgroup on one row (for few, long rows: enough loads in flight to stream
 // HBM), wave totals added in wave order.
 template <int MODE, bool WIDE>
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
                                                        DenseVecs d) {
     if (d.st && d.st->done) return;
     constexpr int L = WIDE ? kBlock : 64;   // lanes per row
-    constexpr int R = WIDE ? 1 : 2;         // rows per wave
+    constexpr int R = WIDE ? 1 : 4;         // rows per wave
     const int64_t row0 = WIDE ? (int64_t)blockIdx.x
                               : (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * R;
     const int32_t lane = WIDE ? (int32_t)threadIdx.x : (int32_t)(threadIdx.x & 63);
@@ -207,7 +207,14 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_partial(const double *__r
             acc = ABSMAX ? fmax(acc, a) : acc + a;
         }
     } else {
-        // eight rows' loads in flight per thread, added in row order
+        // sixteen, then eight rows' loads in flight per thread, added in row order
+        for (; i + 15 < r1; i += 16) {
+            double a[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) a[u] = __builtin_nontemporal_load(Ac + (size_t)(i + u) * n);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc = fma(a[u], w[i + u], acc);
+        }
         for (; i + 7 < r1; i += 8) {
             double a[8];
 #pragma unroll
@@ -358,9 +365,9 @@ static DenseVecs dvecs(Handle &h, int32_t j) {
     return d;
 }
 
-// Few rows (fewer than 4 per CU) get a workgroup each, otherwise a wave each.
+// Few rows (fewer than 4 per CU) get a workgroup each, otherwise a wave per four.
 static bool wide_rows(int32_t m) { return m < 1024; }
-static unsigned row_blocks(int32_t m) { return wide_rows(m) ? (unsigned)std::max(1, m) : dblk((int64_t)(m + 1) / 2 * 64); }
+static unsigned row_blocks(int32_t m) { return wide_rows(m) ? (unsigned)std::max(1, m) : dblk((int64_t)(m + 3) / 4 * 64); }
 
 template <int MODE>
 static void launch_rows(hipStream_t s, const double *A, int32_t m, int32_t n, const double *v,

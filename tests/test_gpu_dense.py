@@ -89,7 +89,7 @@ def _dense_copy(lp):
                                            ("unbounded", 400, 800, 1), ("duplicate_row", 1100, 2200, 4)])
 def test_dense_infeasibility_certificates_match_oracle(pdhg, oracle_lib, kind, m, n, seed):
     """Row-major storage: the dense check kernels produce the same ray terms
-    (a workgroup per row below 1,024 rows, two rows per wave above)."""
+    (a workgroup per row below 1,024 rows, four rows per wave above)."""
     _say(f"case: dense infeasibility detection, {kind} m={m} n={n} seed={seed}")
     lp = _dense_copy(gen.infeasible_lp(kind, m, n, seed=seed))
     xo, yo, ro = oracle_lib.Oracle(lp, iteration_limit=100000).solve()
