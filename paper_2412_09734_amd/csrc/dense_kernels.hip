@@ -2,7 +2,8 @@
 // eq. (pdhg-lp) / eq. (hrpdhg) with the two products done as HBM-streaming
 // passes over A~ (FP64 GEMV has 0.25 flop per byte, far below the FP64 ridge,
 // so the vector units keep up with HBM and matrix cores would not help):
-//   rows pass    : a_i = A~_i . v, one wave per row, fused with the dual step
+//   rows pass    : a_i = A~_i . v, one wave per four rows (a workgroup per four
+//                  rows when there are few), fused with the dual step
 //   columns pass : partial sums of A~' w over 256-column tiles and row splits,
 //                  then a finalize kernel that adds the splits in fixed order
 //                  and applies the primal step.
@@ -11,7 +12,8 @@
 
 namespace pdhg {
 
-constexpr int kDenseSplits = 16;
+constexpr int kDenseSplits = 16;   // most row splits of the column pass
+constexpr int kSplitRows = 256;    // fewest rows per split of the column pass
 
 enum RowMode : int32_t {
     ROW_DUAL = 0,      // y <- Halpern(prox)
@@ -45,19 +47,21 @@ struct DenseVecs {
     double gamma, tau_o, sigma_o;
 };
 
+constexpr int kWideRows = 4;   // rows per workgroup of the WIDE row pass
+
 // Row pass: a = sum_c A[i][c] v[c], or |A| norms. WIDE = false: one wave per
 // four rows (lanes strided over the columns, each v[c] loaded once for the
 // four rows, butterflies), sixteen rows per workgroup; WIDE = true: the whole
-// workgroup on one row (for few, long rows: enough loads in flight to stream
-// HBM), wave totals added in wave order.
+// workgroup on kWideRows rows (for few, long rows: enough loads in flight to
+// stream HBM, each v[c] loaded once for them), wave totals added in wave order.
 template <int MODE, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict__ A, int32_t m,
                                                        int32_t n, const double *__restrict__ v,
                                                        DenseVecs d) {
     if (d.st && d.st->done) return;
     constexpr int L = WIDE ? kBlock : 64;   // lanes per row
-    constexpr int R = WIDE ? 1 : 4;         // rows per wave
-    const int64_t row0 = WIDE ? (int64_t)blockIdx.x
+    constexpr int R = WIDE ? kWideRows : 4;   // rows per workgroup (WIDE) or per wave
+    const int64_t row0 = WIDE ? (int64_t)blockIdx.x * R
                               : (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * R;
     const int32_t lane = WIDE ? (int32_t)threadIdx.x : (int32_t)(threadIdx.x & 63);
     double acc[R];
@@ -115,15 +119,21 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
     }
     double accv = acc[0];
     int64_t row = row0;
-    if (WIDE) {
-        __shared__ double wt[kBlock / 64];
-        if ((threadIdx.x & 63) == 0) wt[threadIdx.x >> 6] = accv;
+    if constexpr (WIDE) {
+        // thread q of the workgroup owns row row0 + q
+        __shared__ double wt[R][kBlock / 64];
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) wt[q][threadIdx.x >> 6] = acc[q];
+        }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = wt[0];
-            for (int w = 1; w < kBlock / 64; ++w) t = MODE == ROW_ABSMAX ? fmax(t, wt[w]) : t + wt[w];
+        const int32_t q = (int32_t)threadIdx.x;
+        if (q < R) {
+            double t = wt[q][0];
+            for (int w = 1; w < kBlock / 64; ++w) t = MODE == ROW_ABSMAX ? fmax(t, wt[q][w]) : t + wt[q][w];
             accv = t;
         }
+        row = row0 + (q < R ? q : 0);
     } else {
         // lane q of the wave owns row row0 + q
 #pragma unroll
@@ -132,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
         row = row0 + (lane < R ? lane : 0);
     }
     const double acc_own = accv;
-    const bool own = row < m && (WIDE ? threadIdx.x == 0 : lane < R);
+    const bool own = row < m && (WIDE ? (int32_t)threadIdx.x < R : lane < R);
     if (MODE == ROW_CHECK_M || MODE == ROW_STORE_SQ) {
         double vals[4] = {0.0, 0.0, 0.0, 0.0};
         double rsum[1] = {0.0}, rmax[2] = {0.0, 0.0};
@@ -185,7 +195,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
     }
 }
 
-// Partial column sums: partials[split][c] = sum over the split's rows of A[i][c] w[i].
+// Partial column sums: partials[split][c] = sum over the split's rows of A[i][c] w[i];
+// the splits are gridDim.y equal runs of rows.
 template <bool ABSMAX, bool ABSSUM>
 __global__ __launch_bounds__(kBlock) void k_dense_cols_partial(const double *__restrict__ A,
                                                                int32_t m, int32_t n,
@@ -195,7 +206,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_partial(const double *__r
     if (st && st->done) return;
     const int64_t col = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int32_t split = blockIdx.y;
-    const int32_t rows_per = (m + kDenseSplits - 1) / kDenseSplits;
+    const int32_t splits = (int32_t)gridDim.y;
+    const int32_t rows_per = (m + splits - 1) / splits;
     const int32_t r0 = split * rows_per, r1 = min(m, r0 + rows_per);
     if (col >= n) return;
     double acc = 0.0;
@@ -229,13 +241,14 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols_partial(const double *__r
 
 // Splits added in order 0..S-1, then the column epilogue.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_dense_cols_final(int32_t n, const double *__restrict__ part,
+__global__ __launch_bounds__(kBlock) void k_dense_cols_final(int32_t n, int32_t splits,
+                                                             const double *__restrict__ part,
                                                              DenseVecs d) {
     if (d.st && d.st->done) return;
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double s = 0.0;
     if (r < n) {
-        for (int q = 0; q < kDenseSplits; ++q) {
+        for (int q = 0; q < splits; ++q) {
             const double p = part[(size_t)q * n + r];
             s = MODE == COL_ABSMAX ? fmax(s, p) : s + p;
         }
@@ -367,7 +380,9 @@ static DenseVecs dvecs(Handle &h, int32_t j) {
 
 // Few rows (fewer than 4 per CU) get a workgroup each, otherwise a wave per four.
 static bool wide_rows(int32_t m) { return m < 1024; }
-static unsigned row_blocks(int32_t m) { return wide_rows(m) ? (unsigned)std::max(1, m) : dblk((int64_t)(m + 3) / 4 * 64); }
+static unsigned row_blocks(int32_t m) {
+    return wide_rows(m) ? (unsigned)std::max<int64_t>(1, ceil_div(m, kWideRows)) : dblk((int64_t)(m + 3) / 4 * 64);
+}
 
 template <int MODE>
 static void launch_rows(hipStream_t s, const double *A, int32_t m, int32_t n, const double *v,
@@ -378,18 +393,22 @@ static void launch_rows(hipStream_t s, const double *A, int32_t m, int32_t n, co
         k_dense_rows<MODE, false><<<row_blocks(m), kBlock, 0, s>>>(A, m, n, v, d);
 }
 static unsigned col_blocks(int32_t n) { return dblk(n); }
+// Row splits of the column pass: up to kDenseSplits, at least kSplitRows rows each.
+static int32_t col_splits(int32_t m) {
+    return (int32_t)std::min<int64_t>(kDenseSplits, std::max<int64_t>(1, m / kSplitRows));
+}
 
 int32_t dense_row_blocks(const Handle &h) { return (int32_t)row_blocks(h.m); }
 int32_t dense_col_blocks(const Handle &h) { return (int32_t)col_blocks(h.n); }
 
 static void cols_partial(Handle &h, const double *w, const DevState *st) {
-    dim3 grid(col_blocks(h.n), kDenseSplits);
+    dim3 grid(col_blocks(h.n), col_splits(h.m));
     k_dense_cols_partial<false, false><<<grid, kBlock, 0, h.stream>>>(h.Ad.p, h.m, h.n, w, h.dpart.p, st);
 }
 
 void dense_primal(Handle &h, int32_t j) {
     cols_partial(h, h.y.p, h.st.p);
-    k_dense_cols_final<COL_PRIMAL><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, h.dpart.p, dvecs(h, j));
+    k_dense_cols_final<COL_PRIMAL><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, col_splits(h.m), h.dpart.p, dvecs(h, j));
 }
 
 void dense_dual(Handle &h, int32_t j) {
@@ -401,7 +420,7 @@ void dense_primal_check(Handle &h, double tau_override) {
     cols_partial(h, h.y.p, h.st.p);
     DenseVecs d = dvecs(h, 0);
     d.tau_o = tau_override;
-    k_dense_cols_final<COL_PRIMAL_CHK><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, h.dpart.p, d);
+    k_dense_cols_final<COL_PRIMAL_CHK><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, col_splits(h.m), h.dpart.p, d);
 }
 
 void dense_dual_check(Handle &h, double sigma_override) {
@@ -418,7 +437,7 @@ void dense_check_sums(Handle &h) {
     d.q0 = h.q0.p;
     d.qhat = h.qhat.p;
     d.rays = h.prn.p;
-    k_dense_cols_final<COL_CHECK_N><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, h.dpart.p, d);
+    k_dense_cols_final<COL_CHECK_N><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, col_splits(h.m), h.dpart.p, d);
     if (h.m > 0) {
         DenseVecs e = dvecs(h, 0);
         e.partials = h.pm.p;
@@ -445,7 +464,7 @@ void dense_cols_sq(Handle &h, const double *w, double *out, double *partials) {
     d.st = nullptr;
     d.out = out;
     d.partials = partials;
-    k_dense_cols_final<COL_STORE_SQ><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, h.dpart.p, d);
+    k_dense_cols_final<COL_STORE_SQ><<<col_blocks(h.n), kBlock, 0, h.stream>>>(h.n, col_splits(h.m), h.dpart.p, d);
 }
 
 void dense_build(Handle &h, const pdhg_problem &p) {
@@ -488,17 +507,17 @@ void dense_scale(Handle &h) {
         DenseVecs d = dvecs(h, 0);
         d.st = nullptr;
         d.out = rn.p;
-        dim3 grid(col_blocks(n), kDenseSplits);
+        dim3 grid(col_blocks(n), col_splits(m));
         if (pc) {
             launch_rows<ROW_ABSSUM>(s, h.Ad.p, m, n, nullptr, d);
             k_dense_cols_partial<false, true><<<grid, kBlock, 0, s>>>(h.Ad.p, m, n, nullptr, h.dpart.p, nullptr);
             d.out = cn.p;
-            k_dense_cols_final<COL_ABSSUM><<<col_blocks(n), kBlock, 0, s>>>(n, h.dpart.p, d);
+            k_dense_cols_final<COL_ABSSUM><<<col_blocks(n), kBlock, 0, s>>>(n, col_splits(m), h.dpart.p, d);
         } else {
             launch_rows<ROW_ABSMAX>(s, h.Ad.p, m, n, nullptr, d);
             k_dense_cols_partial<true, false><<<grid, kBlock, 0, s>>>(h.Ad.p, m, n, nullptr, h.dpart.p, nullptr);
             d.out = cn.p;
-            k_dense_cols_final<COL_ABSMAX><<<col_blocks(n), kBlock, 0, s>>>(n, h.dpart.p, d);
+            k_dense_cols_final<COL_ABSMAX><<<col_blocks(n), kBlock, 0, s>>>(n, col_splits(m), h.dpart.p, d);
         }
         launch_factors(h, rn.p, cn.p);
         k_dense_scale<<<8192, kBlock, 0, s>>>(h.Ad.p, m, n, rn.p, cn.p);
