@@ -191,7 +191,8 @@ def main():
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other", action="store_true",
-                    help="sparse workload: skip the portfolio-QP and dense-knapsack figures of the default run")
+                    help="sparse workload: skip the portfolio-QP and dense-knapsack figures of the default run "
+                         "(also skipped with --iteration-limit or --layout)")
     ap.add_argument("--no-batched", action="store_true",
                     help="sparse workload: skip the batched-vs-plain grid measurement")
     ap.add_argument("--iteration-limit", type=int, default=0,
@@ -369,7 +370,7 @@ def main():
     if not args.no_batched and not infeasible:
         log("bench: batched grid LPs vs the plain solver looped")
         out["config"]["batched"] = batched_vs_plain()
-    if not args.no_other and not infeasible and not args.layout:
+    if not args.no_other and not infeasible and not args.layout and not args.iteration_limit:
         log("bench: 512 portfolio QPs (batched solve and unrolled gradient)")
         out["config"]["qp_portfolio"] = qp_portfolio_run(512, steps=3, warmup=1, envelope=False)
         log("bench: dense knapsack shape, first 10,000 iterations")

@@ -374,4 +374,70 @@ __device__ __forceinline__ double dual_prox(double y, double a, double sigma, do
     return sigma * (v - clampd(v, -uc, -lc));
 }
 
+// f(row) for the Q-value rows p[b * Q, b * Q + Q) of the blocks
+// b = threadIdx.x + kBlock * i of one thread, in increasing b; eight blocks'
+// loads are issued before their f calls.
+template <int Q, class F>
+__device__ __forceinline__ void strided_fold(const double *__restrict__ p, int32_t nb, F f) {
+    int32_t b = (int32_t)threadIdx.x;
+    for (; b + 7 * kBlock < nb; b += 8 * kBlock) {
+        double t[8][Q];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) t[u][q] = p[(size_t)(b + u * kBlock) * Q + q];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) f(t[u]);
+    }
+    for (; b < nb; b += kBlock) {
+        double t[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) t[q] = p[(size_t)b * Q + q];
+        f(t);
+    }
+}
+
+// Totals of a check's per-workgroup partials, for the one-workgroup
+// controllers (every thread ends with the same totals): vn / vm the six
+// column-side and four row-side sums (pn: nbn rows of 6, pm: nbm rows of 4);
+// with rays, rs the three ray sums (prn[b * 4 + 0, 1], prm[b * 3]) and rx the
+// two ray maxima (prn[b * 4 + 2, 3] with prm[b * 3 + 1, 2]), else zeros.
+__device__ __forceinline__ void check_totals(const double *__restrict__ pn, int32_t nbn,
+                                             const double *__restrict__ pm, int32_t nbm,
+                                             const double *__restrict__ prn,
+                                             const double *__restrict__ prm, bool rays,
+                                             double (&vn)[6], double (&vm)[4], double (&rs)[3],
+                                             double (&rx)[2]) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) vn[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) vm[q] = 0.0;
+    rs[0] = rs[1] = rs[2] = 0.0;
+    rx[0] = rx[1] = 0.0;
+    strided_fold<6>(pn, nbn, [&](const double *t) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) vn[q] += t[q];
+    });
+    strided_fold<4>(pm, nbm, [&](const double *t) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) vm[q] += t[q];
+    });
+    block_sum_all<6>(vn);
+    block_sum_all<4>(vm);
+    if (!rays) return;
+    strided_fold<4>(prn, nbn, [&](const double *t) {
+        rs[0] += t[0];
+        rs[1] += t[1];
+        rx[0] = fmax(rx[0], t[2]);
+        rx[1] = fmax(rx[1], t[3]);
+    });
+    strided_fold<3>(prm, nbm, [&](const double *t) {
+        rs[2] += t[0];
+        rx[0] = fmax(rx[0], t[1]);
+        rx[1] = fmax(rx[1], t[2]);
+    });
+    block_sum_all<3>(rs);
+    block_max_all<2>(rx);
+}
+
 }  // namespace pdhg

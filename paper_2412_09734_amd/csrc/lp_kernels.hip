@@ -367,35 +367,11 @@ __global__ __launch_bounds__(kBlock) void k_controller(
     const double *__restrict__ prm, CtlConst K, int32_t chunk_plain, int32_t is_last,
     int32_t last_status) {
     if (st->done) return;
-    double vn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double vm[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int32_t b = threadIdx.x; b < nbn; b += kBlock)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) vn[q] += pn[(size_t)b * 6 + q];
-    for (int32_t b = threadIdx.x; b < nbm; b += kBlock)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) vm[q] += pm[(size_t)b * 4 + q];
-    block_sum_all<6>(vn);
-    block_sum_all<4>(vm);
+    double vn[6], vm[4], rs[3], rx[2];
     // ray totals: 0 dual-ray objective (columns), 1 c'dx, 2 dual-ray objective
     // (rows); maxima: 0 dual-ray violation, 1 primal-ray violation
     const bool rays = K.detect && st->anchor_valid;
-    double rs[3] = {0.0, 0.0, 0.0}, rx[2] = {0.0, 0.0};
-    if (rays) {
-        for (int32_t b = threadIdx.x; b < nbn; b += kBlock) {
-            rs[0] += prn[(size_t)b * 4];
-            rs[1] += prn[(size_t)b * 4 + 1];
-            rx[0] = fmax(rx[0], prn[(size_t)b * 4 + 2]);
-            rx[1] = fmax(rx[1], prn[(size_t)b * 4 + 3]);
-        }
-        for (int32_t b = threadIdx.x; b < nbm; b += kBlock) {
-            rs[2] += prm[(size_t)b * 3];
-            rx[0] = fmax(rx[0], prm[(size_t)b * 3 + 1]);
-            rx[1] = fmax(rx[1], prm[(size_t)b * 3 + 2]);
-        }
-        block_sum_all<3>(rs);
-        block_max_all<2>(rx);
-    }
+    check_totals(pn, nbn, pm, nbm, prn, prm, rays, vn, vm, rs, rx);
     if (threadIdx.x != 0) return;
 
     const int64_t t = st->t_next;
