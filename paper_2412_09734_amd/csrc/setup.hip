@@ -5,6 +5,8 @@
 // weight.
 #include <algorithm>
 #include <cstring>
+#include <exception>
+#include <thread>
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
@@ -1047,6 +1049,32 @@ void compute_weight(Handle &h) {
 // LDS panels of the primal product (rows [0, R) of A~', scaled values) and the
 // hot-column count of the dual product. The panel layout is built on the host
 // from the rows kept at the matrix build and the scaled values of AT.
+// f(t, lo, hi) on T host threads over contiguous ranges [lo, hi) of [0, n),
+// T = min(16, hardware threads, n); the ranges are in order of t. An
+// exception in any range is rethrown here after every thread has ended.
+static int32_t host_threads(int64_t n) {
+    const int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>({16, hw, n}));
+}
+template <class F>
+static void host_parallel(int64_t n, F f) {
+    const int32_t T = host_threads(n);
+    std::vector<std::exception_ptr> err((size_t)T);
+    auto run = [&](int32_t t) {
+        try {
+            f(t, n * t / T, n * (t + 1) / T);
+        } catch (...) {
+            err[(size_t)t] = std::current_exception();
+        }
+    };
+    std::vector<std::thread> th;
+    for (int32_t t = 0; t + 1 < T; ++t) th.emplace_back(run, t);
+    run(T - 1);
+    for (auto &x : th) x.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
+}
+
 void build_fast_layouts(Handle &h) {
     hipStream_t s = h.stream;
     const int32_t m = h.m, n = h.n;
@@ -1092,28 +1120,54 @@ void build_fast_layouts(Handle &h) {
     std::vector<uint64_t> mask((size_t)P.W64 * R, 0);
     std::vector<int32_t> xcount((size_t)R, 0);
     int64_t nx = 0;
-    for (int32_t r = 0; r < R; ++r) {
-        int64_t e = rp[r];
-        const int64_t e1 = rp[r + 1];
-        while (e < e1) {
-            const int32_t p = ci[(size_t)e] / S;   // entries of a row are sorted by y index
-            int64_t f = e;
-            while (f < e1 && ci[(size_t)f] / S == p) ++f;
-            mask[(size_t)(p >> 6) * R + r] |= 1ull << (p & 63);
-            for (int64_t q = e; q < f; q += kPanelPiece) {
-                const int32_t len = (int32_t)std::min<int64_t>(kPanelPiece, f - q);
-                int32_t slot = -1;
-                if (q == e) {
-                    slot = (int32_t)((int64_t)p * R + r);
-                } else {
-                    slot = -2;   // numbered below, in row order
-                    ++xcount[(size_t)r];
-                    ++nx;
+    {
+        // rows in contiguous ranges per host thread, each collecting its pieces
+        // per panel; the ranges are then joined in row order
+        std::vector<std::vector<std::vector<Piece>>> local;
+        std::vector<int64_t> lnx;
+        const int32_t T = host_threads(R);
+        local.resize((size_t)T, std::vector<std::vector<Piece>>((size_t)P.P));
+        lnx.assign((size_t)T, 0);
+        host_parallel(R, [&](int32_t t, int64_t r0, int64_t r1) {
+            auto &mine = local[(size_t)t];
+            for (int64_t r = r0; r < r1; ++r) {
+                int64_t e = rp[(size_t)r];
+                const int64_t e1 = rp[(size_t)r + 1];
+                while (e < e1) {
+                    const int32_t p = ci[(size_t)e] / S;   // entries of a row are sorted by y index
+                    int64_t f = e;
+                    while (f < e1 && ci[(size_t)f] / S == p) ++f;
+                    mask[(size_t)(p >> 6) * R + (size_t)r] |= 1ull << (p & 63);
+                    for (int64_t q = e; q < f; q += kPanelPiece) {
+                        const int32_t len = (int32_t)std::min<int64_t>(kPanelPiece, f - q);
+                        int32_t slot = -1;
+                        if (q == e) {
+                            slot = (int32_t)((int64_t)p * R + r);
+                        } else {
+                            slot = -2;   // numbered below, in row order
+                            ++xcount[(size_t)r];
+                            ++lnx[(size_t)t];
+                        }
+                        mine[(size_t)p].push_back(Piece{(int32_t)r, len, q, slot});
+                    }
+                    e = f;
                 }
-                pieces[(size_t)p].push_back(Piece{r, len, q, slot});
             }
-            e = f;
-        }
+        });
+        for (int32_t t = 0; t < T; ++t) nx += lnx[(size_t)t];
+        host_parallel(P.P, [&](int32_t, int64_t p0, int64_t p1) {
+            for (int64_t p = p0; p < p1; ++p) {
+                size_t total = 0;
+                for (int32_t t = 0; t < T; ++t) total += local[(size_t)t][(size_t)p].size();
+                std::vector<Piece> &v = pieces[(size_t)p];
+                v.reserve(total);
+                for (int32_t t = 0; t < T; ++t) {
+                    std::vector<Piece> &l = local[(size_t)t][(size_t)p];
+                    v.insert(v.end(), l.begin(), l.end());
+                    std::vector<Piece>().swap(l);
+                }
+            }
+        });
     }
     if ((int64_t)P.P * R + nx >= INT32_MAX) fail(PDHG_ERR_UNSUPPORTED, "too many panel partials");
     // extra pieces: slots P*R + x, x in row order then panel order
@@ -1129,40 +1183,67 @@ void build_fast_layouts(Handle &h) {
                 xslot[(size_t)x] = pc.slot;
             }
     P.nx = (int32_t)nx;
-    // SELL-64 slices per panel, pieces sorted by length (stable)
-    std::vector<int32_t> pslice((size_t)P.P + 1, 0), soff(1, 0), slot;
-    std::vector<uint16_t> idx;
-    std::vector<double> val;
-    for (int32_t p = 0; p < P.P; ++p) {
-        std::vector<Piece> &v = pieces[(size_t)p];
-        std::stable_sort(v.begin(), v.end(), [](const Piece &a, const Piece &b) { return a.len > b.len; });
-        const int32_t ns = (int32_t)ceil_div((int64_t)v.size(), 64);
-        for (int32_t sl = 0; sl < ns; ++sl) {
-            const size_t first = (size_t)sl * 64;
-            const int32_t w = v[first].len;
-            const size_t base = idx.size();
-            idx.resize(base + (size_t)64 * w, 0);
-            val.resize(base + (size_t)64 * w, 0.0);
-            for (int32_t l = 0; l < 64; ++l) {
-                const size_t q = first + (size_t)l;
-                if (q >= v.size()) {
-                    slot.push_back(-1);
-                    continue;
-                }
-                const Piece &pc = v[q];
-                slot.push_back(pc.slot);
-                for (int32_t k = 0; k < pc.len; ++k) {
-                    const int64_t e = pc.e0 + k;
-                    idx[base + (size_t)64 * k + l] = (uint16_t)(ci[(size_t)e] - p * S);
-                    val[base + (size_t)64 * k + l] = value(pc.row, e - rp[pc.row]);
-                }
-            }
-            if (idx.size() >= (size_t)INT32_MAX) fail(PDHG_ERR_UNSUPPORTED, "panel layout too large");
-            soff.push_back((int32_t)idx.size());
+    // SELL-64 slices per panel, pieces sorted by length (stable, longest
+    // first). Per panel on host threads: the order by a counting sort on the
+    // length (at most kPanelPiece), then, after the panels' sizes are added
+    // up in panel order, each panel fills its own range of the arrays.
+    std::vector<std::vector<int32_t>> order((size_t)P.P);
+    std::vector<int64_t> p_entries((size_t)P.P, 0);
+    std::vector<int32_t> p_slices((size_t)P.P, 0);
+    host_parallel(P.P, [&](int32_t, int64_t p0, int64_t p1) {
+        for (int64_t p = p0; p < p1; ++p) {
+            const std::vector<Piece> &v = pieces[(size_t)p];
+            std::vector<int32_t> cnt((size_t)kPanelPiece + 2, 0);
+            for (const Piece &pc : v) ++cnt[(size_t)(kPanelPiece - pc.len + 1)];
+            for (size_t b = 1; b < cnt.size(); ++b) cnt[b] += cnt[b - 1];
+            std::vector<int32_t> &o = order[(size_t)p];
+            o.resize(v.size());
+            for (size_t q = 0; q < v.size(); ++q) o[(size_t)cnt[(size_t)(kPanelPiece - v[q].len)]++] = (int32_t)q;
+            const int32_t ns = (int32_t)ceil_div((int64_t)v.size(), 64);
+            int64_t ent = 0;
+            for (int32_t sl = 0; sl < ns; ++sl) ent += (int64_t)64 * v[(size_t)o[(size_t)sl * 64]].len;
+            p_entries[(size_t)p] = ent;
+            p_slices[(size_t)p] = ns;
         }
-        pslice[p + 1] = pslice[p] + ns;
-        std::vector<Piece>().swap(v);
+    });
+    std::vector<int32_t> pslice((size_t)P.P + 1, 0);
+    std::vector<int64_t> ebase((size_t)P.P + 1, 0);
+    for (int32_t p = 0; p < P.P; ++p) {
+        pslice[(size_t)p + 1] = pslice[(size_t)p] + p_slices[(size_t)p];
+        ebase[(size_t)p + 1] = ebase[(size_t)p] + p_entries[(size_t)p];
     }
+    if (ebase[(size_t)P.P] >= (int64_t)INT32_MAX) fail(PDHG_ERR_UNSUPPORTED, "panel layout too large");
+    std::vector<uint16_t> idx((size_t)ebase[(size_t)P.P], 0);
+    std::vector<double> val((size_t)ebase[(size_t)P.P], 0.0);
+    std::vector<int32_t> soff((size_t)pslice[(size_t)P.P] + 1, 0);
+    std::vector<int32_t> slot((size_t)pslice[(size_t)P.P] * 64, -1);
+    host_parallel(P.P, [&](int32_t, int64_t p0, int64_t p1) {
+        for (int64_t p = p0; p < p1; ++p) {
+            const std::vector<Piece> &v = pieces[(size_t)p];
+            const std::vector<int32_t> &o = order[(size_t)p];
+            const int32_t ns = p_slices[(size_t)p];
+            size_t base = (size_t)ebase[(size_t)p];
+            for (int32_t sl = 0; sl < ns; ++sl) {
+                const size_t first = (size_t)sl * 64;
+                const int32_t w = v[(size_t)o[first]].len;
+                const size_t gs = (size_t)pslice[(size_t)p] + (size_t)sl;
+                for (int32_t l = 0; l < 64; ++l) {
+                    const size_t q = first + (size_t)l;
+                    if (q >= v.size()) continue;
+                    const Piece &pc = v[(size_t)o[q]];
+                    slot[gs * 64 + (size_t)l] = pc.slot;
+                    for (int32_t k = 0; k < pc.len; ++k) {
+                        const int64_t e = pc.e0 + k;
+                        idx[base + (size_t)64 * k + l] = (uint16_t)(ci[(size_t)e] - p * S);
+                        val[base + (size_t)64 * k + l] = value(pc.row, e - rp[pc.row]);
+                    }
+                }
+                base += (size_t)64 * w;
+                soff[gs + 1] = (int32_t)base;
+            }
+        }
+    });
+    for (auto &v : pieces) std::vector<Piece>().swap(v);
     P.nslices = pslice[P.P];
     // workgroups: W per panel, all of a panel's workgroups on one XCD (workgroup
     // b runs on XCD b mod 8), so the panel's partial-sum lines meet in one L2
