@@ -47,7 +47,8 @@ struct DenseVecs {
     double gamma, tau_o, sigma_o;
 };
 
-constexpr int kWideRows = 4;   // rows per workgroup of the WIDE row pass
+constexpr int kWideRows = 4;     // rows per workgroup of the WIDE row pass
+constexpr int kWideBlock = 512;  // threads per workgroup of the WIDE row pass
 
 // Row pass: a = sum_c A[i][c] v[c], or |A| norms. WIDE = false: one wave per
 // four rows (lanes strided over the columns, each v[c] loaded once for the
@@ -55,11 +56,11 @@ constexpr int kWideRows = 4;   // rows per workgroup of the WIDE row pass
 // workgroup on kWideRows rows (for few, long rows: enough loads in flight to
 // stream HBM, each v[c] loaded once for them), wave totals added in wave order.
 template <int MODE, bool WIDE>
-__global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict__ A, int32_t m,
-                                                       int32_t n, const double *__restrict__ v,
-                                                       DenseVecs d) {
+__global__ __launch_bounds__(WIDE ? kWideBlock : kBlock) void k_dense_rows(
+    const double *__restrict__ A, int32_t m, int32_t n, const double *__restrict__ v, DenseVecs d) {
     if (d.st && d.st->done) return;
-    constexpr int L = WIDE ? kBlock : 64;   // lanes per row
+    constexpr int BS = WIDE ? kWideBlock : kBlock;   // threads per workgroup
+    constexpr int L = WIDE ? BS : 64;                 // lanes per row
     constexpr int R = WIDE ? kWideRows : 4;   // rows per workgroup (WIDE) or per wave
     const int64_t row0 = WIDE ? (int64_t)blockIdx.x * R
                               : (((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6) * R;
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
     int64_t row = row0;
     if constexpr (WIDE) {
         // thread q of the workgroup owns row row0 + q
-        __shared__ double wt[R][kBlock / 64];
+        __shared__ double wt[R][BS / 64];
         if ((threadIdx.x & 63) == 0) {
 #pragma unroll
             for (int q = 0; q < R; ++q) wt[q][threadIdx.x >> 6] = acc[q];
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
         const int32_t q = (int32_t)threadIdx.x;
         if (q < R) {
             double t = wt[q][0];
-            for (int w = 1; w < kBlock / 64; ++w) t = MODE == ROW_ABSMAX ? fmax(t, wt[q][w]) : t + wt[q][w];
+            for (int w = 1; w < BS / 64; ++w) t = MODE == ROW_ABSMAX ? fmax(t, wt[q][w]) : t + wt[q][w];
             accv = t;
         }
         row = row0 + (q < R ? q : 0);
@@ -170,11 +171,11 @@ __global__ __launch_bounds__(kBlock) void k_dense_rows(const double *__restrict_
         }
         if (MODE == ROW_STORE_SQ) {
             double q[1] = {vals[0]};
-            block_sum_store<1>(q, d.partials + blockIdx.x);
+            block_sum_store<1, BS>(q, d.partials + blockIdx.x);
         } else {
-            block_sum_store<4>(vals, d.partials + (size_t)blockIdx.x * 4);
-            block_sum_store<1>(rsum, d.rays + (size_t)blockIdx.x * 3);
-            block_max_store<2>(rmax, d.rays + (size_t)blockIdx.x * 3 + 1);
+            block_sum_store<4, BS>(vals, d.partials + (size_t)blockIdx.x * 4);
+            block_sum_store<1, BS>(rsum, d.rays + (size_t)blockIdx.x * 3);
+            block_max_store<2, BS>(rmax, d.rays + (size_t)blockIdx.x * 3 + 1);
         }
         return;
     }
@@ -388,7 +389,7 @@ template <int MODE>
 static void launch_rows(hipStream_t s, const double *A, int32_t m, int32_t n, const double *v,
                         const DenseVecs &d) {
     if (wide_rows(m))
-        k_dense_rows<MODE, true><<<row_blocks(m), kBlock, 0, s>>>(A, m, n, v, d);
+        k_dense_rows<MODE, true><<<row_blocks(m), kWideBlock, 0, s>>>(A, m, n, v, d);
     else
         k_dense_rows<MODE, false><<<row_blocks(m), kBlock, 0, s>>>(A, m, n, v, d);
 }

@@ -235,10 +235,11 @@ __device__ __forceinline__ double wave_sum(double s) {
 }
 
 // Deterministic workgroup sum of K values per thread: wave butterflies, then
-// the 4 wave totals in fixed order. Result written by threads 0..K-1 to out.
-template <int K>
+// the BT / 64 wave totals in fixed order (BT: threads of the workgroup).
+// Result written by threads 0..K-1 to out.
+template <int K, int BT = kBlock>
 __device__ __forceinline__ void block_sum_store(const double (&v)[K], double *__restrict__ out) {
-    __shared__ double sh[K][kBlock / 64];
+    __shared__ double sh[K][BT / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
@@ -249,7 +250,7 @@ __device__ __forceinline__ void block_sum_store(const double (&v)[K], double *__
     if ((int)threadIdx.x < K) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += sh[threadIdx.x][w];
+        for (int w = 0; w < BT / 64; ++w) s += sh[threadIdx.x][w];
         out[threadIdx.x] = s;
     }
 }
@@ -282,10 +283,10 @@ __device__ __forceinline__ double wave_max(double s) {
 }
 
 // Workgroup maxima of K values per thread (order-free), written by threads
-// 0..K-1 to out.
-template <int K>
+// 0..K-1 to out (BT: threads of the workgroup).
+template <int K, int BT = kBlock>
 __device__ __forceinline__ void block_max_store(const double (&v)[K], double *__restrict__ out) {
-    __shared__ double sh[K][kBlock / 64];
+    __shared__ double sh[K][BT / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
@@ -296,7 +297,7 @@ __device__ __forceinline__ void block_max_store(const double (&v)[K], double *__
     if ((int)threadIdx.x < K) {
         double s = sh[threadIdx.x][0];
 #pragma unroll
-        for (int w = 1; w < kBlock / 64; ++w) s = fmax(s, sh[threadIdx.x][w]);
+        for (int w = 1; w < BT / 64; ++w) s = fmax(s, sh[threadIdx.x][w]);
         out[threadIdx.x] = s;
     }
 }
