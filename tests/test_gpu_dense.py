@@ -56,6 +56,21 @@ def test_dense_small_step_and_solve(pdhg, oracle_lib):
     assert abs(rg["primal_obj"] - ro["primal_obj"]) <= 1e-6 * (1 + abs(ro["primal_obj"]))
 
 
+def test_dense_knapsack_shape_step_and_solve(pdhg, oracle_lib):
+    """Few long rows, as in the knapsack shape: a workgroup per four rows with
+    every lane through the unrolled loads (20,000 columns), one row split in
+    the column pass; step and solve against the oracle."""
+    _say("case: dense knapsack-shaped LP 30 x 20000, step and solve parity")
+    lp = gen.dense_knapsack_lp(d=30, items=20000, seed=2501)
+    _step(pdhg, oracle_lib, lp)
+    xo, yo, ro = oracle_lib.Oracle(lp).solve()
+    with pdhg.Solver.from_lp(lp) as s:
+        xg, yg, rg = s.solve()
+    _say(f"  iterations gpu={rg['iterations']} oracle={ro['iterations']}")
+    assert ro["status_name"] == "optimal" and rg["status_name"] == "optimal" and rg["kkt_rel"] <= 1e-4
+    assert abs(rg["primal_obj"] - ro["primal_obj"]) <= 1e-6 * (1 + abs(ro["primal_obj"]))
+
+
 def test_dense_matches_csr_path(pdhg):
     _say("case: dense and CSR storage of the same LP give the same solve")
     lp = gen.dense_planted_lp(120, 260, seed=2002)
