@@ -45,6 +45,23 @@ __device__ __forceinline__ void primal_update(int32_t r, double s, double *__res
     primal_store(r, s, primal_load(r, x, x0, c, lv, uv), x, xext, st, j, gamma);
 }
 
+// Check-iteration primal step of row r given s = (A~'y)_r: the PDHG point
+// xhat, xext = 2 xhat - x, and s kept for the checks.
+__device__ __forceinline__ void primal_chk_store(int32_t r, double s, const double *__restrict__ x,
+                                                 const double *__restrict__ c,
+                                                 const double *__restrict__ lv,
+                                                 const double *__restrict__ uv,
+                                                 double *__restrict__ xhat, double *__restrict__ xext,
+                                                 double *__restrict__ aty, const DevState *st,
+                                                 double tau_override) {
+    const double tau = tau_override > 0.0 ? tau_override : st->tau;
+    const double xr = x[r];
+    const double xh = clampd(xr - tau * (c[r] - s), lv[r], uv[r]);
+    xhat[r] = xh;
+    xext[r] = 2.0 * xh - xr;
+    aty[r] = s;
+}
+
 // Dual update of row r given a = (A~ xext)_r: dual prox and the Halpern step.
 struct DualIn {
     double y, y0, lc, uc;
@@ -199,6 +216,32 @@ __global__ __launch_bounds__(kBlock) void k_primal_panels(
     primal_store(r, panel_sum(P, r), in, x, xext, st, j, gamma);
 }
 
+// The check iteration's primal step in the panel layout: k_primal_sell and
+// k_primal_panels with the check epilogue (primal_chk_store).
+__global__ __launch_bounds__(kBlock) void k_primal_sell_chk(
+    MatView M, int32_t skip, const double *__restrict__ y, const double *__restrict__ x,
+    const double *__restrict__ c, const double *__restrict__ lv, const double *__restrict__ uv,
+    double *__restrict__ xhat, double *__restrict__ xext, double *__restrict__ aty,
+    const DevState *__restrict__ st, double tau_override) {
+    if (st->done) return;
+    const int32_t sl = skip + (int32_t)blockIdx.x * (kBlock / 64) + (int32_t)(threadIdx.x >> 6);
+    const int32_t r = M.R_long + sl * 64 + (int32_t)(threadIdx.x & 63);
+    const bool valid = sl < M.nslices && r < M.rows;
+    const RowSum rs = sell_row_dot(M, y, sl);
+    if (valid) primal_chk_store(r, rs.s, x, c, lv, uv, xhat, xext, aty, st, tau_override);
+}
+
+__global__ __launch_bounds__(kBlock) void k_primal_panels_chk(
+    PanelView P, const double *__restrict__ x, const double *__restrict__ c,
+    const double *__restrict__ lv, const double *__restrict__ uv, double *__restrict__ xhat,
+    double *__restrict__ xext, double *__restrict__ aty, const DevState *__restrict__ st,
+    double tau_override) {
+    if (st->done) return;
+    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (r >= P.R) return;
+    primal_chk_store(r, panel_sum(P, r), x, c, lv, uv, xhat, xext, aty, st, tau_override);
+}
+
 // Dual step over the SELL-64 slices of A~ with x_ext[0, H) staged in LDS
 // (columns are sorted by length, so these are the most gathered entries).
 // Persistent workgroups take the slices round robin. The sums are formed in
@@ -248,16 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_primal_chk(
     const DevState *__restrict__ st, double tau_override) {
     if (st->done) return;
     const RowSum rs = mat_row_dot(M, y);
-    const double s = rs.s;
-    if (rs.valid) {
-        const int32_t r = rs.row;
-        const double tau = tau_override > 0.0 ? tau_override : st->tau;
-        const double xr = x[r];
-        const double xh = clampd(xr - tau * (c[r] - s), lv[r], uv[r]);
-        xhat[r] = xh;
-        xext[r] = 2.0 * xh - xr;
-        aty[r] = s;
-    }
+    if (rs.valid) primal_chk_store(rs.row, rs.s, x, c, lv, uv, xhat, xext, aty, st, tau_override);
 }
 
 __global__ __launch_bounds__(kBlock) void k_dual_chk(
@@ -667,6 +701,23 @@ void launch_primal_check(Handle &h, double tau_override) {
         return;
     }
     if (h.AT.nblocks() == 0) return;
+    if (h.PT.R > 0) {
+        // as launch_primal: the panel rows on stream2 beside the SELL-64 rest
+        PDHG_HIP(hipEventRecord(h.ev_fork, h.stream));
+        PDHG_HIP(hipStreamWaitEvent(h.stream2, h.ev_fork, 0));
+        const PanelView P = view(h.PT);
+        k_panel_dot<<<h.PT.nwg, kPanelThreads, 0, h.stream2>>>(P, h.y.p, h.st.p);
+        k_primal_panels_chk<<<(unsigned)ceil_div(h.PT.R, kBlock), kBlock, 0, h.stream2>>>(
+            P, h.x.p, h.c.p, h.lv.p, h.uv.p, h.xhat.p, h.xext.p, h.aty.p, h.st.p, tau_override);
+        PDHG_HIP(hipEventRecord(h.ev_join, h.stream2));
+        const int32_t ns = h.AT.nslices - h.sell_skip;
+        if (ns > 0)
+            k_primal_sell_chk<<<(unsigned)ceil_div(ns, kBlock / 64), kBlock, 0, h.stream>>>(
+                view(h.AT), h.sell_skip, h.y.p, h.x.p, h.c.p, h.lv.p, h.uv.p, h.xhat.p, h.xext.p,
+                h.aty.p, h.st.p, tau_override);
+        PDHG_HIP(hipStreamWaitEvent(h.stream, h.ev_join, 0));
+        return;
+    }
     k_primal_chk<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
         view(h.AT), h.y.p, h.x.p, h.c.p, h.lv.p, h.uv.p,
         h.xhat.p, h.xext.p, h.aty.p, h.st.p, tau_override);
