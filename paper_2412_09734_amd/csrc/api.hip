@@ -463,6 +463,7 @@ pdhg_err pdhg_create(const pdhg_problem *prob, const pdhg_options *opt, void *st
             qp_estimate_norm(h);
         } else if (!h.dense) {
             build_fast_layouts(h);
+            h.nbn = check_n_blocks(h);
             if (h.PT.R > 0) {
                 PDHG_HIP(hipStreamCreateWithFlags(&h.stream2, hipStreamNonBlocking));
                 PDHG_HIP(hipEventCreateWithFlags(&h.ev_fork, hipEventDisableTiming));

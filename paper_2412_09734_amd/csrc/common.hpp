@@ -330,6 +330,7 @@ void dense_check_sums(Handle &h);
 void dense_rows_sq(Handle &h, const double *v, double *out, double *partials);
 void dense_cols_sq(Handle &h, const double *w, double *out, double *partials);
 int32_t dense_row_blocks(const Handle &h);
+int32_t check_n_blocks(const Handle &h);
 int32_t dense_col_blocks(const Handle &h);
 void launch_factors(Handle &h, double *rn, double *cn);
 

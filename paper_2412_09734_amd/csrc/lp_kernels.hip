@@ -315,6 +315,33 @@ __global__ __launch_bounds__(kBlock) void k_dual_chk(
 // A'dy = (q - A~'y0) / D_c), per workgroup into rays[4]: sums of the dual
 // ray's l_v'lam+ - u_v'lam- and of c'dx, maxima of |g - lam| and of the
 // distance of dx to the recession cone of [l_v, u_v]. q is kept in qhat.
+// Column side of a check for row r of A~' given q = (A~'yhat)_r (see k_check_n).
+__device__ __forceinline__ void check_n_terms(
+    int32_t r, double q, const double *__restrict__ xhat, const double *__restrict__ x,
+    const double *__restrict__ x0, const double *__restrict__ aty, const double *__restrict__ Dc,
+    const double *__restrict__ c_o, const double *__restrict__ lv_o, const double *__restrict__ uv_o,
+    const double *__restrict__ q0, double *__restrict__ qhat, double (&v)[6], double (&rsum)[2],
+    double (&rmax)[2]) {
+    const double xh = xhat[r];
+    const double dx = xh - x[r];
+    v[0] = dx * dx;
+    v[1] = (q - aty[r]) * dx;
+    const double d0 = xh - x0[r];
+    v[2] = d0 * d0;
+    const double d = Dc[r];
+    const double xo = d * xh;
+    const double g = c_o[r] - q / d;
+    const double lo = lv_o[r], hi = uv_o[r];
+    const bool lf = isfinite(lo), uf = isfinite(hi);
+    const double lam = (!lf && !uf) ? 0.0 : (lf && !uf) ? fmax(g, 0.0) : (!lf && uf) ? fmin(g, 0.0) : g;
+    const double rd = g - lam;
+    v[3] = rd * rd;
+    v[4] = c_o[r] * xo;
+    v[5] = (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
+    qhat[r] = q;
+    ray_col_terms(q, q0[r], d, d0, c_o[r], lo, hi, rsum, rmax);
+}
+
 __global__ __launch_bounds__(kBlock) void k_check_n(
     MatView M, const double *__restrict__ yhat, const double *__restrict__ xhat,
     const double *__restrict__ x, const double *__restrict__ x0, const double *__restrict__ aty,
@@ -324,33 +351,54 @@ __global__ __launch_bounds__(kBlock) void k_check_n(
     const DevState *__restrict__ st) {
     if (st->done) return;
     const RowSum rs = mat_row_dot(M, yhat);
-    const double q = rs.s;
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double rsum[2] = {0.0, 0.0}, rmax[2] = {0.0, 0.0};
-    if (rs.valid) {
-        const int32_t r = rs.row;
-        const double xh = xhat[r];
-        const double dx = xh - x[r];
-        v[0] = dx * dx;
-        v[1] = (q - aty[r]) * dx;
-        const double d0 = xh - x0[r];
-        v[2] = d0 * d0;
-        const double d = Dc[r];
-        const double xo = d * xh;
-        const double g = c_o[r] - q / d;
-        const double lo = lv_o[r], hi = uv_o[r];
-        const bool lf = isfinite(lo), uf = isfinite(hi);
-        const double lam = (!lf && !uf) ? 0.0 : (lf && !uf) ? fmax(g, 0.0) : (!lf && uf) ? fmin(g, 0.0) : g;
-        const double rd = g - lam;
-        v[3] = rd * rd;
-        v[4] = c_o[r] * xo;
-        v[5] = (lf ? lo * fmax(lam, 0.0) : 0.0) - (uf ? hi * fmax(-lam, 0.0) : 0.0);
-        qhat[r] = q;
-        ray_col_terms(q, q0[r], d, d0, c_o[r], lo, hi, rsum, rmax);
-    }
+    if (rs.valid)
+        check_n_terms(rs.row, rs.s, xhat, x, x0, aty, Dc, c_o, lv_o, uv_o, q0, qhat, v, rsum, rmax);
     block_sum_store<6>(v, partials + (size_t)blockIdx.x * 6);
     block_sum_store<2>(rsum, rays + (size_t)blockIdx.x * 4);
     block_max_store<2>(rmax, rays + (size_t)blockIdx.x * 4 + 2);
+}
+
+// The column side of a check in the panel layout: the SELL-64 rows from slice
+// skip on (workgroup b writes block b of the partials), and the panel rows
+// [0, R) (workgroup b writes block b0 + b), each with k_check_n's terms.
+__global__ __launch_bounds__(kBlock) void k_check_n_sell(
+    MatView M, int32_t skip, const double *__restrict__ yhat, const double *__restrict__ xhat,
+    const double *__restrict__ x, const double *__restrict__ x0, const double *__restrict__ aty,
+    const double *__restrict__ Dc, const double *__restrict__ c_o, const double *__restrict__ lv_o,
+    const double *__restrict__ uv_o, double *__restrict__ partials,
+    const double *__restrict__ q0, double *__restrict__ qhat, double *__restrict__ rays,
+    const DevState *__restrict__ st) {
+    if (st->done) return;
+    const int32_t sl = skip + (int32_t)blockIdx.x * (kBlock / 64) + (int32_t)(threadIdx.x >> 6);
+    const int32_t r = M.R_long + sl * 64 + (int32_t)(threadIdx.x & 63);
+    const bool valid = sl < M.nslices && r < M.rows;
+    const RowSum rs = sell_row_dot(M, yhat, sl);
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double rsum[2] = {0.0, 0.0}, rmax[2] = {0.0, 0.0};
+    if (valid) check_n_terms(r, rs.s, xhat, x, x0, aty, Dc, c_o, lv_o, uv_o, q0, qhat, v, rsum, rmax);
+    block_sum_store<6>(v, partials + (size_t)blockIdx.x * 6);
+    block_sum_store<2>(rsum, rays + (size_t)blockIdx.x * 4);
+    block_max_store<2>(rmax, rays + (size_t)blockIdx.x * 4 + 2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_n_panels(
+    PanelView P, int32_t b0, const double *__restrict__ xhat, const double *__restrict__ x,
+    const double *__restrict__ x0, const double *__restrict__ aty, const double *__restrict__ Dc,
+    const double *__restrict__ c_o, const double *__restrict__ lv_o, const double *__restrict__ uv_o,
+    double *__restrict__ partials, const double *__restrict__ q0, double *__restrict__ qhat,
+    double *__restrict__ rays, const DevState *__restrict__ st) {
+    if (st->done) return;
+    const int32_t r = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double rsum[2] = {0.0, 0.0}, rmax[2] = {0.0, 0.0};
+    if (r < P.R)
+        check_n_terms(r, panel_sum(P, r), xhat, x, x0, aty, Dc, c_o, lv_o, uv_o, q0, qhat, v, rsum, rmax);
+    const size_t b = (size_t)b0 + blockIdx.x;
+    block_sum_store<6>(v, partials + b * 6);
+    block_sum_store<2>(rsum, rays + b * 4);
+    block_max_store<2>(rmax, rays + b * 4 + 2);
 }
 
 // Row side of a check: p = A~ xhat. Sums:
@@ -733,16 +781,42 @@ void launch_dual_check(Handle &h, double sigma_override) {
                                                       h.uc.p, h.yhat.p, h.st.p, sigma_override);
 }
 
+// Blocks of column-side check partials that launch_check_sums writes.
+int32_t check_n_blocks(const Handle &h) {
+    if (h.PT.R == 0) return h.AT.nblocks();
+    const int32_t ns = h.AT.nslices - h.sell_skip;
+    return (ns > 0 ? (int32_t)ceil_div(ns, kBlock / 64) : 0) + (int32_t)ceil_div(h.PT.R, kBlock);
+}
+
 void launch_check_sums(Handle &h) {
     if (h.dense) {
         dense_check_sums(h);
         return;
     }
-    if (h.AT.nblocks())
+    if (h.AT.nblocks() && h.PT.R > 0) {
+        // as launch_primal: the panel rows on stream2 beside the SELL-64 rest;
+        // block partials [0, sell blocks) from the rest, then the panel rows'
+        const PanelView P = view(h.PT);
+        const int32_t ns = h.AT.nslices - h.sell_skip;
+        const int32_t sell_blocks = ns > 0 ? (int32_t)ceil_div(ns, kBlock / 64) : 0;
+        PDHG_HIP(hipEventRecord(h.ev_fork, h.stream));
+        PDHG_HIP(hipStreamWaitEvent(h.stream2, h.ev_fork, 0));
+        k_panel_dot<<<h.PT.nwg, kPanelThreads, 0, h.stream2>>>(P, h.yhat.p, h.st.p);
+        k_check_n_panels<<<(unsigned)ceil_div(h.PT.R, kBlock), kBlock, 0, h.stream2>>>(
+            P, sell_blocks, h.xhat.p, h.x.p, h.x0.p, h.aty.p, h.Dc.p, h.c_o.p, h.lv_o.p, h.uv_o.p,
+            h.pn.p, h.q0.p, h.qhat.p, h.prn.p, h.st.p);
+        PDHG_HIP(hipEventRecord(h.ev_join, h.stream2));
+        if (sell_blocks > 0)
+            k_check_n_sell<<<(unsigned)sell_blocks, kBlock, 0, h.stream>>>(
+                view(h.AT), h.sell_skip, h.yhat.p, h.xhat.p, h.x.p, h.x0.p, h.aty.p, h.Dc.p,
+                h.c_o.p, h.lv_o.p, h.uv_o.p, h.pn.p, h.q0.p, h.qhat.p, h.prn.p, h.st.p);
+        PDHG_HIP(hipStreamWaitEvent(h.stream, h.ev_join, 0));
+    } else if (h.AT.nblocks()) {
         k_check_n<<<grid_of(h.AT), kBlock, 0, h.stream>>>(
             view(h.AT), h.yhat.p, h.xhat.p, h.x.p,
             h.x0.p, h.aty.p, h.Dc.p, h.c_o.p, h.lv_o.p, h.uv_o.p, h.pn.p, h.q0.p, h.qhat.p,
             h.prn.p, h.st.p);
+    }
     if (h.A.nblocks())
         k_check_m<<<grid_of(h.A), kBlock, 0, h.stream>>>(
             view(h.A), h.xhat.p, h.yhat.p, h.y.p, h.y0.p,

@@ -950,7 +950,9 @@ void estimate_steps(Handle &h) {
         // q = A~' u_k - alpha_k v_k, beta_k = |q|, v_{k+1} = q / beta_k. lam_k is
         // the largest eigenvalue of B_k'B_k; the host checks it every 16 steps.
         const int maxit = std::max(1, h.opt.power_max_iters);
-        const int32_t nbA = h.nbm, nbT = h.nbn;
+        // workgroups of the products: the standard layout's blocks (CSR), the
+        // dense passes' row and column blocks (dense)
+        const int32_t nbA = h.dense ? h.nbm : h.A.nblocks(), nbT = h.dense ? h.nbn : h.AT.nblocks();
         const MatView VA = view(h.A), VT = view(h.AT);
         auto mul_a = [&](const double *vin, double *wout, double *part) {
             if (h.dense) dense_rows_sq(h, vin, wout, part);
