@@ -128,9 +128,10 @@ typedef struct {
      * of the second, with the KKT terms of that point. */
     int32_t feasibility_polishing;
     double eps_feas_polish;
-    /* Layouts of the plain-iteration products of a large CSR constraint matrix
-     * (the checks keep the standard layout; results differ only in the order
-     * of summation). -1 selects the automatic choice.
+    /* Layouts of the iteration products of a large CSR constraint matrix
+     * (the panels serve the checks' products with A~' too, the checks'
+     * products with A~ keep the standard layout; results differ only in the
+     * order of summation). -1 selects the automatic choice.
      * panel_rows: entries of y staged in LDS per panel for the product A~'y
      *   over the longest rows of A~' (auto: 20480 when m > 262144, else off;
      *   0: off; at most 20480);

@@ -258,7 +258,8 @@ struct Handle {
     bool dense = false;
     DBuf<double> Ad, dpart;
     int32_t nbn = 0, nbm = 0;            // workgroups of the column / row check passes
-    // plain-iteration layouts of a large sparse A~ (the check kernels keep A, AT):
+    // iteration layouts of a large sparse A~ (the check iterations use them for
+    // their products with A~' as well; those with A~ run on A):
     // LDS panels for the long rows of A~' (their products run beside the SELL-64
     // rest of A~' on stream2), and the leading x_ext entries staged in LDS by
     // the dual product
